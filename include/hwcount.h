@@ -1,0 +1,172 @@
+/*
+ * hwcount.h -- C ABI of libhwcount.so: Hasse-Weil point counts of
+ * hyperelliptic curves over small finite fields on MI355X (gfx950).
+ *
+ * For a curve C_f : y^2 = f(X) = sum_{i<=2g+2} a_i X^i over F_q (q odd,
+ * f square-free of degree 2g+1 or 2g+2; Sec. 1.1 of Raum, "Hyperelliptic
+ * Curves over Small Finite Fields and GPU Accelerators") the library returns
+ * N_k = #C_f(F_{q^k}) for k = 1..g, counted on the model in the weighted
+ * projective plane P(1, g+1, 1):
+ *
+ *   N_k = r^0 + 2 r^square + (1 + chi(a_{2g+2}))        (decomposition of Sec. 1.1)
+ *
+ * with r^0 the roots of f in F_{q^k}, r^square the x with f(x) a nonzero
+ * square, and the last term the points at infinity (one when deg f = 2g+1,
+ * two or none when deg f = 2g+2).  The Hasse-Weil invariant of eq. (1.1) is
+ * a_k = q^k + 1 - N_k.  It also returns the histogram of the tuples
+ * (N_1..N_g), i.e. the a-tuple part of the map N_{g,q} of eq. (1.2), with
+ * every input row counted once.
+ *
+ * Evaluation uses Zech-logarithm arithmetic (Sec. 2.3, encoding (3.1),
+ * table (3.2)) in HIP kernels; every N_k is an exact integer.
+ *
+ * Coefficient codes.  A coefficient is an integer code c in [0, q).  For
+ * q = p^e with e > 1, c = sum_i d_i p^i (0 <= d_i < p) stands for
+ * sum_i d_i t^i in F_p[t]/(P_q) with P_q the lexicographically first
+ * primitive monic polynomial of degree e over F_p (monic polynomials
+ * t^e + b_{e-1} t^{e-1} + ... + b_0 ranked by the integer sum_i b_i p^i).
+ * Rows are a_0 .. a_{2g+2}, constant term first, row-major [n][2g+3].
+ *
+ * Ownership.  The caller owns every input and output buffer; the library
+ * owns its tables and scratch memory.  Functions return HWC_OK (0) or a
+ * negative HWC_ERR_* code; hwc_last_error() gives a message.  Calls on one
+ * context are serialised internally.  Supported: 1 <= g <= 4, and fields
+ * whose tables fit the 160 KiB LDS of one CU (F_{q^g} with q^g - 1 <= 32767,
+ * e.g. q = 13 for g = 4, q = 31 for g = 3, q = 181 for g = 2).
+ */
+#ifndef HWCOUNT_H
+#define HWCOUNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HWC_OK 0
+#define HWC_ERR_NOT_ODD_PRIME_POWER (-1) /* q (or p) is not an odd prime power (prime) */
+#define HWC_ERR_BAD_G (-2)               /* g outside 1..4 */
+#define HWC_ERR_FIELD_TOO_LARGE (-3)     /* tables of F_{q^g} exceed what the kernels hold */
+#define HWC_ERR_COEFF_RANGE (-4)         /* a code outside [0, q) */
+#define HWC_ERR_DEGREE (-5)              /* a_{2g+2} = a_{2g+1} = 0 */
+#define HWC_ERR_HIST_CAPACITY (-6)       /* histogram longer than its capacity; len holds the need */
+#define HWC_ERR_OOM_BUDGET (-7)          /* table cache would exceed the context's HBM budget */
+#define HWC_ERR_DEVICE (-8)              /* HIP error (message in hwc_last_error) */
+#define HWC_ERR_SINGULAR (-9)            /* HWC_VALIDATE found a row that is not square-free */
+#define HWC_ERR_ARG (-10)                /* null pointer, bad size or bad flag */
+#define HWC_ERR_NO_DEVICE (-11)          /* counting asked of a host-only context */
+
+/* flags */
+#define HWC_FULL_SWEEP 1u /* level k sweeps every x of F_{q^k}; default: one x per Frobenius orbit */
+#define HWC_PLAIN 2u      /* one kernel launch per (q, g, k) and a separate assembly; no graph */
+#define HWC_VALIDATE 4u   /* host checks that every row is square-free (host-pointer call only) */
+#define HWC_NO_GRAPH 8u   /* launch kernels directly instead of replaying a captured HIP graph */
+
+typedef struct hwc_ctx hwc_ctx;
+typedef struct hwc_field hwc_field;
+
+typedef struct {
+  uint32_t p, e, k, n;     /* F_Q = F_p[t]/(P), n = e*k, contains F_q, q = p^e */
+  uint64_t q, Q;
+  uint32_t modulus[41];    /* P, lex-first primitive, constant term first, modulus[n] = 1 */
+  uint32_t qmodulus[41];   /* P_q, the same for degree e */
+  uint32_t root_log;       /* log to t of the root of P_q used to embed F_q */
+  uint64_t nprim_orbits;   /* Frobenius orbits of F_Q^x of size exactly k */
+  uint64_t table_bytes;    /* host bytes of exp, log, Zech and embedding tables */
+} hwc_field_desc;
+
+/* Histogram of tuples, sorted ascending lexicographically.  The caller
+ * allocates keys (capacity*g int32) and counts (capacity uint64). */
+typedef struct {
+  uint32_t g;
+  uint64_t capacity;
+  uint64_t len;            /* out: number of distinct tuples */
+  int32_t* keys;
+  uint64_t* counts;
+} hwc_hist;
+
+/* One request of a batch: device pointers, asynchronous. */
+typedef struct {
+  uint32_t q, g;
+  const void* d_coeffs;    /* [n][2g+3] codes, int8 (coeff_bytes 1, q <= 127) or int16 (2) */
+  int coeff_bytes;
+  uint64_t n;
+  int32_t* d_out_N;        /* [n][g]; required */
+  int32_t* d_hist_keys;    /* [hist_capacity][g] or NULL (no histogram) */
+  uint64_t* d_hist_counts; /* [hist_capacity] */
+  uint64_t hist_capacity;
+  uint64_t* d_hist_len;    /* device uint64: number of distinct tuples */
+} hwc_job;
+
+/* Context on HIP device `device` (-1: host-only context, which builds fields
+ * but cannot count).  hbm_budget_bytes bounds the device table cache (0: no
+ * bound).  Creates its own HIP stream.  Ownership of *out passes to the
+ * caller; release it with hwc_ctx_destroy. */
+int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out);
+void hwc_ctx_destroy(hwc_ctx* ctx);
+
+/* Message for the last error on ctx ("" if none).  Valid until the next call. */
+const char* hwc_last_error(const hwc_ctx* ctx);
+
+/* Builds F_{p^(e k)} with F_{p^e} embedded (Sec. 2.3, Sec. 3.1-3.2): the
+ * lex-first primitive modulus, exp/log tables with the zero sentinel Q-1,
+ * the Zech table with the sentinel where 1 + t^L = 0, the embedding of the
+ * F_q codes and the Frobenius orbit representatives.  p must be an odd prime.
+ * Idempotent: a second call with the same (p, e, k) returns a handle to the
+ * same cached tables.  Release the handle with hwc_field_release. */
+int hwc_build_field(hwc_ctx* ctx, uint32_t p, uint32_t e, uint32_t k, hwc_field** out);
+int hwc_field_info(const hwc_field* f, hwc_field_desc* out);
+
+/* Host copies of the tables of a field (any pointer may be NULL):
+ * exp[Q-1] (packed sum_i b_i p^i of t^L), log[Q] (log[0] = Q-1),
+ * zech[Q-1] (Q-1 where 1 + t^L = 0), emb[q] (log of each F_q code, emb[0] = Q-1),
+ * prim_reps[nprim_orbits] (least log of each Frobenius orbit of size k). */
+int hwc_field_tables(const hwc_field* f, uint32_t* exp, uint32_t* log, uint32_t* zech, uint32_t* emb,
+                     uint32_t* prim_reps);
+void hwc_field_release(hwc_field* f);
+
+/* Counts n curves from host memory and waits for the result.
+ * coeffs: [n][2g+3] int16 codes.  out_N: [n][g] int32 or NULL.  out_hist:
+ * histogram or NULL (out_hist->g must equal g).  Returns HWC_ERR_COEFF_RANGE
+ * / HWC_ERR_DEGREE for a bad row, HWC_ERR_HIST_CAPACITY when out_hist is too
+ * short (out_hist->len is then the needed length; out_N is complete). */
+int hwc_count_curves(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs, uint64_t n, int32_t* out_N,
+                     hwc_hist* out_hist, uint32_t flags);
+
+/* Device-pointer form: enqueues the whole count on `stream` (a hipStream_t;
+ * NULL = the context's stream) and returns without waiting.  Row errors are
+ * found on the device and reported by hwc_ctx_status.  The histogram is
+ * written when d_hist_keys is not NULL (d_hist_len receives its length; at
+ * most hist_capacity entries are written).  Buffers must stay valid until
+ * the stream reaches this work. */
+int hwc_count_curves_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
+                         int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts, uint64_t hist_capacity,
+                         uint64_t* d_hist_len, uint32_t flags, void* stream);
+
+/* Several requests, enqueued on `stream` in order (the persistent batched
+ * form; each job is a hwc_count_curves_dev call). */
+int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);
+
+/* Waits for `stream` (NULL = context stream) and returns the first row error
+ * that device-side validation found since the last call (HWC_OK if none). */
+int hwc_ctx_status(hwc_ctx* ctx, void* stream);
+
+/* Profiling.  While enabled, every call is launched directly (no graph) and
+ * HIP events are recorded on its launch stream around three phases: curve
+ * bucketing, the count kernel(s) (with assembly in the plain form), and the
+ * histogram.  hwc_ctx_profile_read waits for the recorded events, returns the
+ * summed milliseconds of each phase and the number of calls, and resets. */
+int hwc_ctx_profile(hwc_ctx* ctx, int enable);
+int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double* hist_ms, uint64_t* calls);
+
+/* Cache statistics: fields built, plans resident, device bytes of tables,
+ * hits and misses of the table cache.  Any pointer may be NULL. */
+int hwc_ctx_stats(const hwc_ctx* ctx, uint64_t* plans_resident, uint64_t* table_bytes, uint64_t* cache_hits,
+                  uint64_t* cache_misses);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWCOUNT_H */

@@ -1,0 +1,313 @@
+// Histogram of point-count tuples (the multiplicities of eq. 1.2, without the
+// factorization partition): every curve's (N_1..N_g) becomes one integer key
+// in mixed radix with N_1 most significant, keys are sorted by a stable LSD
+// radix sort, equal runs are merged, and the keys are decoded back into
+// tuples.  The result is in lexicographic order of the tuples.
+//
+// Radix R_k = 2 q^k + 3 covers every possible N_k (at most two affine points
+// per x and two at infinity), so the key needs no Weil bound and stays valid
+// for any input row.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hwc {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
+constexpr int kRadixBits = 8;
+constexpr int kRadixBins = 1 << kRadixBits;
+constexpr int kScanTile = 4096;
+
+struct KeyRadix {
+  uint32_t g;
+  uint64_t radix[4];   // R_k
+};
+
+__global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N, uint64_t n, KeyRadix kr,
+                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+  uint32_t bad = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t key = 0;
+    for (uint32_t k = 0; k < kr.g; ++k) {
+      int32_t v = N[i * kr.g + k];
+      if (v < 0 || (uint64_t)v >= kr.radix[k]) { bad = 1; v = 0; }
+      key = key * kr.radix[k] + (uint64_t)v;
+    }
+    keys[i] = key;
+  }
+  if (bad) atomicOr(err, 4u);
+}
+
+// ---- device-wide exclusive scan of u32 (chunks of kScanTile) ----
+
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  // sh: blockDim.x entries
+  const uint32_t t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (uint32_t off = 1; off < blockDim.x; off <<= 1) {
+    const uint32_t a = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const uint32_t incl = sh[t];
+  *total = sh[blockDim.x - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* __restrict__ in, uint64_t n,
+                                                          uint32_t* __restrict__ sums) {
+  __shared__ uint32_t sh[256];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t s = 0;
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kScanTile; j += blockDim.x) {
+    const uint64_t i = base + j;
+    if (i < n) s += in[i];
+  }
+  uint32_t tot;
+  block_exclusive_scan(s, sh, &tot);
+  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// exclusive scan of sums[0..nb) in place (one block, nb <= 1024*64); total to *total
+__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ sums, uint32_t nb,
+                                                        uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t per = (nb + blockDim.x - 1) / blockDim.x;
+  const uint32_t lo = threadIdx.x * per;
+  uint32_t s = 0;
+  for (uint32_t j = 0; j < per; ++j)
+    if (lo + j < nb) s += sums[lo + j];
+  uint32_t tot;
+  uint32_t off = block_exclusive_scan(s, sh, &tot);
+  for (uint32_t j = 0; j < per; ++j)
+    if (lo + j < nb) {
+      const uint32_t v = sums[lo + j];
+      sums[lo + j] = off;
+      off += v;
+    }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
+// in and out may be the same array: each thread reads its own run before writing it
+__global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uint64_t n,
+                                                         const uint32_t* __restrict__ offs, uint32_t* out) {
+  __shared__ uint32_t sh[256];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  constexpr uint32_t per = kScanTile / 256;
+  uint32_t v[per];
+  uint32_t s = 0;
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint64_t i = base + threadIdx.x * per + j;
+    v[j] = i < n ? in[i] : 0u;
+    s += v[j];
+  }
+  uint32_t tot;
+  uint32_t off = block_exclusive_scan(s, sh, &tot) + offs[blockIdx.x];
+  for (uint32_t j = 0; j < per; ++j) {
+    const uint64_t i = base + threadIdx.x * per + j;
+    if (i < n) out[i] = off;
+    off += v[j];
+  }
+}
+
+// ---- stable LSD radix sort of u64 keys ----
+
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+                                                                  uint32_t shift, uint32_t nblocks,
+                                                                  uint32_t* __restrict__ bh) {
+  __shared__ uint32_t cnt[kRadixBins];
+  for (uint32_t i = threadIdx.x; i < kRadixBins; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile; j += blockDim.x) {
+    const uint64_t i = base + j;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+  }
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + blockIdx.x] = cnt[d];
+}
+
+// Keys of a block are ranked in 16 rounds of 256 (round-major = index order).
+// Within a round: lanes with equal digits are found by bit ballots, waves are
+// ordered through per-wave digit counts in LDS.
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const uint64_t* __restrict__ in, uint64_t n,
+                                                                     uint32_t shift, uint32_t nblocks,
+                                                                     const uint32_t* __restrict__ bh_scanned,
+                                                                     uint64_t* __restrict__ out) {
+  constexpr int kWaves = kSortThreads / 64;
+  __shared__ uint32_t running[kRadixBins];
+  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  for (uint32_t d = t; d < kRadixBins; d += blockDim.x) running[d] = bh_scanned[(uint64_t)d * nblocks + blockIdx.x];
+  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + t;
+    const bool valid = i < n;
+    const uint64_t key = valid ? in[i] : 0ull;
+    const uint32_t dig = (uint32_t)((key >> shift) & (kRadixBins - 1));
+    for (uint32_t d = t; d < (uint32_t)(kWaves * kRadixBins); d += blockDim.x) (&wcnt[0][0])[d] = 0;
+    __syncthreads();
+    // peers: valid lanes of this wave with the same digit
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+      const uint64_t ones = __ballot(((dig >> b) & 1u) != 0);
+      peers &= ((dig >> b) & 1u) ? ones : ~ones;
+    }
+    const uint32_t rank_w = (uint32_t)__popcll(peers & lt);
+    if (valid && rank_w == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = running[dig] + rank_w;
+      for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][dig];
+      out[pos] = key;
+    }
+    __syncthreads();
+    for (uint32_t d = t; d < kRadixBins; d += blockDim.x) {
+      uint32_t s = 0;
+      for (int w = 0; w < kWaves; ++w) s += wcnt[w][d];
+      running[d] += s;
+    }
+    __syncthreads();
+  }
+}
+
+// ---- run-length encoding of sorted keys ----
+
+__global__ __launch_bounds__(256) void head_flags_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+                                                         uint32_t* __restrict__ flags) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+}
+
+// For each run head i (pos = its run index): decode key into the tuple and
+// store the run start; counts are finished by runs_count_kernel.
+__global__ __launch_bounds__(256) void runs_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+                                                   const uint32_t* __restrict__ flags,
+                                                   const uint32_t* __restrict__ pos, KeyRadix kr, uint64_t cap,
+                                                   int32_t* __restrict__ out_keys, uint64_t* __restrict__ starts) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    if (!flags[i]) continue;
+    const uint64_t j = pos[i];
+    starts[j] = i;
+    if (j < cap) {
+      uint64_t key = keys[i];
+      for (int k = (int)kr.g - 1; k >= 0; --k) {
+        out_keys[j * kr.g + k] = (int32_t)(key % kr.radix[k]);
+        key /= kr.radix[k];
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void runs_count_kernel(const uint64_t* __restrict__ starts,
+                                                         const uint32_t* __restrict__ nruns_p, uint64_t n,
+                                                         uint64_t cap, uint64_t* __restrict__ out_counts,
+                                                         uint64_t* __restrict__ out_len) {
+  const uint64_t D = *nruns_p;
+  for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < D && j < cap;
+       j += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t end = (j + 1 < D) ? starts[j + 1] : n;
+    out_counts[j] = end - starts[j];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && out_len) *out_len = D;
+}
+
+__global__ void hist_empty_kernel(uint64_t* out_len) {
+  if (threadIdx.x == 0) *out_len = 0;
+}
+
+// ----------------------------------------------------------------------------
+
+static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap) {
+  const uint64_t b = (n + block - 1) / block;
+  return (uint32_t)(b < cap ? (b ? b : 1) : cap);
+}
+
+// bytes of scratch needed by hist_run for n keys
+uint64_t hist_scratch_bytes(uint64_t n) {
+  const uint64_t nb_sort = (n + kSortTile - 1) / kSortTile;
+  const uint64_t nbh = nb_sort * kRadixBins;
+  const uint64_t big = (n > nbh ? n : nbh);
+  const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
+  return 2 * n * 8                 // keys ping-pong
+         + nbh * 4                 // block histograms
+         + 2 * n * 4               // flags, pos
+         + n * 8                   // run starts
+         + nsums * 4 + 64;         // scan block sums, totals
+}
+
+static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* sums, uint32_t* total,
+                                 hipStream_t s) {
+  const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
+  if (nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, in, n, sums);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, sums, nb, total);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(256), 0, s, in, n, sums, out);
+  return hipGetLastError();
+}
+
+// Histogram of N[n][g] into out_keys[cap][g] / out_counts[cap]; *out_len gets
+// the number of distinct tuples (which may exceed cap: then only the first
+// cap are written).  scratch: hist_scratch_bytes(n) bytes.  err |= 4 when a
+// value lies outside its radix.
+hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* scratch, int32_t* out_keys,
+                    uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err, hipStream_t s) {
+  if (g < 1 || g > 4) return hipErrorInvalidValue;
+  KeyRadix kr;
+  kr.g = g;
+  double bits = 0;
+  uint64_t qk = 1;
+  for (uint32_t k = 0; k < 4; ++k) {
+    qk *= q;
+    kr.radix[k] = (k < g) ? 2 * qk + 3 : 1;
+    if (k < g) bits += __builtin_log2((double)kr.radix[k]);
+  }
+  if (bits > 63.0) return hipErrorInvalidValue;
+  const uint32_t nbits = (uint32_t)bits + 1;
+  const uint32_t npass = (nbits + kRadixBits - 1) / kRadixBits;
+  uint8_t* p = static_cast<uint8_t*>(scratch);
+  const uint64_t nb_sort = (n + kSortTile - 1) / kSortTile;
+  const uint64_t nbh = nb_sort * kRadixBins;
+  const uint64_t big = (n > nbh ? n : nbh);
+  const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
+  uint64_t* keysA = reinterpret_cast<uint64_t*>(p); p += n * 8;
+  uint64_t* keysB = reinterpret_cast<uint64_t*>(p); p += n * 8;
+  uint64_t* starts = reinterpret_cast<uint64_t*>(p); p += n * 8;
+  uint32_t* bh = reinterpret_cast<uint32_t*>(p); p += nbh * 4;
+  uint32_t* flags = reinterpret_cast<uint32_t*>(p); p += n * 4;
+  uint32_t* pos = reinterpret_cast<uint32_t*>(p); p += n * 4;
+  uint32_t* sums = reinterpret_cast<uint32_t*>(p); p += nsums * 4;
+  uint32_t* totals = reinterpret_cast<uint32_t*>(p);
+  if (n == 0) {
+    if (out_len) hipLaunchKernelGGL(hist_empty_kernel, dim3(1), dim3(64), 0, s, out_len);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(make_keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, n, kr, keysA, err);
+  for (uint32_t pass = 0; pass < npass; ++pass) {
+    const uint32_t shift = pass * kRadixBits;
+    hipLaunchKernelGGL(radix_hist_kernel, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+                       (uint32_t)nb_sort, bh);
+    hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+                       (uint32_t)nb_sort, bh, keysB);
+    uint64_t* tmp = keysA; keysA = keysB; keysB = tmp;
+  }
+  hipLaunchKernelGGL(head_flags_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags);
+  hipError_t e = scan_exclusive(flags, n, pos, sums, totals, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(runs_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags, pos, kr, cap,
+                     out_keys, starts);
+  hipLaunchKernelGGL(runs_count_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, starts, totals, n, cap,
+                     out_counts, out_len);
+  return hipGetLastError();
+}
+
+}  // namespace hwc

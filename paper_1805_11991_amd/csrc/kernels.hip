@@ -1,0 +1,594 @@
+// Counting kernels for gfx950.
+//
+// Work layout.  One wave (64 lanes) counts 64 curves at once, one curve per
+// lane, and all lanes walk the same list of x in F_{q^j} (x is uniform, so
+// its log and every per-x quantity live in scalar registers).  Curves are
+// first bucketed by degree and zero pattern so that a wave's Horner steps are
+// uniform: zero coefficients become scalar branches, never lane divergence.
+//
+// Horner in relative log form.  For f = sum c_i X^i and x = gamma^L write
+// P_i = c_i + x P_{i+1} (P_d = c_d) and A_i = log(P_i / c_i).  Then
+//   A_i = Z(A_{i+1} + g_i L + log c_{i+1} - log c_i),
+// with Z the Zech logarithm (eq. 2.1) and g_i the distance to the previous
+// nonzero coefficient.  The per-curve constant log c_{i+1} - log c_i is
+// precomputed per lane, so each step is one add of three registers and one
+// table read from LDS.  A zero partial sum (1 + gamma^k = 0, the sentinel of
+// table (3.2)) makes the next A equal log 1 = 0.  At the end
+// f(x) = c_low x^low gamma^A, so f(x) = 0 iff A is the zero marker and the
+// quadratic character is (-1)^(A + log c_low + low L) (M = |F^x| is even).
+//
+// Classification and reduction (eq. 3.3) happen in registers: each lane keeps
+// per-level counts of zeros and of odd logs, split by the parity of low*L.
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace hwc {
+
+__device__ __forceinline__ uint32_t lds_u16(const uint8_t* base, uint32_t byte_addr) {
+  return *reinterpret_cast<const uint16_t*>(base + byte_addr);
+}
+
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ----------------------------------------------------------------------------
+// utility
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ----------------------------------------------------------------------------
+// classification: validate rows, compute the pattern of each row and the
+// number of rows per pattern.
+
+template <typename CT>
+__global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t q,
+                                                       uint32_t g, uint16_t* __restrict__ pid,
+                                                       uint32_t* __restrict__ counts, uint32_t* __restrict__ err) {
+  extern __shared__ uint32_t hist[];
+  const uint32_t npat = pattern_count(g);
+  const uint32_t nc = 2 * g + 3;
+  for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  uint32_t bad = 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const CT* row = codes + i * nc;
+    uint32_t mask = 0;
+    const int top = (int)row[nc - 1], sub = (int)row[nc - 2];
+    const uint32_t d = top ? nc - 1 : nc - 2;
+    for (uint32_t j = 0; j < nc; ++j) {
+      const int c = (int)row[j];
+      if (c < 0 || c >= (int)q) bad |= 1u;
+      if (j < d && c != 0) mask |= 1u << j;
+    }
+    if (top == 0 && sub == 0) bad |= 2u;
+    const uint32_t pat = (top ? (1u << (nc - 1)) : 0u) | mask;
+    pid[i] = (uint16_t)pat;
+    atomicAdd(&hist[pat], 1u);
+  }
+  if (bad) atomicOr(err, bad);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x)
+    if (hist[i]) atomicAdd(&counts[i], hist[i]);
+}
+
+// Exclusive scans over patterns (one block of 1024 threads, npat <= 2048).
+__global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, uint32_t npat,
+                                                           uint32_t* __restrict__ bucket_start,
+                                                           uint32_t* __restrict__ tile_start,
+                                                           uint32_t* __restrict__ cursor,
+                                                           uint32_t* __restrict__ ntiles,
+                                                           uint32_t* __restrict__ queue) {
+  __shared__ uint32_t sc[2048], st[2048];
+  for (uint32_t i = threadIdx.x; i < 2048; i += blockDim.x) {
+    const uint32_t c = i < npat ? counts[i] : 0;
+    sc[i] = c;
+    st[i] = (c + kWave - 1) / kWave;
+  }
+  __syncthreads();
+  // Hillis-Steele inclusive scans
+  for (uint32_t off = 1; off < 2048; off <<= 1) {
+    uint32_t a[2], b[2];
+    for (int r = 0; r < 2; ++r) {
+      const uint32_t i = threadIdx.x + r * 1024;
+      a[r] = (i >= off) ? sc[i - off] : 0;
+      b[r] = (i >= off) ? st[i - off] : 0;
+    }
+    __syncthreads();
+    for (int r = 0; r < 2; ++r) {
+      const uint32_t i = threadIdx.x + r * 1024;
+      sc[i] += a[r];
+      st[i] += b[r];
+    }
+    __syncthreads();
+  }
+  for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) {
+    const uint32_t c = counts[i];
+    bucket_start[i] = sc[i] - c;
+    tile_start[i] = st[i] - (c + kWave - 1) / kWave;
+    cursor[i] = 0;
+  }
+  if (threadIdx.x == 0) {
+    *ntiles = st[2047];
+    *queue = 0;
+  }
+}
+
+// tiles[t] for every tile t < ntiles: binary search of the owning pattern
+__global__ void tile_fill_kernel(const uint32_t* __restrict__ counts, const uint32_t* __restrict__ bucket_start,
+                                 const uint32_t* __restrict__ tile_start, uint32_t npat,
+                                 const uint32_t* __restrict__ ntiles, uint64_t* __restrict__ tiles) {
+  const uint32_t nt = *ntiles;
+  for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = npat;  // last pattern with tile_start <= t and a nonzero count
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (tile_start[mid] <= t) lo = mid; else hi = mid;
+    }
+    // tile_start is non-decreasing; skip empty patterns sharing the start
+    uint32_t p = lo;
+    while (p > 0 && counts[p] == 0) --p;
+    const uint32_t k = t - tile_start[p];
+    const uint32_t start = bucket_start[p] + k * kWave;
+    const uint32_t rem = counts[p] - k * kWave;
+    tiles[t] = tile_pack(p, start, rem < (uint32_t)kWave ? rem : (uint32_t)kWave);
+  }
+}
+
+// perm: rows grouped by pattern.  Ranks are taken in LDS first so the global
+// cursor of a pattern sees one atomic per block.
+constexpr int kScatterPerThread = 16;
+__global__ __launch_bounds__(256) void scatter_kernel(const uint16_t* __restrict__ pid, uint64_t n, uint32_t npat,
+                                                      const uint32_t* __restrict__ bucket_start,
+                                                      uint32_t* __restrict__ cursor, uint32_t* __restrict__ perm) {
+  extern __shared__ uint32_t sh[];
+  uint32_t* cnt = sh;          // npat
+  uint32_t* base = sh + npat;  // npat
+  for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const uint64_t chunk0 = (uint64_t)blockIdx.x * blockDim.x * kScatterPerThread;
+  uint32_t rank[kScatterPerThread];
+  uint32_t pat[kScatterPerThread];
+#pragma unroll
+  for (int r = 0; r < kScatterPerThread; ++r) {
+    const uint64_t i = chunk0 + (uint64_t)r * blockDim.x + threadIdx.x;
+    if (i < n) {
+      pat[r] = pid[i];
+      rank[r] = atomicAdd(&cnt[pat[r]], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x)
+    base[i] = cnt[i] ? atomicAdd(&cursor[i], cnt[i]) : 0u;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kScatterPerThread; ++r) {
+    const uint64_t i = chunk0 + (uint64_t)r * blockDim.x + threadIdx.x;
+    if (i < n) perm[bucket_start[pat[r]] + base[pat[r]] + rank[r]] = (uint32_t)i;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// the count
+
+struct LevelCounts {
+  uint32_t z0, z1, o0, o1;  // zeros / odd logs, split by parity of low*L
+  uint32_t n1;              // x with odd low*L (uniform)
+  __device__ __forceinline__ void add(uint32_t cls, uint32_t z, uint32_t o) {
+    z1 += cls ? z : 0u;
+    o1 += cls ? o : 0u;
+    z0 += cls ? 0u : z;
+    o0 += cls ? 0u : o;
+    n1 += cls;
+  }
+};
+
+// Form A: byte-unit table, zero region; one add + one read per step.
+// del[i] already holds 2*delta_i + table offset.
+template <int NC, bool FULL, int D>
+__device__ __forceinline__ void sweep_form_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&del)[NC],
+                                             uint32_t d, uint32_t mask, LevelCounts& c) {
+  const uint32_t M = L.M, S = 6 * M;
+  const uint32_t nx = L.nx;
+  const uint32_t* xs = L.xs;
+  uint32_t ix = 0;
+  for (; ix + 2 <= nx; ix += 2) {
+    const uint32_t x0 = xs ? xs[ix] : ix;
+    const uint32_t x1 = xs ? xs[ix + 1] : ix + 1;
+    uint32_t a0 = 0, a1 = 0;
+    if (FULL) {
+      const uint32_t b0 = 2 * x0, b1 = 2 * x1;
+#pragma unroll
+      for (int i = D - 1; i >= 0; --i) {
+        a0 = lds_u16(lds, a0 + del[i] + b0);
+        a1 = lds_u16(lds, a1 + del[i] + b1);
+      }
+      c.z0 += (a0 == S) + (a1 == S);
+      c.o0 += ((a0 >> 1) & 1u) + ((a1 >> 1) & 1u);
+    } else {
+      uint32_t p0 = 0, p1 = 0;  // pending powers of x (element units, scalar)
+#pragma unroll
+      for (int i = NC - 2; i >= 0; --i) {
+        if ((uint32_t)i < d) {
+          p0 += x0; p0 = p0 >= M ? p0 - M : p0;
+          p1 += x1; p1 = p1 >= M ? p1 - M : p1;
+          if ((mask >> i) & 1u) {
+            a0 = lds_u16(lds, a0 + del[i] + 2 * p0);
+            a1 = lds_u16(lds, a1 + del[i] + 2 * p1);
+            p0 = 0;
+            p1 = 0;
+          }
+        }
+      }
+      const uint32_t z0 = a0 == S, z1 = a1 == S;
+      const uint32_t o0 = (a0 >> 1) & 1u, o1 = (a1 >> 1) & 1u;
+      c.add(p0 & 1u, z0, o0);
+      c.add(p1 & 1u, z1, o1);
+    }
+  }
+  if (ix < nx) {
+    const uint32_t x0 = xs ? xs[ix] : ix;
+    uint32_t a0 = 0, p0 = 0;
+#pragma unroll
+    for (int i = NC - 2; i >= 0; --i) {
+      if ((uint32_t)i < d) {
+        p0 += x0; p0 = p0 >= M ? p0 - M : p0;
+        if ((mask >> i) & 1u) {
+          a0 = lds_u16(lds, a0 + del[i] + 2 * p0);
+          p0 = 0;
+        }
+      }
+    }
+    c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
+  }
+}
+
+// Form C: element-unit table of 2M entries, index folded with one min.  The
+// zero marker M is not absorbing here, so a fast pass flags any lane that met
+// it and the x is recomputed with the exact rule (rare: about d/M per x).
+template <int NC, bool EXACT>
+__device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, uint32_t M, const uint32_t (&del)[NC],
+                                             uint32_t d, uint32_t mask, uint32_t x, uint32_t& pend, bool& hit) {
+  uint32_t a = 0, p = 0;
+#pragma unroll
+  for (int i = NC - 2; i >= 0; --i) {
+    if ((uint32_t)i < d) {
+      p += x; p = p >= M ? p - M : p;
+      if ((mask >> i) & 1u) {
+        const uint32_t idx = a + del[i] + p;           // < 3M
+        const uint32_t r = min(idx, idx - M);          // < 2M
+        const uint32_t v = lds_u16(lds, tab + 2 * r);
+        if (EXACT) a = (a == M) ? 0u : v;
+        else { hit |= (v == M); a = v; }
+        p = 0;
+      }
+    }
+  }
+  pend = p;
+  return a;
+}
+
+template <int NC>
+__device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* lds, const uint32_t (&del)[NC],
+                                             uint32_t d, uint32_t mask, LevelCounts& c) {
+  const uint32_t M = L.M, nx = L.nx, tab = L.tab_off;
+  const uint32_t* xs = L.xs;
+  for (uint32_t ix = 0; ix < nx; ix += 2) {
+    const uint32_t x0 = xs ? xs[ix] : ix;
+    const bool two = ix + 1 < nx;
+    const uint32_t x1 = two ? (xs ? xs[ix + 1] : ix + 1) : x0;
+    bool hit = false;
+    uint32_t p0, p1;
+    uint32_t a0 = horner_c<NC, false>(lds, tab, M, del, d, mask, x0, p0, hit);
+    uint32_t a1 = horner_c<NC, false>(lds, tab, M, del, d, mask, x1, p1, hit);
+    if (__ballot(hit)) {
+      a0 = horner_c<NC, true>(lds, tab, M, del, d, mask, x0, p0, hit);
+      a1 = horner_c<NC, true>(lds, tab, M, del, d, mask, x1, p1, hit);
+    }
+    c.add(p0 & 1u, a0 == M, a0 & 1u);   // M is even: the marker counts as even
+    if (two) c.add(p1 & 1u, a1 == M, a1 & 1u);
+  }
+}
+
+// Counts for one level: returns z | ns << 8 (roots and non-squares among the
+// swept x; squares are nx - z - ns).
+template <int G>
+__device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const uint32_t (&code)[2 * G + 3],
+                                uint32_t top, uint32_t mask) {
+  constexpr int NC = 2 * G + 3;
+  const uint32_t M = L.M;
+  const uint32_t d = top ? NC - 1 : NC - 2;
+  uint32_t lc[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    // nonzero codes have logs below M; only a rejected row can reach M here
+    const uint32_t v = lds_u16(lds, L.emb_off + 2 * code[i]);
+    lc[i] = v < M ? v : M - 1;
+  }
+  uint32_t prev = top ? lc[NC - 1] : lc[NC - 2];
+  uint32_t del[NC];
+#pragma unroll
+  for (int i = NC - 2; i >= 0; --i) {
+    del[i] = 0;
+    if ((uint32_t)i < d && ((mask >> i) & 1u)) {
+      uint32_t v = prev + M - lc[i];
+      v = v >= M ? v - M : v;
+      del[i] = v;
+      prev = lc[i];
+    }
+  }
+  del[NC - 1] = 0;
+  const uint32_t blane = prev & 1u;  // parity of log c_low
+  LevelCounts c = {0, 0, 0, 0, 0};
+  const bool full = mask == ((1u << d) - 1u);
+  if (L.form == kFormA) {
+#pragma unroll
+    for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
+    if (full) {
+      if (top) sweep_form_a<NC, true, NC - 1>(L, lds, del, d, mask, c);
+      else sweep_form_a<NC, true, NC - 2>(L, lds, del, d, mask, c);
+    } else {
+      sweep_form_a<NC, false, 0>(L, lds, del, d, mask, c);
+    }
+  } else {
+    sweep_form_c<NC>(L, lds, del, d, mask, c);
+  }
+  const uint32_t n0 = L.nx - c.n1;
+  const uint32_t z = c.z0 + c.z1;
+  // chi(f(x)) = (-1)^(A + log c_low + low*L); A odd counted in o*, zeros are even
+  const uint32_t ns0 = blane ? (n0 - c.z0 - c.o0) : c.o0;
+  const uint32_t ns1 = blane ? c.o1 : (c.n1 - c.z1 - c.o1);
+  return z | ((ns0 + ns1) << 8);
+}
+
+// N_k from the per-level counts (Sec. 1.1 decomposition; x = 0 and the
+// points at infinity of the model in P(1, g+1, 1) added here).
+template <int G>
+__device__ void assemble(const PlanDesc& P, const uint32_t (&lv)[G], uint32_t c0, uint32_t ctop, uint32_t log0,
+                         uint32_t logtop, int32_t* out) {
+#pragma unroll
+  for (int k = 1; k <= G; ++k) {
+    const int chi0 = (k % 2 == 0) ? 1 : ((log0 & 1u) ? -1 : 1);
+    const int chit = (k % 2 == 0) ? 1 : ((logtop & 1u) ? -1 : 1);
+    int32_t n = (c0 == 0 ? 1 : 1 + chi0) + (ctop == 0 ? 1 : 1 + chit);
+    if (P.orbit) {
+#pragma unroll
+      for (int j = 1; j <= G; ++j) {
+        if (k % j) continue;
+        const uint32_t z = lv[j - 1] & 0xFFu, ns = lv[j - 1] >> 8;
+        const uint32_t s = P.lv[j - 1].nx - z - ns;
+        const uint32_t sq = ((k / j) % 2 == 0) ? s + ns : s;
+        n += (int32_t)(j * z + 2 * j * sq);
+      }
+    } else {
+      const uint32_t z = lv[k - 1] & 0xFFu, ns = lv[k - 1] >> 8;
+      const uint32_t s = P.lv[k - 1].nx - z - ns;
+      n += (int32_t)(z + 2 * s);
+    }
+    out[k - 1] = n;
+  }
+}
+
+template <int G, typename CT>
+__global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __restrict__ codes,
+                                                     const uint32_t* __restrict__ perm,
+                                                     const uint64_t* __restrict__ tiles,
+                                                     const uint32_t* __restrict__ ntiles_p, uint32_t* queue,
+                                                     uint32_t lvl_lo, uint32_t lvl_hi, int32_t* __restrict__ outN,
+                                                     uint32_t* __restrict__ outLv) {
+  constexpr int NC = 2 * G + 3;
+  extern __shared__ uint32_t lds32[];
+  const uint8_t* lds = reinterpret_cast<const uint8_t*>(lds32);
+  for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t ntiles = *ntiles_p;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) / kWave;
+  uint32_t t;
+  if (queue) {
+    uint32_t v = 0;
+    if (lane == 0) v = atomicAdd(queue, 1u);
+    t = uniform(v);
+  } else {
+    t = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  }
+  while (t < ntiles) {
+    const uint64_t w = tiles[t];
+    const uint32_t pat = uniform((uint32_t)(w & 0xFFFFu));
+    const uint32_t cnt = uniform((uint32_t)((w >> 16) & 0xFFFFu) + 1u);
+    const uint32_t start = uniform((uint32_t)(w >> 32));
+    if (lane < cnt) {
+      const uint32_t curve = perm[start + lane];
+      uint32_t code[NC];
+      const CT* row = codes + (uint64_t)curve * NC;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        int v = (int)row[i];
+        v = v < 0 ? 0 : (v >= (int)P.q ? (int)P.q - 1 : v);  // keeps reads in bounds on bad input
+        code[i] = (uint32_t)v;
+      }
+      const uint32_t top = (pat >> (NC - 1)) & 1u;
+      const uint32_t mask = pat & ((1u << (NC - 1)) - 1u);
+      uint32_t lv[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        lv[j] = 0;
+        if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lds, code, top, mask);
+      }
+      if (outN) {
+        const uint32_t log0 = lds_u16(lds, P.lv[0].emb_off + 2 * code[0]);
+        const uint32_t logt = lds_u16(lds, P.lv[0].emb_off + 2 * code[NC - 1]);
+        int32_t n[G];
+        assemble<G>(P, lv, code[0], code[NC - 1], log0, logt, n);
+#pragma unroll
+        for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
+      } else {
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+          if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[(uint64_t)curve * G + j] = lv[j];
+      }
+    }
+    if (queue) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(queue, 1u);
+      t = uniform(v);
+    } else {
+      t += nwaves;
+    }
+  }
+}
+
+// assembly after per-level launches
+template <int G, typename CT>
+__global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __restrict__ codes, uint64_t n,
+                                                       const uint32_t* __restrict__ lv, int32_t* __restrict__ outN) {
+  constexpr int NC = 2 * G + 3;
+  const uint16_t* emb1 = reinterpret_cast<const uint16_t*>(reinterpret_cast<const uint8_t*>(P.image) + P.lv[0].emb_off);
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const CT* row = codes + i * NC;
+    int c0 = (int)row[0], ct = (int)row[NC - 1];
+    c0 = c0 < 0 ? 0 : (c0 >= (int)P.q ? (int)P.q - 1 : c0);
+    ct = ct < 0 ? 0 : (ct >= (int)P.q ? (int)P.q - 1 : ct);
+    uint32_t l[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) l[j] = lv[i * G + j];
+    int32_t out[G];
+    assemble<G>(P, l, (uint32_t)c0, (uint32_t)ct, emb1[c0], emb1[ct], out);
+#pragma unroll
+    for (int k = 0; k < G; ++k) outN[i * G + k] = out[k];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// host-callable launchers (C++ linkage, used by capi.cpp)
+
+template <int G, typename CT>
+static hipError_t launch_count_t(const PlanDesc& P, const void* codes, const uint32_t* perm, const uint64_t* tiles,
+                                 const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi, int32_t* outN,
+                                 uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s) {
+  hipLaunchKernelGGL((count_kernel<G, CT>), dim3(grid), dim3(block), P.image_bytes, s, P,
+                     static_cast<const CT*>(codes), perm, tiles, ntiles, queue, lo, hi, outN, outLv);
+  return hipGetLastError();
+}
+
+template <int G, typename CT>
+static hipError_t allow_big_lds() {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&count_kernel<G, CT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+// Lets every count kernel use the whole 160 KiB of LDS (done once, outside
+// any graph capture).
+hipError_t prepare_kernels() {
+  hipError_t e = hipSuccess;
+#define HWC_PREP(GG)                                                  \
+  if (e == hipSuccess) e = allow_big_lds<GG, int8_t>();               \
+  if (e == hipSuccess) e = allow_big_lds<GG, int16_t>();
+  HWC_PREP(1) HWC_PREP(2) HWC_PREP(3) HWC_PREP(4)
+#undef HWC_PREP
+  return e;
+}
+
+hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, const uint32_t* perm,
+                        const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
+                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s) {
+#define HWC_CASE(GG)                                                                                          \
+  case GG:                                                                                                    \
+    return coeff_bytes == 1                                                                                   \
+               ? launch_count_t<GG, int8_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, \
+                                            block, s)                                                         \
+               : launch_count_t<GG, int16_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, \
+                                             block, s);
+  switch (P.g) {
+    HWC_CASE(1)
+    HWC_CASE(2)
+    HWC_CASE(3)
+    HWC_CASE(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HWC_CASE
+}
+
+hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+#define HWC_OCC(GG, CT) \
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, count_kernel<GG, CT>, block, lds_bytes);
+  if (coeff_bytes == 1) {
+    switch (g) { case 1: HWC_OCC(1, int8_t) case 2: HWC_OCC(2, int8_t) case 3: HWC_OCC(3, int8_t) case 4: HWC_OCC(4, int8_t) }
+  } else {
+    switch (g) { case 1: HWC_OCC(1, int16_t) case 2: HWC_OCC(2, int16_t) case 3: HWC_OCC(3, int16_t) case 4: HWC_OCC(4, int16_t) }
+  }
+#undef HWC_OCC
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,
+                           int32_t* outN, hipStream_t s) {
+  const uint32_t grid = (uint32_t)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+  if (grid == 0) return hipSuccess;
+#define HWC_ASM(GG)                                                                                             \
+  case GG:                                                                                                      \
+    if (coeff_bytes == 1)                                                                                       \
+      hipLaunchKernelGGL((assemble_kernel<GG, int8_t>), dim3(grid), dim3(256), 0, s, P,                         \
+                         static_cast<const int8_t*>(codes), n, lv, outN);                                       \
+    else                                                                                                        \
+      hipLaunchKernelGGL((assemble_kernel<GG, int16_t>), dim3(grid), dim3(256), 0, s, P,                        \
+                         static_cast<const int16_t*>(codes), n, lv, outN);                                      \
+    break;
+  switch (P.g) {
+    HWC_ASM(1) HWC_ASM(2) HWC_ASM(3) HWC_ASM(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HWC_ASM
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_t q, uint32_t g, uint16_t* pid,
+                         uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
+                         uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
+                         uint64_t max_tiles, hipStream_t s) {
+  const uint32_t npat = pattern_count(g);
+  hipError_t e = launch_fill(counts, 0, npat, s);
+  if (e != hipSuccess) return e;
+  if (n > 0) {
+    const uint32_t grid = (uint32_t)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
+    if (coeff_bytes == 1)
+      hipLaunchKernelGGL(classify_kernel<int8_t>, dim3(grid), dim3(256), npat * 4, s,
+                         static_cast<const int8_t*>(codes), n, q, g, pid, counts, err);
+    else
+      hipLaunchKernelGGL(classify_kernel<int16_t>, dim3(grid), dim3(256), npat * 4, s,
+                         static_cast<const int16_t*>(codes), n, q, g, pid, counts, err);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(bucket_scan_kernel, dim3(1), dim3(1024), 0, s, counts, npat, bucket_start, tile_start, cursor,
+                     ntiles, queue);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (n == 0) return hipSuccess;
+  {
+    const uint32_t grid = (uint32_t)((max_tiles + 255) / 256 < 4096 ? (max_tiles + 255) / 256 : 4096);
+    hipLaunchKernelGGL(tile_fill_kernel, dim3(grid), dim3(256), 0, s, counts, bucket_start, tile_start, npat, ntiles,
+                       tiles);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const uint64_t per_block = 256ull * kScatterPerThread;
+    const uint32_t grid = (uint32_t)((n + per_block - 1) / per_block);
+    hipLaunchKernelGGL(scatter_kernel, dim3(grid), dim3(256), 2 * npat * 4, s, pid, n, npat, bucket_start, cursor,
+                       perm);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace hwc

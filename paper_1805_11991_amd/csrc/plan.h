@@ -1,0 +1,58 @@
+// Device-side description of one (q, g) counting plan, shared by the HIP
+// kernels and the host code that builds it.
+//
+// A plan covers the fields F_{q^j}, j = 1..g (one "level" per field).  All
+// of its lookup tables are packed into one image that every workgroup copies
+// into LDS before it starts counting:
+//
+//   form A  (M <= 10922)  "byte units":  5M u16 entries.  Entry i < 3M holds
+//           2*Z(i mod M), or the zero marker 6M when 1 + gamma^(i mod M) = 0;
+//           entries 3M..5M-1 hold 0.  One Horner step is one add and one read.
+//   form C  (M <= 32767)  "element units": 2M u16 entries.  Entry i holds
+//           Z(i mod M), or M as the zero marker.  One Horner step is add,
+//           fold into [0, 2M), scale to bytes, read, and a marker test.
+//   emb     q u16 entries: log of the F_q code c in F_{q^j}, or M for c = 0.
+//
+// Logs are taken to the primitive element gamma of each F_{q^j}; Z is the
+// Zech logarithm Z(k) = log(1 + gamma^k) (eq. 2.1, table (3.2)).
+#pragma once
+#include <cstdint>
+
+namespace hwc {
+
+constexpr int kMaxG = 4;                 // genus handled by the kernels
+constexpr int kMaxCoef = 2 * kMaxG + 3;  // a_0 .. a_{2g+2}
+constexpr uint32_t kFormA = 0, kFormC = 1;
+constexpr uint32_t kFormAMaxM = 10922;   // 6M must fit in u16
+constexpr uint32_t kFormCMaxM = 32767;   // M must fit in 15 bits
+constexpr int kWave = 64;
+
+struct LevelDesc {
+  uint32_t M;         // |F_{q^j}^x|
+  uint32_t form;      // kFormA or kFormC
+  uint32_t tab_off;   // byte offset of the level's table in the image
+  uint32_t emb_off;   // byte offset of the level's emb table in the image
+  uint32_t nx;        // number of x logs swept at this level
+  uint32_t weight;    // points of F_{q^j} each swept x stands for (orbit size, or 1)
+  const uint32_t* xs; // x logs (device), nullptr: x runs over 0..M-1
+};
+
+struct PlanDesc {
+  uint32_t q, g, ncoef;   // ncoef = 2g+3
+  uint32_t orbit;         // 1: level j sweeps primitive Frobenius orbits of F_{q^j}
+  uint32_t image_bytes;   // LDS image size (multiple of 16)
+  const uint32_t* image;  // device copy of the image (dwords)
+  LevelDesc lv[kMaxG];
+};
+
+// A tile is up to 64 curves that share degree and zero pattern.
+// word = pattern | (count-1) << 16 | start << 32
+__host__ __device__ inline uint64_t tile_pack(uint32_t pattern, uint32_t start, uint32_t count) {
+  return (uint64_t)pattern | ((uint64_t)(count - 1) << 16) | ((uint64_t)start << 32);
+}
+
+// Pattern of a row: bit 2g+2 set when deg f = 2g+2; bits 0..d-1 mark the
+// nonzero a_i below the leading term.
+__host__ __device__ inline uint32_t pattern_count(uint32_t g) { return 1u << (2 * g + 3); }
+
+}  // namespace hwc

@@ -1,0 +1,237 @@
+"""GPU parity: libhwcount.so against the CPU oracle, element by element.
+
+Every per-curve N_k must be bit-exact, and every histogram identical to the
+oracle's (sorted distinct tuples and their multiplicities).  Inputs are the
+seeded synthetic sets of the workloads: the full enumeration of g=2 over F_5,
+slices of the g=3 and g=4 sets over F_13, and sets for other (q, g) including
+prime powers.  All four launch forms are checked: the persistent batched
+kernel (default), the plain per-level launches, each with the Frobenius-orbit
+sweep and with the full sweep.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MODES = {
+    "batched-orbit": 0,
+    "batched-full": 1,      # HWC_FULL_SWEEP
+    "plain-orbit": 2,       # HWC_PLAIN
+    "plain-full": 3,
+}
+
+
+@pytest.fixture(scope="module")
+def gctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_11991_amd import hwcount
+    ctx = hwcount.Context(device=0)
+    yield ctx
+    ctx.close()
+
+
+def _hist_np(N):
+    keys, counts = np.unique(N, axis=0, return_counts=True)
+    return keys.astype(np.int32), counts.astype(np.uint64)
+
+
+def _check(gctx, oracle_mod, q, g, curves, modes=MODES, hist=True, Nref=None):
+    if Nref is None:
+        Nref = oracle_mod.count_curves(q, g, curves)
+    kref, cref = oracle_mod.histogram(Nref) if hist else (None, None)
+    for name, flags in modes.items():
+        print(f"  mode {name} q={q} g={g} n={len(curves)}", flush=True)
+        N, H = gctx.count_curves(q, g, curves, flags=flags, hist_capacity=len(curves) if hist else None)
+        bad = np.flatnonzero((N != Nref).any(axis=1))
+        assert bad.size == 0, (name, q, g, bad[:5], N[bad[:5]], Nref[bad[:5]], curves[bad[:5]])
+        if hist:
+            assert np.array_equal(H[0], kref), name
+            assert np.array_equal(H[1], cref), name
+    return Nref
+
+
+def test_g2_q5_full_enumeration(gctx, oracle_mod, curvegen_mod):
+    curves = curvegen_mod.enumerate_all(5, 2)
+    assert len(curves) == 60000
+    _check(gctx, oracle_mod, 5, 2, curves)
+
+
+def test_g3_q13_slice(gctx, oracle_mod, curvegen_mod):
+    curves = curvegen_mod.sample(13, 3, 6000, seed=curvegen_mod.BASE_SEED + 1)
+    _check(gctx, oracle_mod, 13, 3, curves)
+
+
+def test_g4_q13_slice(gctx, oracle_mod, curvegen_mod):
+    curves = curvegen_mod.sample(13, 4, 400, seed=curvegen_mod.BASE_SEED + 3)
+    _check(gctx, oracle_mod, 13, 4, curves)
+
+
+def test_g4_q3_full_enumeration(gctx, oracle_mod, curvegen_mod):
+    curves = curvegen_mod.enumerate_all(3, 4)
+    assert len(curves) == 104976
+    _check(gctx, oracle_mod, 3, 4, curves, modes={"batched-orbit": 0, "plain-full": 3})
+
+
+@pytest.mark.parametrize("q,g,n", [
+    (3, 1, 200), (7, 1, 300), (101, 1, 300),
+    (9, 2, 400), (25, 2, 300), (27, 2, 300), (49, 2, 200), (81, 2, 150), (121, 2, 100), (125, 2, 100),
+    (169, 2, 60), (181, 2, 60),
+    (3, 3, 500), (5, 3, 400), (7, 3, 300), (9, 3, 200), (11, 3, 200), (17, 3, 60), (25, 3, 30), (31, 3, 20),
+    (5, 4, 150), (7, 4, 60), (9, 4, 40), (11, 4, 20),
+])
+def test_other_fields(gctx, oracle_mod, curvegen_mod, q, g, n):
+    curves = curvegen_mod.sample(q, g, n, seed=4242 + q * 10 + g, dtype=np.int16)
+    _check(gctx, oracle_mod, q, g, curves)
+
+
+def test_sparse_patterns(gctx, oracle_mod, curvegen_mod):
+    # rows with many zero coefficients exercise the gap path of the Horner sweep
+    rng = np.random.default_rng(5)
+    for q, g in ((13, 3), (13, 4), (7, 2)):
+        nc = 2 * g + 3
+        rows = []
+        while len(rows) < 300:
+            r = rng.integers(0, q, size=nc)
+            r[rng.random(nc) < 0.6] = 0
+            if r[-1] == 0 and r[-2] == 0:
+                r[-1] = 1
+            if curvegen_mod.is_squarefree(q, r):
+                rows.append(r)
+        rows.append([1] + [0] * (2 * g) + [1, 0])          # x^{2g+1} + 1
+        rows.append([0, 1] + [0] * (2 * g - 1) + [0, 1])   # x^{2g+2} + x
+        curves = np.array(rows, dtype=np.int16)
+        _check(gctx, oracle_mod, q, g, curves)
+
+
+def test_int8_and_int16_agree(gctx, curvegen_mod):
+    import torch
+    curves = curvegen_mod.sample(13, 3, 5000, seed=77)
+    outs = []
+    for dt in (torch.int8, torch.int16):
+        d = torch.from_numpy(curves.astype(np.int16)).to(dt).cuda()
+        N = torch.empty((len(curves), 3), dtype=torch.int32, device="cuda")
+        gctx.count_curves_dev(13, 3, d, N)
+        gctx.status()
+        outs.append(N.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_edge_sizes(gctx, oracle_mod, curvegen_mod):
+    for n in (0, 1, 63, 64, 65, 129):
+        curves = curvegen_mod.sample(13, 3, n, seed=9 + n, dtype=np.int16)
+        N, H = gctx.count_curves(13, 3, curves, hist_capacity=max(n, 1))
+        assert N.shape == (n, 3)
+        if n:
+            ref = oracle_mod.count_curves(13, 3, curves)
+            assert np.array_equal(N, ref)
+            k, c = oracle_mod.histogram(ref)
+            assert np.array_equal(H[0], k) and np.array_equal(H[1], c)
+        else:
+            assert len(H[0]) == 0
+
+
+def test_errors(gctx):
+    from paper_1805_11991_amd import hwcount
+    good = np.array([[1, 0, 0, 0, 0, 1, 0]], dtype=np.int16)
+    cases = [
+        (dict(q=15, g=2, coeffs=good), hwcount.HWC_ERR_NOT_ODD_PRIME_POWER),
+        (dict(q=5, g=0, coeffs=np.zeros((1, 3), np.int16)), hwcount.HWC_ERR_BAD_G),
+        (dict(q=5, g=2, coeffs=np.array([[5, 0, 0, 0, 0, 1, 0]], np.int16)), hwcount.HWC_ERR_COEFF_RANGE),
+        (dict(q=5, g=2, coeffs=np.array([[1, 0, 0, 0, 1, 0, 0]], np.int16)), hwcount.HWC_ERR_DEGREE),
+        (dict(q=41, g=3, coeffs=np.array([[1] + [0] * 7 + [1]], np.int16)), hwcount.HWC_ERR_FIELD_TOO_LARGE),
+    ]
+    for kw, code in cases:
+        with pytest.raises(hwcount.HwcError) as ei:
+            gctx.count_curves(kw["q"], kw["g"], kw["coeffs"])
+        assert ei.value.code == code, kw
+    # (x+1)^2 (x^3+2) over F_5 has a square factor
+    from paper_1805_11991_amd import curvegen
+    sing = np.array([[2, 4, 2, 1, 2, 1, 0]], dtype=np.int16)
+    assert not curvegen.is_squarefree(5, sing[0])
+    with pytest.raises(hwcount.HwcError) as ei:
+        gctx.count_curves(5, 2, sing, flags=hwcount.HWC_VALIDATE)
+    assert ei.value.code == hwcount.HWC_ERR_SINGULAR
+    gctx.count_curves(5, 2, sing)   # without the flag the formula value is returned
+    # histogram capacity
+    curves = np.array([[1, 0, 0, 0, 0, 1, 0], [2, 0, 0, 0, 0, 1, 0], [1, 1, 0, 0, 0, 1, 0]], np.int16)
+    with pytest.raises(hwcount.HwcError) as ei:
+        gctx.count_curves(5, 2, curves, hist_capacity=0)
+    assert ei.value.code == hwcount.HWC_ERR_HIST_CAPACITY
+
+
+def test_device_row_errors_reported_by_status(gctx):
+    import torch
+    from paper_1805_11991_amd import hwcount
+    bad = torch.tensor([[7, 0, 0, 0, 0, 1, 0]], dtype=torch.int16, device="cuda")
+    N = torch.empty((1, 2), dtype=torch.int32, device="cuda")
+    gctx.count_curves_dev(5, 2, bad, N)
+    with pytest.raises(hwcount.HwcError) as ei:
+        gctx.status()
+    assert ei.value.code == hwcount.HWC_ERR_COEFF_RANGE
+    gctx.status()   # cleared
+
+
+def test_graph_replays_match_eager(gctx, curvegen_mod):
+    import torch
+    from paper_1805_11991_amd import hwcount
+    curves = curvegen_mod.sample(13, 3, 20000, seed=31337)
+    d = torch.from_numpy(curves).cuda()
+    ref = torch.empty((len(curves), 3), dtype=torch.int32, device="cuda")
+    gctx.count_curves_dev(13, 3, d, ref, flags=hwcount.HWC_NO_GRAPH)
+    hk = torch.empty((len(curves), 3), dtype=torch.int32, device="cuda")
+    hc = torch.empty(len(curves), dtype=torch.int64, device="cuda")
+    hl = torch.zeros(1, dtype=torch.int64, device="cuda")
+    hk0 = torch.empty_like(hk)
+    hc0 = torch.empty_like(hc)
+    hl0 = torch.zeros_like(hl)
+    gctx.count_curves_dev(13, 3, d, ref, hk0, hc0, hl0, flags=hwcount.HWC_NO_GRAPH)
+    gctx.status()
+    L = int(hl0.item())
+    Nrep = torch.empty((len(curves), 3), dtype=torch.int32, device="cuda")
+    for rep in range(4):     # first call captures the graph, the rest replay it
+        Nrep.fill_(-1)
+        hk.fill_(-1)
+        hc.fill_(0)
+        gctx.count_curves_dev(13, 3, d, Nrep, hk, hc, hl)
+        torch.cuda.synchronize()
+        _ = (d.float().sum() * 2).item()      # unrelated eager work between replays
+        gctx.status()
+        assert torch.equal(Nrep, ref), rep
+        assert int(hl.item()) == L
+        assert torch.equal(hk[:L], hk0[:L]) and torch.equal(hc[:L], hc0[:L])
+
+
+def test_full_size_g3_q13_sampled(gctx, oracle_mod, curvegen_mod):
+    """The 2^24-curve g=3 set in the benchmark's launch form (persistent,
+    graph, orbit sweep), checked on a seeded sample of rows, plus histogram
+    invariants (total = n, strictly increasing tuples)."""
+    import torch
+    n = 1 << 24
+    curves = curvegen_mod.sample(13, 3, n, seed=curvegen_mod.BASE_SEED + 1)
+    d = torch.from_numpy(curves).cuda()
+    N = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    hk = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+    hc = torch.empty(n, dtype=torch.int64, device="cuda")
+    hl = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gctx.count_curves_dev(13, 3, d, N, hk, hc, hl)
+    gctx.status()
+    Nh = N.cpu().numpy()
+    rng = np.random.default_rng(2024)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 1500), [0, n - 1]]))
+    ref = oracle_mod.count_curves(13, 3, curves[idx])
+    assert np.array_equal(Nh[idx], ref)
+    L = int(hl.item())
+    keys = hk[:L].cpu().numpy()
+    cnt = hc[:L].cpu().numpy()
+    assert int(cnt.sum()) == n
+    assert (np.diff(keys[:, 0]) >= 0).all()
+    kk = keys.astype(np.int64)
+    lin = (kk[:, 0] * 400 + kk[:, 1]) * 5000 + kk[:, 2]
+    assert (np.diff(lin) > 0).all()
+    # the histogram equals the one of the per-curve output
+    k2, c2 = _hist_np(Nh)
+    assert np.array_equal(k2, keys) and np.array_equal(c2, cnt.astype(np.uint64))
