@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the Hasse-Weil curve counter on one MI355X.
+
+One step = one pass of the whole path over one batch resident in HBM: curve
+bucketing by zero pattern, the count of N_1..N_g for every curve (Zech-table
+kernel, persistent and fused over all levels), and the sorted histogram of the
+tuples.  Workload of `value`: g = 3 over F_13, 2^24 seeded square-free curves
+(the set the metric is quoted on), Frobenius-orbit sweep, graph replay.
+
+Also measured in the same run: the plain form (one launch per level plus a
+separate assembly, no graph) on the same set, both forms with the full sweep,
+the g = 4 / F_13 set of 2^26 curves in both forms, a profiled loop that times
+the count kernel with HIP events on its launch stream (roofline), and the CPU
+oracle on a bounded sample (cpu_baseline).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LDS_BANKS_PER_CU = 32          # u16 gathers served per clock per CU without conflicts
+NUM_CU = 256
+CLOCK_HZ = 2.4e9
+LDS_PEAK_LOOKUPS = LDS_BANKS_PER_CU * NUM_CU * CLOCK_HZ
+
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def lookups_per_batch(curves, g: int, nx_levels: list[int]) -> int:
+    """Zech lookups the method needs: every Horner step that adds a nonzero
+    coefficient costs one table read, for every swept x of every level."""
+    import numpy as np
+    c = curves.astype(np.int64)
+    nz = (c != 0)
+    top = nz[:, -1]
+    # terms of f: nonzero coefficients up to and including the leading one
+    terms = nz[:, :-1].sum(axis=1) + top
+    steps = terms - 1
+    return int(steps.sum()) * int(sum(nx_levels))
+
+
+def time_loop(fn, steps: int, warmup: int, sync) -> float:
+    for _ in range(warmup):
+        fn()
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    sync()
+    return (time.perf_counter() - t0) / steps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the counter has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1805_11991_amd import curvegen, hwcount
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    sync = torch.cuda.synchronize
+    ctx = hwcount.Context(device=0)
+    hctx = hwcount.Context(device=-1)
+
+    def nx_levels(q, g, orbit=True):
+        out = []
+        for j in range(1, g + 1):
+            f = hctx.build_field(q, 1, j)
+            info = f.info()
+            out.append(int(info.nprim_orbits) if orbit else int(info.Q) - 1)
+        return out
+
+    def setup(q, g, n, seed):
+        t0 = time.perf_counter()
+        curves = curvegen.sample(q, g, n, seed=seed)
+        log(f"generated q={q} g={g} n={n} in {time.perf_counter() - t0:.1f}s")
+        d = torch.from_numpy(curves).to(dev)
+        N = torch.empty((n, g), dtype=torch.int32, device=dev)
+        hk = torch.empty((n, g), dtype=torch.int32, device=dev)
+        hc = torch.empty(n, dtype=torch.int64, device=dev)
+        hl = torch.zeros(1, dtype=torch.int64, device=dev)
+        return curves, d, N, hk, hc, hl
+
+    def runner(q, g, bufs, flags):
+        _, d, N, hk, hc, hl = bufs
+        return lambda: ctx.count_curves_dev(q, g, d, N, hk, hc, hl, flags=flags, stream=stream)
+
+    # ---------------- headline: g = 3, q = 13, 2^24 curves ----------------
+    q, g, n = 13, 3, 1 << 24
+    bufs = setup(q, g, n, curvegen.BASE_SEED + 1)
+    curves = bufs[0]
+    batched = runner(q, g, bufs, 0)
+    ms = time_loop(batched, args.steps, args.warmup, sync) * 1e3
+    ctx.status()
+    value = n / (ms * 1e-3)
+    log(f"g3 q13 batched orbit: {ms:.3f} ms/step, {value:.4g} curves/s")
+    Nref = bufs[2].cpu().numpy()
+    L = int(bufs[5].item())
+
+    # roofline: the count kernel timed with HIP events on its launch stream
+    ctx.profile(True)
+    for _ in range(args.steps):
+        batched()
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    ctx.status()
+    assert np.array_equal(bufs[2].cpu().numpy(), Nref), "profiled run differs from the graph run"
+    count_ms = prof["count_ms"] / prof["calls"]
+    nx = nx_levels(q, g, orbit=True)
+    lookups = lookups_per_batch(curves, g, nx)
+    achieved = lookups / (count_ms * 1e-3)
+    roofline = {
+        "bound": "lds",
+        "achieved": round(achieved / 1e9, 2),
+        "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
+        "unit": "Glookup/s",
+        "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
+        "traffic": None,
+        "kernel": "count_kernel<3,int8>",
+        "kernel_ms": round(count_ms, 4),
+        "lookups_per_launch": lookups,
+        "prep_ms": round(prof["prep_ms"] / prof["calls"], 4),
+        "hist_ms": round(prof["hist_ms"] / prof["calls"], 4),
+    }
+    log(f"roofline: count kernel {count_ms:.3f} ms, {achieved / 1e9:.1f} Glookup/s "
+        f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak)")
+
+    extra = {}
+    if not args.quick:
+        for name, flags in (("plain_orbit", hwcount.HWC_PLAIN), ("batched_full", hwcount.HWC_FULL_SWEEP),
+                            ("plain_full", hwcount.HWC_PLAIN | hwcount.HWC_FULL_SWEEP)):
+            fn = runner(q, g, bufs, flags)
+            m = time_loop(fn, max(1, min(args.steps, 3)), 1, sync) * 1e3
+            ctx.status()
+            assert np.array_equal(bufs[2].cpu().numpy(), Nref), f"{name} differs from batched"
+            assert int(bufs[5].item()) == L
+            extra[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n / (m * 1e-3), 1)}
+            log(f"g3 q13 {name}: {m:.3f} ms/step")
+        extra["batched_vs_plain"] = round(extra["plain_orbit"]["ms_per_step"] / ms, 3)
+        del bufs
+        torch.cuda.empty_cache()
+        # ---------------- g = 4, q = 13, 2^26 curves ----------------
+        n4 = 1 << 26
+        bufs4 = setup(13, 4, n4, curvegen.BASE_SEED + 3)
+        g4 = {}
+        steps4 = max(1, min(args.steps, 3))
+        for name, flags in (("batched_orbit", 0), ("plain_orbit", hwcount.HWC_PLAIN)):
+            fn = runner(13, 4, bufs4, flags)
+            m = time_loop(fn, steps4, 1, sync) * 1e3
+            ctx.status()
+            g4[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n4 / (m * 1e-3), 1)}
+            log(f"g4 q13 {name}: {m:.3f} ms/step")
+        g4["batched_vs_plain"] = round(g4["plain_orbit"]["ms_per_step"] / g4["batched_orbit"]["ms_per_step"], 3)
+        ctx.profile(True)
+        runner(13, 4, bufs4, 0)()
+        p4 = ctx.profile_read()
+        ctx.profile(False)
+        lk4 = lookups_per_batch(bufs4[0], 4, nx_levels(13, 4))
+        g4["count_kernel_ms"] = round(p4["count_ms"], 3)
+        g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
+        g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)
+        g4["curves"] = n4
+        extra["g4_q13"] = g4
+        del bufs4
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        threads = min(os.cpu_count() or 1, 16)
+        sample = 1 << 17
+        t0 = time.perf_counter()
+        ref = oracle.count_curves(q, g, curves[:sample], threads=threads)
+        dt = time.perf_counter() - t0
+        assert np.array_equal(ref, Nref[:sample]), "oracle disagrees with the GPU on the CPU sample"
+        cpu = {"value": round(sample / dt, 1), "unit": "curves/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {sample} curves of the g=3 q=13 set, all k=1..3 ({dt:.1f} s)"}
+        log(f"cpu oracle: {sample / dt:.1f} curves/s on {threads} threads")
+
+    out = {
+        "metric": "curves/s (all k) at g=3 q=13 and g=4 q=13; batched vs plain, bit-exact",
+        "value": round(value, 1),
+        "unit": "curves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic: seeded uniform square-free curves (SplitMix64/Lemire rejection), no dataset",
+        "config": {"workload": "g3_q13_2^24_curves_batched_orbit_sweep", "q": q, "g": g, "curves": n,
+                   "levels_nx": nx, "histogram_distinct": L},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
