@@ -106,7 +106,8 @@ typedef struct {
 int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out);
 void hwc_ctx_destroy(hwc_ctx* ctx);
 
-/* Message for the last error on ctx ("" if none).  Valid until the next call. */
+/* Message for the last error on ctx ("" if none).  Valid until the next call.
+ * With ctx = NULL: why the calling thread's last hwc_ctx_create failed. */
 const char* hwc_last_error(const hwc_ctx* ctx);
 
 /* Builds F_{p^(e k)} with F_{p^e} embedded (Sec. 2.3, Sec. 3.1-3.2): the

@@ -34,6 +34,12 @@ hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_
                          uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
                          uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
                          uint64_t max_tiles, hipStream_t s);
+hipError_t launch_batch(const JobDesc* jobs, const uint64_t* chunks, const uint32_t* nchunks, uint32_t* queue,
+                        uint32_t lds_bytes, uint32_t grid, uint32_t block, hipStream_t s);
+hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint32_t njobs, uint32_t per,
+                              uint32_t* chunk_start, uint64_t* chunks, uint64_t max_chunks, uint32_t* nchunks,
+                              uint32_t* queue, hipStream_t s);
+hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 uint64_t hist_scratch_bytes(uint64_t n);
 hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* scratch, int32_t* out_keys,
                     uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err, hipStream_t s);
@@ -41,7 +47,7 @@ hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* 
 
 namespace {
 
-constexpr uint32_t kLdsLimit = 160 * 1024;
+constexpr uint32_t kLdsLimit = hwc::kLdsImageLimit;
 constexpr size_t kMaxGraphs = 8;
 
 struct FieldEntry {
@@ -54,10 +60,14 @@ struct DevPlan {
   std::vector<uint32_t> image;  // dwords
   hwc::PlanDesc desc{};
   void* d_image = nullptr;
+  hwc::PlanDesc* d_desc = nullptr;   // device copy of desc (multi-plan launches)
   std::vector<uint32_t*> d_reps;
+  std::vector<uint32_t*> d_gtab;     // form D tables
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
   uint32_t block = 256, grid = 0;
+  double tile_cost = 0;
+  uint32_t pins = 0;                 // > 0 while a batch being assembled uses the plan
 };
 
 struct Buf {
@@ -65,28 +75,22 @@ struct Buf {
   size_t bytes = 0;
 };
 
-struct GraphKey {
-  const DevPlan* plan;
-  uint64_t n;
-  int cb;
-  const void* codes;
-  const int32_t* N;
-  const int32_t* hk;
-  const uint64_t* hc;
-  uint64_t hcap;
-  const uint64_t* hlen;
-  uint32_t flags;
-  bool operator==(const GraphKey& o) const {
-    return plan == o.plan && n == o.n && cb == o.cb && codes == o.codes && N == o.N && hk == o.hk && hc == o.hc &&
-           hcap == o.hcap && hlen == o.hlen && flags == o.flags;
-  }
-};
-
 struct GraphEntry {
-  GraphKey key;
+  std::vector<uint64_t> key;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  void* jobs = nullptr;   // job descriptors owned by a multi-plan graph
 };
+
+struct JobSlot {          // job descriptors of a direct multi-plan launch
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipEvent_t done = nullptr;
+  bool used = false;
+};
+
+constexpr uint32_t kSmallStride = 4 * 2048 + 16;   // per-job bucketing words (u32)
+constexpr int kJobSlots = 4;
 
 }  // namespace
 
@@ -102,12 +106,19 @@ struct hwc_ctx {
   std::string err;
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::shared_ptr<FieldEntry>> fields;
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::unique_ptr<DevPlan>> plans;
-  uint64_t table_bytes = 0, hits = 0, misses = 0, tick = 0;
+  uint64_t table_bytes = 0, hits = 0, misses = 0, tick = 0, evictions = 0;
   int cus = 0;
   // scratch
   Buf pid, small, tiles, perm, lv, N, hist, codes, hout;
   uint32_t* d_err = nullptr;
   std::list<GraphEntry> graphs;
+  // multi-plan scratch
+  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords;
+  JobSlot slots[kJobSlots];
+  int next_slot = 0;
+  // every call's work is ordered after the previous call's, whatever the stream
+  hipEvent_t order_ev = nullptr;
+  bool order_valid = false;
   // profiling: events around the phases of each direct (non-graph) call
   bool profile = false;
   std::vector<std::array<hipEvent_t, 4>> prof;
@@ -127,18 +138,39 @@ int fail(hwc_ctx* c, int code, const std::string& msg) {
     if (_e != hipSuccess) return fail((ctx), HWC_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
   } while (0)
 
+void destroy_graph(GraphEntry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  if (g.jobs) (void)hipFree(g.jobs);
+  g.exec = nullptr;
+  g.graph = nullptr;
+  g.jobs = nullptr;
+}
+
 void drop_graphs(hwc_ctx* c) {
-  for (auto& g : c->graphs) {
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
-  }
+  if (!c->graphs.empty()) (void)hipDeviceSynchronize();
+  for (auto& g : c->graphs) destroy_graph(g);
   c->graphs.clear();
+}
+
+// order this call's work on s after everything the context enqueued before
+int order_begin(hwc_ctx* c, hipStream_t s) {
+  if (c->order_valid) HIPX(c, hipStreamWaitEvent(s, c->order_ev, 0));
+  return HWC_OK;
+}
+int order_end(hwc_ctx* c, hipStream_t s) {
+  HIPX(c, hipEventRecord(c->order_ev, s));
+  c->order_valid = true;
+  return HWC_OK;
 }
 
 int ensure(hwc_ctx* c, Buf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return HWC_OK;
   drop_graphs(c);  // captured graphs may hold the old pointer
-  if (b.p) HIPX(c, hipFree(b.p));
+  if (b.p) {
+    HIPX(c, hipDeviceSynchronize());  // queued work may still use the old buffer
+    HIPX(c, hipFree(b.p));
+  }
   b.p = nullptr;
   b.bytes = 0;
   size_t want = std::max<size_t>(bytes, 256);
@@ -164,13 +196,45 @@ std::shared_ptr<FieldEntry> get_field(hwc_ctx* c, uint32_t p, uint32_t e, uint32
 
 void free_plan(DevPlan* P) {
   if (P->d_image) (void)hipFree(P->d_image);
+  if (P->d_desc) (void)hipFree(P->d_desc);
   for (auto* r : P->d_reps)
     if (r) (void)hipFree(r);
+  for (auto* t : P->d_gtab)
+    if (t) (void)hipFree(t);
   P->d_image = nullptr;
+  P->d_desc = nullptr;
   P->d_reps.clear();
+  P->d_gtab.clear();
 }
 
 uint32_t align16(uint32_t v) { return (v + 15u) & ~15u; }
+
+// Bytes of LDS a level table takes in a given form (D lives in device memory).
+uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
+  if (form == hwc::kFormA) return align16((uint32_t)(10 * M));
+  if (form == hwc::kFormC) return align16((uint32_t)(4 * M));
+  return 0;
+}
+
+// Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;
+// then move the largest LDS levels to D until the image fits.
+std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g) {
+  std::vector<uint32_t> form(g);
+  std::vector<uint64_t> M(g);
+  uint64_t Qj = 1;
+  for (uint32_t j = 0; j < g; ++j) {
+    Qj *= q;
+    M[j] = Qj - 1;
+    form[j] = M[j] <= hwc::kFormAMaxM ? hwc::kFormA : (M[j] <= hwc::kFormCMaxM ? hwc::kFormC : hwc::kFormD);
+  }
+  auto total = [&]() {
+    uint64_t t = 0;
+    for (uint32_t j = 0; j < g; ++j) t += lds_table_bytes(form[j], M[j]) + align16(4 * q);
+    return t;
+  };
+  for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
+  return form;
+}
 
 // Build (or fetch) the device plan for (q, g, orbit).
 int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) {
@@ -186,16 +250,11 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   uint32_t p, e;
   if (!hwc::factor_odd_prime_power(q, &p, &e)) return fail(c, HWC_ERR_NOT_ODD_PRIME_POWER, "q is not an odd prime power");
   if (g < 1 || g > (uint32_t)hwc::kMaxG) return fail(c, HWC_ERR_BAD_G, "g must be in 1..4");
-  if (q > 32768) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "q too large");
-  // sizes first, so oversize requests fail before any table is built
-  uint64_t Mj = 1, lds = 0;
-  for (uint32_t j = 1; j <= g; ++j) {
-    Mj = Mj * q;
-    const uint64_t M = Mj - 1;
-    if (M > hwc::kFormCMaxM) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "F_{q^g} is too large for the LDS-resident tables");
-    lds += align16((uint32_t)((M <= hwc::kFormAMaxM ? 5 * M : 2 * M) * 2)) + align16((uint32_t)(2 * q));
-  }
-  if (lds > kLdsLimit) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "tables of F_q..F_{q^g} exceed 160 KiB of LDS");
+  double Qg = 1;
+  for (uint32_t j = 0; j < g; ++j) Qg *= q;
+  if (Qg > 16777216.0 || q > 32768) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "F_{q^g} larger than 2^24 elements");
+  const std::vector<uint32_t> form = choose_forms(q, g);
+  if (8 * q > kLdsLimit) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "q too large");
   auto P = std::make_unique<DevPlan>();
   P->q = q; P->g = g; P->orbit = orbit;
   int rc = HWC_OK;
@@ -204,7 +263,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     if (!fe) return rc;
     P->fields.push_back(fe);
   }
-  // LDS image: level tables, then embedding tables
+  // LDS image: level tables (forms A and C), then embedding tables
   std::vector<uint16_t> img;
   auto put = [&](const std::vector<uint16_t>& v) {
     uint32_t off = (uint32_t)img.size() * 2;
@@ -214,25 +273,29 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   };
   hwc::PlanDesc& D = P->desc;
   D.q = q; D.g = g; D.ncoef = 2 * g + 3; D.orbit = orbit;
+  std::vector<std::vector<uint32_t>> gtabs(g);
   for (uint32_t j = 0; j < g; ++j) {
     const hwc::Field& F = P->fields[j]->F;
     const uint32_t M = (uint32_t)F.M;
     hwc::LevelDesc& L = D.lv[j];
     L.M = M;
-    std::vector<uint16_t> tab;
-    if (M <= hwc::kFormAMaxM) {
-      L.form = hwc::kFormA;
-      tab.assign(5 * (size_t)M, 0);
+    L.form = form[j];
+    L.tab_off = 0;
+    if (form[j] == hwc::kFormA) {
+      std::vector<uint16_t> tab(5 * (size_t)M, 0);
       for (uint32_t i = 0; i < 3 * M; ++i) {
         const uint32_t z = F.zech[i % M];
         tab[i] = (uint16_t)(z == M ? 6 * M : 2 * z);
       }
-    } else {
-      L.form = hwc::kFormC;
-      tab.resize(2 * (size_t)M);
+      L.tab_off = put(tab);
+    } else if (form[j] == hwc::kFormC) {
+      std::vector<uint16_t> tab(2 * (size_t)M);
       for (uint32_t i = 0; i < 2 * M; ++i) tab[i] = (uint16_t)F.zech[i % M];
+      L.tab_off = put(tab);
+    } else {
+      gtabs[j].resize(2 * (size_t)M);
+      for (uint32_t i = 0; i < 2 * M; ++i) gtabs[j][i] = F.zech[i % M];
     }
-    L.tab_off = put(tab);
     if (orbit) {
       L.nx = (uint32_t)F.prim_reps.size();
       L.weight = j + 1;
@@ -242,8 +305,13 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     }
   }
   for (uint32_t j = 0; j < g; ++j) {
+    // u32 entries: logs reach M - 1, beyond u16 for the largest fields
     const hwc::Field& F = P->fields[j]->F;
-    std::vector<uint16_t> emb(F.emb.begin(), F.emb.end());
+    std::vector<uint16_t> emb(2 * F.q);
+    for (uint64_t i = 0; i < F.q; ++i) {
+      emb[2 * i] = (uint16_t)(F.emb[i] & 0xFFFFu);
+      emb[2 * i + 1] = (uint16_t)(F.emb[i] >> 16);
+    }
     D.lv[j].emb_off = put(emb);
   }
   D.image_bytes = (uint32_t)img.size() * 2;
@@ -251,19 +319,24 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   P->image.assign(img.size() / 2, 0);
   std::memcpy(P->image.data(), img.data(), img.size() * 2);
   // device memory for the plan, admitted against the budget
-  uint64_t bytes = D.image_bytes;
-  if (orbit)
-    for (uint32_t j = 0; j < g; ++j) bytes += P->fields[j]->F.prim_reps.size() * 4;
+  uint64_t bytes = D.image_bytes + sizeof(hwc::PlanDesc);
+  for (uint32_t j = 0; j < g; ++j) {
+    if (orbit) bytes += P->fields[j]->F.prim_reps.size() * 4;
+    bytes += gtabs[j].size() * 4;
+  }
   if (c->budget) {
-    while (c->table_bytes + bytes > c->budget && !c->plans.empty()) {
-      auto victim = c->plans.begin();
+    while (c->table_bytes + bytes > c->budget) {
+      auto victim = c->plans.end();
       for (auto i2 = c->plans.begin(); i2 != c->plans.end(); ++i2)
-        if (i2->second->last_use < victim->second->last_use) victim = i2;
+        if (i2->second->pins == 0 && (victim == c->plans.end() || i2->second->last_use < victim->second->last_use))
+          victim = i2;
+      if (victim == c->plans.end()) break;
       drop_graphs(c);
-      HIPX(c, hipStreamSynchronize(c->stream));
+      HIPX(c, hipDeviceSynchronize());
       c->table_bytes -= victim->second->dev_bytes;
       free_plan(victim->second.get());
       c->plans.erase(victim);
+      c->evictions++;
     }
     if (c->table_bytes + bytes > c->budget)
       return fail(c, HWC_ERR_OOM_BUDGET, "tables exceed the context's HBM budget");
@@ -272,13 +345,24 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   HIPX(c, hipMemcpy(P->d_image, P->image.data(), D.image_bytes, hipMemcpyHostToDevice));
   D.image = static_cast<const uint32_t*>(P->d_image);
   P->d_reps.assign(g, nullptr);
+  P->d_gtab.assign(g, nullptr);
   for (uint32_t j = 0; j < g; ++j) {
-    if (!orbit) { D.lv[j].xs = nullptr; continue; }
-    const auto& reps = P->fields[j]->F.prim_reps;
-    HIPX(c, hipMalloc(&P->d_reps[j], std::max<size_t>(reps.size(), 1) * 4));
-    if (!reps.empty()) HIPX(c, hipMemcpy(P->d_reps[j], reps.data(), reps.size() * 4, hipMemcpyHostToDevice));
-    D.lv[j].xs = P->d_reps[j];
+    D.lv[j].xs = nullptr;
+    D.lv[j].gtab = nullptr;
+    if (orbit) {
+      const auto& reps = P->fields[j]->F.prim_reps;
+      HIPX(c, hipMalloc(&P->d_reps[j], std::max<size_t>(reps.size(), 1) * 4));
+      if (!reps.empty()) HIPX(c, hipMemcpy(P->d_reps[j], reps.data(), reps.size() * 4, hipMemcpyHostToDevice));
+      D.lv[j].xs = P->d_reps[j];
+    }
+    if (!gtabs[j].empty()) {
+      HIPX(c, hipMalloc(&P->d_gtab[j], gtabs[j].size() * 4));
+      HIPX(c, hipMemcpy(P->d_gtab[j], gtabs[j].data(), gtabs[j].size() * 4, hipMemcpyHostToDevice));
+      D.lv[j].gtab = P->d_gtab[j];
+    }
   }
+  HIPX(c, hipMalloc(&P->d_desc, sizeof(hwc::PlanDesc)));
+  HIPX(c, hipMemcpy(P->d_desc, &D, sizeof(hwc::PlanDesc), hipMemcpyHostToDevice));
   P->dev_bytes = bytes;
   c->table_bytes += bytes;
   // launch shape: many waves per CU; one large block when the tables fill LDS
@@ -287,6 +371,10 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   HIPX(c, hwc::occupancy_count(g, 1, P->block, D.image_bytes, &bpc));
   if (bpc < 1) bpc = 1;
   P->grid = (uint32_t)(c->cus * bpc);
+  // relative cost of one tile, for ordering mixed batches (longest first)
+  P->tile_cost = 0;
+  for (uint32_t j = 0; j < g; ++j)
+    P->tile_cost += (double)D.lv[j].nx * (2 * g + 2) * (form[j] == hwc::kFormA ? 1.0 : form[j] == hwc::kFormC ? 1.5 : 6.0);
   P->last_use = ++c->tick;
   *out = P.get();
   c->plans[key] = std::move(P);
@@ -399,13 +487,20 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   Scratch S;
   if ((rc = get_scratch(c, n, g, (flags & HWC_PLAIN) != 0, hk != nullptr, &S))) return rc;
   const bool use_graph = !(flags & (HWC_PLAIN | HWC_NO_GRAPH)) && n > 0 && !c->profile;
-  if (!use_graph) return enqueue(c, P, S, codes, cb, n, N, hk, hc, hcap, hlen, flags, s, c->profile);
-  GraphKey key{P, n, cb, codes, N, hk, hc, hcap, hlen, flags};
+  if ((rc = order_begin(c, s))) return rc;
+  if (!use_graph) {
+    rc = enqueue(c, P, S, codes, cb, n, N, hk, hc, hcap, hlen, flags, s, c->profile);
+    if (rc) return rc;
+    return order_end(c, s);
+  }
+  std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)P, n, (uint64_t)cb, (uint64_t)(uintptr_t)codes,
+                               (uint64_t)(uintptr_t)N, (uint64_t)(uintptr_t)hk, (uint64_t)(uintptr_t)hc, hcap,
+                               (uint64_t)(uintptr_t)hlen, flags};
   for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
     if (it->key == key) {
       c->graphs.splice(c->graphs.begin(), c->graphs, it);
       HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
-      return HWC_OK;
+      return order_end(c, s);
     }
   }
   // capture on the context stream, replay on s
@@ -425,13 +520,198 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   HIPX(c, hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0));
   c->graphs.push_front(ge);
   while (c->graphs.size() > kMaxGraphs) {
-    auto& b = c->graphs.back();
-    (void)hipGraphExecDestroy(b.exec);
-    (void)hipGraphDestroy(b.graph);
+    destroy_graph(c->graphs.back());
     c->graphs.pop_back();
   }
   HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
+  return order_end(c, s);
+}
+
+// ---- several requests in one persistent launch ----
+
+struct BatchPlan {
+  std::vector<size_t> order;        // jobs, most expensive tiles first
+  std::vector<DevPlan*> plans;      // per job (input order)
+  std::vector<uint64_t> off, toff;  // row and tile offsets (sorted order)
+  std::vector<uint64_t> max_tiles;
+  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0;
+  uint32_t lds = 0, block = 256, grid = 0, per = 8;
+};
+
+int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, const BatchPlan& B, const hwc::JobDesc* d_jobs,
+                  hipStream_t s) {
+  uint16_t* pid = static_cast<uint16_t*>(c->bpid.p);
+  uint32_t* perm = static_cast<uint32_t*>(c->bperm.p);
+  uint64_t* tiles = static_cast<uint64_t*>(c->btiles.p);
+  uint32_t* small = static_cast<uint32_t*>(c->bsmall.p);
+  uint32_t* words = static_cast<uint32_t*>(c->bwords.p);
+  for (size_t r = 0; r < njobs; ++r) {
+    const hwc_job& J = jobs[B.order[r]];
+    const DevPlan* P = B.plans[B.order[r]];
+    uint32_t* sm = small + r * kSmallStride;
+    HIPX(c, hwc::launch_bucket(J.coeff_bytes, J.d_coeffs, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
+                               sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
+                               B.max_tiles[r], s));
+  }
+  HIPX(c, hwc::launch_chunk_build(small + 8192, kSmallStride, (uint32_t)njobs, B.per,
+                                  static_cast<uint32_t*>(c->bcstart.p), static_cast<uint64_t*>(c->bchunks.p),
+                                  B.chunks_max, words, words + 1, s));
+  HIPX(c, hwc::launch_batch(d_jobs, static_cast<uint64_t*>(c->bchunks.p), words, words + 1, B.lds, B.grid, B.block,
+                            s));
+  for (size_t r = 0; r < njobs; ++r) {
+    const hwc_job& J = jobs[B.order[r]];
+    if (!J.d_hist_keys) continue;
+    HIPX(c, hwc::hist_run(J.d_out_N, J.n, J.g, J.q, c->hist.p, J.d_hist_keys, J.d_hist_counts, J.hist_capacity,
+                          J.d_hist_len, c->d_err, s));
+  }
   return HWC_OK;
+}
+
+int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hipStream_t s) {
+  if (njobs == 0) return HWC_OK;
+  if (njobs > 65535) return fail(c, HWC_ERR_ARG, "at most 65535 jobs per batch");
+  if (flags & HWC_PLAIN) {   // the plain form is one launch per level of each job
+    for (size_t i = 0; i < njobs; ++i) {
+      const hwc_job& J = jobs[i];
+      int rc = run_dev(c, J.q, J.g, J.d_coeffs, J.coeff_bytes, J.n, J.d_out_N, J.d_hist_keys, J.d_hist_counts,
+                       J.hist_capacity, J.d_hist_len, flags, s);
+      if (rc) return rc;
+    }
+    return HWC_OK;
+  }
+  int rc;
+  for (size_t i = 0; i < njobs; ++i) {
+    const hwc_job& J = jobs[i];
+    if ((rc = check_args(c, J.q, J.g, flags))) return rc;
+    if (J.coeff_bytes != 1 && J.coeff_bytes != 2) return fail(c, HWC_ERR_ARG, "coeff_bytes must be 1 or 2");
+    if (J.coeff_bytes == 1 && J.q > 127) return fail(c, HWC_ERR_ARG, "int8 codes need q <= 127");
+    if (J.n > 0 && (!J.d_coeffs || !J.d_out_N)) return fail(c, HWC_ERR_ARG, "null device pointer");
+    if (J.d_hist_keys && (!J.d_hist_counts || !J.d_hist_len)) return fail(c, HWC_ERR_ARG, "histogram pointers");
+    if (J.n >= (1ull << 31)) return fail(c, HWC_ERR_ARG, "n too large");
+  }
+  HIPX(c, hipSetDevice(c->device));
+  BatchPlan B;
+  B.plans.assign(njobs, nullptr);
+  const uint32_t orbit = (flags & HWC_FULL_SWEEP) ? 0u : 1u;
+  for (size_t i = 0; i < njobs; ++i) {
+    rc = get_plan(c, jobs[i].q, jobs[i].g, orbit, &B.plans[i]);
+    if (rc) {
+      for (size_t k = 0; k < i; ++k) B.plans[k]->pins--;
+      return rc;
+    }
+    B.plans[i]->pins++;
+  }
+  struct Unpin {
+    BatchPlan& b;
+    ~Unpin() { for (auto* p : b.plans) if (p) p->pins--; }
+  } unpin{B};
+  B.order.resize(njobs);
+  for (size_t i = 0; i < njobs; ++i) B.order[i] = i;
+  std::stable_sort(B.order.begin(), B.order.end(),
+                   [&](size_t a, size_t b) { return B.plans[a]->tile_cost > B.plans[b]->tile_cost; });
+  for (size_t r = 0; r < njobs; ++r) B.lds = std::max(B.lds, B.plans[B.order[r]]->desc.image_bytes);
+  B.block = B.lds > 80 * 1024 ? 1024 : 256;
+  B.per = 2 * (B.block / hwc::kWave);
+  int bpc = 0;
+  HIPX(c, hwc::occupancy_batch(B.block, B.lds, &bpc));
+  B.grid = (uint32_t)(c->cus * std::max(bpc, 1));
+  for (size_t r = 0; r < njobs; ++r) {
+    const hwc_job& J = jobs[B.order[r]];
+    const uint64_t mt = J.n / hwc::kWave + hwc::pattern_count(J.g) + 1;
+    B.off.push_back(B.ntot);
+    B.toff.push_back(B.tiles_tot);
+    B.max_tiles.push_back(mt);
+    B.ntot += J.n;
+    B.tiles_tot += mt;
+    B.chunks_max += mt / B.per + 1;
+    if (J.d_hist_keys) B.nhist = std::max<uint64_t>(B.nhist, J.n);
+  }
+  if ((rc = ensure(c, c->bpid, std::max<uint64_t>(B.ntot, 1) * 2))) return rc;
+  if ((rc = ensure(c, c->bperm, std::max<uint64_t>(B.ntot, 1) * 4))) return rc;
+  if ((rc = ensure(c, c->btiles, B.tiles_tot * 8))) return rc;
+  if ((rc = ensure(c, c->bsmall, njobs * kSmallStride * 4))) return rc;
+  if ((rc = ensure(c, c->bchunks, B.chunks_max * 8))) return rc;
+  if ((rc = ensure(c, c->bcstart, (njobs + 1) * 4))) return rc;
+  if ((rc = ensure(c, c->bwords, 64))) return rc;
+  if (B.nhist && (rc = ensure(c, c->hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
+  std::vector<hwc::JobDesc> hj(njobs);
+  for (size_t r = 0; r < njobs; ++r) {
+    const hwc_job& J = jobs[B.order[r]];
+    hj[r].plan = B.plans[B.order[r]]->d_desc;
+    hj[r].codes = J.d_coeffs;
+    hj[r].perm = static_cast<uint32_t*>(c->bperm.p) + B.off[r];
+    hj[r].tiles = static_cast<uint64_t*>(c->btiles.p) + B.toff[r];
+    hj[r].outN = J.d_out_N;
+    hj[r].cb = (uint32_t)J.coeff_bytes;
+    hj[r].g = J.g;
+  }
+  const size_t jbytes = njobs * sizeof(hwc::JobDesc);
+  if ((rc = order_begin(c, s))) return rc;
+  const bool use_graph = !(flags & HWC_NO_GRAPH) && !c->profile;
+  if (!use_graph) {
+    JobSlot& sl = c->slots[c->next_slot];
+    c->next_slot = (c->next_slot + 1) % kJobSlots;
+    if (sl.used) HIPX(c, hipEventSynchronize(sl.done));
+    if (!sl.done) HIPX(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    if (sl.bytes < jbytes) {
+      if (sl.p) HIPX(c, hipFree(sl.p));
+      sl.p = nullptr;
+      HIPX(c, hipMalloc(&sl.p, jbytes));
+      sl.bytes = jbytes;
+    }
+    HIPX(c, hipMemcpy(sl.p, hj.data(), jbytes, hipMemcpyHostToDevice));
+    rc = enqueue_batch(c, jobs, njobs, B, static_cast<const hwc::JobDesc*>(sl.p), s);
+    if (rc) return rc;
+    HIPX(c, hipEventRecord(sl.done, s));
+    sl.used = true;
+    return order_end(c, s);
+  }
+  std::vector<uint64_t> key = {2, njobs, flags};
+  for (size_t i = 0; i < njobs; ++i) {
+    const hwc_job& J = jobs[i];
+    for (uint64_t v : {(uint64_t)J.q, (uint64_t)J.g, (uint64_t)(uintptr_t)J.d_coeffs, (uint64_t)J.coeff_bytes, J.n,
+                       (uint64_t)(uintptr_t)J.d_out_N, (uint64_t)(uintptr_t)J.d_hist_keys,
+                       (uint64_t)(uintptr_t)J.d_hist_counts, J.hist_capacity, (uint64_t)(uintptr_t)J.d_hist_len,
+                       (uint64_t)(uintptr_t)B.plans[i]->d_desc})
+      key.push_back(v);
+  }
+  for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
+    if (it->key == key) {
+      c->graphs.splice(c->graphs.begin(), c->graphs, it);
+      HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
+      return order_end(c, s);
+    }
+  }
+  if (s != c->stream) HIPX(c, hipStreamSynchronize(c->stream));
+  GraphEntry ge;
+  ge.key = key;
+  HIPX(c, hipMalloc(&ge.jobs, jbytes));
+  hipError_t me = hipMemcpy(ge.jobs, hj.data(), jbytes, hipMemcpyHostToDevice);
+  if (me != hipSuccess) {
+    (void)hipFree(ge.jobs);
+    return fail(c, HWC_ERR_DEVICE, std::string("job copy: ") + hipGetErrorString(me));
+  }
+  HIPX(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  rc = enqueue_batch(c, jobs, njobs, B, static_cast<const hwc::JobDesc*>(ge.jobs), c->stream);
+  hipGraph_t graph = nullptr;
+  hipError_t ee = hipStreamEndCapture(c->stream, &graph);
+  ge.graph = graph;
+  if (rc || ee != hipSuccess) {
+    destroy_graph(ge);
+    return rc ? rc : fail(c, HWC_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(ee));
+  }
+  hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+  if (ie != hipSuccess) {
+    destroy_graph(ge);
+    return fail(c, HWC_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
+  }
+  c->graphs.push_front(ge);
+  while (c->graphs.size() > kMaxGraphs) {
+    destroy_graph(c->graphs.back());
+    c->graphs.pop_back();
+  }
+  HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
+  return order_end(c, s);
 }
 
 // square-free test over F_q with the level-1 tables (codes are packed values)
@@ -486,23 +766,36 @@ bool squarefree_host(const hwc::Field& F, const int16_t* row, int nc) {
 // ---------------------------------------------------------------------------
 extern "C" {
 
+static thread_local std::string g_create_error;
+
+static int create_fail(hipError_t e, const char* what) {
+  g_create_error = std::string(what) + ": " + hipGetErrorString(e);
+  return HWC_ERR_DEVICE;
+}
+
 int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out) {
   if (!out) return HWC_ERR_ARG;
+  g_create_error.clear();
   *out = nullptr;
   auto c = std::make_unique<hwc_ctx>();
   c->device = device;
   c->budget = hbm_budget_bytes;
   if (device >= 0) {
     int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return HWC_ERR_DEVICE;
-    if (hipSetDevice(device) != hipSuccess) return HWC_ERR_DEVICE;
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return HWC_ERR_DEVICE;
+    hipError_t e;
+    if ((e = hipGetDeviceCount(&ndev)) != hipSuccess) return create_fail(e, "hipGetDeviceCount");
+    if (device >= ndev) return create_fail(hipErrorInvalidDevice, "device index");
+    if ((e = hipSetDevice(device)) != hipSuccess) return create_fail(e, "hipSetDevice");
+    if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+      return create_fail(e, "hipStreamCreate");
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return HWC_ERR_DEVICE;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return create_fail(e, "hipGetDeviceProperties");
     c->cus = prop.multiProcessorCount;
-    if (hwc::prepare_kernels() != hipSuccess) return HWC_ERR_DEVICE;
-    if (hipMalloc(reinterpret_cast<void**>(&c->d_err), 256) != hipSuccess) return HWC_ERR_DEVICE;
-    if (hipMemset(c->d_err, 0, 256) != hipSuccess) return HWC_ERR_DEVICE;
+    if ((e = hwc::prepare_kernels()) != hipSuccess) return create_fail(e, "kernel attributes");
+    if ((e = hipMalloc(reinterpret_cast<void**>(&c->d_err), 256)) != hipSuccess) return create_fail(e, "hipMalloc");
+    if ((e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming)) != hipSuccess)
+      return create_fail(e, "hipEventCreate");
+    if ((e = hipMemset(c->d_err, 0, 256)) != hipSuccess) return create_fail(e, "hipMemset");
   }
   *out = c.release();
   return HWC_OK;
@@ -515,8 +808,14 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     drop_graphs(c);
     for (auto& kv : c->plans) free_plan(kv.second.get());
-    for (Buf* b : {&c->pid, &c->small, &c->tiles, &c->perm, &c->lv, &c->N, &c->hist, &c->codes, &c->hout})
+    for (Buf* b : {&c->pid, &c->small, &c->tiles, &c->perm, &c->lv, &c->N, &c->hist, &c->codes, &c->hout, &c->bpid,
+                   &c->bperm, &c->btiles, &c->bsmall, &c->bchunks, &c->bcstart, &c->bwords})
       if (b->p) (void)hipFree(b->p);
+    for (auto& sl : c->slots) {
+      if (sl.p) (void)hipFree(sl.p);
+      if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->d_err) (void)hipFree(c->d_err);
     for (auto& ev : c->prof)
       for (auto e : ev) (void)hipEventDestroy(e);
@@ -526,7 +825,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
   delete c;
 }
 
-const char* hwc_last_error(const hwc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* hwc_last_error(const hwc_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
 
 int hwc_build_field(hwc_ctx* c, uint32_t p, uint32_t e, uint32_t k, hwc_field** out) {
   if (!c || !out) return HWC_ERR_ARG;
@@ -660,13 +959,7 @@ int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flag
   c->err.clear();
   if (flags & HWC_VALIDATE) return fail(c, HWC_ERR_ARG, "HWC_VALIDATE needs host rows");
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  for (size_t i = 0; i < njobs; ++i) {
-    const hwc_job& J = jobs[i];
-    int rc = run_dev(c, J.q, J.g, J.d_coeffs, J.coeff_bytes, J.n, J.d_out_N, J.d_hist_keys, J.d_hist_counts,
-                     J.hist_capacity, J.d_hist_len, flags, s);
-    if (rc) return rc;
-  }
-  return HWC_OK;
+  return run_batch(c, jobs, njobs, flags, s);
 }
 
 int hwc_ctx_status(hwc_ctx* c, void* stream) {

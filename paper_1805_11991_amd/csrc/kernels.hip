@@ -29,6 +29,10 @@ __device__ __forceinline__ uint32_t lds_u16(const uint8_t* base, uint32_t byte_a
   return *reinterpret_cast<const uint16_t*>(base + byte_addr);
 }
 
+__device__ __forceinline__ uint32_t lds_u32(const uint8_t* base, uint32_t byte_addr) {
+  return *reinterpret_cast<const uint32_t*>(base + byte_addr);
+}
+
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ----------------------------------------------------------------------------
@@ -245,12 +249,14 @@ __device__ __forceinline__ void sweep_form_a(const LevelDesc& L, const uint8_t* 
   }
 }
 
-// Form C: element-unit table of 2M entries, index folded with one min.  The
-// zero marker M is not absorbing here, so a fast pass flags any lane that met
-// it and the x is recomputed with the exact rule (rare: about d/M per x).
-template <int NC, bool EXACT>
-__device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, uint32_t M, const uint32_t (&del)[NC],
-                                             uint32_t d, uint32_t mask, uint32_t x, uint32_t& pend, bool& hit) {
+// Forms C and D: element-unit table of 2M entries (u16 in LDS, or u32 in
+// device memory), index folded with one min.  The zero marker M is not
+// absorbing here, so a fast pass flags any lane that met it and the x is
+// recomputed with the exact rule (rare: about d/M per x).
+template <int NC, bool EXACT, bool GLOBAL>
+__device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, const uint32_t* __restrict__ gtab,
+                                             uint32_t M, const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
+                                             uint32_t x, uint32_t& pend, bool& hit) {
   uint32_t a = 0, p = 0;
 #pragma unroll
   for (int i = NC - 2; i >= 0; --i) {
@@ -259,7 +265,7 @@ __device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, u
       if ((mask >> i) & 1u) {
         const uint32_t idx = a + del[i] + p;           // < 3M
         const uint32_t r = min(idx, idx - M);          // < 2M
-        const uint32_t v = lds_u16(lds, tab + 2 * r);
+        const uint32_t v = GLOBAL ? gtab[r] : lds_u16(lds, tab + 2 * r);
         if (EXACT) a = (a == M) ? 0u : v;
         else { hit |= (v == M); a = v; }
         p = 0;
@@ -270,22 +276,23 @@ __device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, u
   return a;
 }
 
-template <int NC>
+template <int NC, bool GLOBAL>
 __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* lds, const uint32_t (&del)[NC],
                                              uint32_t d, uint32_t mask, LevelCounts& c) {
   const uint32_t M = L.M, nx = L.nx, tab = L.tab_off;
   const uint32_t* xs = L.xs;
+  const uint32_t* gtab = L.gtab;
   for (uint32_t ix = 0; ix < nx; ix += 2) {
     const uint32_t x0 = xs ? xs[ix] : ix;
     const bool two = ix + 1 < nx;
     const uint32_t x1 = two ? (xs ? xs[ix + 1] : ix + 1) : x0;
     bool hit = false;
     uint32_t p0, p1;
-    uint32_t a0 = horner_c<NC, false>(lds, tab, M, del, d, mask, x0, p0, hit);
-    uint32_t a1 = horner_c<NC, false>(lds, tab, M, del, d, mask, x1, p1, hit);
+    uint32_t a0 = horner_c<NC, false, GLOBAL>(lds, tab, gtab, M, del, d, mask, x0, p0, hit);
+    uint32_t a1 = horner_c<NC, false, GLOBAL>(lds, tab, gtab, M, del, d, mask, x1, p1, hit);
     if (__ballot(hit)) {
-      a0 = horner_c<NC, true>(lds, tab, M, del, d, mask, x0, p0, hit);
-      a1 = horner_c<NC, true>(lds, tab, M, del, d, mask, x1, p1, hit);
+      a0 = horner_c<NC, true, GLOBAL>(lds, tab, gtab, M, del, d, mask, x0, p0, hit);
+      a1 = horner_c<NC, true, GLOBAL>(lds, tab, gtab, M, del, d, mask, x1, p1, hit);
     }
     c.add(p0 & 1u, a0 == M, a0 & 1u);   // M is even: the marker counts as even
     if (two) c.add(p1 & 1u, a1 == M, a1 & 1u);
@@ -304,7 +311,7 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
     // nonzero codes have logs below M; only a rejected row can reach M here
-    const uint32_t v = lds_u16(lds, L.emb_off + 2 * code[i]);
+    const uint32_t v = lds_u32(lds, L.emb_off + 4 * code[i]);
     lc[i] = v < M ? v : M - 1;
   }
   uint32_t prev = top ? lc[NC - 1] : lc[NC - 2];
@@ -332,8 +339,10 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
     } else {
       sweep_form_a<NC, false, 0>(L, lds, del, d, mask, c);
     }
+  } else if (L.form == kFormC) {
+    sweep_form_c<NC, false>(L, lds, del, d, mask, c);
   } else {
-    sweep_form_c<NC>(L, lds, del, d, mask, c);
+    sweep_form_c<NC, true>(L, lds, del, d, mask, c);
   }
   const uint32_t n0 = L.nx - c.n1;
   const uint32_t z = c.z0 + c.z1;
@@ -371,6 +380,49 @@ __device__ void assemble(const PlanDesc& P, const uint32_t (&lv)[G], uint32_t c0
   }
 }
 
+// One tile (up to 64 curves of one pattern) through levels lvl_lo..lvl_hi.
+template <int G, typename CT>
+__device__ __forceinline__ void process_tile(const PlanDesc& P, const uint8_t* lds, const CT* __restrict__ codes,
+                                             const uint32_t* __restrict__ perm, uint64_t w, uint32_t lvl_lo,
+                                             uint32_t lvl_hi, int32_t* __restrict__ outN,
+                                             uint32_t* __restrict__ outLv) {
+  constexpr int NC = 2 * G + 3;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t pat = uniform((uint32_t)(w & 0xFFFFu));
+  const uint32_t cnt = uniform((uint32_t)((w >> 16) & 0xFFFFu) + 1u);
+  const uint32_t start = uniform((uint32_t)(w >> 32));
+  if (lane >= cnt) return;
+  const uint32_t curve = perm[start + lane];
+  uint32_t code[NC];
+  const CT* row = codes + (uint64_t)curve * NC;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) {
+    int v = (int)row[i];
+    v = v < 0 ? 0 : (v >= (int)P.q ? (int)P.q - 1 : v);  // keeps reads in bounds on bad input
+    code[i] = (uint32_t)v;
+  }
+  const uint32_t top = (pat >> (NC - 1)) & 1u;
+  const uint32_t mask = pat & ((1u << (NC - 1)) - 1u);
+  uint32_t lv[G];
+#pragma unroll
+  for (int j = 0; j < G; ++j) {
+    lv[j] = 0;
+    if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lds, code, top, mask);
+  }
+  if (outN) {
+    const uint32_t log0 = lds_u32(lds, P.lv[0].emb_off + 4 * code[0]);
+    const uint32_t logt = lds_u32(lds, P.lv[0].emb_off + 4 * code[NC - 1]);
+    int32_t n[G];
+    assemble<G>(P, lv, code[0], code[NC - 1], log0, logt, n);
+#pragma unroll
+    for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
+  } else {
+#pragma unroll
+    for (int j = 0; j < G; ++j)
+      if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[(uint64_t)curve * G + j] = lv[j];
+  }
+}
+
 template <int G, typename CT>
 __global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __restrict__ codes,
                                                      const uint32_t* __restrict__ perm,
@@ -378,7 +430,6 @@ __global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __res
                                                      const uint32_t* __restrict__ ntiles_p, uint32_t* queue,
                                                      uint32_t lvl_lo, uint32_t lvl_hi, int32_t* __restrict__ outN,
                                                      uint32_t* __restrict__ outLv) {
-  constexpr int NC = 2 * G + 3;
   extern __shared__ uint32_t lds32[];
   const uint8_t* lds = reinterpret_cast<const uint8_t*>(lds32);
   for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
@@ -395,41 +446,7 @@ __global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __res
     t = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   }
   while (t < ntiles) {
-    const uint64_t w = tiles[t];
-    const uint32_t pat = uniform((uint32_t)(w & 0xFFFFu));
-    const uint32_t cnt = uniform((uint32_t)((w >> 16) & 0xFFFFu) + 1u);
-    const uint32_t start = uniform((uint32_t)(w >> 32));
-    if (lane < cnt) {
-      const uint32_t curve = perm[start + lane];
-      uint32_t code[NC];
-      const CT* row = codes + (uint64_t)curve * NC;
-#pragma unroll
-      for (int i = 0; i < NC; ++i) {
-        int v = (int)row[i];
-        v = v < 0 ? 0 : (v >= (int)P.q ? (int)P.q - 1 : v);  // keeps reads in bounds on bad input
-        code[i] = (uint32_t)v;
-      }
-      const uint32_t top = (pat >> (NC - 1)) & 1u;
-      const uint32_t mask = pat & ((1u << (NC - 1)) - 1u);
-      uint32_t lv[G];
-#pragma unroll
-      for (int j = 0; j < G; ++j) {
-        lv[j] = 0;
-        if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lds, code, top, mask);
-      }
-      if (outN) {
-        const uint32_t log0 = lds_u16(lds, P.lv[0].emb_off + 2 * code[0]);
-        const uint32_t logt = lds_u16(lds, P.lv[0].emb_off + 2 * code[NC - 1]);
-        int32_t n[G];
-        assemble<G>(P, lv, code[0], code[NC - 1], log0, logt, n);
-#pragma unroll
-        for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
-      } else {
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-          if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[(uint64_t)curve * G + j] = lv[j];
-      }
-    }
+    process_tile<G, CT>(P, lds, codes, perm, tiles[t], lvl_lo, lvl_hi, outN, outLv);
     if (queue) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(queue, 1u);
@@ -440,12 +457,118 @@ __global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __res
   }
 }
 
+// ----------------------------------------------------------------------------
+// one persistent launch over several plans: workgroups pop chunks of tiles
+// of one job, restage LDS when the job's plan differs from the staged one.
+
+__device__ __forceinline__ void process_job_tile(const JobDesc& J, const uint8_t* lds, uint64_t w) {
+  const PlanDesc& P = *J.plan;
+#define HWC_JOB(GG)                                                                                    \
+  case GG:                                                                                             \
+    if (J.cb == 1)                                                                                     \
+      process_tile<GG, int8_t>(P, lds, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
+                               nullptr);                                                               \
+    else                                                                                               \
+      process_tile<GG, int16_t>(P, lds, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
+                                J.outN, nullptr);                                                      \
+    break;
+  switch (J.g) {
+    HWC_JOB(1) HWC_JOB(2) HWC_JOB(3) HWC_JOB(4)
+    default: break;
+  }
+#undef HWC_JOB
+}
+
+__global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__ jobs,
+                                                     const uint64_t* __restrict__ chunks,
+                                                     const uint32_t* __restrict__ nchunks_p, uint32_t* queue) {
+  extern __shared__ uint32_t lds32[];
+  __shared__ uint64_t sh_chunk;
+  const uint8_t* lds = reinterpret_cast<const uint8_t*>(lds32);
+  const uint32_t wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const uint32_t nchunks = *nchunks_p;
+  const PlanDesc* staged = nullptr;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const uint32_t c = atomicAdd(queue, 1u);
+      sh_chunk = c < nchunks ? chunks[c] : ~0ull;
+    }
+    __syncthreads();
+    const uint64_t cw = sh_chunk;
+    if (cw == ~0ull) break;
+    const uint32_t job = (uint32_t)(cw & 0xFFFFu), cnt = (uint32_t)((cw >> 16) & 0xFFFFu);
+    const uint32_t t0 = (uint32_t)(cw >> 32);
+    const JobDesc& J = jobs[job];
+    const PlanDesc* P = J.plan;
+    if (P != staged) {
+      const uint32_t* img = P->image;
+      const uint32_t nwords = P->image_bytes / 4;
+      for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) lds32[i] = img[i];
+      __syncthreads();
+      staged = P;
+    }
+    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lds, J.tiles[t]);
+    __syncthreads();
+  }
+}
+
+// chunks for a multi-plan launch: job j contributes ceil(ntiles_j / per)
+// chunks of `per` tiles; ntiles_j sits at ntiles_base[j * stride].  One block
+// scans the per-job chunk counts into chunk_start[0..njobs]; chunk_fill_kernel
+// then writes the chunk words.
+__global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* __restrict__ ntiles_base, uint32_t stride,
+                                                          uint32_t njobs, uint32_t per,
+                                                          uint32_t* __restrict__ chunk_start,
+                                                          uint32_t* __restrict__ nchunks,
+                                                          uint32_t* __restrict__ queue) {
+  __shared__ uint32_t sh[1024];
+  const uint32_t t = threadIdx.x;
+  const uint32_t span = (njobs + blockDim.x - 1) / blockDim.x;
+  const uint32_t j0 = t * span;
+  uint32_t s = 0;
+  for (uint32_t j = j0; j < j0 + span && j < njobs; ++j) s += (ntiles_base[(uint64_t)j * stride] + per - 1) / per;
+  sh[t] = s;
+  __syncthreads();
+  for (uint32_t off = 1; off < blockDim.x; off <<= 1) {
+    const uint32_t v = t >= off ? sh[t - off] : 0u;
+    __syncthreads();
+    sh[t] += v;
+    __syncthreads();
+  }
+  uint32_t pos = sh[t] - s;
+  for (uint32_t j = j0; j < j0 + span && j < njobs; ++j) {
+    chunk_start[j] = pos;
+    pos += (ntiles_base[(uint64_t)j * stride] + per - 1) / per;
+  }
+  if (t == blockDim.x - 1) {
+    chunk_start[njobs] = sh[t];
+    *nchunks = sh[t];
+    *queue = 0;
+  }
+}
+
+__global__ void chunk_fill_kernel(const uint32_t* __restrict__ ntiles_base, uint32_t stride, uint32_t njobs,
+                                  uint32_t per, const uint32_t* __restrict__ chunk_start,
+                                  uint64_t* __restrict__ chunks) {
+  const uint32_t total = chunk_start[njobs];
+  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < total; c += gridDim.x * blockDim.x) {
+    uint32_t lo = 0, hi = njobs;  // last job with chunk_start <= c (it owns c)
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (chunk_start[mid] <= c) lo = mid; else hi = mid;
+    }
+    const uint32_t nt = ntiles_base[(uint64_t)lo * stride];
+    const uint32_t f = (c - chunk_start[lo]) * per;
+    chunks[c] = chunk_pack(lo, f, nt - f < per ? nt - f : per);
+  }
+}
+
 // assembly after per-level launches
 template <int G, typename CT>
 __global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __restrict__ codes, uint64_t n,
                                                        const uint32_t* __restrict__ lv, int32_t* __restrict__ outN) {
   constexpr int NC = 2 * G + 3;
-  const uint16_t* emb1 = reinterpret_cast<const uint16_t*>(reinterpret_cast<const uint8_t*>(P.image) + P.lv[0].emb_off);
+  const uint32_t* emb1 = reinterpret_cast<const uint32_t*>(reinterpret_cast<const uint8_t*>(P.image) + P.lv[0].emb_off);
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     const CT* row = codes + i * NC;
     int c0 = (int)row[0], ct = (int)row[NC - 1];
@@ -476,7 +599,7 @@ static hipError_t launch_count_t(const PlanDesc& P, const void* codes, const uin
 template <int G, typename CT>
 static hipError_t allow_big_lds() {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&count_kernel<G, CT>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageLimit);
 }
 
 // Lets every count kernel use the whole 160 KiB of LDS (done once, outside
@@ -488,6 +611,9 @@ hipError_t prepare_kernels() {
   if (e == hipSuccess) e = allow_big_lds<GG, int16_t>();
   HWC_PREP(1) HWC_PREP(2) HWC_PREP(3) HWC_PREP(4)
 #undef HWC_PREP
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kLdsImageLimit);
   return e;
 }
 
@@ -509,6 +635,27 @@ hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, c
     default: return hipErrorInvalidValue;
   }
 #undef HWC_CASE
+}
+
+hipError_t launch_batch(const JobDesc* jobs, const uint64_t* chunks, const uint32_t* nchunks, uint32_t* queue,
+                        uint32_t lds_bytes, uint32_t grid, uint32_t block, hipStream_t s) {
+  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds_bytes, s, jobs, chunks, nchunks, queue);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint32_t njobs, uint32_t per,
+                              uint32_t* chunk_start, uint64_t* chunks, uint64_t max_chunks, uint32_t* nchunks,
+                              uint32_t* queue, hipStream_t s) {
+  hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, ntiles_base, stride, njobs, per, chunk_start,
+                     nchunks, queue);
+  const uint32_t grid = (uint32_t)((max_chunks + 255) / 256 < 4096 ? (max_chunks + 255) / 256 : 4096);
+  hipLaunchKernelGGL(chunk_fill_kernel, dim3(grid ? grid : 1), dim3(256), 0, s, ntiles_base, stride, njobs, per,
+                     chunk_start, chunks);
+  return hipGetLastError();
+}
+
+hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, block, lds_bytes);
 }
 
 hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {

@@ -11,7 +11,9 @@
 //   form C  (M <= 32767)  "element units": 2M u16 entries.  Entry i holds
 //           Z(i mod M), or M as the zero marker.  One Horner step is add,
 //           fold into [0, 2M), scale to bytes, read, and a marker test.
-//   emb     q u16 entries: log of the F_q code c in F_{q^j}, or M for c = 0.
+//   form D  (any M)  the form C layout with u32 entries, kept in device
+//           memory (L2/MALL-resident) when the level does not fit in LDS.
+//   emb     q u32 entries: log of the F_q code c in F_{q^j}, or M for c = 0.
 //
 // Logs are taken to the primitive element gamma of each F_{q^j}; Z is the
 // Zech logarithm Z(k) = log(1 + gamma^k) (eq. 2.1, table (3.2)).
@@ -22,19 +24,22 @@ namespace hwc {
 
 constexpr int kMaxG = 4;                 // genus handled by the kernels
 constexpr int kMaxCoef = 2 * kMaxG + 3;  // a_0 .. a_{2g+2}
-constexpr uint32_t kFormA = 0, kFormC = 1;
+constexpr uint32_t kFormA = 0, kFormC = 1, kFormD = 2;
 constexpr uint32_t kFormAMaxM = 10922;   // 6M must fit in u16
 constexpr uint32_t kFormCMaxM = 32767;   // M must fit in 15 bits
 constexpr int kWave = 64;
+// LDS of one CU is 160 KiB; 256 bytes stay free for the kernels' own variables
+constexpr uint32_t kLdsImageLimit = 160 * 1024 - 256;
 
 struct LevelDesc {
   uint32_t M;         // |F_{q^j}^x|
-  uint32_t form;      // kFormA or kFormC
+  uint32_t form;      // kFormA, kFormC or kFormD
   uint32_t tab_off;   // byte offset of the level's table in the image
   uint32_t emb_off;   // byte offset of the level's emb table in the image
   uint32_t nx;        // number of x logs swept at this level
   uint32_t weight;    // points of F_{q^j} each swept x stands for (orbit size, or 1)
   const uint32_t* xs; // x logs (device), nullptr: x runs over 0..M-1
+  const uint32_t* gtab;  // form D: 2M entries in device memory
 };
 
 struct PlanDesc {
@@ -44,6 +49,21 @@ struct PlanDesc {
   const uint32_t* image;  // device copy of the image (dwords)
   LevelDesc lv[kMaxG];
 };
+
+// One request of a multi-plan launch (device memory).
+struct JobDesc {
+  const PlanDesc* plan;   // device copy of the job's plan
+  const void* codes;      // [n][2g+3] int8 or int16
+  const uint32_t* perm;   // bucketed order of the job's rows
+  const uint64_t* tiles;  // the job's tile words
+  int32_t* outN;          // [n][g]
+  uint32_t cb, g;         // code bytes, genus
+};
+
+// chunk word of a multi-plan launch: job | tile count << 16 | first tile << 32
+__host__ __device__ inline uint64_t chunk_pack(uint32_t job, uint32_t first, uint32_t count) {
+  return (uint64_t)job | ((uint64_t)count << 16) | ((uint64_t)first << 32);
+}
 
 // A tile is up to 64 curves that share degree and zero pattern.
 // word = pattern | (count-1) << 16 | start << 32

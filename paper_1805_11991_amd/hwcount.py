@@ -148,7 +148,7 @@ class Context:
         h = ctypes.c_void_p()
         rc = lib.hwc_ctx_create(device, hbm_budget_bytes, ctypes.byref(h))
         if rc != HWC_OK:
-            raise HwcError(rc, "hwc_ctx_create failed")
+            raise HwcError(rc, "hwc_ctx_create failed: " + (lib.hwc_last_error(None) or b"").decode())
         self._h = h
         self.device = device
 

@@ -142,7 +142,7 @@ def test_errors(gctx):
         (dict(q=5, g=0, coeffs=np.zeros((1, 3), np.int16)), hwcount.HWC_ERR_BAD_G),
         (dict(q=5, g=2, coeffs=np.array([[5, 0, 0, 0, 0, 1, 0]], np.int16)), hwcount.HWC_ERR_COEFF_RANGE),
         (dict(q=5, g=2, coeffs=np.array([[1, 0, 0, 0, 1, 0, 0]], np.int16)), hwcount.HWC_ERR_DEGREE),
-        (dict(q=41, g=3, coeffs=np.array([[1] + [0] * 7 + [1]], np.int16)), hwcount.HWC_ERR_FIELD_TOO_LARGE),
+        (dict(q=4099, g=2, coeffs=good), hwcount.HWC_ERR_FIELD_TOO_LARGE),   # q^2 > 2^24
     ]
     for kw, code in cases:
         with pytest.raises(hwcount.HwcError) as ei:
@@ -235,3 +235,83 @@ def test_full_size_g3_q13_sampled(gctx, oracle_mod, curvegen_mod):
     # the histogram equals the one of the per-curve output
     k2, c2 = _hist_np(Nh)
     assert np.array_equal(k2, keys) and np.array_equal(c2, cnt.astype(np.uint64))
+
+
+@pytest.mark.parametrize("q,g,n", [(191, 2, 30), (211, 2, 24), (293, 2, 16), (37, 3, 6), (41, 3, 5), (43, 3, 4),
+                                   (49, 3, 3)])
+def test_device_memory_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
+    # q^g - 1 > 32767: the top level's Zech table stays in device memory (form D)
+    curves = curvegen_mod.sample(q, g, n, seed=777 + q, dtype=np.int16)
+    _check(gctx, oracle_mod, q, g, curves)
+
+
+def _batch_specs(curvegen_mod):
+    specs = []
+    specs.append((5, 2, curvegen_mod.enumerate_all(5, 2)[::7]))
+    specs.append((13, 3, curvegen_mod.sample(13, 3, 3000, seed=curvegen_mod.BASE_SEED + 1)))
+    specs.append((3, 4, curvegen_mod.enumerate_all(3, 4)[::50]))
+    specs.append((13, 4, curvegen_mod.sample(13, 4, 90, seed=curvegen_mod.BASE_SEED + 3)))
+    specs.append((9, 2, curvegen_mod.sample(9, 2, 500, seed=91)))
+    specs.append((293, 2, curvegen_mod.sample(293, 2, 10, seed=92)))
+    specs.append((49, 3, curvegen_mod.sample(49, 3, 3, seed=93)))
+    specs.append((7, 1, curvegen_mod.sample(7, 1, 300, seed=94)))
+    specs.append((13, 3, curvegen_mod.sample(13, 3, 0, seed=95)))          # empty request
+    specs.append((11, 4, curvegen_mod.sample(11, 4, 33, seed=96)))
+    return specs
+
+
+def test_multi_plan_batch(gctx, oracle_mod, curvegen_mod):
+    """One persistent launch over requests of different (q, g): every request's
+    N and histogram equal the oracle's, with graph capture, replay, the direct
+    launch and the full sweep."""
+    import torch
+    from paper_1805_11991_amd import hwcount
+    specs = _batch_specs(curvegen_mod)
+    refs = [oracle_mod.count_curves(q, g, c) if len(c) else np.zeros((0, g), np.int32) for q, g, c in specs]
+    jobs = []
+    for (q, g, c) in specs:
+        n = len(c)
+        jobs.append(dict(q=q, g=g, d_coeffs=torch.from_numpy(c).cuda(),
+                         d_out_N=torch.empty((n, g), dtype=torch.int32, device="cuda"),
+                         d_hist_keys=torch.empty((max(n, 1), g), dtype=torch.int32, device="cuda"),
+                         d_hist_counts=torch.empty(max(n, 1), dtype=torch.int64, device="cuda"),
+                         d_hist_len=torch.zeros(1, dtype=torch.int64, device="cuda")))
+    for rep, flags in enumerate((0, 0, 0, hwcount.HWC_NO_GRAPH, hwcount.HWC_FULL_SWEEP)):
+        print(f"  batch rep {rep} flags {flags}", flush=True)
+        for j in jobs:
+            j["d_out_N"].fill_(-1)
+            j["d_hist_len"].fill_(-1)
+        gctx.count_batch(jobs, flags=flags)
+        gctx.status()
+        for (q, g, c), j, ref in zip(specs, jobs, refs):
+            N = j["d_out_N"].cpu().numpy()
+            assert np.array_equal(N, ref), (rep, q, g)
+            L = int(j["d_hist_len"].item())
+            if len(c):
+                k, cnt = oracle_mod.histogram(ref)
+                assert L == len(k)
+                assert np.array_equal(j["d_hist_keys"][:L].cpu().numpy(), k)
+                assert np.array_equal(j["d_hist_counts"][:L].cpu().numpy().astype(np.uint64), cnt)
+            else:
+                assert L == 0
+
+
+def test_two_streams_are_ordered(gctx, oracle_mod, curvegen_mod):
+    """Calls of one context on different streams share scratch; the library
+    orders them, so results stay exact when they are issued back to back."""
+    import torch
+    a = curvegen_mod.sample(13, 3, 4000, seed=501)
+    b = curvegen_mod.sample(7, 4, 300, seed=502)
+    ra, rb = oracle_mod.count_curves(13, 3, a), oracle_mod.count_curves(7, 4, b)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    torch.cuda.synchronize()
+    Na = torch.empty((len(a), 3), dtype=torch.int32, device="cuda")
+    Nb = torch.empty((len(b), 4), dtype=torch.int32, device="cuda")
+    for _ in range(3):
+        gctx.count_curves_dev(13, 3, da, Na, stream=s1)
+        gctx.count_curves_dev(7, 4, db, Nb, stream=s2)
+    torch.cuda.synchronize()
+    gctx.status()
+    assert np.array_equal(Na.cpu().numpy(), ra)
+    assert np.array_equal(Nb.cpu().numpy(), rb)
