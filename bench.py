@@ -36,17 +36,32 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def lookups_per_batch(curves, g: int, nx_levels: list[int]) -> int:
-    """Zech lookups the method needs: every Horner step that adds a nonzero
-    coefficient costs one table read, for every swept x of every level."""
+def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
+    """Table reads the count kernel's algorithm needs for a batch, and the
+    plain-Horner count for reference.
+
+    Plain Horner: one read per nonzero term below the leading one, for every
+    swept x.  Split evaluation (levels with msplit = m): a tuple of m points
+    costs sum_r (terms of class r - 1) reads for the sub-polynomials plus
+    m (m - 1) for the combinations, when every class holds a term; other rows
+    and the single points cost plain Horner."""
     import numpy as np
-    c = curves.astype(np.int64)
-    nz = (c != 0)
-    top = nz[:, -1]
-    # terms of f: nonzero coefficients up to and including the leading one
-    terms = nz[:, :-1].sum(axis=1) + top
-    steps = terms - 1
-    return int(steps.sum()) * int(sum(nx_levels))
+    sup = curves.astype(np.int64) != 0
+    terms = sup.sum(axis=1)
+    horner = terms - 1
+    total = plain = 0
+    for L in levels:
+        plain += int(horner.sum()) * L["nx"]
+        m = L["msplit"]
+        if not m:
+            total += int(horner.sum()) * L["nx"]
+            continue
+        cls = [sup[:, r::m].sum(axis=1) for r in range(m)]
+        ok = np.logical_and.reduce([cc > 0 for cc in cls])
+        per_tuple = sum(cc - 1 for cc in cls) + m * (m - 1)
+        cost = np.where(ok, L["nt"] * per_tuple + L["ns"] * horner, L["nx"] * horner)
+        total += int(cost.sum())
+    return total, plain
 
 
 def time_loop(fn, steps: int, warmup: int, sync) -> float:
@@ -83,15 +98,6 @@ def main():
     stream = torch.cuda.current_stream(dev)
     sync = torch.cuda.synchronize
     ctx = hwcount.Context(device=0)
-    hctx = hwcount.Context(device=-1)
-
-    def nx_levels(q, g, orbit=True):
-        out = []
-        for j in range(1, g + 1):
-            f = hctx.build_field(q, 1, j)
-            info = f.info()
-            out.append(int(info.nprim_orbits) if orbit else int(info.Q) - 1)
-        return out
 
     def setup(q, g, n, seed):
         t0 = time.perf_counter()
@@ -129,8 +135,9 @@ def main():
     ctx.status()
     assert np.array_equal(bufs[2].cpu().numpy(), Nref), "profiled run differs from the graph run"
     count_ms = prof["count_ms"] / prof["calls"]
-    nx = nx_levels(q, g, orbit=True)
-    lookups = lookups_per_batch(curves, g, nx)
+    levels = ctx.plan_info(q, g)
+    nx = [L["nx"] for L in levels]
+    lookups, plain_lookups = lookups_per_batch(curves, levels)
     achieved = lookups / (count_ms * 1e-3)
     roofline = {
         "bound": "lds",
@@ -142,6 +149,8 @@ def main():
         "kernel": "count_kernel<3,int8>",
         "kernel_ms": round(count_ms, 4),
         "lookups_per_launch": lookups,
+        "plain_horner_lookups": plain_lookups,
+        "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit", "nt", "ns")} for L in levels],
         "prep_ms": round(prof["prep_ms"] / prof["calls"], 4),
         "hist_ms": round(prof["hist_ms"] / prof["calls"], 4),
     }
@@ -178,7 +187,7 @@ def main():
         runner(13, 4, bufs4, 0)()
         p4 = ctx.profile_read()
         ctx.profile(False)
-        lk4 = lookups_per_batch(bufs4[0], 4, nx_levels(13, 4))
+        lk4, _ = lookups_per_batch(bufs4[0], ctx.plan_info(13, 4))
         g4["count_kernel_ms"] = round(p4["count_ms"], 3)
         g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
         g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)

@@ -161,6 +161,18 @@ int hwc_ctx_status(hwc_ctx* ctx, void* stream);
 int hwc_ctx_profile(hwc_ctx* ctx, int enable);
 int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double* hist_ms, uint64_t* calls);
 
+/* Geometry of the counting plan for (q, g) and the sweep of `flags` (built
+ * and cached if needed): per level j = 1..g, levels[j-1] receives the order
+ * M of F_{q^j}^x, the table form (0: u16 in LDS, byte units; 1: u16 in LDS,
+ * folded index; 2: u32 in device memory), the number nx of swept x, the
+ * weight of each, the split factor m (0: plain Horner; else the sweep runs nt
+ * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
+ * x^m, plus ns single points), and the LDS bytes of the plan. */
+typedef struct {
+  uint32_t M, form, nx, weight, msplit, nt, ns, lds_bytes;
+} hwc_level_desc;
+int hwc_plan_info(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags, hwc_level_desc* levels);
+
 /* Cache statistics: fields built, plans resident, device bytes of tables,
  * hits and misses of the table cache.  Any pointer may be NULL. */
 int hwc_ctx_stats(const hwc_ctx* ctx, uint64_t* plans_resident, uint64_t* table_bytes, uint64_t* cache_hits,

@@ -63,6 +63,7 @@ struct DevPlan {
   hwc::PlanDesc* d_desc = nullptr;   // device copy of desc (multi-plan launches)
   std::vector<uint32_t*> d_reps;
   std::vector<uint32_t*> d_gtab;     // form D tables
+  std::vector<uint32_t*> d_tup, d_sgl;  // split-evaluation tuple representatives and singles
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
   uint32_t block = 256, grid = 0;
@@ -121,6 +122,7 @@ struct hwc_ctx {
   bool order_valid = false;
   // profiling: events around the phases of each direct (non-graph) call
   bool profile = false;
+  bool split = true;   // split evaluation over mu_m cosets on form A levels
   std::vector<std::array<hipEvent_t, 4>> prof;
   std::vector<hipEvent_t> event_pool;
 };
@@ -201,6 +203,12 @@ void free_plan(DevPlan* P) {
     if (r) (void)hipFree(r);
   for (auto* t : P->d_gtab)
     if (t) (void)hipFree(t);
+  for (auto* t : P->d_tup)
+    if (t) (void)hipFree(t);
+  for (auto* t : P->d_sgl)
+    if (t) (void)hipFree(t);
+  P->d_tup.clear();
+  P->d_sgl.clear();
   P->d_image = nullptr;
   P->d_desc = nullptr;
   P->d_reps.clear();
@@ -361,9 +369,35 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       D.lv[j].gtab = P->d_gtab[j];
     }
   }
+  // split evaluation over mu_m cosets on form A levels (m = 3 when 3 | q-1)
+  P->d_tup.assign(g, nullptr);
+  P->d_sgl.assign(g, nullptr);
+  for (uint32_t j = 0; j < g; ++j) {
+    hwc::LevelDesc& L = D.lv[j];
+    L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
+    if (!c->split || L.form != hwc::kFormA) continue;
+    const uint32_t m = ((q - 1) % 3 == 0) ? 3u : 2u;
+    L.msplit = m;
+    if (!orbit) {
+      L.nt = L.M / m;
+      continue;
+    }
+    std::vector<uint32_t> tup, sgl;
+    hwc::split_orbits(P->fields[j]->F, m, &tup, &sgl);
+    L.nt = (uint32_t)tup.size();
+    L.ns = (uint32_t)sgl.size();
+    HIPX(c, hipMalloc(&P->d_tup[j], std::max<size_t>(tup.size(), 1) * 4));
+    HIPX(c, hipMalloc(&P->d_sgl[j], std::max<size_t>(sgl.size(), 1) * 4));
+    if (!tup.empty()) HIPX(c, hipMemcpy(P->d_tup[j], tup.data(), tup.size() * 4, hipMemcpyHostToDevice));
+    if (!sgl.empty()) HIPX(c, hipMemcpy(P->d_sgl[j], sgl.data(), sgl.size() * 4, hipMemcpyHostToDevice));
+    L.xs_t = P->d_tup[j];
+    L.xs_s = P->d_sgl[j];
+    P->dev_bytes += (tup.size() + sgl.size()) * 4;
+    c->table_bytes += (tup.size() + sgl.size()) * 4;
+  }
   HIPX(c, hipMalloc(&P->d_desc, sizeof(hwc::PlanDesc)));
   HIPX(c, hipMemcpy(P->d_desc, &D, sizeof(hwc::PlanDesc), hipMemcpyHostToDevice));
-  P->dev_bytes = bytes;
+  P->dev_bytes += bytes;
   c->table_bytes += bytes;
   // launch shape: many waves per CU; one large block when the tables fill LDS
   P->block = D.image_bytes > 80 * 1024 ? 1024 : 256;
@@ -1005,6 +1039,28 @@ int hwc_ctx_profile_read(hwc_ctx* c, double* prep_ms, double* count_ms, double* 
   if (prep_ms) *prep_ms = t[0];
   if (count_ms) *count_ms = t[1];
   if (hist_ms) *hist_ms = t[2];
+  return HWC_OK;
+}
+
+int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_desc* levels) {
+  if (!c || !levels) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = check_args(c, q, g, flags);
+  if (rc) return rc;
+  HIPX(c, hipSetDevice(c->device));
+  DevPlan* P = nullptr;
+  if ((rc = get_plan(c, q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u, &P))) return rc;
+  for (uint32_t j = 0; j < g; ++j) {
+    const hwc::LevelDesc& L = P->desc.lv[j];
+    levels[j].M = L.M;
+    levels[j].form = L.form;
+    levels[j].nx = L.nx;
+    levels[j].weight = L.weight;
+    levels[j].msplit = L.msplit;
+    levels[j].nt = L.nt;
+    levels[j].ns = L.ns;
+    levels[j].lds_bytes = P->desc.image_bytes;
+  }
   return HWC_OK;
 }
 

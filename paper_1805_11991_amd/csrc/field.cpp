@@ -173,4 +173,32 @@ std::string build_field(uint32_t p, uint32_t e, uint32_t k, Field* F) {
   return "";
 }
 
+void split_orbits(const Field& F, uint32_t m, std::vector<uint32_t>* tuples, std::vector<uint32_t>* singles) {
+  tuples->clear();
+  singles->clear();
+  const uint64_t M = F.M;
+  // least element of the Frobenius orbit of every primitive element
+  std::vector<uint32_t> rep(M, UINT32_MAX);
+  for (uint32_t r : F.prim_reps) {
+    uint64_t x = r;
+    do {
+      rep[x] = r;
+      x = (x * F.q) % M;
+    } while (x != r);
+  }
+  std::vector<uint8_t> done(M, 0);
+  const uint64_t step = M / m;
+  for (uint32_t r : F.prim_reps) {
+    if (done[r]) continue;
+    const uint32_t r1 = rep[(r + step) % M];
+    if (r1 == r) {                  // the orbit is closed under w
+      singles->push_back(r);
+      done[r] = 1;
+      continue;
+    }
+    tuples->push_back(r);
+    for (uint32_t s = 0; s < m; ++s) done[rep[(r + s * step) % M]] = 1;
+  }
+}
+
 }  // namespace hwc

@@ -38,6 +38,15 @@ bool factor_odd_prime_power(uint64_t q, uint32_t* p, uint32_t* e);
 bool lex_first_primitive(uint32_t p, uint32_t n, std::vector<uint32_t>* poly,
                          std::vector<uint32_t>* exp_out);
 
+// Groups the primitive Frobenius orbits into cosets of mu_m (m | q - 1, so the
+// m-th roots of unity lie in F_q and multiplying by them keeps an element's
+// field of definition).  For a representative x of each group whose points
+// x, wx, .., w^(m-1)x (w = gamma^(M/m)) lie in m distinct Frobenius orbits,
+// the representative's log goes to *tuples; orbits closed under w go to
+// *singles.  Every primitive orbit is covered exactly once:
+// m * tuples.size() + singles.size() == prim_reps.size().
+void split_orbits(const Field& F, uint32_t m, std::vector<uint32_t>* tuples, std::vector<uint32_t>* singles);
+
 // Build every table of F_{p^(e k)} with F_{p^e} embedded.  Returns an empty
 // string on success, else a message.
 std::string build_field(uint32_t p, uint32_t e, uint32_t k, Field* out);

@@ -190,19 +190,36 @@ struct LevelCounts {
 };
 
 // Form A: byte-unit table, zero region; one add + one read per step.
-// del[i] already holds 2*delta_i + table offset.
+// del[i] already holds 2*delta_i + table offset.  Returns the relative log
+// (byte units, or the zero marker 6M) and the pending power low*x in pend.
+template <int NC>
+__device__ __forceinline__ uint32_t horner_a(const uint8_t* lds, const uint32_t (&del)[NC], uint32_t M, uint32_t d,
+                                             uint32_t mask, uint32_t x, uint32_t& pend) {
+  uint32_t a = 0, p = 0;
+#pragma unroll
+  for (int i = NC - 2; i >= 0; --i) {
+    if ((uint32_t)i < d) {
+      p += x; p = p >= M ? p - M : p;
+      if ((mask >> i) & 1u) {
+        a = lds_u16(lds, a + del[i] + 2 * p);
+        p = 0;
+      }
+    }
+  }
+  pend = p;
+  return a;
+}
+
 template <int NC, bool FULL, int D>
-__device__ __forceinline__ void sweep_form_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&del)[NC],
-                                             uint32_t d, uint32_t mask, LevelCounts& c) {
-  const uint32_t M = L.M, S = 6 * M;
-  const uint32_t nx = L.nx;
-  const uint32_t* xs = L.xs;
+__device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, uint32_t M, const uint8_t* lds,
+                                             const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
+  const uint32_t S = 6 * M;
   uint32_t ix = 0;
   for (; ix + 2 <= nx; ix += 2) {
     const uint32_t x0 = xs ? xs[ix] : ix;
     const uint32_t x1 = xs ? xs[ix + 1] : ix + 1;
-    uint32_t a0 = 0, a1 = 0;
     if (FULL) {
+      uint32_t a0 = 0, a1 = 0;
       const uint32_t b0 = 2 * x0, b1 = 2 * x1;
 #pragma unroll
       for (int i = D - 1; i >= 0; --i) {
@@ -212,40 +229,110 @@ __device__ __forceinline__ void sweep_form_a(const LevelDesc& L, const uint8_t* 
       c.z0 += (a0 == S) + (a1 == S);
       c.o0 += ((a0 >> 1) & 1u) + ((a1 >> 1) & 1u);
     } else {
-      uint32_t p0 = 0, p1 = 0;  // pending powers of x (element units, scalar)
-#pragma unroll
-      for (int i = NC - 2; i >= 0; --i) {
-        if ((uint32_t)i < d) {
-          p0 += x0; p0 = p0 >= M ? p0 - M : p0;
-          p1 += x1; p1 = p1 >= M ? p1 - M : p1;
-          if ((mask >> i) & 1u) {
-            a0 = lds_u16(lds, a0 + del[i] + 2 * p0);
-            a1 = lds_u16(lds, a1 + del[i] + 2 * p1);
-            p0 = 0;
-            p1 = 0;
-          }
-        }
-      }
-      const uint32_t z0 = a0 == S, z1 = a1 == S;
-      const uint32_t o0 = (a0 >> 1) & 1u, o1 = (a1 >> 1) & 1u;
-      c.add(p0 & 1u, z0, o0);
-      c.add(p1 & 1u, z1, o1);
+      uint32_t p0, p1;
+      const uint32_t a0 = horner_a<NC>(lds, del, M, d, mask, x0, p0);
+      const uint32_t a1 = horner_a<NC>(lds, del, M, d, mask, x1, p1);
+      c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
+      c.add(p1 & 1u, a1 == S, (a1 >> 1) & 1u);
     }
   }
   if (ix < nx) {
     const uint32_t x0 = xs ? xs[ix] : ix;
-    uint32_t a0 = 0, p0 = 0;
+    uint32_t p0;
+    const uint32_t a0 = horner_a<NC>(lds, del, M, d, mask, x0, p0);
+    c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
+  }
+}
+
+__device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t M) {  // a, b < M
+  const uint32_t s = a + b;
+  return s >= M ? s - M : s;
+}
+
+// Sub-polynomial r of the split (positions i = r mod MS) by relative Horner in
+// y (log Y).  sup has bit d set.  Returns the relative log (byte units or the
+// zero marker) and in pend the power t_r Y of the class's lowest term.
+template <int NC, int MS, int R>
+__device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint32_t (&sdel)[NC], uint32_t M,
+                                                 uint32_t d, uint32_t sup, uint32_t Y, uint32_t& pend) {
+  uint32_t a = 0, p = 0;
+  bool started = false;
 #pragma unroll
-    for (int i = NC - 2; i >= 0; --i) {
-      if ((uint32_t)i < d) {
-        p0 += x0; p0 = p0 >= M ? p0 - M : p0;
-        if ((mask >> i) & 1u) {
-          a0 = lds_u16(lds, a0 + del[i] + 2 * p0);
-          p0 = 0;
-        }
+  for (int i = NC - 1; i >= 0; --i) {
+    if (i % MS != R) continue;
+    if ((uint32_t)i > d) continue;
+    if (started) p = addmod(p, Y, M);
+    if ((sup >> i) & 1u) {
+      if (started) a = lds_u16(lds, a + sdel[i] + 2 * p);
+      started = true;
+      p = 0;
+    }
+  }
+  pend = p;
+  return a;
+}
+
+// Split evaluation over mu_MS cosets (form A).  With w = gamma^(M/MS) in F_q,
+// f(w^s x) = sum_r w^(s r) x^r f_r(x^MS): the MS points of a tuple share the
+// sub-polynomial values at y = x^MS, then cost MS-1 Zech additions each,
+// chained from the top class in relative form:
+//   B = Z(a_2 - a_1), R = Z(B + a_1 - a_0), log f = R + a_0   (MS = 3),
+// a_r = log(w^(s r) x^r f_r(y)).  A vanishing f_r(y) below the top class has
+// no relative log; the wave then evaluates the tuple's points by plain Horner.
+template <int NC, int MS>
+__device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&sdel)[NC],
+                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t dl1,
+                                              uint32_t dl2, uint32_t fix, LevelCounts& c) {
+  const uint32_t M = L.M, S = 6 * M, step = M / MS, tab = L.tab_off;
+  const uint32_t sup = mask | (1u << d);
+  const uint32_t nt = L.nt;
+  for (uint32_t it = 0; it < nt; ++it) {
+    const uint32_t x = L.xs_t ? L.xs_t[it] : it;
+    uint32_t Y = 0;
+#pragma unroll
+    for (int m = 0; m < MS; ++m) Y = addmod(Y, x, M);
+    uint32_t p0, p1, p2 = 0;
+    const uint32_t a0 = horner_class<NC, MS, 0>(lds, sdel, M, d, sup, Y, p0);
+    const uint32_t a1 = horner_class<NC, MS, 1>(lds, sdel, M, d, sup, Y, p1);
+    uint32_t a2 = S;
+    if (MS == 3) a2 = horner_class<NC, MS, 2>(lds, sdel, M, d, sup, Y, p2);
+    const bool inner_zero = (a0 == S) || (MS == 3 && a1 == S);
+    if (__ballot(inner_zero)) {
+      for (uint32_t s = 0; s < MS; ++s) {
+        uint32_t pp;
+        const uint32_t xs = addmod(x, s * step, M);
+        const uint32_t a = horner_a<NC>(lds, del, M, d, mask, xs, pp);
+        c.add(pp & 1u, a == S, (a >> 1) & 1u);
+      }
+      continue;
+    }
+    const uint32_t cls = p0 & 1u;  // parity of t_0 Y
+    if (MS == 2) {
+      uint32_t F1 = 2 * M - a0 + 2 * dl1;              // (0, 4M)
+      F1 = min(F1, F1 - 2 * M);
+      const uint32_t u0 = addmod(addmod(x, p1, M), M - p0 == M ? 0u : M - p0, M);
+#pragma unroll
+      for (uint32_t s = 0; s < 2; ++s) {
+        const uint32_t u = addmod(u0, s * step, M);
+        const uint32_t r = lds_u16(lds, a1 + F1 + (2 * u + tab));
+        c.add(cls, r == S, r == S ? 0u : (((r + a0) >> 1) ^ fix) & 1u);
+      }
+    } else {
+      uint32_t F2 = 2 * M - a1 + 2 * dl2;              // (0, 4M)
+      F2 = min(F2, F2 - 2 * M);
+      uint32_t F1 = a1 + 2 * M - a0 + 2 * dl1;         // (0, 6M)
+      F1 = min(F1, F1 - 2 * M);
+      F1 = min(F1, F1 - 2 * M);
+      const uint32_t v2 = addmod(addmod(x, p2, M), p1 ? M - p1 : 0u, M);
+      const uint32_t v1 = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
+#pragma unroll
+      for (uint32_t s = 0; s < 3; ++s) {
+        const uint32_t u2 = addmod(v2, s * step, M), u1 = addmod(v1, s * step, M);
+        const uint32_t b = lds_u16(lds, a2 + F2 + (2 * u2 + tab));
+        const uint32_t r = lds_u16(lds, b + F1 + (2 * u1 + tab));
+        c.add(cls, r == S, r == S ? 0u : (((r + a0) >> 1) ^ fix) & 1u);
       }
     }
-    c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
   }
 }
 
@@ -331,13 +418,58 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
   LevelCounts c = {0, 0, 0, 0, 0};
   const bool full = mask == ((1u << d) - 1u);
   if (L.form == kFormA) {
+    // split evaluation: needs every class below the top class to hold a term
+    const uint32_t sup = mask | (1u << d);
+    uint32_t ms = L.msplit;
+    if (ms) {
+      uint32_t cls_mask = 0;
 #pragma unroll
-    for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
-    if (full) {
-      if (top) sweep_form_a<NC, true, NC - 1>(L, lds, del, d, mask, c);
-      else sweep_form_a<NC, true, NC - 2>(L, lds, del, d, mask, c);
+      for (int i = 0; i < NC; ++i)
+        if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 3 ? i % 3 : i % 2);
+      if (cls_mask != (1u << ms) - 1u) ms = 0;
+    }
+    if (ms) {
+      // per-class relative deltas, in byte units plus the table offset
+      uint32_t sdel[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) sdel[i] = L.tab_off;
+      uint32_t lowlog[3] = {0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        if (r >= (int)ms) break;
+        bool started = false;
+        uint32_t pv = 0;
+#pragma unroll
+        for (int i = NC - 1; i >= 0; --i) {
+          const uint32_t cl = ms == 3 ? (uint32_t)(i % 3) : (uint32_t)(i % 2);
+          if (cl != (uint32_t)r || (uint32_t)i > d || !((sup >> i) & 1u)) continue;
+          if (started) {
+            uint32_t v = pv + M - lc[i];
+            v = v >= M ? v - M : v;
+            sdel[i] = 2 * v + L.tab_off;
+          }
+          started = true;
+          pv = lc[i];
+        }
+        lowlog[r] = pv;
+      }
+      const uint32_t dl1 = lowlog[1] >= lowlog[0] ? lowlog[1] - lowlog[0] : lowlog[1] + M - lowlog[0];
+      const uint32_t dl2 = lowlog[2] >= lowlog[1] ? lowlog[2] - lowlog[1] : lowlog[2] + M - lowlog[1];
+      const uint32_t fix = (lowlog[0] ^ prev) & 1u;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
+      if (ms == 3) sweep_split_a<NC, 3>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+      else sweep_split_a<NC, 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+      sweep_form_a<NC, false, 0>(L.xs_s, L.ns, M, lds, del, d, mask, c);
     } else {
-      sweep_form_a<NC, false, 0>(L, lds, del, d, mask, c);
+#pragma unroll
+      for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
+      if (full) {
+        if (top) sweep_form_a<NC, true, NC - 1>(L.xs, L.nx, M, lds, del, d, mask, c);
+        else sweep_form_a<NC, true, NC - 2>(L.xs, L.nx, M, lds, del, d, mask, c);
+      } else {
+        sweep_form_a<NC, false, 0>(L.xs, L.nx, M, lds, del, d, mask, c);
+      }
     }
   } else if (L.form == kFormC) {
     sweep_form_c<NC, false>(L, lds, del, d, mask, c);

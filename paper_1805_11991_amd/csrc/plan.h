@@ -40,6 +40,12 @@ struct LevelDesc {
   uint32_t weight;    // points of F_{q^j} each swept x stands for (orbit size, or 1)
   const uint32_t* xs; // x logs (device), nullptr: x runs over 0..M-1
   const uint32_t* gtab;  // form D: 2M entries in device memory
+  // split evaluation over mu_m cosets (form A levels): nt tuple
+  // representatives (points L + s M/m, s < m) and ns single points; together
+  // they are the same nx points.  msplit = 0 turns it off.
+  uint32_t msplit, nt, ns;
+  const uint32_t* xs_t;  // nullptr: representatives 0..M/m-1 (full sweep)
+  const uint32_t* xs_s;
 };
 
 struct PlanDesc {

@@ -36,7 +36,8 @@ HWC_NO_GRAPH = 8
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read")
+           "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
+           "hwc_plan_info")
 
 
 class HwcError(RuntimeError):
@@ -55,6 +56,10 @@ class hwc_field_desc(ctypes.Structure):
 class hwc_hist(ctypes.Structure):
     _fields_ = [("g", ctypes.c_uint32), ("capacity", ctypes.c_uint64), ("len", ctypes.c_uint64),
                 ("keys", ctypes.c_void_p), ("counts", ctypes.c_void_p)]
+
+
+class hwc_level_desc(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("M", "form", "nx", "weight", "msplit", "nt", "ns", "lds_bytes")]
 
 
 class hwc_job(ctypes.Structure):
@@ -91,6 +96,7 @@ def load():
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
                                 ctypes.POINTER(u64)]),
         "hwc_ctx_profile": (i32, [vp, i32]),
+        "hwc_plan_info": (i32, [vp, u32, u32, u32, ctypes.POINTER(hwc_level_desc)]),
         "hwc_ctx_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]),
     }
@@ -238,6 +244,11 @@ class Context:
         n = ctypes.c_uint64()
         self._check(load().hwc_ctx_profile_read(self._h, *(ctypes.byref(x) for x in t), ctypes.byref(n)))
         return {"prep_ms": t[0].value, "count_ms": t[1].value, "hist_ms": t[2].value, "calls": n.value}
+
+    def plan_info(self, q: int, g: int, flags: int = 0) -> list[dict]:
+        arr = (hwc_level_desc * g)()
+        self._check(load().hwc_plan_info(self._h, q, g, flags, arr))
+        return [{f: getattr(a, f) for f, _ in hwc_level_desc._fields_} for a in arr]
 
     def stats(self) -> dict:
         v = [ctypes.c_uint64() for _ in range(4)]
