@@ -124,7 +124,7 @@ def main():
     value = n / (ms * 1e-3)
     log(f"g3 q13 batched orbit: {ms:.3f} ms/step, {value:.4g} curves/s")
     Nref = bufs[2].cpu().numpy()
-    L = int(bufs[5].item())
+    nhist = int(bufs[5].item())
 
     # roofline: the count kernel timed with HIP events on its launch stream
     ctx.profile(True)
@@ -165,7 +165,7 @@ def main():
             m = time_loop(fn, max(1, min(args.steps, 3)), 1, sync) * 1e3
             ctx.status()
             assert np.array_equal(bufs[2].cpu().numpy(), Nref), f"{name} differs from batched"
-            assert int(bufs[5].item()) == L
+            assert int(bufs[5].item()) == nhist
             extra[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n / (m * 1e-3), 1)}
             log(f"g3 q13 {name}: {m:.3f} ms/step")
         extra["batched_vs_plain"] = round(extra["plain_orbit"]["ms_per_step"] / ms, 3)
@@ -223,7 +223,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic: seeded uniform square-free curves (SplitMix64/Lemire rejection), no dataset",
         "config": {"workload": "g3_q13_2^24_curves_batched_orbit_sweep", "q": q, "g": g, "curves": n,
-                   "levels_nx": nx, "histogram_distinct": L},
+                   "levels_nx": nx, "histogram_distinct": nhist},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

@@ -161,6 +161,20 @@ int hwc_ctx_status(hwc_ctx* ctx, void* stream);
 int hwc_ctx_profile(hwc_ctx* ctx, int enable);
 int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double* hist_ms, uint64_t* calls);
 
+/* Launch and layout options of a context (the autotuner's search space).
+ * Setting one drops the cached plans and graphs. */
+#define HWC_OPT_SPLIT 1         /* 1 (default): split evaluation over m-th roots of unity on LDS byte-unit
+                                   levels; 0: plain Horner at every x */
+#define HWC_OPT_BLOCK 2         /* threads per workgroup of the count kernel: 0 (auto), 256, 512, 1024 */
+#define HWC_OPT_WG_PER_CU 3     /* cap on workgroups per CU of the persistent grid; 0: occupancy limit */
+#define HWC_OPT_DEVICE_TABLES 4 /* 1: every level's Zech table in device memory (L2/MALL) instead of LDS */
+#define HWC_OPT_WAVES_PER_SIMD 5 /* count-kernel build that leaves registers for at least 6 or 8 waves per SIMD
+                                    (0 or 1: no constraint) */
+int hwc_ctx_set_option(hwc_ctx* ctx, int opt, int64_t value);
+/* The same option for the plan of (q, g) and the sweep of `flags` only
+ * (overrides the context default; used to apply autotuned settings). */
+int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags, int opt, int64_t value);
+
 /* Geometry of the counting plan for (q, g) and the sweep of `flags` (built
  * and cached if needed): per level j = 1..g, levels[j-1] receives the order
  * M of F_{q^j}^x, the table form (0: u16 in LDS, byte units; 1: u16 in LDS,

@@ -24,8 +24,9 @@
 namespace hwc {
 hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
-                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s);
-hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
+                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s);
+hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, uint32_t wpe,
+                           int* blocks_per_cu);
 hipError_t prepare_kernels();
 hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,
                            int32_t* outN, hipStream_t s);
@@ -54,6 +55,15 @@ struct FieldEntry {
   hwc::Field F;
 };
 
+// Launch and layout choices for one plan (defaults or an autotuned override).
+struct Tuning {
+  bool split = true;            // split evaluation over mu_m cosets on form A levels
+  uint32_t block = 0;           // threads per workgroup, 0: automatic
+  uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
+  uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
+  bool device_tables = false;   // every level's table in device memory
+};
+
 struct DevPlan {
   uint32_t q = 0, g = 0, orbit = 0;
   std::vector<std::shared_ptr<FieldEntry>> fields;
@@ -66,7 +76,7 @@ struct DevPlan {
   std::vector<uint32_t*> d_tup, d_sgl;  // split-evaluation tuple representatives and singles
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
-  uint32_t block = 256, grid = 0;
+  uint32_t block = 256, grid = 0, wpe = 1;
   double tile_cost = 0;
   uint32_t pins = 0;                 // > 0 while a batch being assembled uses the plan
 };
@@ -122,7 +132,8 @@ struct hwc_ctx {
   bool order_valid = false;
   // profiling: events around the phases of each direct (non-graph) call
   bool profile = false;
-  bool split = true;   // split evaluation over mu_m cosets on form A levels
+  Tuning defaults;
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Tuning> tuned;   // per (q, g, orbit)
   std::vector<std::array<hipEvent_t, 4>> prof;
   std::vector<hipEvent_t> event_pool;
 };
@@ -226,7 +237,7 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
 
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;
 // then move the largest LDS levels to D until the image fits.
-std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g) {
+std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, bool all_device) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
   uint64_t Qj = 1;
@@ -241,6 +252,8 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g) {
     return t;
   };
   for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
+  if (all_device)
+    for (uint32_t j = 0; j < g; ++j) form[j] = hwc::kFormD;
   return form;
 }
 
@@ -261,7 +274,12 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   double Qg = 1;
   for (uint32_t j = 0; j < g; ++j) Qg *= q;
   if (Qg > 16777216.0 || q > 32768) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "F_{q^g} larger than 2^24 elements");
-  const std::vector<uint32_t> form = choose_forms(q, g);
+  Tuning T = c->defaults;
+  {
+    auto tt = c->tuned.find(key);
+    if (tt != c->tuned.end()) T = tt->second;
+  }
+  const std::vector<uint32_t> form = choose_forms(q, g, T.device_tables);
   if (8 * q > kLdsLimit) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "q too large");
   auto P = std::make_unique<DevPlan>();
   P->q = q; P->g = g; P->orbit = orbit;
@@ -375,7 +393,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   for (uint32_t j = 0; j < g; ++j) {
     hwc::LevelDesc& L = D.lv[j];
     L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
-    if (!c->split || L.form != hwc::kFormA) continue;
+    if (!T.split || L.form != hwc::kFormA) continue;
     const uint32_t m = ((q - 1) % 3 == 0) ? 3u : 2u;
     L.msplit = m;
     if (!orbit) {
@@ -400,10 +418,12 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   P->dev_bytes += bytes;
   c->table_bytes += bytes;
   // launch shape: many waves per CU; one large block when the tables fill LDS
-  P->block = D.image_bytes > 80 * 1024 ? 1024 : 256;
+  P->block = T.block ? T.block : (D.image_bytes > 80 * 1024 ? 1024 : 256);
   int bpc = 0;
-  HIPX(c, hwc::occupancy_count(g, 1, P->block, D.image_bytes, &bpc));
+  P->wpe = T.wpe ? T.wpe : 1;
+  HIPX(c, hwc::occupancy_count(g, 1, P->block, D.image_bytes, P->wpe, &bpc));
   if (bpc < 1) bpc = 1;
+  if (T.wg_per_cu && (int)T.wg_per_cu < bpc) bpc = (int)T.wg_per_cu;
   P->grid = (uint32_t)(c->cus * bpc);
   // relative cost of one tile, for ordering mixed batches (longest first)
   P->tile_cost = 0;
@@ -480,11 +500,11 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
     if (flags & HWC_PLAIN) {
       for (uint32_t j = 0; j < g; ++j)
         HIPX(c, hwc::launch_count(P->desc, cb, codes, S.perm, S.tiles, S.ntiles, nullptr, j, j, nullptr, S.lv,
-                                  P->grid, P->block, s));
+                                  P->grid, P->block, P->wpe, s));
       HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
     } else {
       HIPX(c, hwc::launch_count(P->desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N, nullptr,
-                                P->grid, P->block, s));
+                                P->grid, P->block, P->wpe, s));
     }
   }
   if (record) HIPX(c, hipEventRecord(ev[2], s));
@@ -795,6 +815,46 @@ bool squarefree_host(const hwc::Field& F, const int16_t* row, int nc) {
   return da == 0;
 }
 
+int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
+  switch (opt) {
+    case HWC_OPT_SPLIT: T.split = value != 0; break;
+    case HWC_OPT_BLOCK:
+      if (value != 0 && value != 256 && value != 512 && value != 1024)
+        return fail(c, HWC_ERR_ARG, "block must be 0, 256, 512 or 1024");
+      T.block = (uint32_t)value;
+      break;
+    case HWC_OPT_WG_PER_CU:
+      if (value < 0 || value > 64) return fail(c, HWC_ERR_ARG, "workgroups per CU must be in 0..64");
+      T.wg_per_cu = (uint32_t)value;
+      break;
+    case HWC_OPT_DEVICE_TABLES: T.device_tables = value != 0; break;
+    case HWC_OPT_WAVES_PER_SIMD:
+      if (value != 0 && value != 1 && value != 6 && value != 8)
+        return fail(c, HWC_ERR_ARG, "waves per SIMD must be 0, 1, 6 or 8");
+      T.wpe = (uint32_t)value;
+      break;
+    default: return fail(c, HWC_ERR_ARG, "unknown option");
+  }
+  return HWC_OK;
+}
+
+// drop cached plans (all, or the one of key) and every graph
+int drop_plans(hwc_ctx* c, const std::tuple<uint32_t, uint32_t, uint32_t>* key) {
+  if (c->device < 0) return HWC_OK;
+  drop_graphs(c);
+  HIPX(c, hipDeviceSynchronize());
+  for (auto it = c->plans.begin(); it != c->plans.end();) {
+    if (!key || it->first == *key) {
+      c->table_bytes -= it->second->dev_bytes;
+      free_plan(it->second.get());
+      it = c->plans.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return HWC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1040,6 +1100,26 @@ int hwc_ctx_profile_read(hwc_ctx* c, double* prep_ms, double* count_ms, double* 
   if (count_ms) *count_ms = t[1];
   if (hist_ms) *hist_ms = t[2];
   return HWC_OK;
+}
+
+int hwc_ctx_set_option(hwc_ctx* c, int opt, int64_t value) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  int rc = set_tuning_field(c, c->defaults, opt, value);
+  if (rc) return rc;
+  return drop_plans(c, nullptr);
+}
+
+int hwc_ctx_set_plan_option(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, int opt, int64_t value) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  const auto key = std::make_tuple(q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u);
+  auto it = c->tuned.find(key);
+  Tuning T = it != c->tuned.end() ? it->second : c->defaults;
+  int rc = set_tuning_field(c, T, opt, value);
+  if (rc) return rc;
+  c->tuned[key] = T;
+  return drop_plans(c, &key);
 }
 
 int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_desc* levels) {

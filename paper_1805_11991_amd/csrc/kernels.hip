@@ -35,6 +35,14 @@ __device__ __forceinline__ uint32_t lds_u32(const uint8_t* base, uint32_t byte_a
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Uniform reads of data no kernel writes while it runs (x lists, tile words):
+// through the constant address space they become scalar loads instead of
+// vector loads that stall the wave on a full memory round trip.
+typedef const __attribute__((address_space(4))) uint32_t* const_u32_ptr;
+typedef const __attribute__((address_space(4))) uint64_t* const_u64_ptr;
+__device__ __forceinline__ uint32_t sload(const uint32_t* p, uint32_t i) { return ((const_u32_ptr)p)[i]; }
+__device__ __forceinline__ uint64_t sload64(const uint64_t* p, uint32_t i) { return ((const_u64_ptr)p)[i]; }
+
 // ----------------------------------------------------------------------------
 // utility
 
@@ -180,6 +188,17 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint16_t* __restrict
 struct LevelCounts {
   uint32_t z0, z1, o0, o1;  // zeros / odd logs, split by parity of low*L
   uint32_t n1;              // x with odd low*L (uniform)
+  // n points of uniform class cls with z zeros and o odd logs
+  __device__ __forceinline__ void add_n(uint32_t cls, uint32_t n, uint32_t z, uint32_t o) {
+    if (cls) {
+      z1 += z;
+      o1 += o;
+      n1 += n;
+    } else {
+      z0 += z;
+      o0 += o;
+    }
+  }
   __device__ __forceinline__ void add(uint32_t cls, uint32_t z, uint32_t o) {
     z1 += cls ? z : 0u;
     o1 += cls ? o : 0u;
@@ -215,9 +234,16 @@ __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, ui
                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
   const uint32_t S = 6 * M;
   uint32_t ix = 0;
+  uint32_t n0 = 0, n1 = 1;
+  if (xs && nx >= 2) { n0 = sload(xs, 0); n1 = sload(xs, 1); }
   for (; ix + 2 <= nx; ix += 2) {
-    const uint32_t x0 = xs ? xs[ix] : ix;
-    const uint32_t x1 = xs ? xs[ix + 1] : ix + 1;
+    const uint32_t x0 = n0, x1 = n1;
+    if (ix + 4 <= nx) {   // next pair, loaded while this one runs
+      n0 = xs ? sload(xs, ix + 2) : ix + 2;
+      n1 = xs ? sload(xs, ix + 3) : ix + 3;
+    } else if (ix + 3 <= nx) {
+      n0 = xs ? sload(xs, ix + 2) : ix + 2;
+    }
     if (FULL) {
       uint32_t a0 = 0, a1 = 0;
       const uint32_t b0 = 2 * x0, b1 = 2 * x1;
@@ -237,7 +263,7 @@ __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, ui
     }
   }
   if (ix < nx) {
-    const uint32_t x0 = xs ? xs[ix] : ix;
+    const uint32_t x0 = xs ? sload(xs, ix) : ix;
     uint32_t p0;
     const uint32_t a0 = horner_a<NC>(lds, del, M, d, mask, x0, p0);
     c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
@@ -252,10 +278,19 @@ __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t M) {
 // Sub-polynomial r of the split (positions i = r mod MS) by relative Horner in
 // y (log Y).  sup has bit d set.  Returns the relative log (byte units or the
 // zero marker) and in pend the power t_r Y of the class's lowest term.
-template <int NC, int MS, int R>
+template <int NC, int MS, int R, bool FULL, int D>
 __device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint32_t (&sdel)[NC], uint32_t M,
                                                  uint32_t d, uint32_t sup, uint32_t Y, uint32_t& pend) {
-  uint32_t a = 0, p = 0;
+  uint32_t a = 0;
+  if (FULL) {  // every position 0..D holds a term: steps of one power of y
+    const uint32_t b = 2 * Y;
+    constexpr int TOP = D - ((D - R) % MS);
+#pragma unroll
+    for (int i = TOP - MS; i >= 0; i -= MS) a = lds_u16(lds, a + sdel[i] + b);
+    pend = 0;
+    return a;
+  }
+  uint32_t p = 0;
   bool started = false;
 #pragma unroll
   for (int i = NC - 1; i >= 0; --i) {
@@ -279,23 +314,27 @@ __device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint3
 //   B = Z(a_2 - a_1), R = Z(B + a_1 - a_0), log f = R + a_0   (MS = 3),
 // a_r = log(w^(s r) x^r f_r(y)).  A vanishing f_r(y) below the top class has
 // no relative log; the wave then evaluates the tuple's points by plain Horner.
-template <int NC, int MS>
+template <int NC, int MS, bool FULL, int D>
 __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&sdel)[NC],
                                               const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t dl1,
                                               uint32_t dl2, uint32_t fix, LevelCounts& c) {
   const uint32_t M = L.M, S = 6 * M, step = M / MS, tab = L.tab_off;
+  const uint32_t K1 = 2 * M + 2 * dl1, K2 = 2 * M + 2 * dl2;
   const uint32_t sup = mask | (1u << d);
   const uint32_t nt = L.nt;
+  const uint32_t* xt = L.xs_t;
+  uint32_t xnext = (xt && nt) ? sload(xt, 0) : 0u;
   for (uint32_t it = 0; it < nt; ++it) {
-    const uint32_t x = L.xs_t ? L.xs_t[it] : it;
+    const uint32_t x = xnext;
+    if (it + 1 < nt) xnext = xt ? sload(xt, it + 1) : it + 1;
     uint32_t Y = 0;
 #pragma unroll
     for (int m = 0; m < MS; ++m) Y = addmod(Y, x, M);
     uint32_t p0, p1, p2 = 0;
-    const uint32_t a0 = horner_class<NC, MS, 0>(lds, sdel, M, d, sup, Y, p0);
-    const uint32_t a1 = horner_class<NC, MS, 1>(lds, sdel, M, d, sup, Y, p1);
+    const uint32_t a0 = horner_class<NC, MS, 0, FULL, D>(lds, sdel, M, d, sup, Y, p0);
+    const uint32_t a1 = horner_class<NC, MS, 1, FULL, D>(lds, sdel, M, d, sup, Y, p1);
     uint32_t a2 = S;
-    if (MS == 3) a2 = horner_class<NC, MS, 2>(lds, sdel, M, d, sup, Y, p2);
+    if (MS == 3) a2 = horner_class<NC, MS, 2, FULL, D>(lds, sdel, M, d, sup, Y, p2);
     const bool inner_zero = (a0 == S) || (MS == 3 && a1 == S);
     if (__ballot(inner_zero)) {
       for (uint32_t s = 0; s < MS; ++s) {
@@ -306,40 +345,45 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
       }
       continue;
     }
-    const uint32_t cls = p0 & 1u;  // parity of t_0 Y
+    const uint32_t cls = FULL ? 0u : (p0 & 1u);  // parity of t_0 Y
+    // zero values contribute bit 1 of 6M = 0; the lane's parity (a0 + fix) is
+    // applied once per tuple: odd = u if even, else (non-zero points) - u
+    uint32_t u = 0, zs = 0;
     if (MS == 2) {
-      uint32_t F1 = 2 * M - a0 + 2 * dl1;              // (0, 4M)
+      uint32_t F1 = K1 - a0;                          // (0, 4M)
       F1 = min(F1, F1 - 2 * M);
-      const uint32_t u0 = addmod(addmod(x, p1, M), M - p0 == M ? 0u : M - p0, M);
+      const uint32_t v1 = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
 #pragma unroll
       for (uint32_t s = 0; s < 2; ++s) {
-        const uint32_t u = addmod(u0, s * step, M);
-        const uint32_t r = lds_u16(lds, a1 + F1 + (2 * u + tab));
-        c.add(cls, r == S, r == S ? 0u : (((r + a0) >> 1) ^ fix) & 1u);
+        const uint32_t w1 = 2 * addmod(v1, s * step, M) + tab;
+        const uint32_t r = lds_u16(lds, a1 + F1 + w1);
+        u += r & 2u;
+        zs += r == S;
       }
     } else {
-      uint32_t F2 = 2 * M - a1 + 2 * dl2;              // (0, 4M)
+      uint32_t F2 = K2 - a1;                          // (0, 4M)
       F2 = min(F2, F2 - 2 * M);
-      uint32_t F1 = a1 + 2 * M - a0 + 2 * dl1;         // (0, 6M)
+      uint32_t F1 = a1 + K1 - a0;                     // (0, 6M)
       F1 = min(F1, F1 - 2 * M);
       F1 = min(F1, F1 - 2 * M);
       const uint32_t v2 = addmod(addmod(x, p2, M), p1 ? M - p1 : 0u, M);
       const uint32_t v1 = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
 #pragma unroll
       for (uint32_t s = 0; s < 3; ++s) {
-        const uint32_t u2 = addmod(v2, s * step, M), u1 = addmod(v1, s * step, M);
-        const uint32_t b = lds_u16(lds, a2 + F2 + (2 * u2 + tab));
-        const uint32_t r = lds_u16(lds, b + F1 + (2 * u1 + tab));
-        c.add(cls, r == S, r == S ? 0u : (((r + a0) >> 1) ^ fix) & 1u);
+        const uint32_t w2 = 2 * addmod(v2, s * step, M) + tab;
+        const uint32_t w1 = 2 * addmod(v1, s * step, M) + tab;
+        const uint32_t b = lds_u16(lds, a2 + F2 + w2);
+        const uint32_t r = lds_u16(lds, b + F1 + w1);
+        u += r & 2u;
+        zs += r == S;
       }
     }
+    u >>= 1;
+    const uint32_t odd = ((a0 >> 1) ^ fix) & 1u ? (MS - zs) - u : u;
+    c.add_n(cls, MS, zs, odd);
   }
 }
 
-// Forms C and D: element-unit table of 2M entries (u16 in LDS, or u32 in
-// device memory), index folded with one min.  The zero marker M is not
-// absorbing here, so a fast pass flags any lane that met it and the x is
-// recomputed with the exact rule (rare: about d/M per x).
 template <int NC, bool EXACT, bool GLOBAL>
 __device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, const uint32_t* __restrict__ gtab,
                                              uint32_t M, const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
@@ -370,9 +414,9 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* 
   const uint32_t* xs = L.xs;
   const uint32_t* gtab = L.gtab;
   for (uint32_t ix = 0; ix < nx; ix += 2) {
-    const uint32_t x0 = xs ? xs[ix] : ix;
+    const uint32_t x0 = xs ? sload(xs, ix) : ix;
     const bool two = ix + 1 < nx;
-    const uint32_t x1 = two ? (xs ? xs[ix + 1] : ix + 1) : x0;
+    const uint32_t x1 = two ? (xs ? sload(xs, ix + 1) : ix + 1) : x0;
     bool hit = false;
     uint32_t p0, p1;
     uint32_t a0 = horner_c<NC, false, GLOBAL>(lds, tab, gtab, M, del, d, mask, x0, p0, hit);
@@ -458,9 +502,21 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
       const uint32_t fix = (lowlog[0] ^ prev) & 1u;
 #pragma unroll
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
-      if (ms == 3) sweep_split_a<NC, 3>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-      else sweep_split_a<NC, 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-      sweep_form_a<NC, false, 0>(L.xs_s, L.ns, M, lds, del, d, mask, c);
+      if (full) {
+        if (top) {
+          if (ms == 3) sweep_split_a<NC, 3, true, NC - 1>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+          else sweep_split_a<NC, 2, true, NC - 1>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+          sweep_form_a<NC, true, NC - 1>(L.xs_s, L.ns, M, lds, del, d, mask, c);
+        } else {
+          if (ms == 3) sweep_split_a<NC, 3, true, NC - 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+          else sweep_split_a<NC, 2, true, NC - 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+          sweep_form_a<NC, true, NC - 2>(L.xs_s, L.ns, M, lds, del, d, mask, c);
+        }
+      } else {
+        if (ms == 3) sweep_split_a<NC, 3, false, 0>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+        else sweep_split_a<NC, 2, false, 0>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
+        sweep_form_a<NC, false, 0>(L.xs_s, L.ns, M, lds, del, d, mask, c);
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
@@ -523,8 +579,10 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, const uint8_t* l
   const uint32_t pat = uniform((uint32_t)(w & 0xFFFFu));
   const uint32_t cnt = uniform((uint32_t)((w >> 16) & 0xFFFFu) + 1u);
   const uint32_t start = uniform((uint32_t)(w >> 32));
-  if (lane >= cnt) return;
-  const uint32_t curve = perm[start + lane];
+  // every lane runs the tile so that pattern branches stay uniform; lanes past
+  // the tile's end shadow its last curve and skip the stores
+  const bool live = lane < cnt;
+  const uint32_t curve = perm[start + (live ? lane : cnt - 1)];
   uint32_t code[NC];
   const CT* row = codes + (uint64_t)curve * NC;
 #pragma unroll
@@ -546,17 +604,20 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, const uint8_t* l
     const uint32_t logt = lds_u32(lds, P.lv[0].emb_off + 4 * code[NC - 1]);
     int32_t n[G];
     assemble<G>(P, lv, code[0], code[NC - 1], log0, logt, n);
+    if (live) {
 #pragma unroll
-    for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
-  } else {
+      for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
+    }
+  } else if (live) {
 #pragma unroll
     for (int j = 0; j < G; ++j)
       if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[(uint64_t)curve * G + j] = lv[j];
   }
 }
 
-template <int G, typename CT>
-__global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __restrict__ codes,
+// WPE: minimum waves per SIMD the register allocation must allow (1: free)
+template <int G, typename CT, int WPE>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) void count_kernel(PlanDesc P, const CT* __restrict__ codes,
                                                      const uint32_t* __restrict__ perm,
                                                      const uint64_t* __restrict__ tiles,
                                                      const uint32_t* __restrict__ ntiles_p, uint32_t* queue,
@@ -575,16 +636,16 @@ __global__ __launch_bounds__(1024) void count_kernel(PlanDesc P, const CT* __res
     if (lane == 0) v = atomicAdd(queue, 1u);
     t = uniform(v);
   } else {
-    t = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    t = uniform((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   }
   while (t < ntiles) {
-    process_tile<G, CT>(P, lds, codes, perm, tiles[t], lvl_lo, lvl_hi, outN, outLv);
+    process_tile<G, CT>(P, lds, codes, perm, sload64(tiles, t), lvl_lo, lvl_hi, outN, outLv);
     if (queue) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(queue, 1u);
       t = uniform(v);
     } else {
-      t += nwaves;
+      t = uniform(t + nwaves);
     }
   }
 }
@@ -639,7 +700,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__
       __syncthreads();
       staged = P;
     }
-    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lds, J.tiles[t]);
+    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lds, sload64(J.tiles, t));
     __syncthreads();
   }
 }
@@ -719,22 +780,26 @@ __global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __r
 // ----------------------------------------------------------------------------
 // host-callable launchers (C++ linkage, used by capi.cpp)
 
-template <int G, typename CT>
+template <int G, typename CT, int WPE>
 static hipError_t launch_count_t(const PlanDesc& P, const void* codes, const uint32_t* perm, const uint64_t* tiles,
                                  const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi, int32_t* outN,
                                  uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s) {
-  hipLaunchKernelGGL((count_kernel<G, CT>), dim3(grid), dim3(block), P.image_bytes, s, P,
+  hipLaunchKernelGGL((count_kernel<G, CT, WPE>), dim3(grid), dim3(block), P.image_bytes, s, P,
                      static_cast<const CT*>(codes), perm, tiles, ntiles, queue, lo, hi, outN, outLv);
   return hipGetLastError();
 }
 
 template <int G, typename CT>
 static hipError_t allow_big_lds() {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&count_kernel<G, CT>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageLimit);
+  hipError_t e = hipSuccess;
+  for (const void* f : {reinterpret_cast<const void*>(&count_kernel<G, CT, 1>),
+                        reinterpret_cast<const void*>(&count_kernel<G, CT, 6>),
+                        reinterpret_cast<const void*>(&count_kernel<G, CT, 8>)})
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageLimit);
+  return e;
 }
 
-// Lets every count kernel use the whole 160 KiB of LDS (done once, outside
+// Lets every count kernel use the whole LDS image budget (done once, outside
 // any graph capture).
 hipError_t prepare_kernels() {
   hipError_t e = hipSuccess;
@@ -749,16 +814,24 @@ hipError_t prepare_kernels() {
   return e;
 }
 
+template <int G, typename CT>
+static hipError_t launch_count_w(const PlanDesc& P, const void* codes, const uint32_t* perm, const uint64_t* tiles,
+                                 const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi, int32_t* outN,
+                                 uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s) {
+  if (wpe >= 8) return launch_count_t<G, CT, 8>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+  if (wpe >= 6) return launch_count_t<G, CT, 6>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+  return launch_count_t<G, CT, 1>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+}
+
 hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
-                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s) {
-#define HWC_CASE(GG)                                                                                          \
-  case GG:                                                                                                    \
-    return coeff_bytes == 1                                                                                   \
-               ? launch_count_t<GG, int8_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, \
-                                            block, s)                                                         \
-               : launch_count_t<GG, int16_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, \
-                                             block, s);
+                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s) {
+#define HWC_CASE(GG)                                                                                           \
+  case GG:                                                                                                     \
+    return coeff_bytes == 1 ? launch_count_w<GG, int8_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN,  \
+                                                         outLv, grid, block, wpe, s)                          \
+                            : launch_count_w<GG, int16_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, \
+                                                          outLv, grid, block, wpe, s);
   switch (P.g) {
     HWC_CASE(1)
     HWC_CASE(2)
@@ -790,16 +863,27 @@ hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_c
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, block, lds_bytes);
 }
 
-hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
-#define HWC_OCC(GG, CT) \
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, count_kernel<GG, CT>, block, lds_bytes);
-  if (coeff_bytes == 1) {
-    switch (g) { case 1: HWC_OCC(1, int8_t) case 2: HWC_OCC(2, int8_t) case 3: HWC_OCC(3, int8_t) case 4: HWC_OCC(4, int8_t) }
-  } else {
-    switch (g) { case 1: HWC_OCC(1, int16_t) case 2: HWC_OCC(2, int16_t) case 3: HWC_OCC(3, int16_t) case 4: HWC_OCC(4, int16_t) }
+template <typename CT, int WPE>
+static hipError_t occ(uint32_t g, uint32_t block, uint32_t lds, int* bpc) {
+  switch (g) {
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, count_kernel<1, CT, WPE>, block, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, count_kernel<2, CT, WPE>, block, lds);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, count_kernel<3, CT, WPE>, block, lds);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(bpc, count_kernel<4, CT, WPE>, block, lds);
+    default: return hipErrorInvalidValue;
   }
-#undef HWC_OCC
-  return hipErrorInvalidValue;
+}
+
+hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, uint32_t wpe,
+                           int* blocks_per_cu) {
+  if (coeff_bytes == 1) {
+    if (wpe >= 8) return occ<int8_t, 8>(g, block, lds_bytes, blocks_per_cu);
+    if (wpe >= 6) return occ<int8_t, 6>(g, block, lds_bytes, blocks_per_cu);
+    return occ<int8_t, 1>(g, block, lds_bytes, blocks_per_cu);
+  }
+  if (wpe >= 8) return occ<int16_t, 8>(g, block, lds_bytes, blocks_per_cu);
+  if (wpe >= 6) return occ<int16_t, 6>(g, block, lds_bytes, blocks_per_cu);
+  return occ<int16_t, 1>(g, block, lds_bytes, blocks_per_cu);
 }
 
 hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,

@@ -33,11 +33,17 @@ HWC_PLAIN = 2
 HWC_VALIDATE = 4
 HWC_NO_GRAPH = 8
 
+HWC_OPT_SPLIT = 1
+HWC_OPT_BLOCK = 2
+HWC_OPT_WG_PER_CU = 3
+HWC_OPT_DEVICE_TABLES = 4
+HWC_OPT_WAVES_PER_SIMD = 5
+
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
            "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
-           "hwc_plan_info")
+           "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
 
 
 class HwcError(RuntimeError):
@@ -96,6 +102,8 @@ def load():
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
                                 ctypes.POINTER(u64)]),
         "hwc_ctx_profile": (i32, [vp, i32]),
+        "hwc_ctx_set_option": (i32, [vp, i32, ctypes.c_int64]),
+        "hwc_ctx_set_plan_option": (i32, [vp, u32, u32, u32, i32, ctypes.c_int64]),
         "hwc_plan_info": (i32, [vp, u32, u32, u32, ctypes.POINTER(hwc_level_desc)]),
         "hwc_ctx_profile_read": (i32, [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]),
@@ -149,7 +157,9 @@ class Field:
 class Context:
     """hwc_ctx: device -1 gives a host-only context (fields only)."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, autotune_db: str | None = "default"):
+        """autotune_db: path of a tuning database, "default" for the one of
+        this architecture shipped with the package (if present), or None."""
         lib = load()
         h = ctypes.c_void_p()
         rc = lib.hwc_ctx_create(device, hbm_budget_bytes, ctypes.byref(h))
@@ -157,6 +167,11 @@ class Context:
             raise HwcError(rc, "hwc_ctx_create failed: " + (lib.hwc_last_error(None) or b"").decode())
         self._h = h
         self.device = device
+        self.tuned_entries = 0
+        if device >= 0 and autotune_db is not None:
+            from . import autotune
+            db = autotune.load_db(None if autotune_db == "default" else autotune_db)
+            self.tuned_entries = autotune.apply_db(self, db)
 
     def _check(self, rc: int):
         if rc != HWC_OK:
@@ -244,6 +259,12 @@ class Context:
         n = ctypes.c_uint64()
         self._check(load().hwc_ctx_profile_read(self._h, *(ctypes.byref(x) for x in t), ctypes.byref(n)))
         return {"prep_ms": t[0].value, "count_ms": t[1].value, "hist_ms": t[2].value, "calls": n.value}
+
+    def set_option(self, opt: int, value: int):
+        self._check(load().hwc_ctx_set_option(self._h, opt, value))
+
+    def set_plan_option(self, q: int, g: int, opt: int, value: int, flags: int = 0):
+        self._check(load().hwc_ctx_set_plan_option(self._h, q, g, flags, opt, value))
 
     def plan_info(self, q: int, g: int, flags: int = 0) -> list[dict]:
         arr = (hwc_level_desc * g)()

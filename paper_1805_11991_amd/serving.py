@@ -1,0 +1,362 @@
+"""Serving loop: continuous batching of curve-count requests of mixed (q, g).
+
+Requests arrive over time.  Pending requests are admitted into the next batch
+while the batch has room (a curve budget); a request larger than the budget is
+split into chunks that ride in successive batches.  Each batch is one call of
+the library's multi-plan persistent launch (``hwc_count_batch``), enqueued on
+one of several streams, so uploads and downloads of one batch overlap the
+counting of another.  Field tables stay resident in the context's device cache,
+which admits plans against an HBM budget (least recently used plans are
+evicted).  A finished batch is detected by an event; results are scattered
+back to their requests and a request completes when its last chunk does.
+
+A request that cannot be served (bad q or g, bad coefficients, a field too
+large, tables over the HBM budget) fails on its own; the loop keeps serving
+the others.  Per-request latency is completion minus arrival time.
+
+The executor is an interface: ``GpuExecutor`` runs batches on the GPU through
+the C ABI; tests drive the same loop with a fake executor on the CPU.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+import time
+from collections import deque
+
+import numpy as np
+
+
+def odd_prime_power(q: int) -> bool:
+    if q < 3 or q % 2 == 0:
+        return False
+    p = next((d for d in range(3, int(math.isqrt(q)) + 1, 2) if q % d == 0), q)
+    while q % p == 0:
+        q //= p
+    return q == 1
+
+
+MAX_FIELD = 1 << 24
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    q: int
+    g: int
+    codes: np.ndarray                  # [n, 2g+3] int8/int16, constant term first
+    arrival: float = 0.0
+    want_hist: bool = True
+    # filled by the server
+    N: np.ndarray | None = None
+    hist: tuple[np.ndarray, np.ndarray] | None = None
+    error: str | None = None
+    done_at: float | None = None
+    chunks_left: int = 0
+    _parts: list = dataclasses.field(default_factory=list)
+
+    @property
+    def n(self) -> int:
+        return int(self.codes.shape[0])
+
+    @property
+    def latency(self) -> float | None:
+        return None if self.done_at is None else self.done_at - self.arrival
+
+
+@dataclasses.dataclass
+class Chunk:
+    req: Request
+    lo: int
+    hi: int
+
+
+def validate(req: Request) -> str | None:
+    """Host-side checks, so a bad request never reaches a batch."""
+    if not odd_prime_power(req.q):
+        return f"q={req.q} is not an odd prime power"
+    if not 1 <= req.g <= 4:
+        return f"g={req.g} outside 1..4"
+    if req.q ** req.g > MAX_FIELD:
+        return f"F_{{q^g}} larger than {MAX_FIELD} elements"
+    c = req.codes
+    if c.ndim != 2 or c.shape[1] != 2 * req.g + 3:
+        return f"coefficients must be [n, {2 * req.g + 3}]"
+    if c.dtype == np.int8 and req.q > 127:
+        return "int8 codes need q <= 127"
+    if c.size and (int(c.min()) < 0 or int(c.max()) >= req.q):
+        return "coefficient code out of range"
+    if c.size and np.any((c[:, -1] == 0) & (c[:, -2] == 0)):
+        return "degree below 2g+1"
+    return None
+
+
+def merge_hist(parts: list[tuple[np.ndarray, np.ndarray]], g: int):
+    """Merge sorted (tuples, counts) histograms of the chunks of one request."""
+    parts = [p for p in parts if len(p[0])]
+    if not parts:
+        return np.zeros((0, g), np.int32), np.zeros(0, np.uint64)
+    if len(parts) == 1:
+        return parts[0]
+    keys = np.concatenate([p[0] for p in parts])
+    counts = np.concatenate([p[1] for p in parts])
+    uniq, inv = np.unique(keys, axis=0, return_inverse=True)
+    tot = np.zeros(len(uniq), np.uint64)
+    np.add.at(tot, inv.reshape(-1), counts)
+    return uniq.astype(np.int32), tot
+
+
+class Server:
+    def __init__(self, executor, batch_curves: int = 1 << 22, max_inflight: int = 2, clock=time.perf_counter):
+        self.ex = executor
+        self.batch_curves = batch_curves
+        self.max_inflight = max_inflight
+        self.clock = clock
+        self.pending: deque[Chunk] = deque()
+        self.inflight: deque = deque()      # (handle, [chunks])
+        self.completed: list[Request] = []
+        self.curves_done = 0
+        self.batches = 0
+
+    # -- intake
+    def submit(self, req: Request):
+        err = validate(req)
+        if err:
+            self._finish(req, error=err)
+            return
+        n = req.n
+        if n == 0:
+            req.N = np.zeros((0, req.g), np.int32)
+            req.hist = (np.zeros((0, req.g), np.int32), np.zeros(0, np.uint64))
+            self._finish(req)
+            return
+        req.chunks_left = math.ceil(n / self.batch_curves)
+        for lo in range(0, n, self.batch_curves):
+            self.pending.append(Chunk(req, lo, min(n, lo + self.batch_curves)))
+
+    # -- the loop
+    def step(self) -> int:
+        """Collects finished batches and launches new ones; returns the number
+        of requests completed in this step."""
+        done_before = len(self.completed)
+        while self.inflight and self.ex.poll(self.inflight[0][0]):
+            handle, chunks = self.inflight.popleft()
+            self._collect(handle, chunks)
+        while self.pending and len(self.inflight) < self.max_inflight:
+            batch, room = [], self.batch_curves
+            while self.pending and self.pending[0].hi - self.pending[0].lo <= room:
+                ch = self.pending.popleft()
+                if ch.req.error:          # an earlier chunk of the request failed
+                    continue
+                batch.append(ch)
+                room -= ch.hi - ch.lo
+            if not batch:
+                break
+            self._launch(batch)
+        return len(self.completed) - done_before
+
+    def drain(self):
+        while self.pending or self.inflight:
+            if not self.step():
+                self.ex.wait_any([h for h, _ in self.inflight])
+
+    # -- internals
+    def _launch(self, batch: list[Chunk]):
+        try:
+            handle = self.ex.submit([(c.req.q, c.req.g, c.req.codes[c.lo:c.hi], c.req.want_hist) for c in batch])
+            self.inflight.append((handle, batch))
+            self.batches += 1
+        except Exception:
+            # isolate the failing request(s): run each chunk on its own
+            for c in batch:
+                try:
+                    handle = self.ex.submit([(c.req.q, c.req.g, c.req.codes[c.lo:c.hi], c.req.want_hist)])
+                    self.inflight.append((handle, [c]))
+                    self.batches += 1
+                except Exception as e:
+                    self._fail_chunk(c, str(e))
+
+    def _collect(self, handle, chunks: list[Chunk]):
+        try:
+            results = self.ex.collect(handle)
+        except Exception as e:
+            for c in chunks:
+                self._fail_chunk(c, str(e))
+            return
+        for c, (N, hist) in zip(chunks, results):
+            req = c.req
+            if req.error:
+                continue
+            req._parts.append((c.lo, N, hist))
+            self.curves_done += c.hi - c.lo
+            req.chunks_left -= 1
+            if req.chunks_left == 0:
+                req._parts.sort(key=lambda t: t[0])
+                req.N = np.concatenate([p[1] for p in req._parts]) if len(req._parts) > 1 else req._parts[0][1]
+                if req.want_hist:
+                    req.hist = merge_hist([p[2] for p in req._parts], req.g)
+                req._parts = []
+                self._finish(req)
+
+    def _fail_chunk(self, c: Chunk, msg: str):
+        if not c.req.error:
+            self._finish(c.req, error=msg)
+
+    def _finish(self, req: Request, error: str | None = None):
+        req.error = error
+        req.done_at = self.clock()
+        self.completed.append(req)
+
+
+class GpuExecutor:
+    """Runs batches with hwc_count_batch on round-robin streams."""
+
+    def __init__(self, ctx, streams: int = 2):
+        import torch
+        self.torch = torch
+        self.ctx = ctx
+        self.streams = [torch.cuda.Stream() for _ in range(streams)]
+        self.k = 0
+
+    def submit(self, jobs):
+        torch = self.torch
+        s = self.streams[self.k % len(self.streams)]
+        self.k += 1
+        bufs = []
+        with torch.cuda.stream(s):
+            for q, g, codes, want_hist in jobs:
+                n = codes.shape[0]
+                d = torch.from_numpy(np.ascontiguousarray(codes)).pin_memory().to("cuda", non_blocking=True)
+                b = {"q": q, "g": g, "d_coeffs": d,
+                     "d_out_N": torch.empty((n, g), dtype=torch.int32, device="cuda")}
+                if want_hist:
+                    b["d_hist_keys"] = torch.empty((max(n, 1), g), dtype=torch.int32, device="cuda")
+                    b["d_hist_counts"] = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+                    b["d_hist_len"] = torch.zeros(1, dtype=torch.int64, device="cuda")
+                bufs.append(b)
+        self.ctx.count_batch(bufs, stream=s)
+        with torch.cuda.stream(s):
+            outs = []
+            for b in bufs:
+                o = {"N": b["d_out_N"].to("cpu", non_blocking=True)}
+                if "d_hist_len" in b:
+                    o["len"] = b["d_hist_len"].to("cpu", non_blocking=True)
+                outs.append(o)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return {"event": ev, "bufs": bufs, "outs": outs, "stream": s}
+
+    def poll(self, h) -> bool:
+        return h["event"].query()
+
+    def wait_any(self, handles):
+        if handles:
+            handles[0]["event"].synchronize()
+
+    def collect(self, h):
+        h["event"].synchronize()
+        self.ctx.status(h["stream"])
+        res = []
+        for b, o in zip(h["bufs"], h["outs"]):
+            N = o["N"].numpy()
+            hist = None
+            if "len" in o:
+                L = int(o["len"].item())
+                hist = (b["d_hist_keys"][:L].cpu().numpy(), b["d_hist_counts"][:L].cpu().numpy().astype(np.uint64))
+            res.append((N, hist))
+        return res
+
+
+def poisson_requests(rate: float, count: int, seed: int, max_log2: int = 20):
+    """Request shapes of the serving workload: arrival gaps exponential with
+    the given rate; n = floor(2^(max_log2 * U)); g uniform in {2, 3, 4}; q
+    uniform over the odd prime powers below 300, 50 and 15 for g = 2, 3, 4."""
+    rng = np.random.default_rng(seed)
+    qs = {2: [q for q in range(3, 300) if odd_prime_power(q)],
+          3: [q for q in range(3, 50) if odd_prime_power(q)],
+          4: [q for q in range(3, 15) if odd_prime_power(q)]}
+    t = 0.0
+    out = []
+    for i in range(count):
+        t += rng.exponential(1.0 / rate)
+        g = int(rng.integers(2, 5))
+        q = int(qs[g][rng.integers(0, len(qs[g]))])
+        n = int(2 ** (max_log2 * rng.random()))
+        out.append((t, q, g, n, int(rng.integers(0, 2 ** 31))))
+    return out
+
+
+def percentile(vals, p):
+    if not vals:
+        return None
+    return float(np.percentile(np.asarray(vals), p))
+
+
+def serve_bench(ctx, rates=(0.25, 0.5, 0.75, 0.9), requests: int = 120, seed: int = 180511995,
+                batch_curves: int = 1 << 22, max_log2: int = 20, log=print) -> dict:
+    """Capacity with every request queued at t = 0, then Poisson arrivals at
+    fractions of that capacity; curves/s and p50/p99 latency per rate."""
+    from . import curvegen
+    ex = GpuExecutor(ctx)
+
+    def make(shapes):
+        reqs = []
+        for i, (t, q, g, n, s) in enumerate(shapes):
+            reqs.append(Request(i, q, g, curvegen.sample(q, g, n, seed=s), arrival=t))
+        return reqs
+
+    shapes = poisson_requests(1.0, requests, seed, max_log2)
+    # warm the table cache and the kernels, then measure capacity
+    warm = Server(ex, batch_curves)
+    for r in make(shapes[:8]):
+        warm.submit(r)
+    warm.drain()
+    reqs = make(shapes)
+    srv = Server(ex, batch_curves)
+    t0 = time.perf_counter()
+    for r in reqs:
+        r.arrival = t0
+        srv.submit(r)
+    srv.drain()
+    wall = time.perf_counter() - t0
+    cap_req = len(reqs) / wall
+    cap_curves = sum(r.n for r in reqs) / wall
+    fails = sum(1 for r in reqs if r.error)
+    log(f"capacity: {cap_req:.1f} req/s, {cap_curves:.4g} curves/s ({fails} failed)")
+    out = {"capacity_req_per_s": round(cap_req, 2), "capacity_curves_per_s": round(cap_curves, 1),
+           "requests": len(reqs), "rates": []}
+    for f in rates:
+        lam = f * cap_req
+        shp = poisson_requests(lam, requests, seed + int(100 * f), max_log2)
+        reqs = make(shp)
+        srv = Server(ex, batch_curves)
+        t0 = time.perf_counter()
+        i = 0
+        while i < len(reqs) or srv.pending or srv.inflight:
+            now = time.perf_counter() - t0
+            while i < len(reqs) and reqs[i].arrival <= now:
+                reqs[i].arrival += t0
+                srv.submit(reqs[i])
+                i += 1
+            if not srv.step():
+                if srv.inflight:
+                    ex.poll(srv.inflight[0][0])
+                time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        lat = [r.latency for r in reqs if r.error is None]
+        row = {"load": f, "arrival_req_per_s": round(lam, 2), "curves_per_s": round(sum(r.n for r in reqs) / wall, 1),
+               "p50_ms": round(1e3 * percentile(lat, 50), 3), "p99_ms": round(1e3 * percentile(lat, 99), 3),
+               "batches": srv.batches, "failed": sum(1 for r in reqs if r.error)}
+        log(f"load {f}: {row}")
+        out["rates"].append(row)
+    out["cache"] = ctx.stats()
+    return out
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from paper_1805_11991_amd import hwcount
+    print(json.dumps(serve_bench(hwcount.Context(device=0))))
