@@ -85,6 +85,15 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1805_11991_amd.build`")
+    # PyTorch ships its own HIP runtime, which its libraries find by a name that
+    # differs from the library's dependency.  Loading torch first lets the
+    # library bind to that same runtime (one runtime per process, so device
+    # pointers and streams are shared); loading the library first would put a
+    # second runtime into the process and leave torch without devices.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
     sig = {

@@ -129,3 +129,16 @@ def test_field_too_large(hctx):
     with pytest.raises(hwcount.HwcError) as ei:
         hctx.build_field(3001, 1, 3)
     assert ei.value.code == hwcount.HWC_ERR_FIELD_TOO_LARGE
+
+
+def test_single_hip_runtime_in_process():
+    """The library binds to the HIP runtime torch already loaded: one
+    libamdhip64 mapping in the process, whichever is imported first."""
+    import subprocess
+    import sys
+    code = ("from paper_1805_11991_amd import hwcount; hwcount.load(); import torch; "
+            "maps = open('/proc/self/maps').read().split('\\n'); "
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"
