@@ -30,6 +30,9 @@ LDS_BANKS_PER_CU = 32          # u16 gathers served per clock per CU without con
 NUM_CU = 256
 CLOCK_HZ = 2.4e9
 LDS_PEAK_LOOKUPS = LDS_BANKS_PER_CU * NUM_CU * CLOCK_HZ
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "count_kernel_g3_q13_2p24_hbm_traffic.md")
+KERNEL_SOURCES = ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
+                  "paper_1805_11991_amd/autotune/gfx950.json")
 
 
 def log(msg: str):
@@ -64,6 +67,49 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
     return total, plain
 
 
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        path = os.path.join(ROOT, rel)
+        if os.path.exists(path):
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic() -> dict | None:
+    """HBM bytes per launch of the count kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
+    reading for a copy of known size); None when the kernel sources have
+    changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_SUMMARY):
+        return None
+    vals = {}
+    with open(TRAFFIC_SUMMARY) as fh:
+        for line in fh:
+            if line.startswith("- ") and ":" in line:
+                k, v = line[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        return {"fetch": int(vals["fetch_bytes_per_launch"]), "write": int(vals["write_bytes_per_launch"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def calibration_copy(torch, dev, nbytes: int = 1 << 30, reps: int = 3):
+    """A plain copy kernel of known size (nbytes read, nbytes written) whose
+    FETCH_SIZE / WRITE_SIZE readings scale the count kernel's."""
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    log(f"calibration copy: {reps} x {nbytes} bytes read and written")
+
+
 def time_loop(fn, steps: int, warmup: int, sync) -> float:
     for _ in range(warmup):
         fn()
@@ -82,6 +128,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB copy kernel (scale for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the counter has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -139,13 +187,16 @@ def main():
     nx = [L["nx"] for L in levels]
     lookups, plain_lookups = lookups_per_batch(curves, levels)
     achieved = lookups / (count_ms * 1e-3)
+    traffic = measured_traffic()
     roofline = {
         "bound": "lds",
         "achieved": round(achieved / 1e9, 2),
         "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
         "unit": "Glookup/s",
         "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
-        "traffic": None,
+        "traffic": None if traffic is None else traffic["fetch"] + traffic["write"],
+        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+        "traffic_detail": traffic,
         "kernel": "count_kernel<3,int8>",
         "kernel_ms": round(count_ms, 4),
         "lookups_per_launch": lookups,
@@ -195,6 +246,9 @@ def main():
         extra["g4_q13"] = g4
         del bufs4
         torch.cuda.empty_cache()
+
+    if args.calib_copy:
+        calibration_copy(torch, dev)
 
     cpu = None
     if not args.no_cpu:

@@ -167,7 +167,8 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
                                    levels; 0: plain Horner at every x */
 #define HWC_OPT_BLOCK 2         /* threads per workgroup of the count kernel: 0 (auto), 256, 512, 1024 */
 #define HWC_OPT_WG_PER_CU 3     /* cap on workgroups per CU of the persistent grid; 0: occupancy limit */
-#define HWC_OPT_DEVICE_TABLES 4 /* 1: every level's Zech table in device memory (L2/MALL) instead of LDS */
+#define HWC_OPT_DEVICE_TABLES 4 /* bit mask over levels: bit j-1 set puts level j's Zech table in device
+                                    memory (served by L2/MALL) instead of LDS; 0..15 */
 #define HWC_OPT_WAVES_PER_SIMD 5 /* count-kernel build that leaves registers for at least 6 or 8 waves per SIMD
                                     (0 or 1: no constraint) */
 int hwc_ctx_set_option(hwc_ctx* ctx, int opt, int64_t value);

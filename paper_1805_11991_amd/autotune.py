@@ -13,7 +13,8 @@ Search space (library options, see include/hwcount.h):
   split           split evaluation over m-th roots of unity on LDS levels (on/off)
   block           threads per workgroup of the count kernel (256, 512, 1024)
   waves_per_simd  register budget of the kernel build (1: free, 6, 8)
-  device_tables   every level's Zech table in device memory instead of LDS (off/on)
+  device_tables   which levels' Zech tables sit in device memory instead of LDS
+                  (none, the top level, all)
 """
 from __future__ import annotations
 
@@ -31,8 +32,12 @@ SPACE = {
     "split": [1, 0],
     "block": [256, 512, 1024],
     "waves_per_simd": [1, 6, 8],
-    "device_tables": [0, 1],
+    "device_tables": ["none", "top", "all"],
 }
+
+
+def _device_mask(choice, g: int) -> int:
+    return {"none": 0, "top": 1 << (g - 1), "all": (1 << g) - 1}[choice] if isinstance(choice, str) else int(choice)
 
 
 def _opt_ids():
@@ -67,6 +72,8 @@ def apply_db(ctx, db: dict) -> int:
         q, g, sweep = key.split(",")
         flags = hw.HWC_FULL_SWEEP if sweep == "full" else 0
         for name, val in ent["options"].items():
+            if name == "device_tables":
+                val = _device_mask(val, int(g))
             ctx.set_plan_option(int(q), int(g), ids[name], int(val), flags)
         n += 1
     return n
@@ -93,7 +100,7 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
         cand = dict(zip(names, values))
         try:
             for k, v in cand.items():
-                ctx.set_plan_option(q, g, ids[k], v, flags)
+                ctx.set_plan_option(q, g, ids[k], _device_mask(v, g) if k == "device_tables" else v, flags)
             ctx.count_curves_dev(q, g, d, N, flags=flags | hw.HWC_NO_GRAPH)   # warm-up, builds the plan
             ctx.status()
             ctx.profile(True)
@@ -118,7 +125,7 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
         raise RuntimeError(f"no candidate ran for q={q} g={g}")
     best = min(table, key=lambda r: r["count_ms"])
     for k, v in best["options"].items():
-        ctx.set_plan_option(q, g, ids[k], v, flags)
+        ctx.set_plan_option(q, g, ids[k], _device_mask(v, g) if k == "device_tables" else v, flags)
     return {"options": best["options"], "count_ms": best["count_ms"], "sample": n, "table": table}
 
 

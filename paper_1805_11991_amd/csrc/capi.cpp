@@ -61,7 +61,7 @@ struct Tuning {
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
-  bool device_tables = false;   // every level's table in device memory
+  uint32_t device_tables = 0;   // bit j-1: level j's table in device memory
 };
 
 struct DevPlan {
@@ -237,7 +237,7 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
 
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;
 // then move the largest LDS levels to D until the image fits.
-std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, bool all_device) {
+std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
   uint64_t Qj = 1;
@@ -251,9 +251,9 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, bool all_device) {
     for (uint32_t j = 0; j < g; ++j) t += lds_table_bytes(form[j], M[j]) + align16(4 * q);
     return t;
   };
+  for (uint32_t j = 0; j < g; ++j)
+    if ((device_mask >> j) & 1u) form[j] = hwc::kFormD;
   for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
-  if (all_device)
-    for (uint32_t j = 0; j < g; ++j) form[j] = hwc::kFormD;
   return form;
 }
 
@@ -827,7 +827,10 @@ int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
       if (value < 0 || value > 64) return fail(c, HWC_ERR_ARG, "workgroups per CU must be in 0..64");
       T.wg_per_cu = (uint32_t)value;
       break;
-    case HWC_OPT_DEVICE_TABLES: T.device_tables = value != 0; break;
+    case HWC_OPT_DEVICE_TABLES:
+      if (value < 0 || value > 15) return fail(c, HWC_ERR_ARG, "device table mask must be in 0..15");
+      T.device_tables = (uint32_t)value;
+      break;
     case HWC_OPT_WAVES_PER_SIMD:
       if (value != 0 && value != 1 && value != 6 && value != 8)
         return fail(c, HWC_ERR_ARG, "waves per SIMD must be 0, 1, 6 or 8");

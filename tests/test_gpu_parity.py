@@ -315,3 +315,31 @@ def test_two_streams_are_ordered(gctx, oracle_mod, curvegen_mod):
     gctx.status()
     assert np.array_equal(Na.cpu().numpy(), ra)
     assert np.array_equal(Nb.cpu().numpy(), rb)
+
+
+OPTION_SETS = [
+    {"split": 0},
+    {"device_tables": 1},          # lowest level only in device memory
+    {"device_tables": 15},         # every level
+    {"block": 1024, "waves_per_simd": 8},
+    {"block": 512, "waves_per_simd": 6, "split": 0},
+]
+
+
+@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000)])
+@pytest.mark.parametrize("opts", range(len(OPTION_SETS)))
+def test_tuning_options_keep_results(gctx, oracle_mod, curvegen_mod, q, g, n, opts):
+    """Every tunable (split, device-memory placement of any level's table,
+    block size, register budget) gives the oracle's counts."""
+    from paper_1805_11991_amd import hwcount as hw
+    ids = {"split": hw.HWC_OPT_SPLIT, "block": hw.HWC_OPT_BLOCK, "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD,
+           "device_tables": hw.HWC_OPT_DEVICE_TABLES}
+    ctx = hw.Context(device=0, autotune_db=None)
+    try:
+        for k, v in OPTION_SETS[opts].items():
+            ctx.set_plan_option(q, g, ids[k], v)
+            ctx.set_plan_option(q, g, ids[k], v, hw.HWC_FULL_SWEEP)
+        curves = curvegen_mod.sample(q, g, n, seed=900 + opts)
+        _check(ctx, oracle_mod, q, g, curves, modes={"batched-orbit": 0, "batched-full": 1, "plain-orbit": 2})
+    finally:
+        ctx.close()
