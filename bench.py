@@ -45,9 +45,11 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
 
     Plain Horner: one read per nonzero term below the leading one, for every
     swept x.  Split evaluation (levels with msplit = m): a tuple of m points
-    costs sum_r (terms of class r - 1) reads for the sub-polynomials plus
-    m (m - 1) for the combinations, when every class holds a term; other rows
-    and the single points cost plain Horner."""
+    costs sum_r (terms of class r - 1) reads for the sub-polynomials plus the
+    combinations, m (m - 1) for m = 2, 3 (chained) and 8 for m = 4 (two
+    radix-2 stages), when every class holds a term; other rows and the single
+    points cost plain Horner.  Recomputations on vanishing bases are not
+    counted."""
     import numpy as np
     sup = curves.astype(np.int64) != 0
     terms = sup.sum(axis=1)
@@ -61,7 +63,7 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
             continue
         cls = [sup[:, r::m].sum(axis=1) for r in range(m)]
         ok = np.logical_and.reduce([cc > 0 for cc in cls])
-        per_tuple = sum(cc - 1 for cc in cls) + m * (m - 1)
+        per_tuple = sum(cc - 1 for cc in cls) + (8 if m == 4 else m * (m - 1))
         cost = np.where(ok, L["nt"] * per_tuple + L["ns"] * horner, L["nx"] * horner)
         total += int(cost.sum())
     return total, plain

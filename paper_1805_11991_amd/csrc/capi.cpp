@@ -387,14 +387,15 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       D.lv[j].gtab = P->d_gtab[j];
     }
   }
-  // split evaluation over mu_m cosets on form A levels (m = 3 when 3 | q-1)
+  // split evaluation over mu_m cosets on form A levels: m = 4 when 4 | q-1,
+  // else 3 when 3 | q-1, else 2
   P->d_tup.assign(g, nullptr);
   P->d_sgl.assign(g, nullptr);
   for (uint32_t j = 0; j < g; ++j) {
     hwc::LevelDesc& L = D.lv[j];
     L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
     if (!T.split || L.form != hwc::kFormA) continue;
-    const uint32_t m = ((q - 1) % 3 == 0) ? 3u : 2u;
+    const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
     L.msplit = m;
     if (!orbit) {
       L.nt = L.M / m;

@@ -188,16 +188,28 @@ void split_orbits(const Field& F, uint32_t m, std::vector<uint32_t>* tuples, std
   }
   std::vector<uint8_t> done(M, 0);
   const uint64_t step = M / m;
+  // x -> w x permutes the primitive orbits (w lies in F_q, so it commutes
+  // with Frobenius); the orbits met by x, wx, .., w^(m-1) x share one
+  // stabiliser.  Trivial stabiliser: m distinct orbits, one tuple.  Else every
+  // orbit met is swept on its own.
+  std::vector<uint32_t> met(m);
   for (uint32_t r : F.prim_reps) {
     if (done[r]) continue;
-    const uint32_t r1 = rep[(r + step) % M];
-    if (r1 == r) {                  // the orbit is closed under w
-      singles->push_back(r);
-      done[r] = 1;
-      continue;
+    bool distinct = true;
+    for (uint32_t s = 0; s < m; ++s) {
+      met[s] = rep[(r + s * step) % M];
+      for (uint32_t t = 0; t < s; ++t) distinct &= met[t] != met[s];
     }
-    tuples->push_back(r);
-    for (uint32_t s = 0; s < m; ++s) done[rep[(r + s * step) % M]] = 1;
+    if (distinct) {
+      tuples->push_back(r);
+    } else {
+      for (uint32_t s = 0; s < m; ++s)
+        if (!done[met[s]]) {
+          singles->push_back(met[s]);
+          done[met[s]] = 1;
+        }
+    }
+    for (uint32_t s = 0; s < m; ++s) done[met[s]] = 1;
   }
 }
 

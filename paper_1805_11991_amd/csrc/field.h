@@ -42,8 +42,9 @@ bool lex_first_primitive(uint32_t p, uint32_t n, std::vector<uint32_t>* poly,
 // m-th roots of unity lie in F_q and multiplying by them keeps an element's
 // field of definition).  For a representative x of each group whose points
 // x, wx, .., w^(m-1)x (w = gamma^(M/m)) lie in m distinct Frobenius orbits,
-// the representative's log goes to *tuples; orbits closed under w go to
-// *singles.  Every primitive orbit is covered exactly once:
+// the representative's log goes to *tuples; the orbits of a group with fewer
+// distinct orbits (some w^s x, 0 < s < m, in the orbit of x) go to *singles.
+// Every primitive orbit is covered exactly once:
 // m * tuples.size() + singles.size() == prim_reps.size().
 void split_orbits(const Field& F, uint32_t m, std::vector<uint32_t>* tuples, std::vector<uint32_t>* singles);
 

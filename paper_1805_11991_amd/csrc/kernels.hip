@@ -307,19 +307,61 @@ __device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint3
   return a;
 }
 
+// Per-curve constants of the split on one level: ll[r] = log of the lowest
+// coefficient of class r, blane = parity of the lowest coefficient's log.
+struct SplitConst {
+  uint32_t ll[4];
+  uint32_t blane;
+};
+
+__device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t M) {  // a, b < M
+  return a >= b ? a - b : a + M - b;
+}
+
+// Zero-safe sum of two field elements given as absolute logs in byte units
+// (2 log, in [0, 2M)) or the zero marker S: one read of the table's first
+// 2M bytes (2 Z(k), or S where 1 + gamma^k = 0).
+__device__ __forceinline__ uint32_t zadd(const uint8_t* lds, uint32_t tab, uint32_t M2, uint32_t S, uint32_t u,
+                                         uint32_t v) {
+  const bool uz = u == S, vz = v == S;
+  uint32_t d = v - u;
+  d = min(d, d + M2);
+  const uint32_t r = lds_u16(lds, tab + ((uz || vz) ? 0u : d));
+  uint32_t s = u + r;
+  s = min(s, s - M2);
+  return uz ? v : (vz ? u : (r == S ? S : s));
+}
+
+__device__ __forceinline__ uint32_t zmul(uint32_t v, uint32_t k, uint32_t M2, uint32_t S) {  // k < 2M bytes
+  uint32_t s = v + k;
+  s = min(s, s - M2);
+  return v == S ? S : s;
+}
+
 // Split evaluation over mu_MS cosets (form A).  With w = gamma^(M/MS) in F_q,
 // f(w^s x) = sum_r w^(s r) x^r f_r(x^MS): the MS points of a tuple share the
-// sub-polynomial values at y = x^MS, then cost MS-1 Zech additions each,
-// chained from the top class in relative form:
-//   B = Z(a_2 - a_1), R = Z(B + a_1 - a_0), log f = R + a_0   (MS = 3),
-// a_r = log(w^(s r) x^r f_r(y)).  A vanishing f_r(y) below the top class has
-// no relative log; the wave then evaluates the tuple's points by plain Horner.
+// sub-polynomial values at y = x^MS.
+//   MS = 2, 3: the MS - 1 Zech additions per point chain from the top class
+//     in relative form, B = Z(a_2 - a_1), R = Z(B + a_1 - a_0), log f = R + a_0
+//     (a_r = log(w^(s r) x^r f_r(y))).  A vanishing f_r(y) below the top
+//     class has no relative log; the wave then evaluates the tuple's points
+//     by plain Horner.
+//   MS = 4 (4 | q - 1): two radix-2 stages, f(x) = E(x^2) + x O(x^2) with
+//     E(v) = f_0(v^2) + v f_2(v^2), O(v) = f_1(v^2) + v f_3(v^2); the points
+//     x, -x share E(x^2), O(x^2), and ix, -ix share E(-x^2), O(-x^2): four
+//     additions for E and O, one per point.  Relative form as above; when a
+//     base vanishes (f_0(y), f_1(y) or E) the wave redoes the eight additions
+//     zero-safe on absolute logs.
 template <int NC, int MS, bool FULL, int D>
 __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&sdel)[NC],
-                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t dl1,
-                                              uint32_t dl2, uint32_t fix, LevelCounts& c) {
-  const uint32_t M = L.M, S = 6 * M, step = M / MS, tab = L.tab_off;
-  const uint32_t K1 = 2 * M + 2 * dl1, K2 = 2 * M + 2 * dl2;
+                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
+                                              const SplitConst& K, LevelCounts& c) {
+  const uint32_t M = L.M, M2 = 2 * M, S = 6 * M, step = M / MS, tab = L.tab_off;
+  const uint32_t dl1 = submod(K.ll[1], K.ll[0], M);
+  const uint32_t K1 = M2 + 2 * dl1;
+  const uint32_t K2 = M2 + 2 * (MS == 4 ? submod(K.ll[2], K.ll[0], M) : submod(K.ll[2], K.ll[1], M));
+  const uint32_t K3 = M2 + 2 * submod(K.ll[3], K.ll[1], M);
+  const uint32_t fix = (K.ll[0] ^ K.blane) & 1u;
   const uint32_t sup = mask | (1u << d);
   const uint32_t nt = L.nt;
   const uint32_t* xt = L.xs_t;
@@ -330,11 +372,72 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
     uint32_t Y = 0;
 #pragma unroll
     for (int m = 0; m < MS; ++m) Y = addmod(Y, x, M);
-    uint32_t p0, p1, p2 = 0;
+    uint32_t p0, p1, p2 = 0, p3 = 0;
     const uint32_t a0 = horner_class<NC, MS, 0, FULL, D>(lds, sdel, M, d, sup, Y, p0);
     const uint32_t a1 = horner_class<NC, MS, 1, FULL, D>(lds, sdel, M, d, sup, Y, p1);
-    uint32_t a2 = S;
-    if (MS == 3) a2 = horner_class<NC, MS, 2, FULL, D>(lds, sdel, M, d, sup, Y, p2);
+    uint32_t a2 = S, a3 = S;
+    if (MS >= 3) a2 = horner_class<NC, MS, 2, FULL, D>(lds, sdel, M, d, sup, Y, p2);
+    if (MS == 4) a3 = horner_class<NC, MS, 3, FULL, D>(lds, sdel, M, d, sup, Y, p3);
+    const uint32_t cls = FULL ? 0u : (p0 & 1u);  // parity of t_0 Y
+    if (MS == 4) {
+      const uint32_t x2 = addmod(x, x, M), h = M / 2;
+      const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);
+      const uint32_t uO = addmod(addmod(x2, p3, M), p1 ? M - p1 : 0u, M);
+      const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
+      // clamped bases keep every index in the table while the wave decides
+      const bool base_zero = (a0 == S) || (a1 == S);
+      const uint32_t b0 = base_zero ? 0u : a0, b1 = base_zero ? 0u : a1;
+      uint32_t FE = K2 - b0;                          // (0, 4M)
+      FE = min(FE, FE - M2);
+      uint32_t FO = K3 - b1;
+      FO = min(FO, FO - M2);
+      const uint32_t Ep = lds_u16(lds, a2 + FE + 2 * uE + tab);
+      const uint32_t Em = lds_u16(lds, a2 + FE + 2 * addmod(uE, h, M) + tab);
+      const uint32_t Op = lds_u16(lds, a3 + FO + 2 * uO + tab);
+      const uint32_t Om = lds_u16(lds, a3 + FO + 2 * addmod(uO, h, M) + tab);
+      uint32_t u = 0, zs = 0, odd;
+      if (!__ballot(base_zero || Ep == S || Em == S)) {
+        uint32_t G = b1 + K1 - b0;                    // (0, 6M)
+        G = min(G, G - M2);
+        G = min(G, G - M2);
+        G += M2;
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s) {
+          const uint32_t E = (s & 1u) ? Em : Ep;
+          const uint32_t O = (s & 1u) ? Om : Op;
+          uint32_t F = G - E;                         // (0, 4M)
+          F = min(F, F - M2);
+          const uint32_t r = lds_u16(lds, O + F + 2 * addmod(vf, s * step, M) + tab);
+          const bool z = r == S;
+          zs += z;
+          u += z ? 0u : (((E + r) >> 1) & 1u);
+        }
+        odd = ((a0 >> 1) ^ fix) & 1u ? (4 - zs) - u : u;
+      } else {
+        // absolute logs (byte units) of f_r(y) w^.. x^..: 2 (ll_r + p_r) + a_r
+        const uint32_t v0 = zmul(a0, 2 * addmod(K.ll[0], p0, M), M2, S);
+        const uint32_t v1 = zmul(a1, 2 * addmod(K.ll[1], p1, M), M2, S);
+        const uint32_t v2 = zmul(a2, 2 * addmod(K.ll[2], p2, M), M2, S);
+        const uint32_t v3 = zmul(a3, 2 * addmod(K.ll[3], p3, M), M2, S);
+        const uint32_t ep = zadd(lds, tab, M2, S, v0, zmul(v2, 2 * x2, M2, S));
+        const uint32_t em = zadd(lds, tab, M2, S, v0, zmul(v2, 2 * addmod(x2, h, M), M2, S));
+        const uint32_t op = zadd(lds, tab, M2, S, v1, zmul(v3, 2 * x2, M2, S));
+        const uint32_t om = zadd(lds, tab, M2, S, v1, zmul(v3, 2 * addmod(x2, h, M), M2, S));
+        odd = 0;
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s) {
+          const uint32_t E = (s & 1u) ? em : ep;
+          const uint32_t O = (s & 1u) ? om : op;
+          const uint32_t f = zadd(lds, tab, M2, S, E, zmul(O, 2 * addmod(x, s * step, M), M2, S));
+          const bool z = f == S;
+          zs += z;
+          // A = log f - log c_low - t_0 Y
+          odd += z ? 0u : (((f >> 1) ^ K.blane ^ cls) & 1u);
+        }
+      }
+      c.add_n(cls, 4, zs, odd);
+      continue;
+    }
     const bool inner_zero = (a0 == S) || (MS == 3 && a1 == S);
     if (__ballot(inner_zero)) {
       for (uint32_t s = 0; s < MS; ++s) {
@@ -345,7 +448,6 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
       }
       continue;
     }
-    const uint32_t cls = FULL ? 0u : (p0 & 1u);  // parity of t_0 Y
     // zero values contribute bit 1 of 6M = 0; the lane's parity (a0 + fix) is
     // applied once per tuple: odd = u if even, else (non-zero points) - u
     uint32_t u = 0, zs = 0;
@@ -462,14 +564,14 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
   LevelCounts c = {0, 0, 0, 0, 0};
   const bool full = mask == ((1u << d) - 1u);
   if (L.form == kFormA) {
-    // split evaluation: needs every class below the top class to hold a term
+    // split evaluation: needs every class to hold a term
     const uint32_t sup = mask | (1u << d);
     uint32_t ms = L.msplit;
     if (ms) {
       uint32_t cls_mask = 0;
 #pragma unroll
       for (int i = 0; i < NC; ++i)
-        if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 3 ? i % 3 : i % 2);
+        if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 4 ? i % 4 : (ms == 3 ? i % 3 : i % 2));
       if (cls_mask != (1u << ms) - 1u) ms = 0;
     }
     if (ms) {
@@ -477,15 +579,17 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
       uint32_t sdel[NC];
 #pragma unroll
       for (int i = 0; i < NC; ++i) sdel[i] = L.tab_off;
-      uint32_t lowlog[3] = {0, 0, 0};
+      SplitConst K;
+      K.ll[0] = K.ll[1] = K.ll[2] = K.ll[3] = 0;
+      K.blane = blane;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) {
+      for (int r = 0; r < 4; ++r) {
         if (r >= (int)ms) break;
         bool started = false;
         uint32_t pv = 0;
 #pragma unroll
         for (int i = NC - 1; i >= 0; --i) {
-          const uint32_t cl = ms == 3 ? (uint32_t)(i % 3) : (uint32_t)(i % 2);
+          const uint32_t cl = ms == 4 ? (uint32_t)(i % 4) : (ms == 3 ? (uint32_t)(i % 3) : (uint32_t)(i % 2));
           if (cl != (uint32_t)r || (uint32_t)i > d || !((sup >> i) & 1u)) continue;
           if (started) {
             uint32_t v = pv + M - lc[i];
@@ -495,28 +599,24 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
           started = true;
           pv = lc[i];
         }
-        lowlog[r] = pv;
+        K.ll[r] = pv;
       }
-      const uint32_t dl1 = lowlog[1] >= lowlog[0] ? lowlog[1] - lowlog[0] : lowlog[1] + M - lowlog[0];
-      const uint32_t dl2 = lowlog[2] >= lowlog[1] ? lowlog[2] - lowlog[1] : lowlog[2] + M - lowlog[1];
-      const uint32_t fix = (lowlog[0] ^ prev) & 1u;
 #pragma unroll
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
+#define HWC_SPLIT(FULLV, DV)                                                            \
+  do {                                                                                  \
+    if (ms == 4) sweep_split_a<NC, 4, FULLV, DV>(L, lds, sdel, del, d, mask, K, c);     \
+    else if (ms == 3) sweep_split_a<NC, 3, FULLV, DV>(L, lds, sdel, del, d, mask, K, c); \
+    else sweep_split_a<NC, 2, FULLV, DV>(L, lds, sdel, del, d, mask, K, c);             \
+    sweep_form_a<NC, FULLV, DV>(L.xs_s, L.ns, M, lds, del, d, mask, c);                 \
+  } while (0)
       if (full) {
-        if (top) {
-          if (ms == 3) sweep_split_a<NC, 3, true, NC - 1>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-          else sweep_split_a<NC, 2, true, NC - 1>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-          sweep_form_a<NC, true, NC - 1>(L.xs_s, L.ns, M, lds, del, d, mask, c);
-        } else {
-          if (ms == 3) sweep_split_a<NC, 3, true, NC - 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-          else sweep_split_a<NC, 2, true, NC - 2>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-          sweep_form_a<NC, true, NC - 2>(L.xs_s, L.ns, M, lds, del, d, mask, c);
-        }
+        if (top) HWC_SPLIT(true, NC - 1);
+        else HWC_SPLIT(true, NC - 2);
       } else {
-        if (ms == 3) sweep_split_a<NC, 3, false, 0>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-        else sweep_split_a<NC, 2, false, 0>(L, lds, sdel, del, d, mask, dl1, dl2, fix, c);
-        sweep_form_a<NC, false, 0>(L.xs_s, L.ns, M, lds, del, d, mask, c);
+        HWC_SPLIT(false, 0);
       }
+#undef HWC_SPLIT
     } else {
 #pragma unroll
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
