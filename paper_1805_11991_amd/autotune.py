@@ -11,6 +11,7 @@ the database's entries as per-plan options when it is created.
 
 Search space (library options, see include/hwcount.h):
   split           split evaluation over m-th roots of unity on LDS levels (on/off)
+  split_min_m     smallest level (nonzero elements) that is split
   block           threads per workgroup of the count kernel (256, 512, 1024)
   waves_per_simd  register budget of the kernel build (1: free, 6, 8)
   device_tables   which levels' Zech tables sit in device memory instead of LDS
@@ -30,9 +31,10 @@ DB_DIR = os.path.join(HERE, "autotune")
 
 SPACE = {
     "split": [1, 0],
+    "split_min_m": [256, 2048],
     "block": [256, 512, 1024],
     "waves_per_simd": [1, 6, 8],
-    "device_tables": ["none", "top", "all"],
+    "device_tables": ["none", "top"],
 }
 
 
@@ -42,8 +44,8 @@ def _device_mask(choice, g: int) -> int:
 
 def _opt_ids():
     from . import hwcount as hw
-    return {"split": hw.HWC_OPT_SPLIT, "block": hw.HWC_OPT_BLOCK, "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD,
-            "device_tables": hw.HWC_OPT_DEVICE_TABLES}
+    return {"split": hw.HWC_OPT_SPLIT, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M, "block": hw.HWC_OPT_BLOCK,
+            "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD, "device_tables": hw.HWC_OPT_DEVICE_TABLES}
 
 
 def db_path(arch: str = "gfx950") -> str:
@@ -98,6 +100,8 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
     names = list(space)
     for values in itertools.product(*(space[k] for k in names)):
         cand = dict(zip(names, values))
+        if cand.get("split") == 0 and cand.get("split_min_m", 0) != space.get("split_min_m", [0])[0]:
+            continue                      # the threshold means nothing without the split
         try:
             for k, v in cand.items():
                 ctx.set_plan_option(q, g, ids[k], _device_mask(v, g) if k == "device_tables" else v, flags)

@@ -58,6 +58,7 @@ struct FieldEntry {
 // Launch and layout choices for one plan (defaults or an autotuned override).
 struct Tuning {
   bool split = true;            // split evaluation over mu_m cosets on form A levels
+  uint32_t split_min_m = 256;   // ... of at least this many nonzero elements
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
@@ -394,7 +395,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   for (uint32_t j = 0; j < g; ++j) {
     hwc::LevelDesc& L = D.lv[j];
     L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
-    if (!T.split || L.form != hwc::kFormA) continue;
+    if (!T.split || L.form != hwc::kFormA || L.M < T.split_min_m) continue;
     const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
     L.msplit = m;
     if (!orbit) {
@@ -827,6 +828,10 @@ int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
     case HWC_OPT_WG_PER_CU:
       if (value < 0 || value > 64) return fail(c, HWC_ERR_ARG, "workgroups per CU must be in 0..64");
       T.wg_per_cu = (uint32_t)value;
+      break;
+    case HWC_OPT_SPLIT_MIN_M:
+      if (value < 0 || value > (1 << 24)) return fail(c, HWC_ERR_ARG, "split threshold must be in 0..2^24");
+      T.split_min_m = (uint32_t)value;
       break;
     case HWC_OPT_DEVICE_TABLES:
       if (value < 0 || value > 15) return fail(c, HWC_ERR_ARG, "device table mask must be in 0..15");

@@ -25,12 +25,15 @@
 
 namespace hwc {
 
-__device__ __forceinline__ uint32_t lds_u16(const uint8_t* base, uint32_t byte_addr) {
-  return *reinterpret_cast<const uint16_t*>(base + byte_addr);
-}
-
-__device__ __forceinline__ uint32_t lds_u32(const uint8_t* base, uint32_t byte_addr) {
-  return *reinterpret_cast<const uint32_t*>(base + byte_addr);
+// LDS reads at absolute LDS byte addresses.  The kernels fold the base of
+// the dynamic LDS block into their per-lane offsets once, so a table step is
+// one add and one read.
+typedef const __attribute__((address_space(3))) uint16_t* lds16_ptr;
+typedef const __attribute__((address_space(3))) uint32_t* lds32_ptr;
+__device__ __forceinline__ uint32_t lds_u16(uint32_t addr) { return *(lds16_ptr)(size_t)addr; }
+__device__ __forceinline__ uint32_t lds_u32(uint32_t addr) { return *(lds32_ptr)(size_t)addr; }
+__device__ __forceinline__ uint32_t lds_base(const uint32_t* p) {
+  return (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)p;
 }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -186,33 +189,27 @@ __global__ __launch_bounds__(256) void scatter_kernel(const uint16_t* __restrict
 // the count
 
 struct LevelCounts {
-  uint32_t z0, z1, o0, o1;  // zeros / odd logs, split by parity of low*L
-  uint32_t n1;              // x with odd low*L (uniform)
+  // zeros / odd logs over all swept points, and among the points whose
+  // power low*L is odd (the others follow by difference); n1 = number of
+  // those points.  Masks rather than selects keep the counters in registers.
+  uint32_t zt, ot, z1, o1, n1;
   // n points of uniform class cls with z zeros and o odd logs
   __device__ __forceinline__ void add_n(uint32_t cls, uint32_t n, uint32_t z, uint32_t o) {
-    if (cls) {
-      z1 += z;
-      o1 += o;
-      n1 += n;
-    } else {
-      z0 += z;
-      o0 += o;
-    }
+    const uint32_t m = 0u - (cls & 1u);
+    zt += z;
+    ot += o;
+    z1 += z & m;
+    o1 += o & m;
+    n1 += n & m;
   }
-  __device__ __forceinline__ void add(uint32_t cls, uint32_t z, uint32_t o) {
-    z1 += cls ? z : 0u;
-    o1 += cls ? o : 0u;
-    z0 += cls ? 0u : z;
-    o0 += cls ? 0u : o;
-    n1 += cls;
-  }
+  __device__ __forceinline__ void add(uint32_t cls, uint32_t z, uint32_t o) { add_n(cls, 1u, z, o); }
 };
 
 // Form A: byte-unit table, zero region; one add + one read per step.
 // del[i] already holds 2*delta_i + table offset.  Returns the relative log
 // (byte units, or the zero marker 6M) and the pending power low*x in pend.
 template <int NC>
-__device__ __forceinline__ uint32_t horner_a(const uint8_t* lds, const uint32_t (&del)[NC], uint32_t M, uint32_t d,
+__device__ __forceinline__ uint32_t horner_a(const uint32_t (&del)[NC], uint32_t M, uint32_t d,
                                              uint32_t mask, uint32_t x, uint32_t& pend) {
   uint32_t a = 0, p = 0;
 #pragma unroll
@@ -220,7 +217,7 @@ __device__ __forceinline__ uint32_t horner_a(const uint8_t* lds, const uint32_t 
     if ((uint32_t)i < d) {
       p += x; p = p >= M ? p - M : p;
       if ((mask >> i) & 1u) {
-        a = lds_u16(lds, a + del[i] + 2 * p);
+        a = lds_u16(a + del[i] + 2 * p);
         p = 0;
       }
     }
@@ -230,7 +227,7 @@ __device__ __forceinline__ uint32_t horner_a(const uint8_t* lds, const uint32_t 
 }
 
 template <int NC, bool FULL, int D>
-__device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, uint32_t M, const uint8_t* lds,
+__device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, uint32_t M,
                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
   const uint32_t S = 6 * M;
   uint32_t ix = 0;
@@ -249,15 +246,15 @@ __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, ui
       const uint32_t b0 = 2 * x0, b1 = 2 * x1;
 #pragma unroll
       for (int i = D - 1; i >= 0; --i) {
-        a0 = lds_u16(lds, a0 + del[i] + b0);
-        a1 = lds_u16(lds, a1 + del[i] + b1);
+        a0 = lds_u16(a0 + del[i] + b0);
+        a1 = lds_u16(a1 + del[i] + b1);
       }
-      c.z0 += (a0 == S) + (a1 == S);
-      c.o0 += ((a0 >> 1) & 1u) + ((a1 >> 1) & 1u);
+      c.zt += (a0 == S) + (a1 == S);
+      c.ot += ((a0 >> 1) & 1u) + ((a1 >> 1) & 1u);
     } else {
       uint32_t p0, p1;
-      const uint32_t a0 = horner_a<NC>(lds, del, M, d, mask, x0, p0);
-      const uint32_t a1 = horner_a<NC>(lds, del, M, d, mask, x1, p1);
+      const uint32_t a0 = horner_a<NC>(del, M, d, mask, x0, p0);
+      const uint32_t a1 = horner_a<NC>(del, M, d, mask, x1, p1);
       c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
       c.add(p1 & 1u, a1 == S, (a1 >> 1) & 1u);
     }
@@ -265,7 +262,7 @@ __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, ui
   if (ix < nx) {
     const uint32_t x0 = xs ? sload(xs, ix) : ix;
     uint32_t p0;
-    const uint32_t a0 = horner_a<NC>(lds, del, M, d, mask, x0, p0);
+    const uint32_t a0 = horner_a<NC>(del, M, d, mask, x0, p0);
     c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
   }
 }
@@ -279,14 +276,14 @@ __device__ __forceinline__ uint32_t addmod(uint32_t a, uint32_t b, uint32_t M) {
 // y (log Y).  sup has bit d set.  Returns the relative log (byte units or the
 // zero marker) and in pend the power t_r Y of the class's lowest term.
 template <int NC, int MS, int R, bool FULL, int D>
-__device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint32_t (&sdel)[NC], uint32_t M,
+__device__ __forceinline__ uint32_t horner_class(const uint32_t (&sdel)[NC], uint32_t M,
                                                  uint32_t d, uint32_t sup, uint32_t Y, uint32_t& pend) {
   uint32_t a = 0;
   if (FULL) {  // every position 0..D holds a term: steps of one power of y
     const uint32_t b = 2 * Y;
     constexpr int TOP = D - ((D - R) % MS);
 #pragma unroll
-    for (int i = TOP - MS; i >= 0; i -= MS) a = lds_u16(lds, a + sdel[i] + b);
+    for (int i = TOP - MS; i >= 0; i -= MS) a = lds_u16(a + sdel[i] + b);
     pend = 0;
     return a;
   }
@@ -298,7 +295,7 @@ __device__ __forceinline__ uint32_t horner_class(const uint8_t* lds, const uint3
     if ((uint32_t)i > d) continue;
     if (started) p = addmod(p, Y, M);
     if ((sup >> i) & 1u) {
-      if (started) a = lds_u16(lds, a + sdel[i] + 2 * p);
+      if (started) a = lds_u16(a + sdel[i] + 2 * p);
       started = true;
       p = 0;
     }
@@ -321,12 +318,12 @@ __device__ __forceinline__ uint32_t submod(uint32_t a, uint32_t b, uint32_t M) {
 // Zero-safe sum of two field elements given as absolute logs in byte units
 // (2 log, in [0, 2M)) or the zero marker S: one read of the table's first
 // 2M bytes (2 Z(k), or S where 1 + gamma^k = 0).
-__device__ __forceinline__ uint32_t zadd(const uint8_t* lds, uint32_t tab, uint32_t M2, uint32_t S, uint32_t u,
+__device__ __forceinline__ uint32_t zadd(uint32_t tab, uint32_t M2, uint32_t S, uint32_t u,
                                          uint32_t v) {
   const bool uz = u == S, vz = v == S;
   uint32_t d = v - u;
   d = min(d, d + M2);
-  const uint32_t r = lds_u16(lds, tab + ((uz || vz) ? 0u : d));
+  const uint32_t r = lds_u16(tab + ((uz || vz) ? 0u : d));
   uint32_t s = u + r;
   s = min(s, s - M2);
   return uz ? v : (vz ? u : (r == S ? S : s));
@@ -353,7 +350,7 @@ __device__ __forceinline__ uint32_t zmul(uint32_t v, uint32_t k, uint32_t M2, ui
 //     base vanishes (f_0(y), f_1(y) or E) the wave redoes the eight additions
 //     zero-safe on absolute logs.
 template <int NC, int MS, bool FULL, int D>
-__device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t* lds, const uint32_t (&sdel)[NC],
+__device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t (&sdel)[NC],
                                               const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
                                               const SplitConst& K, LevelCounts& c) {
   const uint32_t M = L.M, M2 = 2 * M, S = 6 * M, step = M / MS, tab = L.tab_off;
@@ -373,11 +370,11 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
 #pragma unroll
     for (int m = 0; m < MS; ++m) Y = addmod(Y, x, M);
     uint32_t p0, p1, p2 = 0, p3 = 0;
-    const uint32_t a0 = horner_class<NC, MS, 0, FULL, D>(lds, sdel, M, d, sup, Y, p0);
-    const uint32_t a1 = horner_class<NC, MS, 1, FULL, D>(lds, sdel, M, d, sup, Y, p1);
+    const uint32_t a0 = horner_class<NC, MS, 0, FULL, D>(sdel, M, d, sup, Y, p0);
+    const uint32_t a1 = horner_class<NC, MS, 1, FULL, D>(sdel, M, d, sup, Y, p1);
     uint32_t a2 = S, a3 = S;
-    if (MS >= 3) a2 = horner_class<NC, MS, 2, FULL, D>(lds, sdel, M, d, sup, Y, p2);
-    if (MS == 4) a3 = horner_class<NC, MS, 3, FULL, D>(lds, sdel, M, d, sup, Y, p3);
+    if (MS >= 3) a2 = horner_class<NC, MS, 2, FULL, D>(sdel, M, d, sup, Y, p2);
+    if (MS == 4) a3 = horner_class<NC, MS, 3, FULL, D>(sdel, M, d, sup, Y, p3);
     const uint32_t cls = FULL ? 0u : (p0 & 1u);  // parity of t_0 Y
     if (MS == 4) {
       const uint32_t x2 = addmod(x, x, M), h = M / 2;
@@ -391,27 +388,41 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
       FE = min(FE, FE - M2);
       uint32_t FO = K3 - b1;
       FO = min(FO, FO - M2);
-      const uint32_t Ep = lds_u16(lds, a2 + FE + 2 * uE + tab);
-      const uint32_t Em = lds_u16(lds, a2 + FE + 2 * addmod(uE, h, M) + tab);
-      const uint32_t Op = lds_u16(lds, a3 + FO + 2 * uO + tab);
-      const uint32_t Om = lds_u16(lds, a3 + FO + 2 * addmod(uO, h, M) + tab);
+      const uint32_t Ep = lds_u16(a2 + FE + 2 * uE + tab);
+      const uint32_t Em = lds_u16(a2 + FE + 2 * addmod(uE, h, M) + tab);
+      const uint32_t Op = lds_u16(a3 + FO + 2 * uO + tab);
+      const uint32_t Om = lds_u16(a3 + FO + 2 * addmod(uO, h, M) + tab);
       uint32_t u = 0, zs = 0, odd;
       if (!__ballot(base_zero || Ep == S || Em == S)) {
         uint32_t G = b1 + K1 - b0;                    // (0, 6M)
         G = min(G, G - M2);
         G = min(G, G - M2);
         G += M2;
+        // bit 1 of E + r (both even) is bit 1 of E ^ r; a zero point (r = S)
+        // must not count, which the rare branch below takes care of
+        uint32_t r[4];
+        bool anyz = false;
 #pragma unroll
         for (uint32_t s = 0; s < 4; ++s) {
           const uint32_t E = (s & 1u) ? Em : Ep;
           const uint32_t O = (s & 1u) ? Om : Op;
           uint32_t F = G - E;                         // (0, 4M)
           F = min(F, F - M2);
-          const uint32_t r = lds_u16(lds, O + F + 2 * addmod(vf, s * step, M) + tab);
-          const bool z = r == S;
-          zs += z;
-          u += z ? 0u : (((E + r) >> 1) & 1u);
+          r[s] = lds_u16(O + F + 2 * addmod(vf, s * step, M) + tab);
+          u += (E ^ r[s]) & 2u;
+          anyz |= r[s] == S;
         }
+        if (__ballot(anyz)) {
+          u = 0;
+#pragma unroll
+          for (uint32_t s = 0; s < 4; ++s) {
+            const uint32_t E = (s & 1u) ? Em : Ep;
+            const bool z = r[s] == S;
+            zs += z;
+            u += z ? 0u : ((E ^ r[s]) & 2u);
+          }
+        }
+        u >>= 1;
         odd = ((a0 >> 1) ^ fix) & 1u ? (4 - zs) - u : u;
       } else {
         // absolute logs (byte units) of f_r(y) w^.. x^..: 2 (ll_r + p_r) + a_r
@@ -419,16 +430,16 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
         const uint32_t v1 = zmul(a1, 2 * addmod(K.ll[1], p1, M), M2, S);
         const uint32_t v2 = zmul(a2, 2 * addmod(K.ll[2], p2, M), M2, S);
         const uint32_t v3 = zmul(a3, 2 * addmod(K.ll[3], p3, M), M2, S);
-        const uint32_t ep = zadd(lds, tab, M2, S, v0, zmul(v2, 2 * x2, M2, S));
-        const uint32_t em = zadd(lds, tab, M2, S, v0, zmul(v2, 2 * addmod(x2, h, M), M2, S));
-        const uint32_t op = zadd(lds, tab, M2, S, v1, zmul(v3, 2 * x2, M2, S));
-        const uint32_t om = zadd(lds, tab, M2, S, v1, zmul(v3, 2 * addmod(x2, h, M), M2, S));
+        const uint32_t ep = zadd(tab, M2, S, v0, zmul(v2, 2 * x2, M2, S));
+        const uint32_t em = zadd(tab, M2, S, v0, zmul(v2, 2 * addmod(x2, h, M), M2, S));
+        const uint32_t op = zadd(tab, M2, S, v1, zmul(v3, 2 * x2, M2, S));
+        const uint32_t om = zadd(tab, M2, S, v1, zmul(v3, 2 * addmod(x2, h, M), M2, S));
         odd = 0;
 #pragma unroll
         for (uint32_t s = 0; s < 4; ++s) {
           const uint32_t E = (s & 1u) ? em : ep;
           const uint32_t O = (s & 1u) ? om : op;
-          const uint32_t f = zadd(lds, tab, M2, S, E, zmul(O, 2 * addmod(x, s * step, M), M2, S));
+          const uint32_t f = zadd(tab, M2, S, E, zmul(O, 2 * addmod(x, s * step, M), M2, S));
           const bool z = f == S;
           zs += z;
           // A = log f - log c_low - t_0 Y
@@ -443,7 +454,7 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
       for (uint32_t s = 0; s < MS; ++s) {
         uint32_t pp;
         const uint32_t xs = addmod(x, s * step, M);
-        const uint32_t a = horner_a<NC>(lds, del, M, d, mask, xs, pp);
+        const uint32_t a = horner_a<NC>(del, M, d, mask, xs, pp);
         c.add(pp & 1u, a == S, (a >> 1) & 1u);
       }
       continue;
@@ -458,7 +469,7 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
 #pragma unroll
       for (uint32_t s = 0; s < 2; ++s) {
         const uint32_t w1 = 2 * addmod(v1, s * step, M) + tab;
-        const uint32_t r = lds_u16(lds, a1 + F1 + w1);
+        const uint32_t r = lds_u16(a1 + F1 + w1);
         u += r & 2u;
         zs += r == S;
       }
@@ -474,8 +485,8 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
       for (uint32_t s = 0; s < 3; ++s) {
         const uint32_t w2 = 2 * addmod(v2, s * step, M) + tab;
         const uint32_t w1 = 2 * addmod(v1, s * step, M) + tab;
-        const uint32_t b = lds_u16(lds, a2 + F2 + w2);
-        const uint32_t r = lds_u16(lds, b + F1 + w1);
+        const uint32_t b = lds_u16(a2 + F2 + w2);
+        const uint32_t r = lds_u16(b + F1 + w1);
         u += r & 2u;
         zs += r == S;
       }
@@ -487,7 +498,7 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint8_t*
 }
 
 template <int NC, bool EXACT, bool GLOBAL>
-__device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, const uint32_t* __restrict__ gtab,
+__device__ __forceinline__ uint32_t horner_c(uint32_t tab, const uint32_t* __restrict__ gtab,
                                              uint32_t M, const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
                                              uint32_t x, uint32_t& pend, bool& hit) {
   uint32_t a = 0, p = 0;
@@ -498,7 +509,7 @@ __device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, c
       if ((mask >> i) & 1u) {
         const uint32_t idx = a + del[i] + p;           // < 3M
         const uint32_t r = min(idx, idx - M);          // < 2M
-        const uint32_t v = GLOBAL ? gtab[r] : lds_u16(lds, tab + 2 * r);
+        const uint32_t v = GLOBAL ? gtab[r] : lds_u16(tab + 2 * r);
         if (EXACT) a = (a == M) ? 0u : v;
         else { hit |= (v == M); a = v; }
         p = 0;
@@ -510,7 +521,7 @@ __device__ __forceinline__ uint32_t horner_c(const uint8_t* lds, uint32_t tab, c
 }
 
 template <int NC, bool GLOBAL>
-__device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* lds, const uint32_t (&del)[NC],
+__device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t (&del)[NC],
                                              uint32_t d, uint32_t mask, LevelCounts& c) {
   const uint32_t M = L.M, nx = L.nx, tab = L.tab_off;
   const uint32_t* xs = L.xs;
@@ -521,11 +532,11 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* 
     const uint32_t x1 = two ? (xs ? sload(xs, ix + 1) : ix + 1) : x0;
     bool hit = false;
     uint32_t p0, p1;
-    uint32_t a0 = horner_c<NC, false, GLOBAL>(lds, tab, gtab, M, del, d, mask, x0, p0, hit);
-    uint32_t a1 = horner_c<NC, false, GLOBAL>(lds, tab, gtab, M, del, d, mask, x1, p1, hit);
+    uint32_t a0 = horner_c<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x0, p0, hit);
+    uint32_t a1 = horner_c<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x1, p1, hit);
     if (__ballot(hit)) {
-      a0 = horner_c<NC, true, GLOBAL>(lds, tab, gtab, M, del, d, mask, x0, p0, hit);
-      a1 = horner_c<NC, true, GLOBAL>(lds, tab, gtab, M, del, d, mask, x1, p1, hit);
+      a0 = horner_c<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x0, p0, hit);
+      a1 = horner_c<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x1, p1, hit);
     }
     c.add(p0 & 1u, a0 == M, a0 & 1u);   // M is even: the marker counts as even
     if (two) c.add(p1 & 1u, a1 == M, a1 & 1u);
@@ -535,16 +546,20 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint8_t* 
 // Counts for one level: returns z | ns << 8 (roots and non-squares among the
 // swept x; squares are nx - z - ns).
 template <int G>
-__device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const uint32_t (&code)[2 * G + 3],
+__device__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t (&code)[2 * G + 3],
                                 uint32_t top, uint32_t mask) {
   constexpr int NC = 2 * G + 3;
+  // the level with its table offsets made absolute LDS addresses
+  LevelDesc L = Lp;
+  L.tab_off += lb;
+  L.emb_off += lb;
   const uint32_t M = L.M;
   const uint32_t d = top ? NC - 1 : NC - 2;
   uint32_t lc[NC];
 #pragma unroll
   for (int i = 0; i < NC; ++i) {
     // nonzero codes have logs below M; only a rejected row can reach M here
-    const uint32_t v = lds_u32(lds, L.emb_off + 4 * code[i]);
+    const uint32_t v = lds_u32(L.emb_off + 4 * code[i]);
     lc[i] = v < M ? v : M - 1;
   }
   uint32_t prev = top ? lc[NC - 1] : lc[NC - 2];
@@ -605,10 +620,10 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
 #define HWC_SPLIT(FULLV, DV)                                                            \
   do {                                                                                  \
-    if (ms == 4) sweep_split_a<NC, 4, FULLV, DV>(L, lds, sdel, del, d, mask, K, c);     \
-    else if (ms == 3) sweep_split_a<NC, 3, FULLV, DV>(L, lds, sdel, del, d, mask, K, c); \
-    else sweep_split_a<NC, 2, FULLV, DV>(L, lds, sdel, del, d, mask, K, c);             \
-    sweep_form_a<NC, FULLV, DV>(L.xs_s, L.ns, M, lds, del, d, mask, c);                 \
+    if (ms == 4) sweep_split_a<NC, 4, FULLV, DV>(L, sdel, del, d, mask, K, c);     \
+    else if (ms == 3) sweep_split_a<NC, 3, FULLV, DV>(L, sdel, del, d, mask, K, c); \
+    else sweep_split_a<NC, 2, FULLV, DV>(L, sdel, del, d, mask, K, c);             \
+    sweep_form_a<NC, FULLV, DV>(L.xs_s, L.ns, M, del, d, mask, c);                 \
   } while (0)
       if (full) {
         if (top) HWC_SPLIT(true, NC - 1);
@@ -621,21 +636,22 @@ __device__ uint32_t count_level(const LevelDesc& L, const uint8_t* lds, const ui
 #pragma unroll
       for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
       if (full) {
-        if (top) sweep_form_a<NC, true, NC - 1>(L.xs, L.nx, M, lds, del, d, mask, c);
-        else sweep_form_a<NC, true, NC - 2>(L.xs, L.nx, M, lds, del, d, mask, c);
+        if (top) sweep_form_a<NC, true, NC - 1>(L.xs, L.nx, M, del, d, mask, c);
+        else sweep_form_a<NC, true, NC - 2>(L.xs, L.nx, M, del, d, mask, c);
       } else {
-        sweep_form_a<NC, false, 0>(L.xs, L.nx, M, lds, del, d, mask, c);
+        sweep_form_a<NC, false, 0>(L.xs, L.nx, M, del, d, mask, c);
       }
     }
   } else if (L.form == kFormC) {
-    sweep_form_c<NC, false>(L, lds, del, d, mask, c);
+    sweep_form_c<NC, false>(L, del, d, mask, c);
   } else {
-    sweep_form_c<NC, true>(L, lds, del, d, mask, c);
+    sweep_form_c<NC, true>(L, del, d, mask, c);
   }
   const uint32_t n0 = L.nx - c.n1;
-  const uint32_t z = c.z0 + c.z1;
+  const uint32_t z = c.zt;
+  const uint32_t z0 = c.zt - c.z1, o0 = c.ot - c.o1;
   // chi(f(x)) = (-1)^(A + log c_low + low*L); A odd counted in o*, zeros are even
-  const uint32_t ns0 = blane ? (n0 - c.z0 - c.o0) : c.o0;
+  const uint32_t ns0 = blane ? (n0 - z0 - o0) : o0;
   const uint32_t ns1 = blane ? c.o1 : (c.n1 - c.z1 - c.o1);
   return z | ((ns0 + ns1) << 8);
 }
@@ -670,7 +686,7 @@ __device__ void assemble(const PlanDesc& P, const uint32_t (&lv)[G], uint32_t c0
 
 // One tile (up to 64 curves of one pattern) through levels lvl_lo..lvl_hi.
 template <int G, typename CT>
-__device__ __forceinline__ void process_tile(const PlanDesc& P, const uint8_t* lds, const CT* __restrict__ codes,
+__device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, const CT* __restrict__ codes,
                                              const uint32_t* __restrict__ perm, uint64_t w, uint32_t lvl_lo,
                                              uint32_t lvl_hi, int32_t* __restrict__ outN,
                                              uint32_t* __restrict__ outLv) {
@@ -697,11 +713,11 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, const uint8_t* l
 #pragma unroll
   for (int j = 0; j < G; ++j) {
     lv[j] = 0;
-    if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lds, code, top, mask);
+    if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lb, code, top, mask);
   }
   if (outN) {
-    const uint32_t log0 = lds_u32(lds, P.lv[0].emb_off + 4 * code[0]);
-    const uint32_t logt = lds_u32(lds, P.lv[0].emb_off + 4 * code[NC - 1]);
+    const uint32_t log0 = lds_u32(lb + P.lv[0].emb_off + 4 * code[0]);
+    const uint32_t logt = lds_u32(lb + P.lv[0].emb_off + 4 * code[NC - 1]);
     int32_t n[G];
     assemble<G>(P, lv, code[0], code[NC - 1], log0, logt, n);
     if (live) {
@@ -724,7 +740,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
                                                      uint32_t lvl_lo, uint32_t lvl_hi, int32_t* __restrict__ outN,
                                                      uint32_t* __restrict__ outLv) {
   extern __shared__ uint32_t lds32[];
-  const uint8_t* lds = reinterpret_cast<const uint8_t*>(lds32);
+  const uint32_t lb = lds_base(lds32);
   for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
   __syncthreads();
   const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -739,7 +755,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     t = uniform((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   }
   while (t < ntiles) {
-    process_tile<G, CT>(P, lds, codes, perm, sload64(tiles, t), lvl_lo, lvl_hi, outN, outLv);
+    process_tile<G, CT>(P, lb, codes, perm, sload64(tiles, t), lvl_lo, lvl_hi, outN, outLv);
     if (queue) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(queue, 1u);
@@ -754,15 +770,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 // one persistent launch over several plans: workgroups pop chunks of tiles
 // of one job, restage LDS when the job's plan differs from the staged one.
 
-__device__ __forceinline__ void process_job_tile(const JobDesc& J, const uint8_t* lds, uint64_t w) {
+__device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, uint64_t w) {
   const PlanDesc& P = *J.plan;
 #define HWC_JOB(GG)                                                                                    \
   case GG:                                                                                             \
     if (J.cb == 1)                                                                                     \
-      process_tile<GG, int8_t>(P, lds, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
+      process_tile<GG, int8_t>(P, lb, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
                                nullptr);                                                               \
     else                                                                                               \
-      process_tile<GG, int16_t>(P, lds, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
+      process_tile<GG, int16_t>(P, lb, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
                                 J.outN, nullptr);                                                      \
     break;
   switch (J.g) {
@@ -777,7 +793,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__
                                                      const uint32_t* __restrict__ nchunks_p, uint32_t* queue) {
   extern __shared__ uint32_t lds32[];
   __shared__ uint64_t sh_chunk;
-  const uint8_t* lds = reinterpret_cast<const uint8_t*>(lds32);
+  const uint32_t lb = lds_base(lds32);
   const uint32_t wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
   const uint32_t nchunks = *nchunks_p;
   const PlanDesc* staged = nullptr;
@@ -800,7 +816,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__
       __syncthreads();
       staged = P;
     }
-    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lds, sload64(J.tiles, t));
+    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lb, sload64(J.tiles, t));
     __syncthreads();
   }
 }

@@ -38,6 +38,7 @@ HWC_OPT_BLOCK = 2
 HWC_OPT_WG_PER_CU = 3
 HWC_OPT_DEVICE_TABLES = 4
 HWC_OPT_WAVES_PER_SIMD = 5
+HWC_OPT_SPLIT_MIN_M = 6
 
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
