@@ -22,7 +22,7 @@
 #include "plan.h"
 
 namespace hwc {
-hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, const uint32_t* perm,
+hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
                         int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s);
 hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, uint32_t wpe,
@@ -388,15 +388,16 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       D.lv[j].gtab = P->d_gtab[j];
     }
   }
-  // split evaluation over mu_m cosets on form A levels: m = 4 when 4 | q-1,
-  // else 3 when 3 | q-1, else 2
+  // split evaluation over mu_m cosets: m = 4 when 4 | q-1, else (form A
+  // levels only) 3 when 3 | q-1, else 2
   P->d_tup.assign(g, nullptr);
   P->d_sgl.assign(g, nullptr);
   for (uint32_t j = 0; j < g; ++j) {
     hwc::LevelDesc& L = D.lv[j];
     L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
-    if (!T.split || L.form != hwc::kFormA || L.M < T.split_min_m) continue;
+    if (!T.split || L.M < T.split_min_m) continue;
     const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
+    if (L.form != hwc::kFormA && m != 4) continue;   // forms C/D split over mu_4 only
     L.msplit = m;
     if (!orbit) {
       L.nt = L.M / m;
@@ -501,11 +502,11 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
   if (n > 0) {
     if (flags & HWC_PLAIN) {
       for (uint32_t j = 0; j < g; ++j)
-        HIPX(c, hwc::launch_count(P->desc, cb, codes, S.perm, S.tiles, S.ntiles, nullptr, j, j, nullptr, S.lv,
+        HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, nullptr, j, j, nullptr, S.lv,
                                   P->grid, P->block, P->wpe, s));
       HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
     } else {
-      HIPX(c, hwc::launch_count(P->desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N, nullptr,
+      HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N, nullptr,
                                 P->grid, P->block, P->wpe, s));
     }
   }

@@ -45,6 +45,15 @@ typedef const __attribute__((address_space(4))) uint32_t* const_u32_ptr;
 typedef const __attribute__((address_space(4))) uint64_t* const_u64_ptr;
 __device__ __forceinline__ uint32_t sload(const uint32_t* p, uint32_t i) { return ((const_u32_ptr)p)[i]; }
 __device__ __forceinline__ uint64_t sload64(const uint64_t* p, uint32_t i) { return ((const_u64_ptr)p)[i]; }
+__device__ __forceinline__ LevelDesc load_level(const PlanDesc& P, uint32_t j) {
+  static_assert(sizeof(LevelDesc) % 4 == 0, "LevelDesc is copied in dwords");
+  LevelDesc L;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&P.lv[j]);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(&L);
+#pragma unroll
+  for (uint32_t i = 0; i < sizeof(LevelDesc) / 4; ++i) dst[i] = sload(src, i);
+  return L;
+}
 
 // ----------------------------------------------------------------------------
 // utility
@@ -521,10 +530,9 @@ __device__ __forceinline__ uint32_t horner_c(uint32_t tab, const uint32_t* __res
 }
 
 template <int NC, bool GLOBAL>
-__device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t (&del)[NC],
-                                             uint32_t d, uint32_t mask, LevelCounts& c) {
-  const uint32_t M = L.M, nx = L.nx, tab = L.tab_off;
-  const uint32_t* xs = L.xs;
+__device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t* xs, uint32_t nx,
+                                             const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
+  const uint32_t M = L.M, tab = L.tab_off;
   const uint32_t* gtab = L.gtab;
   for (uint32_t ix = 0; ix < nx; ix += 2) {
     const uint32_t x0 = xs ? sload(xs, ix) : ix;
@@ -543,10 +551,178 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t 
   }
 }
 
+// Form C/D table entry r in [0, 2M): Z(r mod M) in element units, M where
+// 1 + gamma^r = 0.
+template <bool GLOBAL>
+__device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t r) {
+  return GLOBAL ? gtab[r] : lds_u16(tab + 2 * r);
+}
+
+__device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v, v - M); }  // [0, 2M) -> [0, M)
+
+// Sub-polynomial r of the split on a form C/D level (element units): as
+// horner_class, with the index folded into the table's two periods.  Not
+// EXACT: a vanishing partial sum sets hit (the caller redoes the tuple).
+template <int NC, int MS, int R, bool FULL, int D, bool EXACT, bool GLOBAL>
+__device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t* __restrict__ gtab,
+                                                   const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
+                                                   uint32_t Y, uint32_t& pend, bool& hit) {
+  uint32_t a = 0;
+  if (FULL) {
+    constexpr int TOP = D - ((D - R) % MS);
+#pragma unroll
+    for (int i = TOP - MS; i >= 0; i -= MS) {
+      const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a + sdel[i] + Y, M));   // index < 3M
+      if (EXACT) a = (a == M) ? 0u : v;
+      else { hit |= v == M; a = v; }
+    }
+    pend = 0;
+    return a;
+  }
+  uint32_t p = 0;
+  bool started = false;
+#pragma unroll
+  for (int i = NC - 1; i >= 0; --i) {
+    if (i % MS != R) continue;
+    if ((uint32_t)i > d) continue;
+    if (started) p = addmod(p, Y, M);
+    if ((sup >> i) & 1u) {
+      if (started) {
+        const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a + sdel[i] + p, M));
+        if (EXACT) a = (a == M) ? 0u : v;
+        else { hit |= v == M; a = v; }
+      }
+      started = true;
+      p = 0;
+    }
+  }
+  pend = p;
+  return a;
+}
+
+// Zero-safe sum in element units (absolute logs in [0, M) or the zero marker M).
+template <bool GLOBAL>
+__device__ __forceinline__ uint32_t zadd_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M, uint32_t u,
+                                           uint32_t v) {
+  const bool uz = u == M, vz = v == M;
+  uint32_t dd = v - u;
+  dd = min(dd, dd + M);
+  const uint32_t r = tab_c<GLOBAL>(tab, gtab, (uz || vz) ? 0u : dd);
+  const uint32_t s = fold(u + r, M);
+  return uz ? v : (vz ? u : (r == M ? M : s));
+}
+
+__device__ __forceinline__ uint32_t zmul_c(uint32_t v, uint32_t k, uint32_t M) {  // k < M
+  return v == M ? M : fold(v + k, M);
+}
+
+// Radix-2x2 split over mu_4 cosets on a form C/D level: the same stages as the
+// MS = 4 case of sweep_split_a in element units.  Without the form A zero
+// region, a vanishing top-class value is selected to relative log 0.
+template <int NC, bool FULL, int D, bool GLOBAL>
+__device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t (&sdel)[NC], uint32_t d,
+                                              uint32_t mask, const SplitConst& K, LevelCounts& c) {
+  const uint32_t M = L.M, step = M / 4, tab = L.tab_off, h = M / 2;
+  const uint32_t* gtab = L.gtab;
+  const uint32_t K1 = M + submod(K.ll[1], K.ll[0], M);
+  const uint32_t K2 = M + submod(K.ll[2], K.ll[0], M);
+  const uint32_t K3 = M + submod(K.ll[3], K.ll[1], M);
+  const uint32_t fix = (K.ll[0] ^ K.blane) & 1u;
+  const uint32_t sup = mask | (1u << d);
+  const uint32_t nt = L.nt;
+  const uint32_t* xt = L.xs_t;
+  uint32_t xnext = (xt && nt) ? sload(xt, 0) : 0u;
+  for (uint32_t it = 0; it < nt; ++it) {
+    const uint32_t x = xnext;
+    if (it + 1 < nt) xnext = xt ? sload(xt, it + 1) : it + 1;
+    const uint32_t x2 = addmod(x, x, M);
+    const uint32_t Y = addmod(x2, x2, M);
+    uint32_t p0, p1, p2, p3;
+    bool hit = false;
+    uint32_t a0 = horner_class_c<NC, 4, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+    uint32_t a1 = horner_class_c<NC, 4, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+    uint32_t a2 = horner_class_c<NC, 4, 2, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+    uint32_t a3 = horner_class_c<NC, 4, 3, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+    if (__ballot(hit)) {
+      a0 = horner_class_c<NC, 4, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+      a1 = horner_class_c<NC, 4, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      a2 = horner_class_c<NC, 4, 2, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+      a3 = horner_class_c<NC, 4, 3, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+    }
+    const uint32_t cls = FULL ? 0u : (p0 & 1u);
+    const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);
+    const uint32_t uO = addmod(addmod(x2, p3, M), p1 ? M - p1 : 0u, M);
+    const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
+    const bool base_zero = (a0 == M) || (a1 == M);
+    const uint32_t b0 = base_zero ? 0u : a0, b1 = base_zero ? 0u : a1;
+    const bool z2 = a2 == M, z3 = a3 == M;
+    const uint32_t c2 = z2 ? 0u : a2, c3 = z3 ? 0u : a3;
+    const uint32_t FE = fold(K2 - b0, M), FO = fold(K3 - b1, M);    // [0, M)
+    uint32_t Ep = tab_c<GLOBAL>(tab, gtab, fold(c2 + FE + uE, M));
+    uint32_t Em = tab_c<GLOBAL>(tab, gtab, fold(c2 + FE + addmod(uE, h, M), M));
+    uint32_t Op = tab_c<GLOBAL>(tab, gtab, fold(c3 + FO + uO, M));
+    uint32_t Om = tab_c<GLOBAL>(tab, gtab, fold(c3 + FO + addmod(uO, h, M), M));
+    // a vanishing top class leaves the base: relative log 0
+    Ep = z2 ? 0u : Ep;
+    Em = z2 ? 0u : Em;
+    Op = z3 ? 0u : Op;
+    Om = z3 ? 0u : Om;
+    uint32_t zs = 0, odd;
+    if (!__ballot(base_zero || Ep == M || Em == M)) {
+      const uint32_t G = fold(fold(b1 + K1 - b0, M), M) + M;       // [M, 2M)
+      uint32_t u = 0;
+      uint32_t r[4];
+      bool anyz = false;
+#pragma unroll
+      for (uint32_t s = 0; s < 4; ++s) {
+        const uint32_t E = (s & 1u) ? Em : Ep;
+        const uint32_t Ow = (s & 1u) ? Om : Op;
+        const bool oz = Ow == M;                      // O vanishes: f = E
+        const uint32_t F = fold(G - E, M);
+        const uint32_t rv = tab_c<GLOBAL>(tab, gtab, fold((oz ? 0u : Ow) + F + addmod(vf, s * step, M), M));
+        r[s] = oz ? 0u : rv;
+        u += (E ^ r[s]) & 1u;
+        anyz |= r[s] == M;
+      }
+      if (__ballot(anyz)) {
+        u = 0;
+#pragma unroll
+        for (uint32_t s = 0; s < 4; ++s) {
+          const uint32_t E = (s & 1u) ? Em : Ep;
+          const bool z = r[s] == M;
+          zs += z;
+          u += z ? 0u : ((E ^ r[s]) & 1u);
+        }
+      }
+      odd = ((a0 ^ fix) & 1u) ? (4 - zs) - u : u;
+    } else {
+      const uint32_t v0 = zmul_c(a0, addmod(K.ll[0], p0, M), M);
+      const uint32_t v1 = zmul_c(a1, addmod(K.ll[1], p1, M), M);
+      const uint32_t v2 = zmul_c(a2, addmod(K.ll[2], p2, M), M);
+      const uint32_t v3 = zmul_c(a3, addmod(K.ll[3], p3, M), M);
+      const uint32_t ep = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v2, x2, M));
+      const uint32_t em = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v2, addmod(x2, h, M), M));
+      const uint32_t op = zadd_c<GLOBAL>(tab, gtab, M, v1, zmul_c(v3, x2, M));
+      const uint32_t om = zadd_c<GLOBAL>(tab, gtab, M, v1, zmul_c(v3, addmod(x2, h, M), M));
+      odd = 0;
+#pragma unroll
+      for (uint32_t s = 0; s < 4; ++s) {
+        const uint32_t E = (s & 1u) ? em : ep;
+        const uint32_t O = (s & 1u) ? om : op;
+        const uint32_t f = zadd_c<GLOBAL>(tab, gtab, M, E, zmul_c(O, addmod(x, s * step, M), M));
+        const bool z = f == M;
+        zs += z;
+        odd += z ? 0u : ((f ^ K.blane ^ cls) & 1u);
+      }
+    }
+    c.add_n(cls, 4, zs, odd);
+  }
+}
+
 // Counts for one level: returns z | ns << 8 (roots and non-squares among the
 // swept x; squares are nx - z - ns).
 template <int G>
-__device__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t (&code)[2 * G + 3],
+__device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t (&code)[2 * G + 3],
                                 uint32_t top, uint32_t mask) {
   constexpr int NC = 2 * G + 3;
   // the level with its table offsets made absolute LDS addresses
@@ -578,52 +754,59 @@ __device__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t
   const uint32_t blane = prev & 1u;  // parity of log c_low
   LevelCounts c = {0, 0, 0, 0, 0};
   const bool full = mask == ((1u << d) - 1u);
-  if (L.form == kFormA) {
-    // split evaluation: needs every class to hold a term
-    const uint32_t sup = mask | (1u << d);
-    uint32_t ms = L.msplit;
-    if (ms) {
-      uint32_t cls_mask = 0;
+  // split evaluation: needs every class to hold a term (forms C/D: m = 4)
+  const uint32_t sup = mask | (1u << d);
+  uint32_t ms = L.msplit;
+  if (L.form != kFormA && ms != 4) ms = 0;
+  if (ms) {
+    uint32_t cls_mask = 0;
 #pragma unroll
-      for (int i = 0; i < NC; ++i)
-        if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 4 ? i % 4 : (ms == 3 ? i % 3 : i % 2));
-      if (cls_mask != (1u << ms) - 1u) ms = 0;
+    for (int i = 0; i < NC; ++i)
+      if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 4 ? i % 4 : (ms == 3 ? i % 3 : i % 2));
+    if (cls_mask != (1u << ms) - 1u) ms = 0;
+  }
+  // per-class relative deltas (element units) and lowest-coefficient logs
+  uint32_t sdel[NC];
+  SplitConst K;
+  K.ll[0] = K.ll[1] = K.ll[2] = K.ll[3] = 0;
+  K.blane = blane;
+#pragma unroll
+  for (int i = 0; i < NC; ++i) sdel[i] = 0;
+  if (ms) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (r >= (int)ms) break;
+      bool started = false;
+      uint32_t pv = 0;
+#pragma unroll
+      for (int i = NC - 1; i >= 0; --i) {
+        const uint32_t cl = ms == 4 ? (uint32_t)(i % 4) : (ms == 3 ? (uint32_t)(i % 3) : (uint32_t)(i % 2));
+        if (cl != (uint32_t)r || (uint32_t)i > d || !((sup >> i) & 1u)) continue;
+        if (started) {
+          uint32_t v = pv + M - lc[i];
+          v = v >= M ? v - M : v;
+          sdel[i] = v;
+        }
+        started = true;
+        pv = lc[i];
+      }
+      K.ll[r] = pv;
+    }
+  }
+  if (L.form == kFormA) {
+    // byte units plus the table offset
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      del[i] = 2 * del[i] + L.tab_off;
+      sdel[i] = 2 * sdel[i] + L.tab_off;
     }
     if (ms) {
-      // per-class relative deltas, in byte units plus the table offset
-      uint32_t sdel[NC];
-#pragma unroll
-      for (int i = 0; i < NC; ++i) sdel[i] = L.tab_off;
-      SplitConst K;
-      K.ll[0] = K.ll[1] = K.ll[2] = K.ll[3] = 0;
-      K.blane = blane;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        if (r >= (int)ms) break;
-        bool started = false;
-        uint32_t pv = 0;
-#pragma unroll
-        for (int i = NC - 1; i >= 0; --i) {
-          const uint32_t cl = ms == 4 ? (uint32_t)(i % 4) : (ms == 3 ? (uint32_t)(i % 3) : (uint32_t)(i % 2));
-          if (cl != (uint32_t)r || (uint32_t)i > d || !((sup >> i) & 1u)) continue;
-          if (started) {
-            uint32_t v = pv + M - lc[i];
-            v = v >= M ? v - M : v;
-            sdel[i] = 2 * v + L.tab_off;
-          }
-          started = true;
-          pv = lc[i];
-        }
-        K.ll[r] = pv;
-      }
-#pragma unroll
-      for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
-#define HWC_SPLIT(FULLV, DV)                                                            \
-  do {                                                                                  \
-    if (ms == 4) sweep_split_a<NC, 4, FULLV, DV>(L, sdel, del, d, mask, K, c);     \
+#define HWC_SPLIT(FULLV, DV)                                                         \
+  do {                                                                               \
+    if (ms == 4) sweep_split_a<NC, 4, FULLV, DV>(L, sdel, del, d, mask, K, c);      \
     else if (ms == 3) sweep_split_a<NC, 3, FULLV, DV>(L, sdel, del, d, mask, K, c); \
-    else sweep_split_a<NC, 2, FULLV, DV>(L, sdel, del, d, mask, K, c);             \
-    sweep_form_a<NC, FULLV, DV>(L.xs_s, L.ns, M, del, d, mask, c);                 \
+    else sweep_split_a<NC, 2, FULLV, DV>(L, sdel, del, d, mask, K, c);              \
+    sweep_form_a<NC, FULLV, DV>(L.xs_s, L.ns, M, del, d, mask, c);                  \
   } while (0)
       if (full) {
         if (top) HWC_SPLIT(true, NC - 1);
@@ -633,8 +816,6 @@ __device__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t
       }
 #undef HWC_SPLIT
     } else {
-#pragma unroll
-      for (int i = 0; i < NC; ++i) del[i] = 2 * del[i] + L.tab_off;
       if (full) {
         if (top) sweep_form_a<NC, true, NC - 1>(L.xs, L.nx, M, del, d, mask, c);
         else sweep_form_a<NC, true, NC - 2>(L.xs, L.nx, M, del, d, mask, c);
@@ -642,10 +823,24 @@ __device__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t
         sweep_form_a<NC, false, 0>(L.xs, L.nx, M, del, d, mask, c);
       }
     }
-  } else if (L.form == kFormC) {
-    sweep_form_c<NC, false>(L, del, d, mask, c);
   } else {
-    sweep_form_c<NC, true>(L, del, d, mask, c);
+#define HWC_FORM_C(GL)                                                                   \
+  do {                                                                                   \
+    if (ms) {                                                                            \
+      if (full) {                                                                        \
+        if (top) sweep_split_c<NC, true, NC - 1, GL>(L, sdel, d, mask, K, c);            \
+        else sweep_split_c<NC, true, NC - 2, GL>(L, sdel, d, mask, K, c);                \
+      } else {                                                                           \
+        sweep_split_c<NC, false, 0, GL>(L, sdel, d, mask, K, c);                         \
+      }                                                                                  \
+      sweep_form_c<NC, GL>(L, L.xs_s, L.ns, del, d, mask, c);                            \
+    } else {                                                                             \
+      sweep_form_c<NC, GL>(L, L.xs, L.nx, del, d, mask, c);                              \
+    }                                                                                    \
+  } while (0)
+    if (L.form == kFormC) HWC_FORM_C(false);
+    else HWC_FORM_C(true);
+#undef HWC_FORM_C
   }
   const uint32_t n0 = L.nx - c.n1;
   const uint32_t z = c.zt;
@@ -709,12 +904,18 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, con
   }
   const uint32_t top = (pat >> (NC - 1)) & 1u;
   const uint32_t mask = pat & ((1u << (NC - 1)) - 1u);
+  // levels one after another (one inlined copy of the level code); the
+  // level descriptor comes in through scalar loads
   uint32_t lv[G];
 #pragma unroll
-  for (int j = 0; j < G; ++j) {
-    lv[j] = 0;
-    if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) lv[j] = count_level<G>(P.lv[j], lb, code, top, mask);
+  for (int j = 0; j < G; ++j) lv[j] = 0;
+#pragma unroll 1
+  for (uint32_t j = lvl_lo; j <= lvl_hi; ++j) {
+    const uint32_t v = count_level<G>(load_level(P, j), lb, code, top, mask);
+#pragma unroll
+    for (int k = 0; k < G; ++k) lv[k] = (uint32_t)k == j ? v : lv[k];
   }
+
   if (outN) {
     const uint32_t log0 = lds_u32(lb + P.lv[0].emb_off + 4 * code[0]);
     const uint32_t logt = lds_u32(lb + P.lv[0].emb_off + 4 * code[NC - 1]);
@@ -733,12 +934,13 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, con
 
 // WPE: minimum waves per SIMD the register allocation must allow (1: free)
 template <int G, typename CT, int WPE>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) void count_kernel(PlanDesc P, const CT* __restrict__ codes,
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) void count_kernel(const PlanDesc* __restrict__ Pd, const CT* __restrict__ codes,
                                                      const uint32_t* __restrict__ perm,
                                                      const uint64_t* __restrict__ tiles,
                                                      const uint32_t* __restrict__ ntiles_p, uint32_t* queue,
                                                      uint32_t lvl_lo, uint32_t lvl_hi, int32_t* __restrict__ outN,
                                                      uint32_t* __restrict__ outLv) {
+  const PlanDesc& P = *Pd;
   extern __shared__ uint32_t lds32[];
   const uint32_t lb = lds_base(lds32);
   for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
@@ -897,10 +1099,10 @@ __global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __r
 // host-callable launchers (C++ linkage, used by capi.cpp)
 
 template <int G, typename CT, int WPE>
-static hipError_t launch_count_t(const PlanDesc& P, const void* codes, const uint32_t* perm, const uint64_t* tiles,
+static hipError_t launch_count_t(const PlanDesc& P, const PlanDesc* dP, const void* codes, const uint32_t* perm, const uint64_t* tiles,
                                  const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi, int32_t* outN,
                                  uint32_t* outLv, uint32_t grid, uint32_t block, hipStream_t s) {
-  hipLaunchKernelGGL((count_kernel<G, CT, WPE>), dim3(grid), dim3(block), P.image_bytes, s, P,
+  hipLaunchKernelGGL((count_kernel<G, CT, WPE>), dim3(grid), dim3(block), P.image_bytes, s, dP,
                      static_cast<const CT*>(codes), perm, tiles, ntiles, queue, lo, hi, outN, outLv);
   return hipGetLastError();
 }
@@ -931,22 +1133,22 @@ hipError_t prepare_kernels() {
 }
 
 template <int G, typename CT>
-static hipError_t launch_count_w(const PlanDesc& P, const void* codes, const uint32_t* perm, const uint64_t* tiles,
+static hipError_t launch_count_w(const PlanDesc& P, const PlanDesc* dP, const void* codes, const uint32_t* perm, const uint64_t* tiles,
                                  const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi, int32_t* outN,
                                  uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s) {
-  if (wpe >= 8) return launch_count_t<G, CT, 8>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
-  if (wpe >= 6) return launch_count_t<G, CT, 6>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
-  return launch_count_t<G, CT, 1>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+  if (wpe >= 8) return launch_count_t<G, CT, 8>(P, dP, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+  if (wpe >= 6) return launch_count_t<G, CT, 6>(P, dP, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
+  return launch_count_t<G, CT, 1>(P, dP, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, grid, block, s);
 }
 
-hipError_t launch_count(const PlanDesc& P, int coeff_bytes, const void* codes, const uint32_t* perm,
+hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
                         int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s) {
 #define HWC_CASE(GG)                                                                                           \
   case GG:                                                                                                     \
-    return coeff_bytes == 1 ? launch_count_w<GG, int8_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN,  \
+    return coeff_bytes == 1 ? launch_count_w<GG, int8_t>(P, dP, codes, perm, tiles, ntiles, queue, lo, hi, outN,  \
                                                          outLv, grid, block, wpe, s)                          \
-                            : launch_count_w<GG, int16_t>(P, codes, perm, tiles, ntiles, queue, lo, hi, outN, \
+                            : launch_count_w<GG, int16_t>(P, dP, codes, perm, tiles, ntiles, queue, lo, hi, outN, \
                                                           outLv, grid, block, wpe, s);
   switch (P.g) {
     HWC_CASE(1)
