@@ -256,7 +256,7 @@ def main():
     if not args.no_cpu:
         import oracle
         threads = min(os.cpu_count() or 1, 16)
-        sample = 1 << 17
+        sample = 1 << 18
         t0 = time.perf_counter()
         ref = oracle.count_curves(q, g, curves[:sample], threads=threads)
         dt = time.perf_counter() - t0

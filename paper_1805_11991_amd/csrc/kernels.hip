@@ -235,6 +235,30 @@ __device__ __forceinline__ uint32_t horner_a(const uint32_t (&del)[NC], uint32_t
   return a;
 }
 
+// horner_a for two x at once: both chains advance inside one (uniform)
+// branch per position, so their reads overlap.
+template <int NC>
+__device__ __forceinline__ void horner_a2(const uint32_t (&del)[NC], uint32_t M, uint32_t d, uint32_t mask,
+                                          uint32_t x0, uint32_t x1, uint32_t& a0, uint32_t& a1, uint32_t& pend0,
+                                          uint32_t& pend1) {
+  uint32_t p0 = 0, p1 = 0;
+  a0 = a1 = 0;
+#pragma unroll
+  for (int i = NC - 2; i >= 0; --i) {
+    if ((uint32_t)i < d) {
+      p0 += x0; p0 = p0 >= M ? p0 - M : p0;
+      p1 += x1; p1 = p1 >= M ? p1 - M : p1;
+      if ((mask >> i) & 1u) {
+        a0 = lds_u16(a0 + del[i] + 2 * p0);
+        a1 = lds_u16(a1 + del[i] + 2 * p1);
+        p0 = p1 = 0;
+      }
+    }
+  }
+  pend0 = p0;
+  pend1 = p1;
+}
+
 template <int NC, bool FULL, int D>
 __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, uint32_t M,
                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
@@ -261,9 +285,8 @@ __device__ __forceinline__ void sweep_form_a(const uint32_t* xs, uint32_t nx, ui
       c.zt += (a0 == S) + (a1 == S);
       c.ot += ((a0 >> 1) & 1u) + ((a1 >> 1) & 1u);
     } else {
-      uint32_t p0, p1;
-      const uint32_t a0 = horner_a<NC>(del, M, d, mask, x0, p0);
-      const uint32_t a1 = horner_a<NC>(del, M, d, mask, x1, p1);
+      uint32_t p0, p1, a0, a1;
+      horner_a2<NC>(del, M, d, mask, x0, x1, a0, a1, p0, p1);
       c.add(p0 & 1u, a0 == S, (a0 >> 1) & 1u);
       c.add(p1 & 1u, a1 == S, (a1 >> 1) & 1u);
     }
@@ -311,6 +334,35 @@ __device__ __forceinline__ uint32_t horner_class(const uint32_t (&sdel)[NC], uin
   }
   pend = p;
   return a;
+}
+
+// The MS sub-polynomials of a sparse row (form A) in one pass over the
+// positions from the top: every position issues its read (a position without
+// a term, or the top term of its class, reads an in-bounds entry that is then
+// discarded), so the classes' reads overlap in straight-line code.
+template <int NC, int MS>
+__device__ __forceinline__ void horner_classes_a(const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
+                                                 uint32_t Y, uint32_t (&a)[4], uint32_t (&pend)[4]) {
+  uint32_t p[4] = {0, 0, 0, 0};
+  bool st[4] = {false, false, false, false};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = 0;
+#pragma unroll
+  for (int i = NC - 1; i >= 0; --i) {
+    const int r = i % MS;
+    if ((uint32_t)i > d) continue;
+    const bool present = (sup >> i) & 1u;
+    if (st[r]) p[r] = addmod(p[r], Y, M);
+    const bool go = present && st[r];
+    const uint32_t v = lds_u16(a[r] + sdel[i] + (go ? 2 * p[r] : 0u));
+    a[r] = go ? v : a[r];
+    if (present) {
+      st[r] = true;
+      p[r] = 0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) pend[r] = p[r];
 }
 
 // Per-curve constants of the split on one level: ll[r] = log of the lowest
@@ -379,11 +431,19 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t
 #pragma unroll
     for (int m = 0; m < MS; ++m) Y = addmod(Y, x, M);
     uint32_t p0, p1, p2 = 0, p3 = 0;
-    const uint32_t a0 = horner_class<NC, MS, 0, FULL, D>(sdel, M, d, sup, Y, p0);
-    const uint32_t a1 = horner_class<NC, MS, 1, FULL, D>(sdel, M, d, sup, Y, p1);
-    uint32_t a2 = S, a3 = S;
-    if (MS >= 3) a2 = horner_class<NC, MS, 2, FULL, D>(sdel, M, d, sup, Y, p2);
-    if (MS == 4) a3 = horner_class<NC, MS, 3, FULL, D>(sdel, M, d, sup, Y, p3);
+    uint32_t a0, a1, a2 = S, a3 = S;
+    if (FULL) {
+      a0 = horner_class<NC, MS, 0, FULL, D>(sdel, M, d, sup, Y, p0);
+      a1 = horner_class<NC, MS, 1, FULL, D>(sdel, M, d, sup, Y, p1);
+      if (MS >= 3) a2 = horner_class<NC, MS, 2, FULL, D>(sdel, M, d, sup, Y, p2);
+      if (MS == 4) a3 = horner_class<NC, MS, 3, FULL, D>(sdel, M, d, sup, Y, p3);
+    } else {
+      uint32_t av[4], pv[4];
+      horner_classes_a<NC, MS>(sdel, M, d, sup, Y, av, pv);
+      a0 = av[0]; a1 = av[1]; p0 = pv[0]; p1 = pv[1];
+      if (MS >= 3) { a2 = av[2]; p2 = pv[2]; }
+      if (MS == 4) { a3 = av[3]; p3 = pv[3]; }
+    }
     const uint32_t cls = FULL ? 0u : (p0 & 1u);  // parity of t_0 Y
     if (MS == 4) {
       const uint32_t x2 = addmod(x, x, M), h = M / 2;
@@ -506,27 +566,41 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t
   }
 }
 
+// Form C/D relative Horner for two x at once (element units, index folded
+// into the table's two periods; reads of both chains inside one uniform
+// branch per position).  Not EXACT: a vanishing partial sum sets hit and the
+// caller redoes the pair with EXACT, which restarts from the coefficient.
 template <int NC, bool EXACT, bool GLOBAL>
-__device__ __forceinline__ uint32_t horner_c(uint32_t tab, const uint32_t* __restrict__ gtab,
-                                             uint32_t M, const uint32_t (&del)[NC], uint32_t d, uint32_t mask,
-                                             uint32_t x, uint32_t& pend, bool& hit) {
-  uint32_t a = 0, p = 0;
+__device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M,
+                                          const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t x0,
+                                          uint32_t x1, uint32_t& a0, uint32_t& a1, uint32_t& pend0, uint32_t& pend1,
+                                          bool& hit) {
+  uint32_t p0 = 0, p1 = 0;
+  a0 = a1 = 0;
 #pragma unroll
   for (int i = NC - 2; i >= 0; --i) {
     if ((uint32_t)i < d) {
-      p += x; p = p >= M ? p - M : p;
+      p0 += x0; p0 = p0 >= M ? p0 - M : p0;
+      p1 += x1; p1 = p1 >= M ? p1 - M : p1;
       if ((mask >> i) & 1u) {
-        const uint32_t idx = a + del[i] + p;           // < 3M
-        const uint32_t r = min(idx, idx - M);          // < 2M
-        const uint32_t v = GLOBAL ? gtab[r] : lds_u16(tab + 2 * r);
-        if (EXACT) a = (a == M) ? 0u : v;
-        else { hit |= (v == M); a = v; }
-        p = 0;
+        const uint32_t r0 = min(a0 + del[i] + p0, a0 + del[i] + p0 - M);   // < 2M
+        const uint32_t r1 = min(a1 + del[i] + p1, a1 + del[i] + p1 - M);
+        const uint32_t v0 = GLOBAL ? gtab[r0] : lds_u16(tab + 2 * r0);
+        const uint32_t v1 = GLOBAL ? gtab[r1] : lds_u16(tab + 2 * r1);
+        if (EXACT) {
+          a0 = (a0 == M) ? 0u : v0;
+          a1 = (a1 == M) ? 0u : v1;
+        } else {
+          hit |= (v0 == M) | (v1 == M);
+          a0 = v0;
+          a1 = v1;
+        }
+        p0 = p1 = 0;
       }
     }
   }
-  pend = p;
-  return a;
+  pend0 = p0;
+  pend1 = p1;
 }
 
 template <int NC, bool GLOBAL>
@@ -539,13 +613,9 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t*
     const bool two = ix + 1 < nx;
     const uint32_t x1 = two ? (xs ? sload(xs, ix + 1) : ix + 1) : x0;
     bool hit = false;
-    uint32_t p0, p1;
-    uint32_t a0 = horner_c<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x0, p0, hit);
-    uint32_t a1 = horner_c<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x1, p1, hit);
-    if (__ballot(hit)) {
-      a0 = horner_c<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x0, p0, hit);
-      a1 = horner_c<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x1, p1, hit);
-    }
+    uint32_t p0, p1, a0, a1;
+    horner_c2<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x0, x1, a0, a1, p0, p1, hit);
+    if (__ballot(hit)) horner_c2<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x0, x1, a0, a1, p0, p1, hit);
     c.add(p0 & 1u, a0 == M, a0 & 1u);   // M is even: the marker counts as even
     if (two) c.add(p1 & 1u, a1 == M, a1 & 1u);
   }
@@ -600,6 +670,38 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
   return a;
 }
 
+// The four sub-polynomials of a sparse row on a form C/D level in one pass
+// (as horner_classes_a); not EXACT: a vanishing partial sum sets hit.
+template <int NC, bool EXACT, bool GLOBAL>
+__device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* __restrict__ gtab,
+                                                 const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
+                                                 uint32_t Y, uint32_t (&a)[4], uint32_t (&pend)[4], bool& hit) {
+  uint32_t p[4] = {0, 0, 0, 0};
+  bool st[4] = {false, false, false, false};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) a[r] = 0;
+#pragma unroll
+  for (int i = NC - 1; i >= 0; --i) {
+    const int r = i % 4;
+    if ((uint32_t)i > d) continue;
+    const bool present = (sup >> i) & 1u;
+    if (st[r]) p[r] = addmod(p[r], Y, M);
+    const bool go = present && st[r];
+    const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a[r] + sdel[i] + (go ? p[r] : 0u), M));
+    if (EXACT) a[r] = go ? ((a[r] == M) ? 0u : v) : a[r];
+    else {
+      hit |= go && v == M;
+      a[r] = go ? v : a[r];
+    }
+    if (present) {
+      st[r] = true;
+      p[r] = 0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) pend[r] = p[r];
+}
+
 // Zero-safe sum in element units (absolute logs in [0, M) or the zero marker M).
 template <bool GLOBAL>
 __device__ __forceinline__ uint32_t zadd_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M, uint32_t u,
@@ -638,16 +740,25 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
     const uint32_t x2 = addmod(x, x, M);
     const uint32_t Y = addmod(x2, x2, M);
     uint32_t p0, p1, p2, p3;
+    uint32_t a0, a1, a2, a3;
     bool hit = false;
-    uint32_t a0 = horner_class_c<NC, 4, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-    uint32_t a1 = horner_class_c<NC, 4, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
-    uint32_t a2 = horner_class_c<NC, 4, 2, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
-    uint32_t a3 = horner_class_c<NC, 4, 3, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
-    if (__ballot(hit)) {
-      a0 = horner_class_c<NC, 4, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-      a1 = horner_class_c<NC, 4, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
-      a2 = horner_class_c<NC, 4, 2, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
-      a3 = horner_class_c<NC, 4, 3, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+    if (FULL) {
+      a0 = horner_class_c<NC, 4, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+      a1 = horner_class_c<NC, 4, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      a2 = horner_class_c<NC, 4, 2, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+      a3 = horner_class_c<NC, 4, 3, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+      if (__ballot(hit)) {
+        a0 = horner_class_c<NC, 4, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+        a1 = horner_class_c<NC, 4, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+        a2 = horner_class_c<NC, 4, 2, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+        a3 = horner_class_c<NC, 4, 3, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+      }
+    } else {
+      uint32_t av[4], pv[4];
+      horner_classes_c<NC, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      if (__ballot(hit)) horner_classes_c<NC, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      a0 = av[0]; a1 = av[1]; a2 = av[2]; a3 = av[3];
+      p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3];
     }
     const uint32_t cls = FULL ? 0u : (p0 & 1u);
     const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);

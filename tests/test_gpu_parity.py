@@ -343,3 +343,100 @@ def test_tuning_options_keep_results(gctx, oracle_mod, curvegen_mod, q, g, n, op
         _check(ctx, oracle_mod, q, g, curves, modes={"batched-orbit": 0, "batched-full": 1, "plain-orbit": 2})
     finally:
         ctx.close()
+
+
+def test_full_size_g4_q13_sampled(gctx, oracle_mod, curvegen_mod):
+    """The 2^26-curve g=4 set over F_13 in the benchmark's launch form,
+    checked on a seeded sample of rows, plus histogram invariants."""
+    import torch
+    n = 1 << 26
+    curves = curvegen_mod.sample(13, 4, n, seed=curvegen_mod.BASE_SEED + 3)
+    d = torch.from_numpy(curves).cuda()
+    N = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    hk = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+    hc = torch.empty(n, dtype=torch.int64, device="cuda")
+    hl = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gctx.count_curves_dev(13, 4, d, N, hk, hc, hl)
+    gctx.status()
+    Nh = N.cpu().numpy()
+    rng = np.random.default_rng(4096)
+    idx = np.unique(np.concatenate([rng.integers(0, n, 300), [0, n - 1]]))
+    ref = oracle_mod.count_curves(13, 4, curves[idx])
+    assert np.array_equal(Nh[idx], ref)
+    L = int(hl.item())
+    cnt = hc[:L].cpu().numpy()
+    assert int(cnt.sum()) == n
+    keys = hk[:L].cpu().numpy().astype(np.int64)
+    # strictly increasing tuples (lexicographic)
+    d01 = np.diff(keys, axis=0)
+    first = np.argmax(d01 != 0, axis=1)
+    assert (d01[np.arange(len(d01)), first] > 0).all()
+
+
+def _odd_prime_powers_below(bound):
+    out = []
+    for q in range(3, bound, 2):
+        p = next(f for f in range(3, q + 1, 2) if q % f == 0)
+        r = q
+        while r % p == 0:
+            r //= p
+        if r == 1:
+            out.append(q)
+    return out
+
+
+def test_batch_all_fields_below_300_g2_sampled(gctx, oracle_mod, curvegen_mod):
+    """All 71 odd prime powers q < 300 at g = 2, 2^16 curves each, in one
+    multi-plan persistent launch (tables in LDS for small q, in device memory
+    beyond 2^15 elements); sampled rows against the oracle, every job's
+    histogram total and order."""
+    import torch
+    qs = _odd_prime_powers_below(300)
+    assert len(qs) == 71
+    n = 1 << 16
+    jobs, sets = [], []
+    for q in qs:
+        c = curvegen_mod.sample(q, 2, n, seed=curvegen_mod.BASE_SEED + 2 + q)
+        sets.append(c)
+        jobs.append(dict(q=q, g=2, d_coeffs=torch.from_numpy(c).cuda(),
+                         d_out_N=torch.empty((n, 2), dtype=torch.int32, device="cuda"),
+                         d_hist_keys=torch.empty((n, 2), dtype=torch.int32, device="cuda"),
+                         d_hist_counts=torch.empty(n, dtype=torch.int64, device="cuda"),
+                         d_hist_len=torch.zeros(1, dtype=torch.int64, device="cuda")))
+    gctx.count_batch(jobs)
+    gctx.status()
+    rng = np.random.default_rng(300)
+    for q, c, j in zip(qs, sets, jobs):
+        N = j["d_out_N"].cpu().numpy()
+        idx = np.unique(np.concatenate([rng.integers(0, n, 12), [n - 1]]))
+        assert np.array_equal(N[idx], oracle_mod.count_curves(q, 2, c[idx])), q
+        L = int(j["d_hist_len"].item())
+        k, cnt = _hist_np(N)
+        assert L == len(k), q
+        assert np.array_equal(j["d_hist_keys"][:L].cpu().numpy(), k), q
+        assert np.array_equal(j["d_hist_counts"][:L].cpu().numpy().astype(np.uint64), cnt), q
+
+
+def test_batch_g4_small_fields_sampled(gctx, oracle_mod, curvegen_mod):
+    """g = 4 over q in {3, 5, 7, 9, 11, 13} in one launch: q = 3 fully
+    enumerated (104 976 curves, all checked), the others 2^18 curves each,
+    sampled."""
+    import torch
+    specs = [(3, curvegen_mod.enumerate_all(3, 4))]
+    for q in (5, 7, 9, 11, 13):
+        specs.append((q, curvegen_mod.sample(q, 4, 1 << 18, seed=curvegen_mod.BASE_SEED + 3 + q)))
+    jobs = []
+    for q, c in specs:
+        n = len(c)
+        jobs.append(dict(q=q, g=4, d_coeffs=torch.from_numpy(c).cuda(),
+                         d_out_N=torch.empty((n, 4), dtype=torch.int32, device="cuda")))
+    gctx.count_batch(jobs)
+    gctx.status()
+    rng = np.random.default_rng(15)
+    for (q, c), j in zip(specs, jobs):
+        N = j["d_out_N"].cpu().numpy()
+        if q == 3:
+            assert np.array_equal(N, oracle_mod.count_curves(3, 4, c))
+        else:
+            idx = np.unique(np.concatenate([rng.integers(0, len(c), 40), [len(c) - 1]]))
+            assert np.array_equal(N[idx], oracle_mod.count_curves(q, 4, c[idx])), q
