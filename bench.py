@@ -222,6 +222,17 @@ def main():
             extra[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n / (m * 1e-3), 1)}
             log(f"g3 q13 {name}: {m:.3f} ms/step")
         extra["batched_vs_plain"] = round(extra["plain_orbit"]["ms_per_step"] / ms, 3)
+        # host buffers through the synchronous entry point: PCIe copies of the
+        # codes, N and the histogram included (never the headline value)
+        Nh = None
+        curves16 = curves.astype(np.int16)          # the host entry point takes int16 codes
+        t0 = time.perf_counter()
+        for _ in range(2):
+            Nh, _hist = ctx.count_curves(q, g, curves16, hist_capacity=n)
+        mh = (time.perf_counter() - t0) / 2 * 1e3
+        assert np.array_equal(Nh, Nref), "host-buffer path differs"
+        extra["host_buffers"] = {"ms_per_step": round(mh, 3), "curves_per_s": round(n / (mh * 1e-3), 1)}
+        log(f"g3 q13 host buffers (PCIe included): {mh:.3f} ms/step")
         del bufs
         torch.cuda.empty_cache()
         # ---------------- g = 4, q = 13, 2^26 curves ----------------
