@@ -764,34 +764,29 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
     const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);
     const uint32_t uO = addmod(addmod(x2, p3, M), p1 ? M - p1 : 0u, M);
     const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
-    const bool base_zero = (a0 == M) || (a1 == M);
-    const uint32_t b0 = base_zero ? 0u : a0, b1 = base_zero ? 0u : a1;
-    const bool z2 = a2 == M, z3 = a3 == M;
-    const uint32_t c2 = z2 ? 0u : a2, c3 = z3 ? 0u : a3;
-    const uint32_t FE = fold(K2 - b0, M), FO = fold(K3 - b1, M);    // [0, M)
-    uint32_t Ep = tab_c<GLOBAL>(tab, gtab, fold(c2 + FE + uE, M));
-    uint32_t Em = tab_c<GLOBAL>(tab, gtab, fold(c2 + FE + addmod(uE, h, M), M));
-    uint32_t Op = tab_c<GLOBAL>(tab, gtab, fold(c3 + FO + uO, M));
-    uint32_t Om = tab_c<GLOBAL>(tab, gtab, fold(c3 + FO + addmod(uO, h, M), M));
-    // a vanishing top class leaves the base: relative log 0
-    Ep = z2 ? 0u : Ep;
-    Em = z2 ? 0u : Em;
-    Op = z3 ? 0u : Op;
-    Om = z3 ? 0u : Om;
+    // Every index below stays under 3M whatever the marker values (a_r <= M,
+    // folded offsets < M), so no clamps are needed.  Any vanishing
+    // sub-polynomial, E or O value sends the wave through the zero-safe
+    // recomputation, which keeps the common path free of selects.
+    const bool rare = (a0 == M) | (a1 == M) | (a2 == M) | (a3 == M);
+    const uint32_t FE = fold(K2 - a0, M), FO = fold(K3 - a1, M);    // [0, M)
+    const uint32_t Ep = tab_c<GLOBAL>(tab, gtab, fold(a2 + FE + uE, M));
+    const uint32_t Em = tab_c<GLOBAL>(tab, gtab, fold(a2 + FE + addmod(uE, h, M), M));
+    const uint32_t Op = tab_c<GLOBAL>(tab, gtab, fold(a3 + FO + uO, M));
+    const uint32_t Om = tab_c<GLOBAL>(tab, gtab, fold(a3 + FO + addmod(uO, h, M), M));
     uint32_t zs = 0, odd;
-    if (!__ballot(base_zero || Ep == M || Em == M)) {
-      const uint32_t G = fold(fold(b1 + K1 - b0, M), M) + M;       // [M, 2M)
+    if (!__ballot(rare | (Ep == M) | (Em == M) | (Op == M) | (Om == M))) {
+      const uint32_t G = fold(fold(a1 + K1 - a0, M), M) + M;       // [M, 2M)
+      const uint32_t Fp = fold(G - Ep, M), Fm = fold(G - Em, M);
       uint32_t u = 0;
       uint32_t r[4];
       bool anyz = false;
 #pragma unroll
       for (uint32_t s = 0; s < 4; ++s) {
         const uint32_t E = (s & 1u) ? Em : Ep;
-        const uint32_t Ow = (s & 1u) ? Om : Op;
-        const bool oz = Ow == M;                      // O vanishes: f = E
-        const uint32_t F = fold(G - E, M);
-        const uint32_t rv = tab_c<GLOBAL>(tab, gtab, fold((oz ? 0u : Ow) + F + addmod(vf, s * step, M), M));
-        r[s] = oz ? 0u : rv;
+        const uint32_t O = (s & 1u) ? Om : Op;
+        const uint32_t F = (s & 1u) ? Fm : Fp;
+        r[s] = tab_c<GLOBAL>(tab, gtab, fold(O + F + addmod(vf, s * step, M), M));
         u += (E ^ r[s]) & 1u;
         anyz |= r[s] == M;
       }
