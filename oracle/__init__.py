@@ -48,6 +48,9 @@ def _load():
     lib.orc_square_table.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
     lib.orc_field_mul.restype = ctypes.c_int64
     lib.orc_field_mul.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int64, ctypes.c_int64]
+    lib.orc_factor_degrees.restype = ctypes.c_int
+    lib.orc_factor_degrees.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_void_p, ctypes.c_int]
     lib.orc_histogram.restype = ctypes.c_int64
     lib.orc_histogram.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64]
@@ -70,6 +73,25 @@ def count_curves(q: int, g: int, codes, kmax: int | None = None, threads: int | 
         threads = min(os.cpu_count() or 1, 16)
     variant = (1 if modulus_last else 0) | (2 if root_last else 0)
     rc = lib.orc_count_curves(q, g, kmax, c.ctypes.data, n, out.ctypes.data, threads, variant)
+    if rc != 0:
+        raise ValueError(f"oracle rejected input (code {rc})")
+    return out
+
+
+def factor_degrees(q: int, g: int, codes, threads: int | None = None) -> np.ndarray:
+    """lambda(f) of every row (Sec. 1.1): uint8 [n, 2g+2], entry j-1 = number of
+    irreducible factors of degree j over F_q, with the extra part 1 of an odd
+    degree row counted in column 0.  Distinct-degree factorization in plain
+    polynomial arithmetic."""
+    lib = _load()
+    c = np.ascontiguousarray(np.asarray(codes), dtype=np.int16)
+    if c.ndim != 2 or c.shape[1] != 2 * g + 3:
+        raise ValueError(f"codes must be [n, {2 * g + 3}]")
+    n = c.shape[0]
+    out = np.zeros((n, 2 * g + 2), dtype=np.uint8)
+    if threads is None:
+        threads = min(os.cpu_count() or 1, 16)
+    rc = lib.orc_factor_degrees(q, g, c.ctypes.data, n, out.ctypes.data, threads)
     if rc != 0:
         raise ValueError(f"oracle rejected input (code {rc})")
     return out

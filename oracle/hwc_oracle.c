@@ -38,11 +38,17 @@
  *     counts, since two roots differ by a Frobenius automorphism.
  * Coefficient rows are a_0 .. a_{2g+2}, constant term first.
  *
+ * It also returns the factorization partition lambda(f) of eq. (1.2) by
+ * distinct-degree factorization (see orc_factor_degrees below).
+ *
  * Parity pins (tests/test_oracle_pins.py): brute-force pair counting on
  * tiny fields, the Weil bound, the quadratic twist in its corrected form,
  * the L-polynomial prediction of N_{g+1}, L(1) > 0, a closed form for
  * x^{2g+1} + c, invariance under X -> aX + b, f -> s^2 f and coefficient
- * reversal, and independence of the modulus and of the root.
+ * reversal, and independence of the modulus and of the root.  Pins of
+ * lambda (tests/test_oracle_lambda_pins.py): trial division by every monic
+ * polynomial of small degree in table-built field models, and Gauss's count
+ * of irreducible polynomials over full enumerations.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -409,4 +415,225 @@ int64_t orc_histogram(const int32_t *N, int64_t ncurves, int width, int32_t *key
   }
   free(idx);
   return distinct;
+}
+
+/* ---------- factorization partition lambda(f) (Sec. 1.1, eq. 1.2) ----------
+ *
+ * lambda(f) is the partition of 2g+2 given by the degrees of the irreducible
+ * factors of f over F_q, with an extra part 1 when deg f = 2g+1.  The oracle
+ * finds it by distinct-degree factorization (the textbook algorithm: the
+ * product of the monic irreducible factors of degree k of a square-free
+ * monic h is gcd(h, X^{q^k} - X) once all factors of smaller degree have
+ * been divided out), with plain polynomial arithmetic over F_q: coefficients
+ * are digit vectors of F_p[t]/(P_q) (the code convention above), products
+ * are schoolbook, inverses are a^{q-2}.
+ */
+
+#define ORC_MAXDEG 40                     /* > 2 * (2g+2) for g <= 8 */
+
+typedef struct {
+  orc_field F;                            /* F_q */
+  int64_t q;
+} orc_fq;
+
+typedef struct {
+  int deg;                                /* -1 for the zero polynomial */
+  int c[ORC_MAXDEG + 1][ORC_MAXN];
+} orc_poly;
+
+static void fq_set(const orc_fq *K, int *a, int64_t code) {
+  memset(a, 0, sizeof(int) * ORC_MAXN);
+  orc_unpack(&K->F, code, a);
+}
+
+static void fq_sub(const orc_fq *K, const int *a, const int *b, int *out) {
+  for (int i = 0; i < K->F.n; ++i) {
+    int s = a[i] - b[i];
+    out[i] = s < 0 ? s + K->F.p : s;
+  }
+}
+
+static void fq_pow(const orc_fq *K, const int *a, int64_t e, int *out) {
+  int base[ORC_MAXN], acc[ORC_MAXN], tmp[ORC_MAXN];
+  memcpy(base, a, sizeof(base));
+  memset(acc, 0, sizeof(acc));
+  acc[0] = 1;
+  while (e > 0) {
+    if (e & 1) { orc_mul(&K->F, acc, base, tmp); memcpy(acc, tmp, sizeof(acc)); }
+    orc_mul(&K->F, base, base, tmp);
+    memcpy(base, tmp, sizeof(base));
+    e >>= 1;
+  }
+  memcpy(out, acc, sizeof(acc));
+}
+
+static void fq_inv(const orc_fq *K, const int *a, int *out) { fq_pow(K, a, K->q - 2, out); }
+
+static void poly_trim(const orc_fq *K, orc_poly *a) {
+  while (a->deg >= 0 && orc_is_zero(&K->F, a->c[a->deg])) --a->deg;
+}
+
+static void poly_zero(orc_poly *a) { memset(a, 0, sizeof(*a)); a->deg = -1; }
+
+/* a <- a mod b (b != 0) */
+static void poly_mod(const orc_fq *K, orc_poly *a, const orc_poly *b) {
+  int inv[ORC_MAXN], f[ORC_MAXN], t[ORC_MAXN];
+  fq_inv(K, b->c[b->deg], inv);
+  poly_trim(K, a);
+  while (a->deg >= b->deg) {
+    int s = a->deg - b->deg;
+    orc_mul(&K->F, a->c[a->deg], inv, f);
+    for (int i = 0; i <= b->deg; ++i) {
+      orc_mul(&K->F, f, b->c[i], t);
+      fq_sub(K, a->c[s + i], t, a->c[s + i]);
+    }
+    poly_trim(K, a);
+  }
+}
+
+/* out <- a * b mod m */
+static void poly_mulmod(const orc_fq *K, const orc_poly *a, const orc_poly *b, const orc_poly *m, orc_poly *out) {
+  orc_poly r;
+  poly_zero(&r);
+  int t[ORC_MAXN];
+  if (a->deg >= 0 && b->deg >= 0) {
+    r.deg = a->deg + b->deg;
+    for (int i = 0; i <= a->deg; ++i)
+      for (int j = 0; j <= b->deg; ++j) {
+        orc_mul(&K->F, a->c[i], b->c[j], t);
+        orc_add(&K->F, r.c[i + j], t, r.c[i + j]);
+      }
+  }
+  poly_mod(K, &r, m);
+  *out = r;
+}
+
+static void poly_gcd(const orc_fq *K, const orc_poly *a0, const orc_poly *b0, orc_poly *out) {
+  orc_poly a = *a0, b = *b0;
+  poly_trim(K, &a);
+  poly_trim(K, &b);
+  while (b.deg >= 0) {
+    poly_mod(K, &a, &b);
+    orc_poly t = a; a = b; b = t;
+  }
+  *out = a;
+}
+
+/* a <- a / b exactly (b divides a) */
+static void poly_divexact(const orc_fq *K, orc_poly *a, const orc_poly *b) {
+  orc_poly qt;
+  poly_zero(&qt);
+  int inv[ORC_MAXN], f[ORC_MAXN], t[ORC_MAXN];
+  fq_inv(K, b->c[b->deg], inv);
+  poly_trim(K, a);
+  qt.deg = a->deg - b->deg;
+  while (a->deg >= b->deg && a->deg >= 0) {
+    int s = a->deg - b->deg;
+    orc_mul(&K->F, a->c[a->deg], inv, f);
+    memcpy(qt.c[s], f, sizeof(f));
+    for (int i = 0; i <= b->deg; ++i) {
+      orc_mul(&K->F, f, b->c[i], t);
+      fq_sub(K, a->c[s + i], t, a->c[s + i]);
+    }
+    poly_trim(K, a);
+  }
+  poly_trim(K, &qt);
+  *a = qt;
+}
+
+/* multiplicities of the factor degrees of one row: out[j-1] = number of
+ * irreducible factors of degree j, j = 1..2g+2 (plus the part 1 at infinity
+ * for odd degree) */
+static void orc_lambda_one(const orc_fq *K, int g, const int16_t *codes, uint8_t *out) {
+  int ncoef = 2 * g + 3;
+  memset(out, 0, (size_t)(ncoef - 1));
+  orc_poly f;
+  poly_zero(&f);
+  for (int i = 0; i < ncoef; ++i) fq_set(K, f.c[i], codes[i]);
+  f.deg = ncoef - 1;
+  poly_trim(K, &f);
+  int d = f.deg;
+  if (d == 2 * g + 1) out[0] += 1;
+  /* h = X mod f, then the distinct-degree loop */
+  orc_poly rest = f, h, xq, x;
+  poly_zero(&x);
+  x.deg = 1;
+  x.c[1][0] = 1;
+  h = x;
+  for (int k = 1; 2 * k <= rest.deg; ++k) {
+    /* h <- h^q mod rest */
+    orc_poly acc, base = h;
+    poly_zero(&acc);
+    acc.deg = 0;
+    acc.c[0][0] = 1;
+    for (int64_t e = K->q; e > 0; e >>= 1) {
+      if (e & 1) poly_mulmod(K, &acc, &base, &rest, &acc);
+      poly_mulmod(K, &base, &base, &rest, &base);
+    }
+    h = acc;
+    /* gcd(rest, h - X) */
+    xq = h;
+    if (xq.deg < 1) xq.deg = 1;
+    fq_sub(K, xq.c[1], x.c[1], xq.c[1]);
+    poly_trim(K, &xq);
+    orc_poly gk;
+    if (xq.deg < 0) gk = rest;            /* h = X: every remaining factor has degree dividing k */
+    else poly_gcd(K, &rest, &xq, &gk);
+    if (gk.deg > 0) {
+      out[k - 1] += (uint8_t)(gk.deg / k);
+      poly_divexact(K, &rest, &gk);
+      poly_mod(K, &h, &rest);
+    }
+  }
+  if (rest.deg > 0) out[rest.deg - 1] += 1;
+}
+
+typedef struct {
+  const orc_fq *K;
+  int g;
+  const int16_t *codes;
+  uint8_t *out;
+  int64_t start, count;
+} orc_lam_job;
+
+static void *orc_lam_worker(void *arg) {
+  orc_lam_job *J = (orc_lam_job *)arg;
+  int w = 2 * J->g + 2, nc = 2 * J->g + 3;
+  for (int64_t i = J->start; i < J->start + J->count; ++i)
+    orc_lambda_one(J->K, J->g, J->codes + i * nc, J->out + i * w);
+  return NULL;
+}
+
+/* Factor-degree multiplicities for every row: out[i*(2g+2) + j-1].  Returns 0
+ * or a negative code as orc_count_curves. */
+int orc_factor_degrees(int q, int g, const int16_t *codes, int64_t ncurves, uint8_t *out, int threads) {
+  int p, e;
+  if (orc_factor(q, &p, &e) || q > 4096) return -1;
+  if (g < 1 || 4 * g + 4 > ORC_MAXDEG) return -2;
+  int rc = orc_check_rows(q, g, codes, ncurves);
+  if (rc) return rc;
+  orc_fq K;
+  if (orc_primitive(p, e, 0, &K.F)) return -3;
+  K.q = q;
+  if (threads < 1) threads = 1;
+  if (threads > 256) threads = 256;
+  pthread_t th[256];
+  orc_lam_job jobs[256];
+  int64_t per = (ncurves + threads - 1) / threads;
+  int used = 0;
+  for (int t = 0; t < threads; ++t) {
+    int64_t s = (int64_t)t * per;
+    if (s >= ncurves) break;
+    jobs[t].K = &K; jobs[t].g = g; jobs[t].codes = codes; jobs[t].out = out;
+    jobs[t].start = s; jobs[t].count = (ncurves - s < per) ? ncurves - s : per;
+    used++;
+  }
+  int started = 0;
+  for (int t = 0; t < used; ++t) {
+    if (pthread_create(&th[t], NULL, orc_lam_worker, &jobs[t])) break;
+    started++;
+  }
+  for (int t = started; t < used; ++t) orc_lam_worker(&jobs[t]);
+  for (int t = 0; t < started; ++t) pthread_join(th[t], NULL);
+  return 0;
 }
