@@ -222,6 +222,21 @@ def main():
             extra[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n / (m * 1e-3), 1)}
             log(f"g3 q13 {name}: {m:.3f} ms/step")
         extra["batched_vs_plain"] = round(extra["plain_orbit"]["ms_per_step"] / ms, 3)
+        # counts plus the factorization partition lambda and the (N, lambda)
+        # histogram (the full map of eq. 1.2)
+        lam = torch.empty(n, dtype=torch.int32, device=dev)
+        hk1 = torch.empty((n, g + 1), dtype=torch.int32, device=dev)
+        _, d, N, _, hc, hl = bufs
+
+        def with_lambda():
+            ctx.count_lambda_dev(q, g, d, N, lam, hk1, hc, hl, stream=stream)
+        ml = time_loop(with_lambda, max(1, min(args.steps, 3)), 1, sync) * 1e3
+        ctx.status()
+        assert np.array_equal(N.cpu().numpy(), Nref), "lambda mode changed N"
+        extra["with_lambda"] = {"ms_per_step": round(ml, 3), "curves_per_s": round(n / (ml * 1e-3), 1),
+                                "histogram_distinct": int(hl.item())}
+        log(f"g3 q13 with lambda: {ml:.3f} ms/step ({int(hl.item())} distinct (N, lambda))")
+        del lam, hk1
         # host buffers through the synchronous entry point: PCIe copies of the
         # codes, N and the histogram included (never the headline value)
         Nh = None

@@ -145,6 +145,22 @@ int hwc_count_curves_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coe
                          int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts, uint64_t hist_capacity,
                          uint64_t* d_hist_len, uint32_t flags, void* stream);
 
+/* As hwc_count_curves_dev, plus the factorization partition lambda(f) of
+ * every row (Sec. 1.1: the partition of 2g+2 by the degrees of the
+ * irreducible factors of f over F_q, with an extra part 1 when deg f = 2g+1),
+ * the second argument of the map N_{g,q} of eq. (1.2) -- Algorithm 1 takes
+ * it from the root counts r^0 where they decide it, else by factoring.
+ * d_out_lambda: [n] uint32 codes; the multiplicity of part j (1 <= j <= 10)
+ * sits in bits [s_j, s_j + w_j) with s = 0, 4, 7, 9, 11, 13, 14, 15, 16, 17
+ * and w = 4, 3, 2, 2, 2, 1, 1, 1, 1, 1; 0xFFFFFFFF marks a row whose root
+ * counts are inconsistent with a square-free f.  The histogram (when
+ * d_hist_keys is not NULL) has g+1 columns: N_1..N_g and the code, sorted
+ * lexicographically.  Needs q <= 10923 (HWC_ERR_FIELD_TOO_LARGE otherwise);
+ * other errors and ownership as hwc_count_curves_dev. */
+int hwc_count_lambda_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
+                         int32_t* d_out_N, uint32_t* d_out_lambda, int32_t* d_hist_keys, uint64_t* d_hist_counts,
+                         uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream);
+
 /* Several requests, enqueued on `stream` in order (the persistent batched
  * form; each job is a hwc_count_curves_dev call). */
 int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);

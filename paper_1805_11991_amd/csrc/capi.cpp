@@ -42,8 +42,11 @@ hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint
                               uint32_t* queue, hipStream_t s);
 hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 uint64_t hist_scratch_bytes(uint64_t n);
-hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* scratch, int32_t* out_keys,
-                    uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err, hipStream_t s);
+hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t g, uint32_t q, void* scratch,
+                    int32_t* out_keys, uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err,
+                    hipStream_t s);
+hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, uint64_t n,
+                         const uint32_t* lv, uint32_t* lam, hipStream_t s);
 }  // namespace hwc
 
 namespace {
@@ -299,7 +302,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     return off;
   };
   hwc::PlanDesc& D = P->desc;
-  D.q = q; D.g = g; D.ncoef = 2 * g + 3; D.orbit = orbit;
+  D.q = q; D.p = p; D.g = g; D.ncoef = 2 * g + 3; D.orbit = orbit;
   std::vector<std::vector<uint32_t>> gtabs(g);
   for (uint32_t j = 0; j < g; ++j) {
     const hwc::Field& F = P->fields[j]->F;
@@ -449,6 +452,7 @@ struct Scratch {
 };
 
 int get_scratch(hwc_ctx* c, uint64_t n, uint32_t g, bool plain, bool hist, Scratch* s) {
+  // plain: per-level results (also needed for the factorization partition)
   const uint32_t npat = hwc::pattern_count(g);
   s->max_tiles = n / hwc::kWave + npat + 1;
   int rc;
@@ -485,7 +489,7 @@ int take_event(hwc_ctx* c, hipEvent_t* ev) {
 }
 
 int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb, uint64_t n, int32_t* N,
-            int32_t* hk, uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s,
+            uint32_t* lam, int32_t* hk, uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s,
             bool record = false) {
   const uint32_t g = P->g;
   std::array<hipEvent_t, 4> ev{};
@@ -506,12 +510,13 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
                                   P->grid, P->block, P->wpe, s));
       HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
     } else {
-      HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N, nullptr,
-                                P->grid, P->block, P->wpe, s));
+      HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N,
+                                lam ? S.lv : nullptr, P->grid, P->block, P->wpe, s));
     }
+    if (lam) HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, s));
   }
   if (record) HIPX(c, hipEventRecord(ev[2], s));
-  if (hk) HIPX(c, hwc::hist_run(N, n, g, P->q, S.hist, hk, hc, hcap, hlen, c->d_err, s));
+  if (hk) HIPX(c, hwc::hist_run(N, lam, n, g, P->q, S.hist, hk, hc, hcap, hlen, c->d_err, s));
   if (record) {
     HIPX(c, hipEventRecord(ev[3], s));
     c->prof.push_back(ev);
@@ -530,7 +535,7 @@ int check_args(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags) {
 }
 
 int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N, int32_t* hk,
-            uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s) {
+            uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s, uint32_t* lam = nullptr) {
   int rc = check_args(c, q, g, flags);
   if (rc) return rc;
   if (cb != 1 && cb != 2) return fail(c, HWC_ERR_ARG, "coeff_bytes must be 1 or 2");
@@ -541,18 +546,20 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   HIPX(c, hipSetDevice(c->device));
   DevPlan* P = nullptr;
   if ((rc = get_plan(c, q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u, &P))) return rc;
+  if (lam && P->desc.lv[0].form != hwc::kFormA)
+    return fail(c, HWC_ERR_FIELD_TOO_LARGE, "the factorization partition needs q <= 10923");
   Scratch S;
-  if ((rc = get_scratch(c, n, g, (flags & HWC_PLAIN) != 0, hk != nullptr, &S))) return rc;
+  if ((rc = get_scratch(c, n, g, (flags & HWC_PLAIN) != 0 || lam != nullptr, hk != nullptr, &S))) return rc;
   const bool use_graph = !(flags & (HWC_PLAIN | HWC_NO_GRAPH)) && n > 0 && !c->profile;
   if ((rc = order_begin(c, s))) return rc;
   if (!use_graph) {
-    rc = enqueue(c, P, S, codes, cb, n, N, hk, hc, hcap, hlen, flags, s, c->profile);
+    rc = enqueue(c, P, S, codes, cb, n, N, lam, hk, hc, hcap, hlen, flags, s, c->profile);
     if (rc) return rc;
     return order_end(c, s);
   }
   std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)P, n, (uint64_t)cb, (uint64_t)(uintptr_t)codes,
                                (uint64_t)(uintptr_t)N, (uint64_t)(uintptr_t)hk, (uint64_t)(uintptr_t)hc, hcap,
-                               (uint64_t)(uintptr_t)hlen, flags};
+                               (uint64_t)(uintptr_t)hlen, flags, (uint64_t)(uintptr_t)lam};
   for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
     if (it->key == key) {
       c->graphs.splice(c->graphs.begin(), c->graphs, it);
@@ -565,7 +572,7 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   GraphEntry ge;
   ge.key = key;
   HIPX(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue(c, P, S, codes, cb, n, N, hk, hc, hcap, hlen, flags, c->stream);
+  rc = enqueue(c, P, S, codes, cb, n, N, lam, hk, hc, hcap, hlen, flags, c->stream);
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(c->stream, &graph);
   if (rc) {
@@ -618,7 +625,7 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, const BatchPlan
   for (size_t r = 0; r < njobs; ++r) {
     const hwc_job& J = jobs[B.order[r]];
     if (!J.d_hist_keys) continue;
-    HIPX(c, hwc::hist_run(J.d_out_N, J.n, J.g, J.q, c->hist.p, J.d_hist_keys, J.d_hist_counts, J.hist_capacity,
+    HIPX(c, hwc::hist_run(J.d_out_N, nullptr, J.n, J.g, J.q, c->hist.p, J.d_hist_keys, J.d_hist_counts, J.hist_capacity,
                           J.d_hist_len, c->d_err, s));
   }
   return HWC_OK;
@@ -1055,6 +1062,19 @@ int hwc_count_curves_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeff
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   return run_dev(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity, d_hist_len,
                  flags, s);
+}
+
+int hwc_count_lambda_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
+                         int32_t* d_out_N, uint32_t* d_out_lambda, int32_t* d_hist_keys, uint64_t* d_hist_counts,
+                         uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (flags & HWC_VALIDATE) return fail(c, HWC_ERR_ARG, "HWC_VALIDATE needs host rows");
+  if (!d_out_lambda) return fail(c, HWC_ERR_ARG, "null device pointer");
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  return run_dev(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity, d_hist_len,
+                 flags, s, d_out_lambda);
 }
 
 int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream) {

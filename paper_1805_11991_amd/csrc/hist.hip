@@ -11,6 +11,8 @@
 
 #include <cstdint>
 
+#include "plan.h"
+
 namespace hwc {
 
 constexpr int kSortThreads = 256;
@@ -21,11 +23,13 @@ constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kScanTile = 4096;
 
 struct KeyRadix {
-  uint32_t g;
-  uint64_t radix[4];   // R_k
+  uint32_t g;          // columns taken from N
+  uint32_t width;      // g, or g + 1 with the factorization code as last column
+  uint64_t radix[5];   // R_k, then 2^18 for the code
 };
 
-__global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N, uint64_t n, KeyRadix kr,
+__global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N,
+                                                        const uint32_t* __restrict__ lam, uint64_t n, KeyRadix kr,
                                                         uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
   uint32_t bad = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
@@ -34,6 +38,11 @@ __global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restric
       int32_t v = N[i * kr.g + k];
       if (v < 0 || (uint64_t)v >= kr.radix[k]) { bad = 1; v = 0; }
       key = key * kr.radix[k] + (uint64_t)v;
+    }
+    if (lam) {
+      uint32_t v = lam[i];
+      if ((uint64_t)v >= kr.radix[kr.g]) { bad = 1; v = 0; }
+      key = key * kr.radix[kr.g] + v;
     }
     keys[i] = key;
   }
@@ -198,8 +207,8 @@ __global__ __launch_bounds__(256) void runs_kernel(const uint64_t* __restrict__ 
     starts[j] = i;
     if (j < cap) {
       uint64_t key = keys[i];
-      for (int k = (int)kr.g - 1; k >= 0; --k) {
-        out_keys[j * kr.g + k] = (int32_t)(key % kr.radix[k]);
+      for (int k = (int)kr.width - 1; k >= 0; --k) {
+        out_keys[j * kr.width + k] = (int32_t)(key % kr.radix[k]);
         key /= kr.radix[k];
       }
     }
@@ -253,21 +262,28 @@ static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, 
   return hipGetLastError();
 }
 
-// Histogram of N[n][g] into out_keys[cap][g] / out_counts[cap]; *out_len gets
-// the number of distinct tuples (which may exceed cap: then only the first
-// cap are written).  scratch: hist_scratch_bytes(n) bytes.  err |= 4 when a
-// value lies outside its radix.
-hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* scratch, int32_t* out_keys,
-                    uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err, hipStream_t s) {
+// Histogram of N[n][g] (and, when lam is given, the factorization codes
+// lam[n] as a last column) into out_keys[cap][width] / out_counts[cap];
+// *out_len gets the number of distinct tuples (which may exceed cap: then only
+// the first cap are written).  scratch: hist_scratch_bytes(n) bytes.  err |= 4
+// when a value lies outside its radix.
+hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t g, uint32_t q, void* scratch,
+                    int32_t* out_keys, uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err,
+                    hipStream_t s) {
   if (g < 1 || g > 4) return hipErrorInvalidValue;
   KeyRadix kr;
   kr.g = g;
+  kr.width = g + (lam ? 1u : 0u);
   double bits = 0;
   uint64_t qk = 1;
-  for (uint32_t k = 0; k < 4; ++k) {
-    qk *= q;
+  for (uint32_t k = 0; k < 5; ++k) {
+    if (k < 4) qk *= q;
     kr.radix[k] = (k < g) ? 2 * qk + 3 : 1;
     if (k < g) bits += __builtin_log2((double)kr.radix[k]);
+  }
+  if (lam) {
+    kr.radix[g] = 1ull << kLamBits;
+    bits += kLamBits;
   }
   if (bits > 63.0) return hipErrorInvalidValue;
   const uint32_t nbits = (uint32_t)bits + 1;
@@ -289,7 +305,7 @@ hipError_t hist_run(const int32_t* N, uint64_t n, uint32_t g, uint32_t q, void* 
     if (out_len) hipLaunchKernelGGL(hist_empty_kernel, dim3(1), dim3(64), 0, s, out_len);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(make_keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, n, kr, keysA, err);
+  hipLaunchKernelGGL(make_keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, lam, n, kr, keysA, err);
   for (uint32_t pass = 0; pass < npass; ++pass) {
     const uint32_t shift = pass * kRadixBits;
     hipLaunchKernelGGL(radix_hist_kernel, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,

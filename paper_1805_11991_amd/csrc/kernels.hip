@@ -21,6 +21,8 @@
 // per-level counts of zeros and of odd logs, split by the parity of low*L.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "plan.h"
 
 namespace hwc {
@@ -1031,7 +1033,8 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, con
 #pragma unroll
       for (int k = 0; k < G; ++k) outN[(uint64_t)curve * G + k] = n[k];
     }
-  } else if (live) {
+  }
+  if (outLv && live) {
 #pragma unroll
     for (int j = 0; j < G; ++j)
       if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[(uint64_t)curve * G + j] = lv[j];
@@ -1198,6 +1201,143 @@ __global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __r
     assemble<G>(P, l, (uint32_t)c0, (uint32_t)ct, emb1[c0], emb1[ct], out);
 #pragma unroll
     for (int k = 0; k < G; ++k) outN[i * G + k] = out[k];
+  }
+}
+
+// ----------------------------------------------------------------------------
+// factorization partition lambda(f) (Sec. 1.1, eq. 1.2; Algorithm 1 takes it
+// from r^0 where it can, else by factoring)
+//
+// The roots found by the count give the small factors: with the orbit sweep,
+// level j's zero count is the number of irreducible factors of degree exactly
+// j (each contributes one Frobenius orbit of primitive roots), plus the
+// factor X when c_0 = 0; with the full sweep the counts r_j = sum_{d | j}
+// d n_d are Moebius-inverted.  Odd degree adds the part 1 at infinity.  The
+// rest R = 2g+2 - sum_{j <= g} j n_j consists of factors of degree > g, so it
+// is one factor unless R = 2g+2, where f is either irreducible or the product
+// of two irreducibles of degree g+1.  Stickelberger's theorem tells them
+// apart: disc f is a square in F_q iff deg f minus the number of irreducible
+// factors is even.  disc f = (-1)^{D(D-1)/2} Res(f, f') / lc f with f' of
+// formal degree D-1; only the parity of log Res is needed, taken along the
+// Euclidean remainder sequence
+// (Res(A, B) = (-1)^{deg A deg B} lc(B)^{deg A - deg R} Res(B, R)) in Zech
+// arithmetic over F_q with the level-1 tables of the plan.
+
+__device__ __forceinline__ uint32_t fq_add(const uint16_t* __restrict__ ztab, uint32_t M, uint32_t a, uint32_t b) {
+  if (a == M) return b;
+  if (b == M) return a;
+  const uint32_t d = b >= a ? b - a : b + M - a;
+  const uint32_t v = ztab[d];                    // 2 Z(d), or 6M where 1 + gamma^d = 0
+  if (v == 6 * M) return M;
+  const uint32_t s = a + (v >> 1);
+  return s >= M ? s - M : s;
+}
+
+template <int G, typename CT>
+__global__ __launch_bounds__(256) void lambda_kernel(const PlanDesc* __restrict__ Pd, const CT* __restrict__ codes,
+                                                     uint64_t n, const uint32_t* __restrict__ lv,
+                                                     uint32_t* __restrict__ lam) {
+  constexpr int NC = 2 * G + 3, D2 = 2 * G + 2;
+  const PlanDesc& P = *Pd;
+  const uint32_t q = P.q, p = P.p, M = P.lv[0].M;           // level 1 is F_q
+  const uint8_t* img = reinterpret_cast<const uint8_t*>(P.image);
+  const uint16_t* ztab = reinterpret_cast<const uint16_t*>(img + P.lv[0].tab_off);
+  const uint32_t* emb = reinterpret_cast<const uint32_t*>(img + P.lv[0].emb_off);
+  const uint32_t chim1 = (M / 2) & 1u;                      // parity of log(-1)
+  const bool orbit = P.orbit != 0;
+  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const CT* row = codes + i * NC;
+    uint32_t code[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      int v = (int)row[k];
+      code[k] = (uint32_t)(v < 0 ? 0 : (v >= (int)q ? (int)q - 1 : v));
+    }
+    const uint32_t x0 = code[0] == 0 ? 1u : 0u;               // X divides f
+    const bool top = code[NC - 1] != 0;
+    uint32_t r[G + 1], nj[G + 1];
+#pragma unroll
+    for (int j = 1; j <= G; ++j) r[j] = (lv[i * G + j - 1] & 0xFFu) + (orbit ? 0u : x0);
+    bool ok = true;
+#pragma unroll
+    for (int j = 1; j <= G; ++j) {
+      if (orbit) {
+        nj[j] = r[j] + (j == 1 ? x0 : 0u);
+      } else {
+        // j n_j = sum_{d | j} mu(j / d) r_d
+        int s = 0;
+#pragma unroll
+        for (int d = 1; d <= j; ++d) {
+          if (j % d) continue;
+          const int m = j / d;
+          const int mu = m == 1 ? 1 : (m == 2 || m == 3) ? -1 : 0;   // j <= 4
+          s += mu * (int)r[d];
+        }
+        ok &= s >= 0 && s % j == 0;
+        nj[j] = s >= 0 ? (uint32_t)(s / j) : 0u;
+      }
+    }
+    uint32_t c = 0, deg = 0;
+    const uint32_t m1 = nj[1] + (top ? 0u : 1u);             // the part at infinity of odd degree
+    c |= m1;
+    deg += m1;
+#pragma unroll
+    for (int j = 2; j <= G; ++j) {
+      c |= nj[j] << lam_shift(j);
+      deg += (uint32_t)j * nj[j];
+    }
+    ok &= deg <= (uint32_t)D2;
+    const uint32_t R = ok ? (uint32_t)D2 - deg : 0u;
+    if (R > 0 && R < (uint32_t)D2) {
+      ok &= R > (uint32_t)G;
+      c |= 1u << lam_shift(R);
+    } else if (R == (uint32_t)D2) {
+      uint32_t A[NC], B[NC];
+#pragma unroll
+      for (int k = 0; k < NC; ++k) A[k] = emb[code[k]];
+#pragma unroll
+      for (int k = 0; k + 1 < NC; ++k) {                     // f' = sum (k+1) c_{k+1} X^k
+        const uint32_t li = emb[(uint32_t)(k + 1) % p];      // log of the integer k+1 in F_q
+        B[k] = (A[k + 1] == M || li == M) ? M : (A[k + 1] + li) % M;
+      }
+      B[NC - 1] = M;
+      int dA = NC - 1, dB = NC - 2;
+      while (dB >= 0 && B[dB] == M) --dB;
+      // f' shorter than deg f - 1 (p | deg f): Res with the formal degree
+      // deg f - 1 carries lc(f)^(deg f - 1 - deg f') in front
+      uint32_t par = A[NC - 1] & (uint32_t)(NC - 2 - dB) & 1u;
+      bool bad = dB < 0;
+      while (!bad && dB > 0) {
+        for (int t = dA; t >= dB; --t) {                     // A <- A mod B
+          if (A[t] == M) continue;
+          const uint32_t fac = submod(A[t], B[dB], M);
+          for (int k = 0; k < dB; ++k) {
+            if (B[k] == M) continue;
+            const uint32_t neg = addmod(addmod(fac, B[k], M), M / 2, M);
+            A[t - dB + k] = fq_add(ztab, M, A[t - dB + k], neg);
+          }
+          A[t] = M;
+        }
+        int dR = dB - 1;
+        while (dR >= 0 && A[dR] == M) --dR;
+        if (dR < 0) { bad = true; break; }                   // common factor: not square-free
+        par ^= ((uint32_t)(dA * dB) & 1u) & chim1;
+        par ^= B[dB] & (uint32_t)(dA - dR) & 1u;
+#pragma unroll
+        for (int k = 0; k < NC; ++k) {
+          const uint32_t t = A[k];
+          A[k] = B[k];
+          B[k] = t;
+        }
+        dA = dB;
+        dB = dR;
+      }
+      ok &= !bad;
+      par ^= B[0] & (uint32_t)dA & 1u;
+      const uint32_t pd = par ^ ((uint32_t)((D2 * (D2 - 1) / 2) & 1) & chim1) ^ (emb[code[NC - 1]] & 1u);
+      c |= pd ? (1u << lam_shift(D2)) : (2u << lam_shift(G + 1));
+    }
+    lam[i] = ok ? c : kLamInvalid;
   }
 }
 
@@ -1376,6 +1516,28 @@ hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_
     e = hipGetLastError();
   }
   return e;
+}
+
+
+hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, uint64_t n,
+                         const uint32_t* lv, uint32_t* lam, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
+#define HWC_LAM(GG)                                                                                        \
+  case GG:                                                                                                 \
+    if (coeff_bytes == 1)                                                                                  \
+      hipLaunchKernelGGL((lambda_kernel<GG, int8_t>), dim3(grid), dim3(256), 0, s, dP,                      \
+                         static_cast<const int8_t*>(codes), n, lv, lam);                                  \
+    else                                                                                                   \
+      hipLaunchKernelGGL((lambda_kernel<GG, int16_t>), dim3(grid), dim3(256), 0, s, dP,                     \
+                         static_cast<const int16_t*>(codes), n, lv, lam);                                 \
+    break;
+  switch (P.g) {
+    HWC_LAM(1) HWC_LAM(2) HWC_LAM(3) HWC_LAM(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HWC_LAM
+  return hipGetLastError();
 }
 
 }  // namespace hwc

@@ -18,6 +18,8 @@
 // Logs are taken to the primitive element gamma of each F_{q^j}; Z is the
 // Zech logarithm Z(k) = log(1 + gamma^k) (eq. 2.1, table (3.2)).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace hwc {
@@ -49,12 +51,22 @@ struct LevelDesc {
 };
 
 struct PlanDesc {
-  uint32_t q, g, ncoef;   // ncoef = 2g+3
+  uint32_t q, p, g, ncoef;   // q = p^e; ncoef = 2g+3
   uint32_t orbit;         // 1: level j sweeps primitive Frobenius orbits of F_{q^j}
   uint32_t image_bytes;   // LDS image size (multiple of 16)
   const uint32_t* image;  // device copy of the image (dwords)
   LevelDesc lv[kMaxG];
 };
+
+// Factorization partition code (eq. 1.2): the multiplicity of part j
+// (j = 1..10, i.e. 2g+2 <= 10) sits in bits [lam_shift(j), lam_shift(j) + w_j)
+// with widths w = 4, 3, 2, 2, 2, 1, 1, 1, 1, 1 -- enough for every partition
+// of 10 -- so a code fits in kLamBits bits.
+constexpr uint32_t kLamBits = 18;
+constexpr uint32_t kLamInvalid = 0xFFFFFFFFu;   // root counts inconsistent with a square-free row
+__host__ __device__ constexpr uint32_t lam_shift(uint32_t j) {
+  return j == 1 ? 0u : j == 2 ? 4u : j == 3 ? 7u : j == 4 ? 9u : j == 5 ? 11u : 7u + j;
+}
 
 // One request of a multi-plan launch (device memory).
 struct JobDesc {

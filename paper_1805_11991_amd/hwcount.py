@@ -43,7 +43,7 @@ HWC_OPT_SPLIT_MIN_M = 6
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
+           "hwc_count_lambda_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
            "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
 
 
@@ -107,6 +107,7 @@ def load():
         "hwc_field_release": (None, [vp]),
         "hwc_count_curves": (i32, [vp, u32, u32, vp, u64, vp, ctypes.POINTER(hwc_hist), u32]),
         "hwc_count_curves_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, u64, vp, u32, vp]),
+        "hwc_count_lambda_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, vp, u64, vp, u32, vp]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -247,6 +248,17 @@ class Context:
                                                 _ptr(d_hist_keys), _ptr(d_hist_counts), cap, _ptr(d_hist_len),
                                                 flags, s))
 
+    def count_lambda_dev(self, q: int, g: int, d_coeffs, d_out_N, d_out_lambda, d_hist_keys=None,
+                         d_hist_counts=None, d_hist_len=None, flags: int = 0, stream=None):
+        """N and the factorization partition code of every row (torch tensors:
+        d_out_lambda int32/uint32 [n]; histogram keys [cap, g+1])."""
+        cap = 0 if d_hist_keys is None else d_hist_keys.shape[0]
+        s = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+        self._check(load().hwc_count_lambda_dev(self._h, q, g, _ptr(d_coeffs), d_coeffs.element_size(),
+                                                d_coeffs.shape[0], _ptr(d_out_N), _ptr(d_out_lambda),
+                                                _ptr(d_hist_keys), _ptr(d_hist_counts), cap, _ptr(d_hist_len),
+                                                flags, s))
+
     def count_batch(self, jobs: list[dict], flags: int = 0, stream=None):
         arr = (hwc_job * max(len(jobs), 1))()
         for i, j in enumerate(jobs):
@@ -285,3 +297,28 @@ class Context:
         v = [ctypes.c_uint64() for _ in range(4)]
         self._check(load().hwc_ctx_stats(self._h, *(ctypes.byref(x) for x in v)))
         return dict(zip(("plans_resident", "table_bytes", "cache_hits", "cache_misses"), (x.value for x in v)))
+
+
+LAMBDA_SHIFT = (0, 4, 7, 9, 11, 13, 14, 15, 16, 17)
+LAMBDA_WIDTH = (4, 3, 2, 2, 2, 1, 1, 1, 1, 1)
+LAMBDA_INVALID = 0xFFFFFFFF
+
+
+def lambda_multiplicities(codes, g: int):
+    """Decode factorization codes into multiplicities: int array [n, 2g+2],
+    column j-1 = number of parts equal to j."""
+    c = np.asarray(codes).astype(np.uint64) & 0xFFFFFFFF
+    out = np.zeros((c.shape[0], 2 * g + 2), dtype=np.int64)
+    for j in range(1, 2 * g + 3):
+        out[:, j - 1] = (c >> LAMBDA_SHIFT[j - 1]) & ((1 << LAMBDA_WIDTH[j - 1]) - 1)
+    return out
+
+
+def lambda_code(mults) -> int:
+    """Code of one partition given by its multiplicities (index j-1 = part j)."""
+    v = 0
+    for j, m in enumerate(mults, start=1):
+        if m:
+            assert m < (1 << LAMBDA_WIDTH[j - 1])
+            v |= int(m) << LAMBDA_SHIFT[j - 1]
+    return v
