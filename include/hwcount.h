@@ -161,6 +161,22 @@ int hwc_count_lambda_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coe
                          int32_t* d_out_N, uint32_t* d_out_lambda, int32_t* d_hist_keys, uint64_t* d_hist_counts,
                          uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream);
 
+/* The map N_{g,q} of eq. (1.2) over every square-free f of degree 2g+1 and
+ * 2g+2, by Algorithm 1: the reduced, twist-reduced representatives of
+ * Sec. 1.2-1.3 are generated and counted on the device (with lambda), each
+ * weighted by its multiplicity mult(f) and entered twice, for f and for its
+ * quadratic twist (Algorithm 1 adds both; the twist's invariants follow from
+ * the corrected relation a_k(nf) = (-1)^k a_k(f)).  Output (host memory, in
+ * lexicographic order): keys[len][g+1] = a_1..a_g, lambda code (a_k = q^k + 1
+ * - N_k, eq. 1.1; code as in hwc_count_lambda_dev) and counts[len]; *len is
+ * the number of entries (HWC_ERR_HIST_CAPACITY when it exceeds capacity),
+ * *reps (may be NULL) the number of representatives evaluated.  The counts
+ * add up to (q-1)(q^{2g+2} - q^{2g+1}) + (q-1)(q^{2g+1} - q^{2g}), the number
+ * of square-free polynomials of those degrees.  Synchronous; needs
+ * q <= 10923. */
+int hwc_count_map(hwc_ctx* ctx, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts, uint64_t capacity,
+                  uint64_t* len, uint64_t* reps, uint32_t flags);
+
 /* Several requests, enqueued on `stream` in order (the persistent batched
  * form; each job is a hwc_count_curves_dev call). */
 int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);

@@ -16,6 +16,8 @@
 #include <string>
 #include <tuple>
 #include <vector>
+#include <unordered_map>
+#include <cmath>
 
 #include "../../include/hwcount.h"
 #include "field.h"
@@ -46,7 +48,10 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
                     int32_t* out_keys, uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err,
                     hipStream_t s);
 hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, uint64_t n,
-                         const uint32_t* lv, uint32_t* lam, hipStream_t s);
+                         const uint32_t* lv, uint32_t* lam, uint32_t sqf, hipStream_t s);
+hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t d, uint32_t i, int32_t j,
+                           const uint32_t* cj, uint32_t ncj, uint64_t start, uint64_t count, void* out,
+                           hipStream_t s);
 }  // namespace hwc
 
 namespace {
@@ -57,6 +62,10 @@ constexpr size_t kMaxGraphs = 8;
 struct FieldEntry {
   hwc::Field F;
 };
+
+// internal flag: the factorization kernel also marks rows that are not
+// square-free (code 0), used by the map of eq. (1.2)
+constexpr uint32_t kFlagSqf = 1u << 30;
 
 // Launch and layout choices for one plan (defaults or an autotuned override).
 struct Tuning {
@@ -125,6 +134,7 @@ struct hwc_ctx {
   int cus = 0;
   // scratch
   Buf pid, small, tiles, perm, lv, N, hist, codes, hout;
+  Buf mcodes, mN, mlam, mhk, mhc, mcj;   // map of eq. (1.2): one chunk of representatives
   uint32_t* d_err = nullptr;
   std::list<GraphEntry> graphs;
   // multi-plan scratch
@@ -513,7 +523,7 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
       HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N,
                                 lam ? S.lv : nullptr, P->grid, P->block, P->wpe, s));
     }
-    if (lam) HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, s));
+    if (lam) HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, (flags & kFlagSqf) ? 1u : 0u, s));
   }
   if (record) HIPX(c, hipEventRecord(ev[2], s));
   if (hk) HIPX(c, hwc::hist_run(N, lam, n, g, P->q, S.hist, hk, hc, hcap, hlen, c->d_err, s));
@@ -536,7 +546,7 @@ int check_args(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags) {
 
 int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N, int32_t* hk,
             uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s, uint32_t* lam = nullptr) {
-  int rc = check_args(c, q, g, flags);
+  int rc = check_args(c, q, g, flags & ~kFlagSqf);
   if (rc) return rc;
   if (cb != 1 && cb != 2) return fail(c, HWC_ERR_ARG, "coeff_bytes must be 1 or 2");
   if (cb == 1 && q > 127) return fail(c, HWC_ERR_ARG, "int8 codes need q <= 127");
@@ -872,6 +882,171 @@ int drop_plans(hwc_ctx* c, const std::tuple<uint32_t, uint32_t, uint32_t>* key) 
   return HWC_OK;
 }
 
+// ---- the map N_{g,q} of eq. (1.2) by Algorithm 1 ----
+//
+// Classes of reduced representatives (Sec. 1.2-1.3), per degree d:
+//  * p does not divide d: a translation makes c_{d-1} = 0; i is the highest
+//    nonzero position below d (i <= d-2), j the next one (or none); scalings
+//    X -> aX and f -> f / e^2 put c_j / c_i in R_{i-j} and c_i in R_2.  The
+//    number of polynomials behind a representative is q (q-1)^2 / (2
+//    gcd(q-1, i-j)), or q (q-1) / 2 without j.  The paper's list leaves out
+//    the rows c_d X^d + c_1 X (i = 1, no j); they are a class like the others.
+//  * p divides d: the translation step does not reduce every row, so only
+//    the scalings are used: i <= d-1, multiplicities (q-1)^2 / (2 gcd(q-1,
+//    i-j)) and (q-1) / 2.
+// The twist-reduced set fixes c_i = 1; each representative also stands for
+// its twist n f (n a nonsquare) with the same multiplicity, whose counts
+// follow from the corrected twist relation: N_k(nf) = 2(q^k+1) - N_k(f) for
+// odd k, N_k(f) for even k.  Rows that are not square-free are dropped on the
+// device (factorization code 0).
+
+struct RepClass {
+  uint32_t d, i;
+  int32_t j;                  // -1: no j
+  uint64_t nrep, mult;
+  std::vector<uint32_t> cj;   // codes of R_{i-j}
+};
+
+uint64_t gcd64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+std::vector<RepClass> rep_classes(const hwc::Field& Fq, uint32_t q, uint32_t p, uint32_t g) {
+  std::vector<RepClass> out;
+  const uint64_t qm = q - 1;
+  for (uint32_t d = 2 * g + 1; d <= 2 * g + 2; ++d) {
+    const bool trans = d % p != 0;
+    const uint32_t imax = trans ? d - 2 : d - 1;
+    for (uint32_t i = 0; i <= imax; ++i) {
+      out.push_back(RepClass{d, i, -1, qm, trans ? (uint64_t)q * qm / 2 : qm / 2, {}});
+      uint64_t qj = 1;
+      for (uint32_t j = 0; j < i; ++j) {
+        const uint64_t gk = gcd64(qm, i - j);
+        RepClass c{d, i, (int32_t)j, qm * gk * qj, (trans ? (uint64_t)q : 1u) * qm * qm / (2 * gk), {}};
+        for (uint64_t L = 0; L < gk; ++L) c.cj.push_back(Fq.exp[L]);   // gamma^L: codes of R_{i-j}
+        out.push_back(std::move(c));
+        qj *= q;
+      }
+    }
+  }
+  return out;
+}
+
+int run_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts, uint64_t capacity,
+            uint64_t* out_len, uint64_t* out_reps, uint32_t flags) {
+  uint32_t p, e;
+  int rc = check_args(c, q, g, flags);
+  if (rc) return rc;
+  hwc::factor_odd_prime_power(q, &p, &e);
+  if (q > hwc::kFormAMaxM + 1) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "the map needs q <= 10923");
+  HIPX(c, hipSetDevice(c->device));
+  auto fe = get_field(c, p, e, 1, &rc);
+  if (!fe) return rc;
+  const uint32_t nc = 2 * g + 3, cb = q <= 127 ? 1 : 2;
+  // host key: N_1..N_g and the code in mixed radix (as the device histogram)
+  std::vector<uint64_t> radix(g + 1);
+  std::vector<int64_t> qpow(g);
+  double bits = hwc::kLamBits;
+  uint64_t qk = 1;
+  for (uint32_t k = 0; k < g; ++k) {
+    qk *= q;
+    qpow[k] = (int64_t)qk;
+    radix[k] = 2 * qk + 3;
+    bits += std::log2((double)radix[k]);
+  }
+  radix[g] = 1ull << hwc::kLamBits;
+  if (bits > 63.0) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "map key wider than 63 bits");
+  const uint64_t kChunk = 1ull << 22;
+  if ((rc = ensure(c, c->mcodes, kChunk * nc * cb))) return rc;
+  if ((rc = ensure(c, c->mN, kChunk * g * 4))) return rc;
+  if ((rc = ensure(c, c->mlam, kChunk * 4))) return rc;
+  if ((rc = ensure(c, c->mhk, kChunk * (g + 1) * 4))) return rc;
+  if ((rc = ensure(c, c->mhc, kChunk * 8 + 64))) return rc;
+  if ((rc = ensure(c, c->mcj, 4096 * 4))) return rc;
+  const std::vector<RepClass> classes = rep_classes(fe->F, q, p, g);
+  std::unordered_map<uint64_t, uint64_t> acc;
+  std::vector<int32_t> hk;
+  std::vector<uint64_t> hcnt;
+  uint64_t reps = 0;
+  uint64_t* d_len = reinterpret_cast<uint64_t*>(static_cast<uint8_t*>(c->mhc.p) + kChunk * 8);
+  HIPX(c, hwc::launch_fill(c->d_err, 0, 1, c->stream));
+  for (const RepClass& cl : classes) {
+    if (cl.j >= 0) {
+      if (cl.cj.size() > 4096) return fail(c, HWC_ERR_ARG, "too many representatives of R_k");
+      HIPX(c, hipMemcpyAsync(c->mcj.p, cl.cj.data(), cl.cj.size() * 4, hipMemcpyHostToDevice, c->stream));
+    }
+    for (uint64_t start = 0; start < cl.nrep; start += kChunk) {
+      const uint64_t cnt = std::min(kChunk, cl.nrep - start);
+      HIPX(c, hwc::launch_gen_reps((int)cb, q, nc, cl.d, cl.i, cl.j, static_cast<const uint32_t*>(c->mcj.p),
+                                   (uint32_t)cl.cj.size(), start, cnt, c->mcodes.p, c->stream));
+      rc = run_dev(c, q, g, c->mcodes.p, (int)cb, cnt, static_cast<int32_t*>(c->mN.p),
+                   static_cast<int32_t*>(c->mhk.p), static_cast<uint64_t*>(c->mhc.p), cnt, d_len,
+                   flags | HWC_NO_GRAPH | kFlagSqf, c->stream, static_cast<uint32_t*>(c->mlam.p));
+      if (rc) return rc;
+      uint64_t len = 0;
+      HIPX(c, hipMemcpyAsync(&len, d_len, 8, hipMemcpyDeviceToHost, c->stream));
+      HIPX(c, hipStreamSynchronize(c->stream));
+      hk.resize(len * (g + 1));
+      hcnt.resize(len);
+      if (len) {
+        HIPX(c, hipMemcpyAsync(hk.data(), c->mhk.p, len * (g + 1) * 4, hipMemcpyDeviceToHost, c->stream));
+        HIPX(c, hipMemcpyAsync(hcnt.data(), c->mhc.p, len * 8, hipMemcpyDeviceToHost, c->stream));
+        HIPX(c, hipStreamSynchronize(c->stream));
+      }
+      for (uint64_t r = 0; r < len; ++r) {
+        const int32_t* row = hk.data() + r * (g + 1);
+        const uint32_t code = (uint32_t)row[g];
+        if (code == 0) continue;                       // not square-free
+        const uint64_t w = hcnt[r] * cl.mult;
+        uint64_t k1 = 0, k2 = 0;
+        for (uint32_t k = 0; k < g; ++k) {
+          const int64_t Nk = row[k];
+          const int64_t Nt = (k % 2 == 0) ? 2 * (qpow[k] + 1) - Nk : Nk;   // k = 0 holds N_1 (odd degree)
+          if (Nt < 0 || (uint64_t)Nt >= radix[k]) return fail(c, HWC_ERR_DEVICE, "twisted count outside its range");
+          k1 = k1 * radix[k] + (uint64_t)Nk;
+          k2 = k2 * radix[k] + (uint64_t)Nt;
+        }
+        k1 = k1 * radix[g] + code;
+        k2 = k2 * radix[g] + code;
+        acc[k1] += w;
+        acc[k2] += w;
+      }
+      reps += cnt;
+    }
+  }
+  uint32_t derr = 0;
+  HIPX(c, hipMemcpy(&derr, c->d_err, 4, hipMemcpyDeviceToHost));
+  if (derr & 4u) return fail(c, HWC_ERR_DEVICE, "a representative's counts or partition fall outside the key range");
+  // (a_1..a_g, code) with a_k = q^k + 1 - N_k, in lexicographic order
+  std::vector<std::pair<std::vector<int64_t>, uint64_t>> rows;
+  rows.reserve(acc.size());
+  for (const auto& kv : acc) {
+    std::vector<int64_t> t(g + 1);
+    uint64_t key = kv.first;
+    t[g] = (int64_t)(key % radix[g]);
+    key /= radix[g];
+    for (int k = (int)g - 1; k >= 0; --k) {
+      t[k] = qpow[k] + 1 - (int64_t)(key % radix[k]);
+      key /= radix[k];
+    }
+    rows.emplace_back(std::move(t), kv.second);
+  }
+  std::sort(rows.begin(), rows.end());
+  if (out_len) *out_len = rows.size();
+  if (out_reps) *out_reps = reps;
+  if (rows.size() > capacity) return fail(c, HWC_ERR_HIST_CAPACITY, "map longer than the capacity");
+  for (size_t r = 0; r < rows.size(); ++r) {
+    for (uint32_t k = 0; k <= g; ++k) keys[r * (g + 1) + k] = (int32_t)rows[r].first[k];
+    counts[r] = rows[r].second;
+  }
+  return HWC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -920,7 +1095,8 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     drop_graphs(c);
     for (auto& kv : c->plans) free_plan(kv.second.get());
     for (Buf* b : {&c->pid, &c->small, &c->tiles, &c->perm, &c->lv, &c->N, &c->hist, &c->codes, &c->hout, &c->bpid,
-                   &c->bperm, &c->btiles, &c->bsmall, &c->bchunks, &c->bcstart, &c->bwords})
+                   &c->bperm, &c->btiles, &c->bsmall, &c->bchunks, &c->bcstart, &c->bwords, &c->mcodes, &c->mN,
+                   &c->mlam, &c->mhk, &c->mhc, &c->mcj})
       if (b->p) (void)hipFree(b->p);
     for (auto& sl : c->slots) {
       if (sl.p) (void)hipFree(sl.p);
@@ -1075,6 +1251,16 @@ int hwc_count_lambda_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeff
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   return run_dev(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity, d_hist_len,
                  flags, s, d_out_lambda);
+}
+
+int hwc_count_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts, uint64_t capacity,
+                  uint64_t* len, uint64_t* reps, uint32_t flags) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (flags & HWC_VALIDATE) return fail(c, HWC_ERR_ARG, "HWC_VALIDATE does not apply to the map");
+  if (capacity && (!keys || !counts)) return fail(c, HWC_ERR_ARG, "null output buffer");
+  return run_map(c, q, g, keys, counts, capacity, len, reps, flags);
 }
 
 int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream) {

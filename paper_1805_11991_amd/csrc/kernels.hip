@@ -1233,10 +1233,65 @@ __device__ __forceinline__ uint32_t fq_add(const uint16_t* __restrict__ ztab, ui
   return s >= M ? s - M : s;
 }
 
+// Parity of log disc(f) over F_q (1: disc is a nonsquare), f given by its
+// codes with deg f = NC-1 (top code nonzero); nsf is set when f and f' share
+// a factor (the remainder sequence hits zero before a constant).
+template <int NC>
+__device__ uint32_t disc_parity(const uint32_t (&code)[NC], const uint16_t* __restrict__ ztab,
+                                const uint32_t* __restrict__ emb, uint32_t M, uint32_t p, uint32_t chim1,
+                                bool& nsf) {
+  constexpr int D = NC - 1;
+  int top = D;
+  while (top > 0 && code[top] == 0) --top;                   // actual degree (2g+1 rows too)
+  uint32_t A[NC], B[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) A[k] = emb[code[k]];
+#pragma unroll
+  for (int k = 0; k + 1 < NC; ++k) {                         // f' = sum (k+1) c_{k+1} X^k
+    const uint32_t li = emb[(uint32_t)(k + 1) % p];          // log of the integer k+1 in F_q
+    B[k] = (A[k + 1] == M || li == M) ? M : (A[k + 1] + li) % M;
+  }
+  B[NC - 1] = M;
+  int dA = top, dB = top - 1;
+  while (dB >= 0 && B[dB] == M) --dB;
+  // f' shorter than deg f - 1 (p | deg f): Res with the formal degree
+  // deg f - 1 carries lc(f)^(deg f - 1 - deg f') in front
+  uint32_t par = dB >= 0 ? (A[top] & (uint32_t)(top - 1 - dB) & 1u) : 0u;
+  bool bad = dB < 0;
+  while (!bad && dB > 0) {
+    for (int t = dA; t >= dB; --t) {                         // A <- A mod B
+      if (A[t] == M) continue;
+      const uint32_t fac = submod(A[t], B[dB], M);
+      for (int k = 0; k < dB; ++k) {
+        if (B[k] == M) continue;
+        const uint32_t neg = addmod(addmod(fac, B[k], M), M / 2, M);
+        A[t - dB + k] = fq_add(ztab, M, A[t - dB + k], neg);
+      }
+      A[t] = M;
+    }
+    int dR = dB - 1;
+    while (dR >= 0 && A[dR] == M) --dR;
+    if (dR < 0) { bad = true; break; }                       // common factor: not square-free
+    par ^= ((uint32_t)(dA * dB) & 1u) & chim1;
+    par ^= B[dB] & (uint32_t)(dA - dR) & 1u;
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      const uint32_t t = A[k];
+      A[k] = B[k];
+      B[k] = t;
+    }
+    dA = dB;
+    dB = dR;
+  }
+  nsf = bad;
+  if (!bad) par ^= B[0] & (uint32_t)dA & 1u;
+  return par ^ ((uint32_t)((top * (top - 1) / 2) & 1) & chim1) ^ (emb[code[top]] & 1u);
+}
+
 template <int G, typename CT>
 __global__ __launch_bounds__(256) void lambda_kernel(const PlanDesc* __restrict__ Pd, const CT* __restrict__ codes,
                                                      uint64_t n, const uint32_t* __restrict__ lv,
-                                                     uint32_t* __restrict__ lam) {
+                                                     uint32_t* __restrict__ lam, uint32_t sqf) {
   constexpr int NC = 2 * G + 3, D2 = 2 * G + 2;
   const PlanDesc& P = *Pd;
   const uint32_t q = P.q, p = P.p, M = P.lv[0].M;           // level 1 is F_q
@@ -1291,53 +1346,47 @@ __global__ __launch_bounds__(256) void lambda_kernel(const PlanDesc* __restrict_
     if (R > 0 && R < (uint32_t)D2) {
       ok &= R > (uint32_t)G;
       c |= 1u << lam_shift(R);
-    } else if (R == (uint32_t)D2) {
-      uint32_t A[NC], B[NC];
-#pragma unroll
-      for (int k = 0; k < NC; ++k) A[k] = emb[code[k]];
-#pragma unroll
-      for (int k = 0; k + 1 < NC; ++k) {                     // f' = sum (k+1) c_{k+1} X^k
-        const uint32_t li = emb[(uint32_t)(k + 1) % p];      // log of the integer k+1 in F_q
-        B[k] = (A[k + 1] == M || li == M) ? M : (A[k + 1] + li) % M;
-      }
-      B[NC - 1] = M;
-      int dA = NC - 1, dB = NC - 2;
-      while (dB >= 0 && B[dB] == M) --dB;
-      // f' shorter than deg f - 1 (p | deg f): Res with the formal degree
-      // deg f - 1 carries lc(f)^(deg f - 1 - deg f') in front
-      uint32_t par = A[NC - 1] & (uint32_t)(NC - 2 - dB) & 1u;
-      bool bad = dB < 0;
-      while (!bad && dB > 0) {
-        for (int t = dA; t >= dB; --t) {                     // A <- A mod B
-          if (A[t] == M) continue;
-          const uint32_t fac = submod(A[t], B[dB], M);
-          for (int k = 0; k < dB; ++k) {
-            if (B[k] == M) continue;
-            const uint32_t neg = addmod(addmod(fac, B[k], M), M / 2, M);
-            A[t - dB + k] = fq_add(ztab, M, A[t - dB + k], neg);
-          }
-          A[t] = M;
-        }
-        int dR = dB - 1;
-        while (dR >= 0 && A[dR] == M) --dR;
-        if (dR < 0) { bad = true; break; }                   // common factor: not square-free
-        par ^= ((uint32_t)(dA * dB) & 1u) & chim1;
-        par ^= B[dB] & (uint32_t)(dA - dR) & 1u;
-#pragma unroll
-        for (int k = 0; k < NC; ++k) {
-          const uint32_t t = A[k];
-          A[k] = B[k];
-          B[k] = t;
-        }
-        dA = dB;
-        dB = dR;
-      }
-      ok &= !bad;
-      par ^= B[0] & (uint32_t)dA & 1u;
-      const uint32_t pd = par ^ ((uint32_t)((D2 * (D2 - 1) / 2) & 1) & chim1) ^ (emb[code[NC - 1]] & 1u);
+    }
+    bool nsf = false;                                        // common factor with f'
+    uint32_t pd = 0;
+    if (R == (uint32_t)D2 || sqf) pd = disc_parity<NC>(code, ztab, emb, M, p, chim1, nsf);
+    if (R == (uint32_t)D2) {
+      ok &= !nsf;
       c |= pd ? (1u << lam_shift(D2)) : (2u << lam_shift(G + 1));
     }
+    if (sqf && nsf) {
+      lam[i] = 0;                                            // not square-free: no partition
+      continue;
+    }
     lam[i] = ok ? c : kLamInvalid;
+  }
+}
+
+// ----------------------------------------------------------------------------
+// reduced representatives of Algorithm 1 (Sec. 1.2-1.3): one class is every
+// row with c_d in F_q^x (codes 1..q-1), c_i = 1 (the twist-reduced choice),
+// c_j one of the ncj codes in cj (when j >= 0), every position below j free,
+// all other positions zero.  Row r of the class is the mixed-radix number
+// (c_0, .., c_{j-1}, index of c_j, c_d - 1), c_0 least significant.
+
+template <typename CT>
+__global__ __launch_bounds__(256) void gen_reps_kernel(uint32_t q, uint32_t ncoef, uint32_t d, uint32_t i, int32_t j,
+                                                       const uint32_t* __restrict__ cj, uint32_t ncj, uint64_t start,
+                                                       uint64_t count, CT* __restrict__ out) {
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < count; t += (uint64_t)gridDim.x * blockDim.x) {
+    uint64_t r = start + t;
+    CT* row = out + t * ncoef;
+    for (uint32_t k = 0; k < ncoef; ++k) row[k] = 0;
+    for (int32_t k = 0; k < j; ++k) {
+      row[k] = (CT)(r % q);
+      r /= q;
+    }
+    if (j >= 0) {
+      row[j] = (CT)cj[r % ncj];
+      r /= ncj;
+    }
+    row[i] = 1;
+    row[d] = (CT)(1 + r);
   }
 }
 
@@ -1520,23 +1569,38 @@ hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_
 
 
 hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, uint64_t n,
-                         const uint32_t* lv, uint32_t* lam, hipStream_t s) {
+                         const uint32_t* lv, uint32_t* lam, uint32_t sqf, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
 #define HWC_LAM(GG)                                                                                        \
   case GG:                                                                                                 \
     if (coeff_bytes == 1)                                                                                  \
       hipLaunchKernelGGL((lambda_kernel<GG, int8_t>), dim3(grid), dim3(256), 0, s, dP,                      \
-                         static_cast<const int8_t*>(codes), n, lv, lam);                                  \
+                         static_cast<const int8_t*>(codes), n, lv, lam, sqf);                             \
     else                                                                                                   \
       hipLaunchKernelGGL((lambda_kernel<GG, int16_t>), dim3(grid), dim3(256), 0, s, dP,                     \
-                         static_cast<const int16_t*>(codes), n, lv, lam);                                 \
+                         static_cast<const int16_t*>(codes), n, lv, lam, sqf);                            \
     break;
   switch (P.g) {
     HWC_LAM(1) HWC_LAM(2) HWC_LAM(3) HWC_LAM(4)
     default: return hipErrorInvalidValue;
   }
 #undef HWC_LAM
+  return hipGetLastError();
+}
+
+
+hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t d, uint32_t i, int32_t j,
+                           const uint32_t* cj, uint32_t ncj, uint64_t start, uint64_t count, void* out,
+                           hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((count + 255) / 256, 65536);
+  if (coeff_bytes == 1)
+    hipLaunchKernelGGL(gen_reps_kernel<int8_t>, dim3(grid), dim3(256), 0, s, q, ncoef, d, i, j, cj, ncj, start,
+                       count, static_cast<int8_t*>(out));
+  else
+    hipLaunchKernelGGL(gen_reps_kernel<int16_t>, dim3(grid), dim3(256), 0, s, q, ncoef, d, i, j, cj, ncj, start,
+                       count, static_cast<int16_t*>(out));
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ HWC_OPT_SPLIT_MIN_M = 6
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_lambda_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
+           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
            "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
 
 
@@ -108,6 +108,7 @@ def load():
         "hwc_count_curves": (i32, [vp, u32, u32, vp, u64, vp, ctypes.POINTER(hwc_hist), u32]),
         "hwc_count_curves_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, u64, vp, u32, vp]),
         "hwc_count_lambda_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, vp, u64, vp, u32, vp]),
+        "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -258,6 +259,23 @@ class Context:
                                                 d_coeffs.shape[0], _ptr(d_out_N), _ptr(d_out_lambda),
                                                 _ptr(d_hist_keys), _ptr(d_hist_counts), cap, _ptr(d_hist_len),
                                                 flags, s))
+
+    def count_map(self, q: int, g: int, flags: int = 0, capacity: int = 1 << 20):
+        """The map N_{g,q} of eq. (1.2) by Algorithm 1.  Returns (keys [len, g+1]
+        int32: a_1..a_g and the factorization code, counts [len] uint64, number
+        of representatives evaluated)."""
+        while True:
+            keys = np.zeros((max(capacity, 1), g + 1), np.int32)
+            counts = np.zeros(max(capacity, 1), np.uint64)
+            n = ctypes.c_uint64()
+            reps = ctypes.c_uint64()
+            rc = load().hwc_count_map(self._h, q, g, keys.ctypes.data, counts.ctypes.data, capacity,
+                                      ctypes.byref(n), ctypes.byref(reps), flags)
+            if rc == HWC_ERR_HIST_CAPACITY and n.value > capacity:
+                capacity = int(n.value)
+                continue
+            self._check(rc)
+            return keys[:n.value].copy(), counts[:n.value].copy(), int(reps.value)
 
     def count_batch(self, jobs: list[dict], flags: int = 0, stream=None):
         arr = (hwc_job * max(len(jobs), 1))()
