@@ -275,6 +275,17 @@ def main():
         del bufs4
         torch.cuda.empty_cache()
 
+    if not args.quick:
+        # the whole map N_{3,13} of eq. (1.2) by Algorithm 1 (reduced representatives)
+        t0 = time.perf_counter()
+        mk, mc, mreps = ctx.count_map(13, 3)
+        mt = time.perf_counter() - t0
+        total = 12 * (13 ** 8 - 13 ** 7) + 12 * (13 ** 7 - 13 ** 6)
+        assert int(mc.sum()) == total
+        extra["map_g3_q13"] = {"seconds": round(mt, 3), "representatives": mreps, "curves_covered": total,
+                               "entries": int(len(mk)), "curves_covered_per_s": round(total / mt, 1)}
+        log(f"map N_(3,13): {mt:.3f} s, {mreps} representatives for {total} curves, {len(mk)} entries")
+
     if args.calib_copy:
         calibration_copy(torch, dev)
 
