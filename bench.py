@@ -286,6 +286,28 @@ def main():
                                "entries": int(len(mk)), "curves_covered_per_s": round(total / mt, 1)}
         log(f"map N_(3,13): {mt:.3f} s, {mreps} representatives for {total} curves, {len(mk)} entries")
 
+    if not args.quick:
+        # Table 1 (Sec. 4): one curve over F_{p^2}, lane per x; the paper's K80
+        # evaluation times are printed beside for context only
+        k80_eval_ms = {101: 0.36, 211: 1.47, 307: 3.11, 401: 0.95, 503: 1.25, 1009: 2.93, 1511: 394.0,
+                       2003: 11.5, 3001: 15.4}
+        curve = [17, 12, 16, 11, 10, 13, 12]
+        rows = []
+        for p, k80 in k80_eval_ms.items():
+            row = np.array([c % p for c in curve], dtype=np.int16)
+            t0 = time.perf_counter()
+            Nf, tf = ctx.count_single(p, 2, row, 2, flags=hwcount.HWC_FULL_SWEEP)   # builds the tables
+            first = (time.perf_counter() - t0) * 1e3
+            Nf, tf = ctx.count_single(p, 2, row, 2, flags=hwcount.HWC_FULL_SWEEP)
+            No, to = ctx.count_single(p, 2, row, 2)
+            assert Nf.tolist() == No.tolist()
+            rows.append({"p": p, "N1": int(Nf[0]), "N2": int(Nf[1]), "first_call_ms": round(first, 2),
+                         "kernel_ms_full_sweep": round(tf["kernel_ms"], 4),
+                         "kernel_ms_orbit_sweep": round(to["kernel_ms"], 4), "paper_k80_eval_ms": k80})
+            log(f"table 1 p={p}: N2={int(Nf[1])} kernels {tf['kernel_ms']:.3f} ms full, "
+                f"{to['kernel_ms']:.3f} ms orbits (first call {first:.0f} ms with tables)")
+        extra["table1_single_curve"] = rows
+
     if args.calib_copy:
         calibration_copy(torch, dev)
 

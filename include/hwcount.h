@@ -177,6 +177,19 @@ int hwc_count_lambda_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coe
 int hwc_count_map(hwc_ctx* ctx, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts, uint64_t capacity,
                   uint64_t* len, uint64_t* reps, uint32_t flags);
 
+/* One curve over large fields -- the single-curve experiment of Table 1
+ * (Sec. 4), with the paper's lane-per-x layout: every device lane evaluates
+ * f at its own x.  coeffs: [2g+3] int16 codes (host).  Counts N_1..N_kmax
+ * into out_N[kmax] (int64, host) for q^kmax <= 2^24; level j sweeps the
+ * primitive Frobenius orbits of F_{q^j} (HWC_FULL_SWEEP: every nonzero x).
+ * The Zech tables (one period, u32, built on the host and kept on the device
+ * per field) serve from L2/MALL.  timings (may be NULL): [3] milliseconds of
+ * table construction on the host, table upload, and the kernels (HIP
+ * events).  Synchronous; the row must be square-free for N to be a point
+ * count (not checked). */
+int hwc_count_single(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs, uint32_t kmax, int64_t* out_N,
+                     double* timings, uint32_t flags);
+
 /* Several requests, enqueued on `stream` in order (the persistent batched
  * form; each job is a hwc_count_curves_dev call). */
 int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);

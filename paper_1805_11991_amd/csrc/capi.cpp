@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cstdio>
 #include <cstring>
 #include <list>
@@ -52,6 +53,8 @@ hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes,
 hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t d, uint32_t i, int32_t j,
                            const uint32_t* cj, uint32_t ncj, uint64_t start, uint64_t count, void* out,
                            hipStream_t s);
+hipError_t launch_single(const uint32_t* zech, const uint32_t* xs, uint64_t nx, const SingleDesc& f,
+                         unsigned long long* out, hipStream_t s);
 }  // namespace hwc
 
 namespace {
@@ -99,6 +102,13 @@ struct Buf {
   size_t bytes = 0;
 };
 
+// Device tables of one field for the single-curve kernel.
+struct SingleTabs {
+  uint32_t* d_zech = nullptr;   // Zech table, one period (M entries)
+  uint32_t* d_reps = nullptr;   // primitive Frobenius orbit representatives
+  uint64_t nreps = 0;
+};
+
 struct GraphEntry {
   std::vector<uint64_t> key;
   hipGraph_t graph = nullptr;
@@ -135,6 +145,7 @@ struct hwc_ctx {
   // scratch
   Buf pid, small, tiles, perm, lv, N, hist, codes, hout;
   Buf mcodes, mN, mlam, mhk, mhc, mcj;   // map of eq. (1.2): one chunk of representatives
+  std::map<std::tuple<uint32_t, uint32_t, uint32_t>, SingleTabs> single;   // one-curve tables
   uint32_t* d_err = nullptr;
   std::list<GraphEntry> graphs;
   // multi-plan scratch
@@ -1047,6 +1058,120 @@ int run_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts,
   return HWC_OK;
 }
 
+// ---- one curve over large fields (Table 1): lane-per-x ----
+
+int single_tables(hwc_ctx* c, uint32_t p, uint32_t e, uint32_t k, std::shared_ptr<FieldEntry>* fe_out,
+                  SingleTabs** out, double* build_ms, double* upload_ms) {
+  int rc = HWC_OK;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto fe = get_field(c, p, e, k, &rc);
+  if (!fe) return rc;
+  const auto t1 = std::chrono::steady_clock::now();
+  *build_ms += std::chrono::duration<double, std::milli>(t1 - t0).count();
+  *fe_out = fe;
+  auto key = std::make_tuple(p, e, k);
+  auto it = c->single.find(key);
+  if (it != c->single.end()) {
+    *out = &it->second;
+    return HWC_OK;
+  }
+  SingleTabs T;
+  const hwc::Field& F = fe->F;
+  HIPX(c, hipMalloc(&T.d_zech, std::max<size_t>(F.zech.size(), 1) * 4));
+  HIPX(c, hipMemcpy(T.d_zech, F.zech.data(), F.zech.size() * 4, hipMemcpyHostToDevice));
+  T.nreps = F.prim_reps.size();
+  HIPX(c, hipMalloc(&T.d_reps, std::max<size_t>(T.nreps, 1) * 4));
+  if (T.nreps) HIPX(c, hipMemcpy(T.d_reps, F.prim_reps.data(), T.nreps * 4, hipMemcpyHostToDevice));
+  *upload_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+  auto ins = c->single.emplace(key, T);
+  *out = &ins.first->second;
+  return HWC_OK;
+}
+
+int run_single(hwc_ctx* c, uint32_t q, uint32_t g, const int16_t* coeffs, uint32_t kmax, int64_t* out_N,
+               double* timings, uint32_t flags) {
+  if (flags & ~(HWC_FULL_SWEEP)) return fail(c, HWC_ERR_ARG, "unknown flag");
+  int rc = check_args(c, q, g, flags);
+  if (rc) return rc;
+  if (!coeffs || !out_N) return fail(c, HWC_ERR_ARG, "null pointer");
+  if (kmax < 1 || kmax > 24) return fail(c, HWC_ERR_ARG, "k must be in 1..24");
+  uint32_t p, e;
+  hwc::factor_odd_prime_power(q, &p, &e);
+  const uint32_t nc = 2 * g + 3;
+  for (uint32_t j = 0; j < nc; ++j)
+    if (coeffs[j] < 0 || (uint32_t)coeffs[j] >= q) return fail(c, HWC_ERR_COEFF_RANGE, "coefficient code out of range");
+  if (coeffs[nc - 1] == 0 && coeffs[nc - 2] == 0) return fail(c, HWC_ERR_DEGREE, "degree below 2g+1");
+  double Qk = 1;
+  for (uint32_t j = 0; j < kmax; ++j) Qk *= q;
+  if (Qk > 16777216.0) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "F_{q^k} larger than 2^24 elements");
+  HIPX(c, hipSetDevice(c->device));
+  const bool orbit = !(flags & HWC_FULL_SWEEP);
+  const uint32_t d = coeffs[nc - 1] ? nc - 1 : nc - 2;
+  if ((rc = ensure(c, c->hout, 64))) return rc;
+  unsigned long long* d_cnt = static_cast<unsigned long long*>(c->hout.p);
+  std::vector<uint64_t> z(kmax + 1), ns(kmax + 1), nx(kmax + 1);
+  double build_ms = 0, upload_ms = 0, eval_ms = 0;
+  hipEvent_t ev0, ev1;
+  HIPX(c, hipEventCreate(&ev0));
+  HIPX(c, hipEventCreate(&ev1));
+  int out_rc = HWC_OK;
+  for (uint32_t j = 1; j <= kmax && out_rc == HWC_OK; ++j) {
+    std::shared_ptr<FieldEntry> fe;
+    SingleTabs* T = nullptr;
+    if ((out_rc = single_tables(c, p, e, j, &fe, &T, &build_ms, &upload_ms))) break;
+    const hwc::Field& F = fe->F;
+    hwc::SingleDesc f{};
+    f.M = (uint32_t)F.M;
+    f.d = d;
+    for (uint32_t i = 0; i < nc; ++i) f.lc[i] = F.emb[(uint32_t)coeffs[i]];
+    const uint64_t n = orbit ? T->nreps : F.M;
+    nx[j] = n;
+    unsigned long long host[2] = {0, 0};
+    if (hipMemsetAsync(d_cnt, 0, 16, c->stream) != hipSuccess ||
+        hipEventRecord(ev0, c->stream) != hipSuccess ||
+        hwc::launch_single(T->d_zech, orbit ? T->d_reps : nullptr, n, f, d_cnt, c->stream) != hipSuccess ||
+        hipEventRecord(ev1, c->stream) != hipSuccess ||
+        hipMemcpyAsync(host, d_cnt, 16, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+      out_rc = fail(c, HWC_ERR_DEVICE, "single-curve count failed");
+      break;
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, ev0, ev1);
+    eval_ms += ms;
+    z[j] = host[0];
+    ns[j] = host[1];
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (out_rc) return out_rc;
+  // N_k (Sec. 1.1): affine points from the levels j | k (orbit sweep: weight j,
+  // and a nonsquare of F_{q^j} is a square in F_{q^k} when k/j is even), plus
+  // x = 0 and the points at infinity
+  auto fq = get_field(c, p, e, 1, &rc);
+  if (!fq) return rc;
+  const uint32_t l0 = fq->F.emb[(uint32_t)coeffs[0]], lt = fq->F.emb[(uint32_t)coeffs[nc - 1]];
+  for (uint32_t k = 1; k <= kmax; ++k) {
+    int64_t N = 0;
+    for (uint32_t j = 1; j <= k; ++j) {
+      if (orbit ? (k % j) : (j != k)) continue;
+      const uint64_t s = nx[j] - z[j] - ns[j];
+      const uint64_t sq = ((k / j) % 2 == 0) ? s + ns[j] : s;
+      N += (int64_t)(orbit ? j : 1) * (int64_t)(z[j] + 2 * sq);
+    }
+    const bool keven = k % 2 == 0;
+    N += coeffs[0] == 0 ? 1 : (keven || (l0 & 1u) == 0 ? 2 : 0);
+    N += coeffs[nc - 1] == 0 ? 1 : (keven || (lt & 1u) == 0 ? 2 : 0);
+    out_N[k - 1] = N;
+  }
+  if (timings) {
+    timings[0] = build_ms;
+    timings[1] = upload_ms;
+    timings[2] = eval_ms;
+  }
+  return HWC_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1101,6 +1226,10 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     for (auto& sl : c->slots) {
       if (sl.p) (void)hipFree(sl.p);
       if (sl.done) (void)hipEventDestroy(sl.done);
+    }
+    for (auto& kv : c->single) {
+      if (kv.second.d_zech) (void)hipFree(kv.second.d_zech);
+      if (kv.second.d_reps) (void)hipFree(kv.second.d_reps);
     }
     if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->d_err) (void)hipFree(c->d_err);
@@ -1261,6 +1390,14 @@ int hwc_count_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* c
   if (flags & HWC_VALIDATE) return fail(c, HWC_ERR_ARG, "HWC_VALIDATE does not apply to the map");
   if (capacity && (!keys || !counts)) return fail(c, HWC_ERR_ARG, "null output buffer");
   return run_map(c, q, g, keys, counts, capacity, len, reps, flags);
+}
+
+int hwc_count_single(hwc_ctx* c, uint32_t q, uint32_t g, const int16_t* coeffs, uint32_t kmax, int64_t* out_N,
+                     double* timings, uint32_t flags) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  return run_single(c, q, g, coeffs, kmax, out_N, timings, flags);
 }
 
 int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream) {

@@ -1391,6 +1391,46 @@ __global__ __launch_bounds__(256) void gen_reps_kernel(uint32_t q, uint32_t ncoe
 }
 
 // ----------------------------------------------------------------------------
+// one curve over a large field (the single-curve experiment of Table 1): the
+// paper's lane-per-x layout.  Every lane takes its own x (an orbit
+// representative or any nonzero element, by log), evaluates f(x) by Horner
+// in absolute logs with zero-safe Zech additions (table of one period, M u32
+// entries, in device memory: at F_{3001^2} it is 36 MB and lives in L2/MALL),
+// and counts roots and nonsquares; waves sum by ballots, one atomic per wave.
+
+__device__ __forceinline__ uint32_t mod_once(uint32_t v, uint32_t M) { return v >= M ? v - M : v; }
+
+__global__ __launch_bounds__(256) void single_kernel(const uint32_t* __restrict__ zech, const uint32_t* __restrict__ xs,
+                                                     uint64_t nx, SingleDesc f, unsigned long long* __restrict__ out) {
+  const uint32_t M = f.M;
+  uint64_t zeros = 0, odd = 0;
+  for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nx; t += (uint64_t)gridDim.x * blockDim.x) {
+    const uint32_t x = xs ? xs[t] : (uint32_t)t;
+    uint32_t acc = f.lc[f.d];
+    for (int i = (int)f.d - 1; i >= 0; --i) {
+      acc = acc == M ? M : mod_once(acc + x, M);          // times x
+      const uint32_t c = f.lc[i];
+      if (c == M) continue;                               // zero coefficient
+      if (acc == M) { acc = c; continue; }
+      // acc + c = c (1 + gamma^(acc - c))
+      const uint32_t z = zech[acc >= c ? acc - c : acc + M - c];
+      acc = z == M ? M : mod_once(c + z, M);
+    }
+    zeros += acc == M;
+    odd += (acc != M) & (acc & 1u);
+  }
+  // wave sums, then one atomic per wave
+  for (int off = 32; off > 0; off >>= 1) {
+    zeros += __shfl_down(zeros, off);
+    odd += __shfl_down(odd, off);
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicAdd(out, (unsigned long long)zeros);
+    atomicAdd(out + 1, (unsigned long long)odd);
+  }
+}
+
+// ----------------------------------------------------------------------------
 // host-callable launchers (C++ linkage, used by capi.cpp)
 
 template <int G, typename CT, int WPE>
@@ -1601,6 +1641,15 @@ hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t
   else
     hipLaunchKernelGGL(gen_reps_kernel<int16_t>, dim3(grid), dim3(256), 0, s, q, ncoef, d, i, j, cj, ncj, start,
                        count, static_cast<int16_t*>(out));
+  return hipGetLastError();
+}
+
+
+hipError_t launch_single(const uint32_t* zech, const uint32_t* xs, uint64_t nx, const SingleDesc& f,
+                         unsigned long long* out, hipStream_t s) {
+  if (nx == 0) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((nx + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(single_kernel, dim3(grid), dim3(256), 0, s, zech, xs, nx, f, out);
   return hipGetLastError();
 }
 

@@ -68,6 +68,13 @@ __host__ __device__ constexpr uint32_t lam_shift(uint32_t j) {
   return j == 1 ? 0u : j == 2 ? 4u : j == 3 ? 7u : j == 4 ? 9u : j == 5 ? 11u : 7u + j;
 }
 
+// One curve for the lane-per-x kernel: coefficient logs in F_{q^k} (M where
+// the coefficient is zero), degree d, M = q^k - 1.
+struct SingleDesc {
+  uint32_t lc[2 * kMaxG + 3];
+  uint32_t d, M;
+};
+
 // One request of a multi-plan launch (device memory).
 struct JobDesc {
   const PlanDesc* plan;   // device copy of the job's plan

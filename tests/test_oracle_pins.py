@@ -281,3 +281,16 @@ def test_rejects_bad_input(oracle_mod):
         oracle_mod.count_curves(5, 2, np.array([[1, 0, 0, 0, 0, 0, 0]], dtype=np.int16))
     with pytest.raises(ValueError):
         oracle_mod.count_curves(5, 2, np.array([[5, 0, 0, 0, 0, 1, 0]], dtype=np.int16))
+
+
+def test_table1_golden_is_the_oracle(oracle_mod):
+    """tests/golden/table1_counts.txt holds oracle counts; recheck the small primes."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_counts.txt")
+    rows = [list(map(int, l.split())) for l in open(path) if l.strip() and not l.startswith("#")]
+    curve = [17, 12, 16, 11, 10, 13, 12]
+    for p, n1, n2 in rows[:3]:
+        r = np.array([[c % p for c in curve]], dtype=np.int16)
+        assert oracle_mod.count_curves(p, 2, r, kmax=2)[0].tolist() == [n1, n2]
+    for p, n1, n2 in rows:                                      # Weil bound, g = 2
+        assert (n1 - p - 1) ** 2 <= 16 * p and (n2 - p * p - 1) ** 2 <= 16 * p * p
