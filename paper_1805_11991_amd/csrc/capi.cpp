@@ -325,13 +325,26 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   hwc::PlanDesc& D = P->desc;
   D.q = q; D.p = p; D.g = g; D.ncoef = 2 * g + 3; D.orbit = orbit;
   std::vector<std::vector<uint32_t>> gtabs(g);
+  // forms C and D hold 2 Z (byte units) with the marker 2M over two periods;
+  // the (single) form C table goes first, at byte offset 0 of the image
+  for (uint32_t j = 0; j < g; ++j) {
+    if (form[j] != hwc::kFormC) continue;
+    const hwc::Field& F = P->fields[j]->F;
+    const uint32_t M = (uint32_t)F.M;
+    if (!img.empty()) return fail(c, HWC_ERR_DEVICE, "two LDS levels in element form");
+    std::vector<uint16_t> tab(2 * (size_t)M);
+    for (uint32_t i = 0; i < 2 * M; ++i) {
+      const uint32_t z = F.zech[i % M];
+      tab[i] = (uint16_t)(z == M ? 2 * M : 2 * z);
+    }
+    D.lv[j].tab_off = put(tab);
+  }
   for (uint32_t j = 0; j < g; ++j) {
     const hwc::Field& F = P->fields[j]->F;
     const uint32_t M = (uint32_t)F.M;
     hwc::LevelDesc& L = D.lv[j];
     L.M = M;
     L.form = form[j];
-    L.tab_off = 0;
     if (form[j] == hwc::kFormA) {
       std::vector<uint16_t> tab(5 * (size_t)M, 0);
       for (uint32_t i = 0; i < 3 * M; ++i) {
@@ -339,13 +352,13 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
         tab[i] = (uint16_t)(z == M ? 6 * M : 2 * z);
       }
       L.tab_off = put(tab);
-    } else if (form[j] == hwc::kFormC) {
-      std::vector<uint16_t> tab(2 * (size_t)M);
-      for (uint32_t i = 0; i < 2 * M; ++i) tab[i] = (uint16_t)F.zech[i % M];
-      L.tab_off = put(tab);
-    } else {
+    } else if (form[j] == hwc::kFormD) {
+      L.tab_off = 0;
       gtabs[j].resize(2 * (size_t)M);
-      for (uint32_t i = 0; i < 2 * M; ++i) gtabs[j][i] = F.zech[i % M];
+      for (uint32_t i = 0; i < 2 * M; ++i) {
+        const uint32_t z = F.zech[i % M];
+        gtabs[j][i] = z == M ? 2 * M : 2 * z;
+      }
     }
     if (orbit) {
       L.nx = (uint32_t)F.prim_reps.size();

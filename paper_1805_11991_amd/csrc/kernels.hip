@@ -27,16 +27,15 @@
 
 namespace hwc {
 
-// LDS reads at absolute LDS byte addresses.  The kernels fold the base of
-// the dynamic LDS block into their per-lane offsets once, so a table step is
-// one add and one read.
+// LDS reads at absolute LDS byte addresses.  The count and batch kernels
+// declare no static LDS, so their dynamic block -- the table image -- starts
+// at address 0 (prepare_kernels checks this on the host), and a table step is
+// one add and one read with no base to add.
 typedef const __attribute__((address_space(3))) uint16_t* lds16_ptr;
 typedef const __attribute__((address_space(3))) uint32_t* lds32_ptr;
 __device__ __forceinline__ uint32_t lds_u16(uint32_t addr) { return *(lds16_ptr)(size_t)addr; }
 __device__ __forceinline__ uint32_t lds_u32(uint32_t addr) { return *(lds32_ptr)(size_t)addr; }
-__device__ __forceinline__ uint32_t lds_base(const uint32_t* p) {
-  return (uint32_t)(size_t)(const __attribute__((address_space(3))) uint32_t*)p;
-}
+constexpr uint32_t kImageBase = 0;   // LDS address of the dynamic block
 
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -568,10 +567,16 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t
   }
 }
 
-// Form C/D relative Horner for two x at once (element units, index folded
-// into the table's two periods; reads of both chains inside one uniform
-// branch per position).  Not EXACT: a vanishing partial sum sets hit and the
-// caller redoes the pair with EXACT, which restarts from the coefficient.
+// Forms C and D work in byte units like form A: every log, delta and power
+// is doubled, the period is M2 = 2M and the zero marker is M2, so a folded
+// index is the byte offset of the entry (form C's table sits at the start of
+// the LDS image) and a log's parity is its bit 1.  In the functions below
+// the parameter M is this byte period.
+//
+// Form C/D relative Horner for two x at once (index folded into the table's
+// two periods; reads of both chains inside one uniform branch per position).
+// Not EXACT: a vanishing partial sum sets hit and the caller redoes the pair
+// with EXACT, which restarts from the coefficient.
 template <int NC, bool EXACT, bool GLOBAL>
 __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M,
                                           const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t x0,
@@ -587,8 +592,8 @@ __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restri
       if ((mask >> i) & 1u) {
         const uint32_t r0 = min(a0 + del[i] + p0, a0 + del[i] + p0 - M);   // < 2M
         const uint32_t r1 = min(a1 + del[i] + p1, a1 + del[i] + p1 - M);
-        const uint32_t v0 = GLOBAL ? gtab[r0] : lds_u16(tab + 2 * r0);
-        const uint32_t v1 = GLOBAL ? gtab[r1] : lds_u16(tab + 2 * r1);
+        const uint32_t v0 = GLOBAL ? gtab[r0 >> 1] : lds_u16(tab + r0);
+        const uint32_t v1 = GLOBAL ? gtab[r1 >> 1] : lds_u16(tab + r1);
         if (EXACT) {
           a0 = (a0 == M) ? 0u : v0;
           a1 = (a1 == M) ? 0u : v1;
@@ -608,31 +613,34 @@ __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restri
 template <int NC, bool GLOBAL>
 __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t* xs, uint32_t nx,
                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
-  const uint32_t M = L.M, tab = L.tab_off;
+  const uint32_t M = 2 * L.M, tab = L.tab_off;
   const uint32_t* gtab = L.gtab;
+  uint32_t delb[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) delb[i] = 2 * del[i];
   for (uint32_t ix = 0; ix < nx; ix += 2) {
-    const uint32_t x0 = xs ? sload(xs, ix) : ix;
+    const uint32_t x0 = 2 * (xs ? sload(xs, ix) : ix);
     const bool two = ix + 1 < nx;
-    const uint32_t x1 = two ? (xs ? sload(xs, ix + 1) : ix + 1) : x0;
+    const uint32_t x1 = two ? 2 * (xs ? sload(xs, ix + 1) : ix + 1) : x0;
     bool hit = false;
     uint32_t p0, p1, a0, a1;
-    horner_c2<NC, false, GLOBAL>(tab, gtab, M, del, d, mask, x0, x1, a0, a1, p0, p1, hit);
-    if (__ballot(hit)) horner_c2<NC, true, GLOBAL>(tab, gtab, M, del, d, mask, x0, x1, a0, a1, p0, p1, hit);
-    c.add(p0 & 1u, a0 == M, a0 & 1u);   // M is even: the marker counts as even
-    if (two) c.add(p1 & 1u, a1 == M, a1 & 1u);
+    horner_c2<NC, false, GLOBAL>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
+    if (__ballot(hit)) horner_c2<NC, true, GLOBAL>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
+    c.add((p0 >> 1) & 1u, a0 == M, (a0 >> 1) & 1u);   // bit 1 of the marker 2M is 0
+    if (two) c.add((p1 >> 1) & 1u, a1 == M, (a1 >> 1) & 1u);
   }
 }
 
-// Form C/D table entry r in [0, 2M): Z(r mod M) in element units, M where
-// 1 + gamma^r = 0.
+// Form C/D table entry at byte offset r in [0, 2 M2): 2 Z((r/2) mod M), or the
+// marker M2 where 1 + gamma^(r/2) = 0.
 template <bool GLOBAL>
 __device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t r) {
-  return GLOBAL ? gtab[r] : lds_u16(tab + 2 * r);
+  return GLOBAL ? gtab[r >> 1] : lds_u16(tab + r);
 }
 
 __device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v, v - M); }  // [0, 2M) -> [0, M)
 
-// Sub-polynomial r of the split on a form C/D level (element units): as
+// Sub-polynomial r of the split on a form C/D level (byte units): as
 // horner_class, with the index folded into the table's two periods.  Not
 // EXACT: a vanishing partial sum sets hit (the caller redoes the tuple).
 template <int NC, int MS, int R, bool FULL, int D, bool EXACT, bool GLOBAL>
@@ -704,7 +712,7 @@ __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* _
   for (int r = 0; r < 4; ++r) pend[r] = p[r];
 }
 
-// Zero-safe sum in element units (absolute logs in [0, M) or the zero marker M).
+// Zero-safe sum (absolute logs in [0, M) or the zero marker M, byte units).
 template <bool GLOBAL>
 __device__ __forceinline__ uint32_t zadd_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M, uint32_t u,
                                            uint32_t v) {
@@ -721,23 +729,28 @@ __device__ __forceinline__ uint32_t zmul_c(uint32_t v, uint32_t k, uint32_t M) {
 }
 
 // Radix-2x2 split over mu_4 cosets on a form C/D level: the same stages as the
-// MS = 4 case of sweep_split_a in element units.  Without the form A zero
-// region, a vanishing top-class value is selected to relative log 0.
+// MS = 4 case of sweep_split_a (byte units, K.ll doubled by the caller).
 template <int NC, bool FULL, int D, bool GLOBAL>
-__device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t (&sdel)[NC], uint32_t d,
-                                              uint32_t mask, const SplitConst& K, LevelCounts& c) {
-  const uint32_t M = L.M, step = M / 4, tab = L.tab_off, h = M / 2;
+__device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t (&sdel_e)[NC], uint32_t d,
+                                              uint32_t mask, const SplitConst& Ke, LevelCounts& c) {
+  uint32_t sdel[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) sdel[i] = 2 * sdel_e[i];
+  SplitConst K = Ke;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) K.ll[r] = 2 * Ke.ll[r];
+  const uint32_t M = 2 * L.M, step = M / 4, tab = L.tab_off, h = M / 2;
   const uint32_t* gtab = L.gtab;
   const uint32_t K1 = M + submod(K.ll[1], K.ll[0], M);
   const uint32_t K2 = M + submod(K.ll[2], K.ll[0], M);
   const uint32_t K3 = M + submod(K.ll[3], K.ll[1], M);
-  const uint32_t fix = (K.ll[0] ^ K.blane) & 1u;
+  const uint32_t fix = ((K.ll[0] >> 1) ^ K.blane) & 1u;
   const uint32_t sup = mask | (1u << d);
   const uint32_t nt = L.nt;
   const uint32_t* xt = L.xs_t;
   uint32_t xnext = (xt && nt) ? sload(xt, 0) : 0u;
   for (uint32_t it = 0; it < nt; ++it) {
-    const uint32_t x = xnext;
+    const uint32_t x = 2 * xnext;
     if (it + 1 < nt) xnext = xt ? sload(xt, it + 1) : it + 1;
     const uint32_t x2 = addmod(x, x, M);
     const uint32_t Y = addmod(x2, x2, M);
@@ -762,7 +775,7 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
       a0 = av[0]; a1 = av[1]; a2 = av[2]; a3 = av[3];
       p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3];
     }
-    const uint32_t cls = FULL ? 0u : (p0 & 1u);
+    const uint32_t cls = FULL ? 0u : ((p0 >> 1) & 1u);
     const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);
     const uint32_t uO = addmod(addmod(x2, p3, M), p1 ? M - p1 : 0u, M);
     const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
@@ -789,7 +802,7 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
         const uint32_t O = (s & 1u) ? Om : Op;
         const uint32_t F = (s & 1u) ? Fm : Fp;
         r[s] = tab_c<GLOBAL>(tab, gtab, fold(O + F + addmod(vf, s * step, M), M));
-        u += (E ^ r[s]) & 1u;
+        u += ((E ^ r[s]) >> 1) & 1u;
         anyz |= r[s] == M;
       }
       if (__ballot(anyz)) {
@@ -799,10 +812,10 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
           const uint32_t E = (s & 1u) ? Em : Ep;
           const bool z = r[s] == M;
           zs += z;
-          u += z ? 0u : ((E ^ r[s]) & 1u);
+          u += z ? 0u : (((E ^ r[s]) >> 1) & 1u);
         }
       }
-      odd = ((a0 ^ fix) & 1u) ? (4 - zs) - u : u;
+      odd = (((a0 >> 1) ^ fix) & 1u) ? (4 - zs) - u : u;
     } else {
       const uint32_t v0 = zmul_c(a0, addmod(K.ll[0], p0, M), M);
       const uint32_t v1 = zmul_c(a1, addmod(K.ll[1], p1, M), M);
@@ -820,7 +833,7 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
         const uint32_t f = zadd_c<GLOBAL>(tab, gtab, M, E, zmul_c(O, addmod(x, s * step, M), M));
         const bool z = f == M;
         zs += z;
-        odd += z ? 0u : ((f ^ K.blane ^ cls) & 1u);
+        odd += z ? 0u : (((f >> 1) ^ K.blane ^ cls) & 1u);
       }
     }
     c.add_n(cls, 4, zs, odd);
@@ -932,6 +945,8 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
       }
     }
   } else {
+    // byte units; form C's table starts the LDS image
+    L.tab_off = lb;
 #define HWC_FORM_C(GL)                                                                   \
   do {                                                                                   \
     if (ms) {                                                                            \
@@ -1051,7 +1066,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
                                                      uint32_t* __restrict__ outLv) {
   const PlanDesc& P = *Pd;
   extern __shared__ uint32_t lds32[];
-  const uint32_t lb = lds_base(lds32);
+  constexpr uint32_t lb = kImageBase;
   for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
   __syncthreads();
   const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -1099,12 +1114,16 @@ __device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, 
 #undef HWC_JOB
 }
 
+// slot: byte offset, past every image, of the word that broadcasts the
+// popped chunk to the workgroup (inside the dynamic block, so the kernel has
+// no static LDS)
 __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__ jobs,
                                                      const uint64_t* __restrict__ chunks,
-                                                     const uint32_t* __restrict__ nchunks_p, uint32_t* queue) {
+                                                     const uint32_t* __restrict__ nchunks_p, uint32_t* queue,
+                                                     uint32_t slot) {
   extern __shared__ uint32_t lds32[];
-  __shared__ uint64_t sh_chunk;
-  const uint32_t lb = lds_base(lds32);
+  uint64_t& sh_chunk = *reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(lds32) + slot);
+  constexpr uint32_t lb = kImageBase;
   const uint32_t wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
   const uint32_t nchunks = *nchunks_p;
   const PlanDesc* staged = nullptr;
@@ -1463,7 +1482,21 @@ hipError_t prepare_kernels() {
 #undef HWC_PREP
   if (e == hipSuccess)
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsImageLimit);
+                            kLdsImageLimit + 16);
+  // the table image must start at LDS address 0: no static LDS in these kernels
+  auto no_static = [&](const void* f) {
+    hipFuncAttributes a{};
+    if (e == hipSuccess) e = hipFuncGetAttributes(&a, f);
+    if (e == hipSuccess && a.sharedSizeBytes != 0) e = hipErrorInvalidKernelFile;
+  };
+#define HWC_NOSTATIC(GG, CT)                                              \
+  no_static(reinterpret_cast<const void*>(&count_kernel<GG, CT, 1>));    \
+  no_static(reinterpret_cast<const void*>(&count_kernel<GG, CT, 6>));    \
+  no_static(reinterpret_cast<const void*>(&count_kernel<GG, CT, 8>));
+  HWC_NOSTATIC(1, int8_t) HWC_NOSTATIC(2, int8_t) HWC_NOSTATIC(3, int8_t) HWC_NOSTATIC(4, int8_t)
+  HWC_NOSTATIC(1, int16_t) HWC_NOSTATIC(2, int16_t) HWC_NOSTATIC(3, int16_t) HWC_NOSTATIC(4, int16_t)
+#undef HWC_NOSTATIC
+  no_static(reinterpret_cast<const void*>(&batch_kernel));
   return e;
 }
 
@@ -1497,7 +1530,8 @@ hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, 
 
 hipError_t launch_batch(const JobDesc* jobs, const uint64_t* chunks, const uint32_t* nchunks, uint32_t* queue,
                         uint32_t lds_bytes, uint32_t grid, uint32_t block, hipStream_t s) {
-  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), lds_bytes, s, jobs, chunks, nchunks, queue);
+  const uint32_t slot = (lds_bytes + 15u) & ~15u;
+  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), slot + 16, s, jobs, chunks, nchunks, queue, slot);
   return hipGetLastError();
 }
 
@@ -1513,7 +1547,8 @@ hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint
 }
 
 hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, block, lds_bytes);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, block,
+                                                      ((lds_bytes + 15u) & ~15u) + 16);
 }
 
 template <typename CT, int WPE>
