@@ -107,6 +107,7 @@ struct SingleTabs {
   uint32_t* d_zech = nullptr;   // Zech table, one period (M entries)
   uint32_t* d_reps = nullptr;   // primitive Frobenius orbit representatives
   uint64_t nreps = 0;
+  uint64_t last_use = 0;
 };
 
 struct GraphEntry {
@@ -1093,8 +1094,20 @@ int single_tables(hwc_ctx* c, uint32_t p, uint32_t e, uint32_t k, std::shared_pt
   auto key = std::make_tuple(p, e, k);
   auto it = c->single.find(key);
   if (it != c->single.end()) {
+    it->second.last_use = ++c->tick;
     *out = &it->second;
     return HWC_OK;
+  }
+  // keep the tables of a few fields only (each can be tens of MB)
+  constexpr size_t kMaxSingleFields = 8;
+  while (c->single.size() >= kMaxSingleFields) {
+    HIPX(c, hipDeviceSynchronize());
+    auto victim = c->single.begin();
+    for (auto v = c->single.begin(); v != c->single.end(); ++v)
+      if (v->second.last_use < victim->second.last_use) victim = v;
+    (void)hipFree(victim->second.d_zech);
+    (void)hipFree(victim->second.d_reps);
+    c->single.erase(victim);
   }
   SingleTabs T;
   const hwc::Field& F = fe->F;
@@ -1104,6 +1117,7 @@ int single_tables(hwc_ctx* c, uint32_t p, uint32_t e, uint32_t k, std::shared_pt
   HIPX(c, hipMalloc(&T.d_reps, std::max<size_t>(T.nreps, 1) * 4));
   if (T.nreps) HIPX(c, hipMemcpy(T.d_reps, F.prim_reps.data(), T.nreps * 4, hipMemcpyHostToDevice));
   *upload_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t1).count();
+  T.last_use = ++c->tick;
   auto ins = c->single.emplace(key, T);
   *out = &ins.first->second;
   return HWC_OK;
