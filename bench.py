@@ -207,8 +207,14 @@ def main():
         "prep_ms": round(prof["prep_ms"] / prof["calls"], 4),
         "hist_ms": round(prof["hist_ms"] / prof["calls"], 4),
     }
+    # the practical ceiling of that bound on this device: a kernel doing
+    # nothing but dependent random reads of a table the size of the top level's
+    ceiling = ctx.lds_gather_rate(2 * (q ** g - 1), chains=4)
+    roofline["gather_ceiling"] = round(ceiling / 1e9, 2)
+    roofline["frac_of_gather_ceiling"] = round(achieved / ceiling, 4)
     log(f"roofline: count kernel {count_ms:.3f} ms, {achieved / 1e9:.1f} Glookup/s "
-        f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak)")
+        f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak, {achieved / ceiling:.3f} of the "
+        f"measured gather ceiling {ceiling / 1e9:.0f} Glookup/s)")
 
     extra = {}
     if not args.quick:

@@ -190,6 +190,13 @@ int hwc_count_map(hwc_ctx* ctx, uint32_t q, uint32_t g, int32_t* keys, uint64_t*
 int hwc_count_single(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs, uint32_t kmax, int64_t* out_N,
                      double* timings, uint32_t flags);
 
+/* Diagnostic: the rate of dependent random u16 gathers from an LDS table of
+ * table_entries entries (the count kernel's bound, Sec. 3.2 tables read at
+ * random), measured with `chains` (1, 2 or 4) independent chains per lane on
+ * a grid of 32 workgroups of 256 lanes per CU.  *lookups_per_s receives the
+ * best of two timed runs.  Synchronous. */
+int hwc_lds_gather_rate(hwc_ctx* ctx, uint32_t table_entries, uint32_t chains, double* lookups_per_s);
+
 /* Several requests, enqueued on `stream` in order (the persistent batched
  * form; each job is a hwc_count_curves_dev call). */
 int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);

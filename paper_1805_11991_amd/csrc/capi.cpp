@@ -55,6 +55,8 @@ hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t
                            hipStream_t s);
 hipError_t launch_single(const uint32_t* zech, const uint32_t* xs, uint64_t nx, const SingleDesc& f,
                          unsigned long long* out, hipStream_t s);
+hipError_t launch_lds_gather(uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid, uint32_t* sink,
+                             hipStream_t s);
 }  // namespace hwc
 
 namespace {
@@ -1433,6 +1435,42 @@ int hwc_count_single(hwc_ctx* c, uint32_t q, uint32_t g, const int16_t* coeffs, 
   std::lock_guard<std::mutex> lk(c->mu);
   c->err.clear();
   return run_single(c, q, g, coeffs, kmax, out_N, timings, flags);
+}
+
+int hwc_lds_gather_rate(hwc_ctx* c, uint32_t table_entries, uint32_t chains, double* lookups_per_s) {
+  if (!c || !lookups_per_s) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (c->device < 0) return fail(c, HWC_ERR_NO_DEVICE, "host-only context");
+  if (table_entries < 64 || table_entries > hwc::kLdsImageLimit / 2) return fail(c, HWC_ERR_ARG, "table size");
+  if (chains != 1 && chains != 2 && chains != 4) return fail(c, HWC_ERR_ARG, "chains must be 1, 2 or 4");
+  HIPX(c, hipSetDevice(c->device));
+  int rc;
+  if ((rc = ensure(c, c->hout, 64))) return rc;
+  int ncu = 0;
+  HIPX(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const uint32_t grid = (uint32_t)ncu * 32, steps = 4096;
+  uint32_t* sink = static_cast<uint32_t*>(c->hout.p);
+  hipEvent_t e0, e1;
+  HIPX(c, hipEventCreate(&e0));
+  HIPX(c, hipEventCreate(&e1));
+  float best = 0;
+  for (int rep = 0; rep < 3; ++rep) {   // warm-up, then the best of two
+    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+        hwc::launch_lds_gather(table_entries, chains, steps, grid, sink, c->stream) != hipSuccess ||
+        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(c, HWC_ERR_DEVICE, "gather benchmark failed");
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0 && (best == 0 || ms < best)) best = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *lookups_per_s = (double)grid * 256.0 * steps * chains / (best * 1e-3);
+  return HWC_OK;
 }
 
 int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream) {

@@ -43,7 +43,7 @@ HWC_OPT_SPLIT_MIN_M = 6
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
+           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
            "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
 
 
@@ -110,6 +110,7 @@ def load():
         "hwc_count_lambda_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, vp, u64, vp, u32, vp]),
         "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_single": (i32, [vp, u32, u32, vp, u32, vp, vp, u32]),
+        "hwc_lds_gather_rate": (i32, [vp, u32, u32, ctypes.POINTER(ctypes.c_double)]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -289,6 +290,12 @@ class Context:
         self._check(load().hwc_count_single(self._h, q, g, c.ctypes.data, kmax, out.ctypes.data, t.ctypes.data,
                                             flags))
         return out, {"tables_ms": float(t[0]), "upload_ms": float(t[1]), "kernel_ms": float(t[2])}
+
+    def lds_gather_rate(self, table_entries: int, chains: int = 4) -> float:
+        """Measured dependent random u16 LDS gathers per second (diagnostic)."""
+        r = ctypes.c_double()
+        self._check(load().hwc_lds_gather_rate(self._h, table_entries, chains, ctypes.byref(r)))
+        return r.value
 
     def count_batch(self, jobs: list[dict], flags: int = 0, stream=None):
         arr = (hwc_job * max(len(jobs), 1))()

@@ -440,3 +440,17 @@ def test_batch_g4_small_fields_sampled(gctx, oracle_mod, curvegen_mod):
         else:
             idx = np.unique(np.concatenate([rng.integers(0, len(c), 40), [len(c) - 1]]))
             assert np.array_equal(N[idx], oracle_mod.count_curves(q, 4, c[idx])), q
+
+
+@pytest.mark.gpu
+def test_lds_gather_rate_is_below_the_bank_peak(gctx):
+    from paper_1805_11991_amd import hwcount
+    # the diagnostic gather kernel: a positive rate no faster than 32 u16 reads
+    # per CU per clock (256 CUs, at most 2.4 GHz), and bad arguments rejected
+    peak = 32 * 256 * 2.4e9
+    for chains in (1, 4):
+        r = gctx.lds_gather_rate(4392, chains)
+        assert 0 < r <= peak * 1.05, r
+    for entries, chains in ((10, 4), (1 << 20, 4), (4392, 3)):
+        with pytest.raises(hwcount.HwcError):
+            gctx.lds_gather_rate(entries, chains)
