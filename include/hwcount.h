@@ -223,7 +223,7 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
                                     memory (served by L2/MALL) instead of LDS; 0..15 */
 #define HWC_OPT_WAVES_PER_SIMD 5 /* count-kernel build that leaves registers for at least 6 or 8 waves per SIMD
                                     (0 or 1: no constraint) */
-#define HWC_OPT_SPLIT_MIN_M 6     /* split only levels with at least this many nonzero elements (default 256):
+#define HWC_OPT_SPLIT_MIN_M 6     /* split only levels with at least this many nonzero elements (default 64):
                                     on small fields a wave meets vanishing bases too often */
 int hwc_ctx_set_option(hwc_ctx* ctx, int opt, int64_t value);
 /* The same option for the plan of (q, g) and the sweep of `flags` only

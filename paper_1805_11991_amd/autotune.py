@@ -31,7 +31,7 @@ DB_DIR = os.path.join(HERE, "autotune")
 
 SPACE = {
     "split": [1, 0],
-    "split_min_m": [256, 2048],
+    "split_min_m": [64, 2048],
     "block": [256, 512, 1024],
     "waves_per_simd": [1, 6, 8],
     "device_tables": ["none", "top"],

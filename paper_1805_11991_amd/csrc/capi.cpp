@@ -75,7 +75,7 @@ constexpr uint32_t kFlagSqf = 1u << 30;
 // Launch and layout choices for one plan (defaults or an autotuned override).
 struct Tuning {
   bool split = true;            // split evaluation over mu_m cosets on form A levels
-  uint32_t split_min_m = 256;   // ... of at least this many nonzero elements
+  uint32_t split_min_m = 64;    // ... of at least this many nonzero elements
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
@@ -263,6 +263,15 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
   return 0;
 }
 
+// Split factor of a level: m = 4 when 4 | q-1, else (form A levels only) 3
+// when 3 | q-1, else 2; 0 when the level is not split.
+uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
+  if (!T.split || M < T.split_min_m) return 0;
+  const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
+  if (form != hwc::kFormA && m != 4) return 0;   // forms C/D split over mu_4 only
+  return m;
+}
+
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;
 // then move the largest LDS levels to D until the image fits.
 std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
@@ -428,16 +437,14 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       D.lv[j].gtab = P->d_gtab[j];
     }
   }
-  // split evaluation over mu_m cosets: m = 4 when 4 | q-1, else (form A
-  // levels only) 3 when 3 | q-1, else 2
+  // split evaluation over mu_m cosets
   P->d_tup.assign(g, nullptr);
   P->d_sgl.assign(g, nullptr);
   for (uint32_t j = 0; j < g; ++j) {
     hwc::LevelDesc& L = D.lv[j];
     L.msplit = 0; L.nt = 0; L.ns = 0; L.xs_t = nullptr; L.xs_s = nullptr;
-    if (!T.split || L.M < T.split_min_m) continue;
-    const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
-    if (L.form != hwc::kFormA && m != 4) continue;   // forms C/D split over mu_4 only
+    const uint32_t m = split_factor(q, L.form, L.M, T);
+    if (!m) continue;
     L.msplit = m;
     if (!orbit) {
       L.nt = L.M / m;

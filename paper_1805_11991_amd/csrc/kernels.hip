@@ -338,9 +338,11 @@ __device__ __forceinline__ uint32_t horner_class(const uint32_t (&sdel)[NC], uin
 }
 
 // The MS sub-polynomials of a sparse row (form A) in one pass over the
-// positions from the top: every position issues its read (a position without
-// a term, or the top term of its class, reads an in-bounds entry that is then
-// discarded), so the classes' reads overlap in straight-line code.
+// positions from the top: every position issues its read, so the classes'
+// reads overlap in straight-line code.  A position without a term, or the top
+// term of its class, reads the table's first entry on every lane (sdel of the
+// top position is the bare table offset) and discards it: one address for
+// the whole wave, so the LDS serves it as a broadcast, with no bank conflicts.
 template <int NC, int MS>
 __device__ __forceinline__ void horner_classes_a(const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
                                                  uint32_t Y, uint32_t (&a)[4], uint32_t (&pend)[4]) {
@@ -355,7 +357,7 @@ __device__ __forceinline__ void horner_classes_a(const uint32_t (&sdel)[NC], uin
     const bool present = (sup >> i) & 1u;
     if (st[r]) p[r] = addmod(p[r], Y, M);
     const bool go = present && st[r];
-    const uint32_t v = lds_u16(a[r] + sdel[i] + (go ? 2 * p[r] : 0u));
+    const uint32_t v = lds_u16(go ? a[r] + sdel[i] + 2 * p[r] : sdel[NC - 1]);
     a[r] = go ? v : a[r];
     if (present) {
       st[r] = true;
@@ -697,7 +699,8 @@ __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* _
     const bool present = (sup >> i) & 1u;
     if (st[r]) p[r] = addmod(p[r], Y, M);
     const bool go = present && st[r];
-    const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a[r] + sdel[i] + (go ? p[r] : 0u), M));
+    // a position that does not step reads entry 0 on every lane (a broadcast)
+    const uint32_t v = tab_c<GLOBAL>(tab, gtab, go ? fold(a[r] + sdel[i] + p[r], M) : 0u);
     if (EXACT) a[r] = go ? ((a[r] == M) ? 0u : v) : a[r];
     else {
       hit |= go && v == M;
