@@ -69,6 +69,16 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
     return total, plain
 
 
+def evaluated_rows(ctx, q: int, g: int, d_rows):
+    """The rows the count kernel evaluates for d_rows (rows with zero
+    coefficients replaced by their dense translates), on the host."""
+    import torch
+    out = torch.empty_like(d_rows)
+    ctx.translate_dev(q, g, d_rows, out)
+    ctx.status()
+    return out.cpu().numpy()
+
+
 def kernel_source_hash() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -187,7 +197,8 @@ def main():
     count_ms = prof["count_ms"] / prof["calls"]
     levels = ctx.plan_info(q, g)
     nx = [L["nx"] for L in levels]
-    lookups, plain_lookups = lookups_per_batch(curves, levels)
+    # the rows the kernel evaluates: zero-coefficient rows become dense translates
+    lookups, plain_lookups = lookups_per_batch(evaluated_rows(ctx, q, g, bufs[1]), levels)
     achieved = lookups / (count_ms * 1e-3)
     traffic = measured_traffic()
     roofline = {
@@ -272,7 +283,7 @@ def main():
         runner(13, 4, bufs4, 0)()
         p4 = ctx.profile_read()
         ctx.profile(False)
-        lk4, _ = lookups_per_batch(bufs4[0], ctx.plan_info(13, 4))
+        lk4, _ = lookups_per_batch(evaluated_rows(ctx, 13, 4, bufs4[1]), ctx.plan_info(13, 4))
         g4["count_kernel_ms"] = round(p4["count_ms"], 3)
         g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
         g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)

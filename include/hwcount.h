@@ -161,6 +161,20 @@ int hwc_count_lambda_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coe
                          int32_t* d_out_N, uint32_t* d_out_lambda, int32_t* d_hist_keys, uint64_t* d_hist_counts,
                          uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream);
 
+/* The rows the counting entry points evaluate in place of the caller's.  A
+ * translate f(x + t), t in F_q, has the same N_k, factorization pattern and
+ * discriminant as f (x -> x + t permutes every F_{q^k} and keeps the degree
+ * and leading coefficient; Algorithm 1 divides out the same equivalence).
+ * When the plan of (q, g) translates (q <= 32 and HWC_OPT_SHIFT on, the
+ * default), a row with a zero coefficient below its leading one becomes
+ * f(x + t) for the first code t = 1, 2, .., 8 that leaves no such zero, since
+ * such dense rows are cheaper to count; every other row is copied.  d_coeffs
+ * as in hwc_count_curves_dev; d_out: [n][2g+3] of the same coeff_bytes, device
+ * memory, owned by the caller, not overlapping d_coeffs.  Enqueued on
+ * `stream`; errors as hwc_count_curves_dev (rows are not validated here). */
+int hwc_translate_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
+                      void* d_out, void* stream);
+
 /* The map N_{g,q} of eq. (1.2) over every square-free f of degree 2g+1 and
  * 2g+2, by Algorithm 1: the reduced, twist-reduced representatives of
  * Sec. 1.2-1.3 are generated and counted on the device (with lambda), each
@@ -225,6 +239,11 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
                                     (0 or 1: no constraint) */
 #define HWC_OPT_SPLIT_MIN_M 6     /* split only levels with at least this many nonzero elements (default 64):
                                     on small fields a wave meets vanishing bases too often */
+#define HWC_OPT_SHIFT 7           /* 1 (default): for q <= 32, a row with a zero coefficient below its leading
+                                    one is counted as f(x + t), t in F_q, when some t (of the first 8 tried)
+                                    leaves no such zero -- same N_k, factorization pattern and discriminant
+                                    (x -> x + t permutes F_{q^k}); the caller's rows are not modified.
+                                    0: rows are counted as given */
 int hwc_ctx_set_option(hwc_ctx* ctx, int opt, int64_t value);
 /* The same option for the plan of (q, g) and the sweep of `flags` only
  * (overrides the context default; used to apply autotuned settings). */

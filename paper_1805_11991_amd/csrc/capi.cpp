@@ -34,6 +34,8 @@ hipError_t prepare_kernels();
 hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,
                            int32_t* outN, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n, uint32_t q, const uint32_t* step,
+                        void* out, hipStream_t s);
 hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_t q, uint32_t g, uint16_t* pid,
                          uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
                          uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
@@ -76,6 +78,7 @@ constexpr uint32_t kFlagSqf = 1u << 30;
 struct Tuning {
   bool split = true;            // split evaluation over mu_m cosets on form A levels
   uint32_t split_min_m = 64;    // ... of at least this many nonzero elements
+  bool shift = true;            // count rows with zero coefficients as dense translates f(x + t)
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
@@ -92,6 +95,7 @@ struct DevPlan {
   std::vector<uint32_t*> d_reps;
   std::vector<uint32_t*> d_gtab;     // form D tables
   std::vector<uint32_t*> d_tup, d_sgl;  // split-evaluation tuple representatives and singles
+  uint32_t* d_shift = nullptr;       // q^3-byte step table of the dense translates, or nullptr
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
   uint32_t block = 256, grid = 0, wpe = 1;
@@ -146,13 +150,13 @@ struct hwc_ctx {
   uint64_t table_bytes = 0, hits = 0, misses = 0, tick = 0, evictions = 0;
   int cus = 0;
   // scratch
-  Buf pid, small, tiles, perm, lv, N, hist, codes, hout;
+  Buf pid, small, tiles, perm, lv, N, hist, codes, hout, tcodes;
   Buf mcodes, mN, mlam, mhk, mhc, mcj;   // map of eq. (1.2): one chunk of representatives
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, SingleTabs> single;   // one-curve tables
   uint32_t* d_err = nullptr;
   std::list<GraphEntry> graphs;
   // multi-plan scratch
-  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords;
+  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords, btcodes;
   JobSlot slots[kJobSlots];
   int next_slot = 0;
   // every call's work is ordered after the previous call's, whatever the stream
@@ -246,6 +250,8 @@ void free_plan(DevPlan* P) {
     if (t) (void)hipFree(t);
   for (auto* t : P->d_sgl)
     if (t) (void)hipFree(t);
+  if (P->d_shift) (void)hipFree(P->d_shift);
+  P->d_shift = nullptr;
   P->d_tup.clear();
   P->d_sgl.clear();
   P->d_image = nullptr;
@@ -463,6 +469,32 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     P->dev_bytes += (tup.size() + sgl.size()) * 4;
     c->table_bytes += (tup.size() + sgl.size()) * 4;
   }
+  // dense translates: step[t][a][b] = a + t b over F_q (codes), q^3 bytes
+  if (T.shift && q <= hwc::kShiftMaxQ) {
+    const hwc::Field& F1 = P->fields[0]->F;   // F_q itself: emb = log of a code
+    std::vector<uint32_t> expq(q - 1);
+    for (uint32_t cc = 1; cc < q; ++cc) expq[F1.emb[cc]] = cc;
+    auto add = [&](uint32_t a, uint32_t b) {   // digit-wise in base p
+      uint32_t r = 0, pw = 1;
+      for (uint32_t i = 0; i < e; ++i, pw *= p) r += ((a / pw % p + b / pw % p) % p) * pw;
+      return r;
+    };
+    auto mul = [&](uint32_t a, uint32_t b) -> uint32_t {
+      if (a == 0 || b == 0) return 0;
+      return expq[(F1.emb[a] + F1.emb[b]) % (q - 1)];
+    };
+    const size_t q3 = (size_t)q * q * q;
+    std::vector<uint8_t> st((q3 + 3) / 4 * 4, 0);
+    for (uint32_t t = 0; t < q; ++t)
+      for (uint32_t b = 0; b < q; ++b) {
+        const uint32_t tb = mul(t, b);
+        for (uint32_t a = 0; a < q; ++a) st[((size_t)t * q + a) * q + b] = (uint8_t)add(a, tb);
+      }
+    HIPX(c, hipMalloc(&P->d_shift, st.size()));
+    HIPX(c, hipMemcpy(P->d_shift, st.data(), st.size(), hipMemcpyHostToDevice));
+    P->dev_bytes += st.size();
+    c->table_bytes += st.size();
+  }
   HIPX(c, hipMalloc(&P->d_desc, sizeof(hwc::PlanDesc)));
   HIPX(c, hipMemcpy(P->d_desc, &D, sizeof(hwc::PlanDesc), hipMemcpyHostToDevice));
   P->dev_bytes += bytes;
@@ -492,6 +524,7 @@ struct Scratch {
   uint32_t* perm;
   uint32_t* lv;
   void* hist;
+  void* tcodes;   // dense translates of the rows (plans with a step table)
   uint64_t max_tiles;
 };
 
@@ -518,6 +551,7 @@ int get_scratch(hwc_ctx* c, uint64_t n, uint32_t g, bool plain, bool hist, Scrat
   s->perm = static_cast<uint32_t*>(c->perm.p);
   s->lv = plain ? static_cast<uint32_t*>(c->lv.p) : nullptr;
   s->hist = hist ? c->hist.p : nullptr;
+  s->tcodes = nullptr;
   return HWC_OK;
 }
 
@@ -543,6 +577,10 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
       if (rc) return rc;
     }
     HIPX(c, hipEventRecord(ev[0], s));
+  }
+  if (P->d_shift && n > 0) {
+    HIPX(c, hwc::launch_shift(cb, g, codes, n, P->q, P->d_shift, S.tcodes, s));
+    codes = S.tcodes;
   }
   HIPX(c, hwc::launch_bucket(cb, codes, n, P->q, g, S.pid, S.counts, c->d_err, S.bucket_start, S.tile_start,
                              S.cursor, S.ntiles, S.queue, S.tiles, S.perm, S.max_tiles, s));
@@ -602,6 +640,10 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   }
   Scratch S;
   if ((rc = get_scratch(c, n, g, (flags & HWC_PLAIN) != 0 || lam != nullptr, hk != nullptr, &S))) return rc;
+  if (P->d_shift) {
+    if ((rc = ensure(c, c->tcodes, std::max<uint64_t>(n, 1) * (2 * g + 3) * cb))) return rc;
+    S.tcodes = c->tcodes.p;
+  }
   const bool use_graph = !(flags & (HWC_PLAIN | HWC_NO_GRAPH)) && n > 0 && !c->profile;
   if ((rc = order_begin(c, s))) return rc;
   if (!use_graph) {
@@ -650,9 +692,18 @@ struct BatchPlan {
   std::vector<DevPlan*> plans;      // per job (input order)
   std::vector<uint64_t> off, toff;  // row and tile offsets (sorted order)
   std::vector<uint64_t> max_tiles;
-  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0;
+  std::vector<uint64_t> tco;        // byte offset of the job's dense translates, or kNoShift
+  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0, tbytes = 0;
   uint32_t lds = 0, block = 256, grid = 0, per = 8;
 };
+
+constexpr uint64_t kNoShift = ~0ull;
+
+// Rows the batch kernel reads for sorted job r: the dense translates when its
+// plan has a step table, else the caller's rows.
+const void* batch_rows(hwc_ctx* c, const hwc_job& J, const BatchPlan& B, size_t r) {
+  return B.tco[r] == kNoShift ? J.d_coeffs : static_cast<const void*>(static_cast<char*>(c->btcodes.p) + B.tco[r]);
+}
 
 int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, const BatchPlan& B, const hwc::JobDesc* d_jobs,
                   hipStream_t s) {
@@ -665,7 +716,10 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, const BatchPlan
     const hwc_job& J = jobs[B.order[r]];
     const DevPlan* P = B.plans[B.order[r]];
     uint32_t* sm = small + r * kSmallStride;
-    HIPX(c, hwc::launch_bucket(J.coeff_bytes, J.d_coeffs, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
+    const void* rows = batch_rows(c, J, B, r);
+    if (rows != J.d_coeffs)
+      HIPX(c, hwc::launch_shift(J.coeff_bytes, J.g, J.d_coeffs, J.n, P->q, P->d_shift, const_cast<void*>(rows), s));
+    HIPX(c, hwc::launch_bucket(J.coeff_bytes, rows, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
                                sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
                                B.max_tiles[r], s));
   }
@@ -739,6 +793,12 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     B.max_tiles.push_back(mt);
     B.ntot += J.n;
     B.tiles_tot += mt;
+    if (B.plans[B.order[r]]->d_shift && J.n > 0) {
+      B.tco.push_back(B.tbytes);
+      B.tbytes += (J.n * (2 * J.g + 3) * J.coeff_bytes + 255) / 256 * 256;
+    } else {
+      B.tco.push_back(kNoShift);
+    }
     B.chunks_max += mt / B.per + 1;
     if (J.d_hist_keys) B.nhist = std::max<uint64_t>(B.nhist, J.n);
   }
@@ -749,12 +809,13 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
   if ((rc = ensure(c, c->bchunks, B.chunks_max * 8))) return rc;
   if ((rc = ensure(c, c->bcstart, (njobs + 1) * 4))) return rc;
   if ((rc = ensure(c, c->bwords, 64))) return rc;
+  if (B.tbytes && (rc = ensure(c, c->btcodes, B.tbytes))) return rc;
   if (B.nhist && (rc = ensure(c, c->hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
   std::vector<hwc::JobDesc> hj(njobs);
   for (size_t r = 0; r < njobs; ++r) {
     const hwc_job& J = jobs[B.order[r]];
     hj[r].plan = B.plans[B.order[r]]->d_desc;
-    hj[r].codes = J.d_coeffs;
+    hj[r].codes = batch_rows(c, J, B, r);
     hj[r].perm = static_cast<uint32_t*>(c->bperm.p) + B.off[r];
     hj[r].tiles = static_cast<uint64_t*>(c->btiles.p) + B.toff[r];
     hj[r].outN = J.d_out_N;
@@ -888,6 +949,10 @@ int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
     case HWC_OPT_WG_PER_CU:
       if (value < 0 || value > 64) return fail(c, HWC_ERR_ARG, "workgroups per CU must be in 0..64");
       T.wg_per_cu = (uint32_t)value;
+      break;
+    case HWC_OPT_SHIFT:
+      if (value != 0 && value != 1) return fail(c, HWC_ERR_ARG, "shift must be 0 or 1");
+      T.shift = value != 0;
       break;
     case HWC_OPT_SPLIT_MIN_M:
       if (value < 0 || value > (1 << 24)) return fail(c, HWC_ERR_ARG, "split threshold must be in 0..2^24");
@@ -1265,7 +1330,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     for (auto& kv : c->plans) free_plan(kv.second.get());
     for (Buf* b : {&c->pid, &c->small, &c->tiles, &c->perm, &c->lv, &c->N, &c->hist, &c->codes, &c->hout, &c->bpid,
                    &c->bperm, &c->btiles, &c->bsmall, &c->bchunks, &c->bcstart, &c->bwords, &c->mcodes, &c->mN,
-                   &c->mlam, &c->mhk, &c->mhc, &c->mcj})
+                   &c->mlam, &c->mhk, &c->mhc, &c->mcj, &c->tcodes, &c->btcodes})
       if (b->p) (void)hipFree(b->p);
     for (auto& sl : c->slots) {
       if (sl.p) (void)hipFree(sl.p);
@@ -1424,6 +1489,30 @@ int hwc_count_lambda_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeff
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   return run_dev(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity, d_hist_len,
                  flags, s, d_out_lambda);
+}
+
+int hwc_translate_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
+                      void* d_out, void* stream) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  int rc = check_args(c, q, g, 0);
+  if (rc) return rc;
+  if (coeff_bytes != 1 && coeff_bytes != 2) return fail(c, HWC_ERR_ARG, "coeff_bytes must be 1 or 2");
+  if (coeff_bytes == 1 && q > 127) return fail(c, HWC_ERR_ARG, "int8 codes need q <= 127");
+  if (n == 0) return HWC_OK;
+  if (!d_coeffs || !d_out) return fail(c, HWC_ERR_ARG, "null device pointer");
+  const uint64_t bytes = n * (2 * g + 3) * (uint64_t)coeff_bytes;
+  const char* a = static_cast<const char*>(d_coeffs);
+  const char* b = static_cast<const char*>(d_out);
+  if (a < b + bytes && b < a + bytes) return fail(c, HWC_ERR_ARG, "d_out overlaps d_coeffs");
+  HIPX(c, hipSetDevice(c->device));
+  DevPlan* P = nullptr;
+  if ((rc = get_plan(c, q, g, 1u, &P))) return rc;
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  if (P->d_shift) HIPX(c, hwc::launch_shift(coeff_bytes, g, d_coeffs, n, q, P->d_shift, d_out, s));
+  else HIPX(c, hipMemcpyAsync(d_out, d_coeffs, bytes, hipMemcpyDeviceToDevice, s));
+  return HWC_OK;
 }
 
 int hwc_count_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts, uint64_t capacity,

@@ -99,6 +99,73 @@ __global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ co
     if (hist[i]) atomicAdd(&counts[i], hist[i]);
 }
 
+// Dense translates.  x -> x + t (t in F_q) permutes every F_{q^k} and keeps
+// the degree and the leading coefficient, so f(x + t) has the same N_k, the
+// same factorization pattern and the same discriminant as f (the same
+// equivalence the reduced enumeration of Algorithm 1 divides out).  A row with
+// a zero coefficient below its leading one is replaced by f(x + t) for the
+// first code t = 1, 2, .. (at most kShiftTries of them) that leaves no such
+// zero; a row without one, or with codes out of range, is copied as it is.
+// Dense rows take the counting kernels' straight-line path, which is cheaper
+// than the sparse one even though it has more terms.
+//
+// The coefficients of f(x + t) come from repeated synthetic division: for
+// k = 0 .. D-1 and i = D-1 down to k, w_i <- w_i + t w_{i+1}.  Each step is one
+// read of the LDS table step[t][a][b] = a + t b (F_q codes, q^3 bytes); fully
+// unrolled, the steps' dependences form a triangle whose longest chain is 2D.
+template <int NC, typename CT>
+__global__ __launch_bounds__(256) void shift_kernel(const CT* __restrict__ in, uint64_t n, uint32_t q,
+                                                    const uint32_t* __restrict__ step, CT* __restrict__ out) {
+  extern __shared__ uint32_t sh32[];
+  const uint32_t qq = q * q, words = (qq * q + 3) / 4;
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) sh32[i] = step[i];
+  __syncthreads();
+  const uint8_t* tab = reinterpret_cast<const uint8_t*>(sh32);
+  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+    CT raw[NC];
+    uint32_t c[NC];
+    bool valid = true;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) {
+      raw[i] = in[r * NC + i];
+      const int v = (int)raw[i];
+      valid = valid && v >= 0 && v < (int)q;
+      c[i] = (v >= 0 && v < (int)q) ? (uint32_t)v : 0u;
+    }
+    const uint32_t d = c[NC - 1] ? NC - 1 : NC - 2;
+    bool need = false;
+#pragma unroll
+    for (int i = 0; i < NC - 1; ++i) need = need || ((uint32_t)i < d && c[i] == 0);
+    need = need && valid && c[d] != 0;
+    bool done = false;
+    uint32_t w[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) w[i] = c[i];
+    for (uint32_t t = 1; t < q && t <= kShiftTries; ++t) {
+      if (!__ballot(need && !done)) break;
+      const uint32_t base = t * qq;
+      uint32_t v[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) v[i] = c[i];
+#pragma unroll
+      for (int k = 0; k < NC - 1; ++k) {
+#pragma unroll
+        for (int i = NC - 2; i >= k; --i) v[i] = tab[base + v[i] * q + v[i + 1]];
+      }
+      bool dense = true;
+#pragma unroll
+      for (int i = 0; i < NC - 1; ++i) dense = dense && ((uint32_t)i >= d || v[i] != 0);
+      if (need && !done && dense) {
+#pragma unroll
+        for (int i = 0; i < NC; ++i) w[i] = v[i];
+        done = true;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NC; ++i) out[r * NC + i] = done ? (CT)w[i] : raw[i];
+  }
+}
+
 // Exclusive scans over patterns (one block of 1024 threads, npat <= 2048).
 __global__ __launch_bounds__(1024) void bucket_scan_kernel(const uint32_t* __restrict__ counts, uint32_t npat,
                                                            uint32_t* __restrict__ bucket_start,
@@ -1602,6 +1669,29 @@ hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   if (n == 0) return hipSuccess;
   const uint32_t grid = (uint32_t)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n, uint32_t q, const uint32_t* step,
+                        void* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (q > kShiftMaxQ || q < 3) return hipErrorInvalidValue;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
+  const uint32_t lds = (q * q * q + 3) / 4 * 4;
+#define HWC_SHIFT(GG)                                                                                       \
+  case GG:                                                                                                  \
+    if (coeff_bytes == 1)                                                                                   \
+      hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int8_t>), dim3(grid), dim3(256), lds, s,                   \
+                         static_cast<const int8_t*>(in), n, q, step, static_cast<int8_t*>(out));           \
+    else                                                                                                    \
+      hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int16_t>), dim3(grid), dim3(256), lds, s,                  \
+                         static_cast<const int16_t*>(in), n, q, step, static_cast<int16_t*>(out));         \
+    break;
+  switch (g) {
+    HWC_SHIFT(1) HWC_SHIFT(2) HWC_SHIFT(3) HWC_SHIFT(4)
+    default: return hipErrorInvalidValue;
+  }
+#undef HWC_SHIFT
   return hipGetLastError();
 }
 

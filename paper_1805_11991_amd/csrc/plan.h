@@ -32,6 +32,10 @@ constexpr uint32_t kFormCMaxM = 32767;   // M must fit in 15 bits
 constexpr int kWave = 64;
 // LDS of one CU is 160 KiB; 256 bytes stay free for the kernels' own variables
 constexpr uint32_t kLdsImageLimit = 160 * 1024 - 256;
+// Dense translates (rows replaced by f(x + t), see shift_kernel): fields with
+// q <= kShiftMaxQ, whose q^3-byte step table fits LDS, at most kShiftTries t.
+constexpr uint32_t kShiftMaxQ = 32;
+constexpr uint32_t kShiftTries = 8;
 
 struct LevelDesc {
   uint32_t M;         // |F_{q^j}^x|

@@ -39,12 +39,14 @@ HWC_OPT_WG_PER_CU = 3
 HWC_OPT_DEVICE_TABLES = 4
 HWC_OPT_WAVES_PER_SIMD = 5
 HWC_OPT_SPLIT_MIN_M = 6
+HWC_OPT_SHIFT = 7
 
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile", "hwc_ctx_profile_read",
-           "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
+           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate",
+           "hwc_translate_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile",
+           "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
 
 
 class HwcError(RuntimeError):
@@ -111,6 +113,7 @@ def load():
         "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_single": (i32, [vp, u32, u32, vp, u32, vp, vp, u32]),
         "hwc_lds_gather_rate": (i32, [vp, u32, u32, ctypes.POINTER(ctypes.c_double)]),
+        "hwc_translate_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
@@ -290,6 +293,15 @@ class Context:
         self._check(load().hwc_count_single(self._h, q, g, c.ctypes.data, kmax, out.ctypes.data, t.ctypes.data,
                                             flags))
         return out, {"tables_ms": float(t[0]), "upload_ms": float(t[1]), "kernel_ms": float(t[2])}
+
+    def translate_dev(self, q: int, g: int, d_coeffs, d_out, stream=None):
+        """The rows the counting calls evaluate (dense translates), into d_out
+        (torch tensor shaped and typed like d_coeffs)."""
+        if d_out.shape != d_coeffs.shape or d_out.dtype != d_coeffs.dtype:
+            raise ValueError("d_out must match d_coeffs in shape and dtype")
+        s = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+        self._check(load().hwc_translate_dev(self._h, q, g, _ptr(d_coeffs), d_coeffs.element_size(),
+                                             d_coeffs.shape[0], _ptr(d_out), s))
 
     def lds_gather_rate(self, table_entries: int, chains: int = 4) -> float:
         """Measured dependent random u16 LDS gathers per second (diagnostic)."""
