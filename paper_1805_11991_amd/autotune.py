@@ -13,7 +13,8 @@ Search space (library options, see include/hwcount.h):
   split           split evaluation over m-th roots of unity on LDS levels (on/off)
   split_min_m     smallest level (nonzero elements) that is split
   block           threads per workgroup of the count kernel (256, 512, 1024)
-  waves_per_simd  register budget of the kernel build (1: free, 6, 8)
+  waves_per_simd  register budget of the kernel build (1: free, 6; the 8-wave build
+                  spills registers to scratch at g = 3 and 4 and is left out)
   device_tables   which levels' Zech tables sit in device memory instead of LDS
                   (none, the top level, all)
 """
@@ -33,7 +34,7 @@ SPACE = {
     "split": [1, 0],
     "split_min_m": [64, 2048],
     "block": [256, 512, 1024],
-    "waves_per_simd": [1, 6, 8],
+    "waves_per_simd": [1, 6],
     "device_tables": ["none", "top"],
 }
 
