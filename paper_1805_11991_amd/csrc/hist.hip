@@ -28,9 +28,10 @@ struct KeyRadix {
   uint64_t radix[5];   // R_k, then 2^18 for the code
 };
 
+template <typename K>
 __global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N,
                                                         const uint32_t* __restrict__ lam, uint64_t n, KeyRadix kr,
-                                                        uint64_t* __restrict__ keys, uint32_t* __restrict__ err) {
+                                                        K* __restrict__ keys, uint32_t* __restrict__ err) {
   uint32_t bad = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t key = 0;
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restric
       if ((uint64_t)v >= kr.radix[kr.g]) { bad = 1; v = 0; }
       key = key * kr.radix[kr.g] + v;
     }
-    keys[i] = key;
+    keys[i] = (K)key;
   }
   if (bad) atomicOr(err, 4u);
 }
@@ -124,9 +125,10 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uin
   }
 }
 
-// ---- stable LSD radix sort of u64 keys ----
+// ---- stable LSD radix sort of u32 or u64 keys (u32 when the key fits) ----
 
-__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __restrict__ keys, uint64_t n,
                                                                   uint32_t shift, uint32_t nblocks,
                                                                   uint32_t* __restrict__ bh) {
   __shared__ uint32_t cnt[kRadixBins];
@@ -144,10 +146,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const uint64_t
 // Keys of a block are ranked in 16 rounds of 256 (round-major = index order).
 // Within a round: lanes with equal digits are found by bit ballots, waves are
 // ordered through per-wave digit counts in LDS.
-__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const uint64_t* __restrict__ in, uint64_t n,
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __restrict__ in, uint64_t n,
                                                                      uint32_t shift, uint32_t nblocks,
                                                                      const uint32_t* __restrict__ bh_scanned,
-                                                                     uint64_t* __restrict__ out) {
+                                                                     K* __restrict__ out) {
   constexpr int kWaves = kSortThreads / 64;
   __shared__ uint32_t running[kRadixBins];
   __shared__ uint32_t wcnt[kWaves][kRadixBins];
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const uint6
   for (int r = 0; r < kSortItems; ++r) {
     const uint64_t i = base + (uint64_t)r * kSortThreads + t;
     const bool valid = i < n;
-    const uint64_t key = valid ? in[i] : 0ull;
+    const K key = valid ? in[i] : (K)0;
     const uint32_t dig = (uint32_t)((key >> shift) & (kRadixBins - 1));
     for (uint32_t d = t; d < (uint32_t)(kWaves * kRadixBins); d += blockDim.x) (&wcnt[0][0])[d] = 0;
     __syncthreads();
@@ -189,7 +192,8 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const uint6
 
 // ---- run-length encoding of sorted keys ----
 
-__global__ __launch_bounds__(256) void head_flags_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+template <typename K>
+__global__ __launch_bounds__(256) void head_flags_kernel(const K* __restrict__ keys, uint64_t n,
                                                          uint32_t* __restrict__ flags) {
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
     flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
@@ -197,7 +201,8 @@ __global__ __launch_bounds__(256) void head_flags_kernel(const uint64_t* __restr
 
 // For each run head i (pos = its run index): decode key into the tuple and
 // store the run start; counts are finished by runs_count_kernel.
-__global__ __launch_bounds__(256) void runs_kernel(const uint64_t* __restrict__ keys, uint64_t n,
+template <typename K>
+__global__ __launch_bounds__(256) void runs_kernel(const K* __restrict__ keys, uint64_t n,
                                                    const uint32_t* __restrict__ flags,
                                                    const uint32_t* __restrict__ pos, KeyRadix kr, uint64_t cap,
                                                    int32_t* __restrict__ out_keys, uint64_t* __restrict__ starts) {
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(256) void runs_kernel(const uint64_t* __restrict__ 
     const uint64_t j = pos[i];
     starts[j] = i;
     if (j < cap) {
-      uint64_t key = keys[i];
+      uint64_t key = (uint64_t)keys[i];
       for (int k = (int)kr.width - 1; k >= 0; --k) {
         out_keys[j * kr.width + k] = (int32_t)(key % kr.radix[k]);
         key /= kr.radix[k];
@@ -262,6 +267,34 @@ static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, 
   return hipGetLastError();
 }
 
+// The sort, run-length and decode steps of hist_run on keys of type K.
+template <typename K>
+static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t n, const KeyRadix& kr,
+                                 uint32_t npass, uint64_t nb_sort, uint64_t nbh, K* keysA, K* keysB,
+                                 uint64_t* starts, uint32_t* bh, uint32_t* flags, uint32_t* pos, uint32_t* sums,
+                                 uint32_t* totals, int32_t* out_keys, uint64_t* out_counts, uint64_t cap,
+                                 uint64_t* out_len, uint32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(make_keys_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, lam, n, kr, keysA, err);
+  for (uint32_t pass = 0; pass < npass; ++pass) {
+    const uint32_t shift = pass * kRadixBits;
+    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+                       (uint32_t)nb_sort, bh);
+    hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+                       (uint32_t)nb_sort, bh, keysB);
+    K* tmp = keysA; keysA = keysB; keysB = tmp;
+  }
+  hipLaunchKernelGGL(head_flags_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags);
+  hipError_t e = scan_exclusive(flags, n, pos, sums, totals, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(runs_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags, pos, kr, cap,
+                     out_keys, starts);
+  hipLaunchKernelGGL(runs_count_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, starts, totals, n, cap,
+                     out_counts, out_len);
+  return hipGetLastError();
+}
+
 // Histogram of N[n][g] (and, when lam is given, the factorization codes
 // lam[n] as a last column) into out_keys[cap][width] / out_counts[cap];
 // *out_len gets the number of distinct tuples (which may exceed cap: then only
@@ -305,25 +338,12 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
     if (out_len) hipLaunchKernelGGL(hist_empty_kernel, dim3(1), dim3(64), 0, s, out_len);
     return hipGetLastError();
   }
-  hipLaunchKernelGGL(make_keys_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, lam, n, kr, keysA, err);
-  for (uint32_t pass = 0; pass < npass; ++pass) {
-    const uint32_t shift = pass * kRadixBits;
-    hipLaunchKernelGGL(radix_hist_kernel, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
-                       (uint32_t)nb_sort, bh);
-    hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
-                       (uint32_t)nb_sort, bh, keysB);
-    uint64_t* tmp = keysA; keysA = keysB; keysB = tmp;
-  }
-  hipLaunchKernelGGL(head_flags_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags);
-  hipError_t e = scan_exclusive(flags, n, pos, sums, totals, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(runs_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags, pos, kr, cap,
-                     out_keys, starts);
-  hipLaunchKernelGGL(runs_count_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, starts, totals, n, cap,
-                     out_counts, out_len);
-  return hipGetLastError();
+  if (nbits <= 32)
+    return sort_and_count<uint32_t>(N, lam, n, kr, npass, nb_sort, nbh, reinterpret_cast<uint32_t*>(keysA),
+                                    reinterpret_cast<uint32_t*>(keysB), starts, bh, flags, pos, sums, totals,
+                                    out_keys, out_counts, cap, out_len, err, s);
+  return sort_and_count<uint64_t>(N, lam, n, kr, npass, nb_sort, nbh, keysA, keysB, starts, bh, flags, pos, sums,
+                                  totals, out_keys, out_counts, cap, out_len, err, s);
 }
 
 }  // namespace hwc
