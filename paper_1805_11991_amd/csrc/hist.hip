@@ -18,8 +18,6 @@ namespace hwc {
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;  // keys per block
-constexpr int kRadixBits = 8;
-constexpr int kRadixBins = 1 << kRadixBits;
 constexpr int kScanTile = 4096;
 
 struct KeyRadix {
@@ -127,10 +125,11 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uin
 
 // ---- stable LSD radix sort of u32 or u64 keys (u32 when the key fits) ----
 
-template <typename K>
+template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __restrict__ keys, uint64_t n,
                                                                   uint32_t shift, uint32_t nblocks,
                                                                   uint32_t* __restrict__ bh) {
+  constexpr uint32_t kRadixBins = 1u << RB;
   __shared__ uint32_t cnt[kRadixBins];
   for (uint32_t i = threadIdx.x; i < kRadixBins; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
@@ -146,12 +145,13 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __res
 // Keys of a block are ranked in 16 rounds of 256 (round-major = index order).
 // Within a round: lanes with equal digits are found by bit ballots, waves are
 // ordered through per-wave digit counts in LDS.
-template <typename K>
+template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __restrict__ in, uint64_t n,
                                                                      uint32_t shift, uint32_t nblocks,
                                                                      const uint32_t* __restrict__ bh_scanned,
                                                                      K* __restrict__ out) {
   constexpr int kWaves = kSortThreads / 64;
+  constexpr uint32_t kRadixBins = 1u << RB;
   __shared__ uint32_t running[kRadixBins];
   __shared__ uint32_t wcnt[kWaves][kRadixBins];
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
     // peers: valid lanes of this wave with the same digit
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
+    for (int b = 0; b < RB; ++b) {
       const uint64_t ones = __ballot(((dig >> b) & 1u) != 0);
       peers &= ((dig >> b) & 1u) ? ones : ~ones;
     }
@@ -247,7 +247,7 @@ static uint32_t grid_for(uint64_t n, uint32_t block, uint32_t cap) {
 // bytes of scratch needed by hist_run for n keys
 uint64_t hist_scratch_bytes(uint64_t n) {
   const uint64_t nb_sort = (n + kSortTile - 1) / kSortTile;
-  const uint64_t nbh = nb_sort * kRadixBins;
+  const uint64_t nbh = nb_sort * 512;   // digits of up to 9 bits
   const uint64_t big = (n > nbh ? n : nbh);
   const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
   return 2 * n * 8                 // keys ping-pong
@@ -268,7 +268,7 @@ static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, 
 }
 
 // The sort, run-length and decode steps of hist_run on keys of type K.
-template <typename K>
+template <typename K, int RB>
 static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t n, const KeyRadix& kr,
                                  uint32_t npass, uint64_t nb_sort, uint64_t nbh, K* keysA, K* keysB,
                                  uint64_t* starts, uint32_t* bh, uint32_t* flags, uint32_t* pos, uint32_t* sums,
@@ -276,12 +276,12 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
                                  uint64_t* out_len, uint32_t* err, hipStream_t s) {
   hipLaunchKernelGGL(make_keys_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, lam, n, kr, keysA, err);
   for (uint32_t pass = 0; pass < npass; ++pass) {
-    const uint32_t shift = pass * kRadixBits;
-    hipLaunchKernelGGL(radix_hist_kernel<K>, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+    const uint32_t shift = pass * RB;
+    hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
                        (uint32_t)nb_sort, bh);
     hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(radix_scatter_kernel<K>, dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
+    hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
                        (uint32_t)nb_sort, bh, keysB);
     K* tmp = keysA; keysA = keysB; keysB = tmp;
   }
@@ -320,10 +320,13 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
   }
   if (bits > 63.0) return hipErrorInvalidValue;
   const uint32_t nbits = (uint32_t)bits + 1;
-  const uint32_t npass = (nbits + kRadixBits - 1) / kRadixBits;
+  // 9-bit digits when they save a pass over 8-bit ones
+  const uint32_t p8 = (nbits + 7) / 8, p9 = (nbits + 8) / 9;
+  const int rb = p9 < p8 ? 9 : 8;
+  const uint32_t npass = rb == 9 ? p9 : p8;
   uint8_t* p = static_cast<uint8_t*>(scratch);
   const uint64_t nb_sort = (n + kSortTile - 1) / kSortTile;
-  const uint64_t nbh = nb_sort * kRadixBins;
+  const uint64_t nbh = nb_sort * (1u << rb);
   const uint64_t big = (n > nbh ? n : nbh);
   const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
   uint64_t* keysA = reinterpret_cast<uint64_t*>(p); p += n * 8;
@@ -338,12 +341,18 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
     if (out_len) hipLaunchKernelGGL(hist_empty_kernel, dim3(1), dim3(64), 0, s, out_len);
     return hipGetLastError();
   }
-  if (nbits <= 32)
-    return sort_and_count<uint32_t>(N, lam, n, kr, npass, nb_sort, nbh, reinterpret_cast<uint32_t*>(keysA),
-                                    reinterpret_cast<uint32_t*>(keysB), starts, bh, flags, pos, sums, totals,
-                                    out_keys, out_counts, cap, out_len, err, s);
-  return sort_and_count<uint64_t>(N, lam, n, kr, npass, nb_sort, nbh, keysA, keysB, starts, bh, flags, pos, sums,
-                                  totals, out_keys, out_counts, cap, out_len, err, s);
+  uint32_t* keysA32 = reinterpret_cast<uint32_t*>(keysA);
+  uint32_t* keysB32 = reinterpret_cast<uint32_t*>(keysB);
+#define HWC_SORT(KT, RBV, A, B)                                                                                \
+  return sort_and_count<KT, RBV>(N, lam, n, kr, npass, nb_sort, nbh, A, B, starts, bh, flags, pos, sums, totals, \
+                                 out_keys, out_counts, cap, out_len, err, s)
+  if (nbits <= 32) {
+    if (rb == 9) HWC_SORT(uint32_t, 9, keysA32, keysB32);
+    HWC_SORT(uint32_t, 8, keysA32, keysB32);
+  }
+  if (rb == 9) HWC_SORT(uint64_t, 9, keysA, keysB);
+  HWC_SORT(uint64_t, 8, keysA, keysB);
+#undef HWC_SORT
 }
 
 }  // namespace hwc
