@@ -239,6 +239,10 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
                                     (0 or 1: no constraint) */
 #define HWC_OPT_SPLIT_MIN_M 6     /* split only levels with at least this many nonzero elements (default 64):
                                     on small fields a wave meets vanishing bases too often */
+#define HWC_OPT_MFMA 8            /* 1 (default): for prime q <= 31, when the level images fit LDS, f(x) is
+                                    evaluated as an int8 matrix product of the coefficients with the
+                                    coordinates of the powers x^i over F_q (Sec. 1.1's sums, exact in int32),
+                                    the character read from a table; 0: Zech logarithms for every plan */
 #define HWC_OPT_SHIFT 7           /* 1 (default): for q <= 32, a row with a zero coefficient below its leading
                                     one is counted as f(x + t), t in F_q, when some t (of the first 8 tried)
                                     leaves no such zero -- same N_k, factorization pattern and discriminant
@@ -255,9 +259,11 @@ int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags
  * folded index; 2: u32 in device memory), the number nx of swept x, the
  * weight of each, the split factor m (0: plain Horner; else the sweep runs nt
  * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
- * x^m, plus ns single points), and the LDS bytes of the plan. */
+ * x^m, plus ns single points), the LDS bytes of the plan, and mfma = 1 when
+ * the plan counts by int8 matrix products (HWC_OPT_MFMA) instead of Zech
+ * logarithms. */
 typedef struct {
-  uint32_t M, form, nx, weight, msplit, nt, ns, lds_bytes;
+  uint32_t M, form, nx, weight, msplit, nt, ns, lds_bytes, mfma;
 } hwc_level_desc;
 int hwc_plan_info(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags, hwc_level_desc* levels);
 

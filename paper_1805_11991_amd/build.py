@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libhwcount.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "hist.hip", "diag.hip", "capi.cpp", "field.cpp"]
+SOURCES = ["kernels.hip", "vcount.hip", "hist.hip", "diag.hip", "capi.cpp", "field.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]

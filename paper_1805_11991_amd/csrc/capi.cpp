@@ -31,6 +31,11 @@ hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, 
 hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, uint32_t wpe,
                            int* blocks_per_cu);
 hipError_t prepare_kernels();
+hipError_t prepare_vcount();
+hipError_t occupancy_vcount(uint32_t g, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_vcount(const VPlanDesc& V, const VPlanDesc* dV, int coeff_bytes, const void* codes, uint64_t n,
+                         uint32_t lvl_lo, uint32_t lvl_hi, int32_t* outN, uint32_t* outLv, uint32_t* err,
+                         uint32_t grid, uint32_t block, hipStream_t s);
 hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,
                            int32_t* outN, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -79,6 +84,7 @@ struct Tuning {
   bool split = true;            // split evaluation over mu_m cosets on form A levels
   uint32_t split_min_m = 64;    // ... of at least this many nonzero elements
   bool shift = true;            // count rows with zero coefficients as dense translates f(x + t)
+  bool mfma = true;             // prime q <= 31: count by int8 matrix products where the image fits LDS
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
@@ -96,6 +102,12 @@ struct DevPlan {
   std::vector<uint32_t*> d_gtab;     // form D tables
   std::vector<uint32_t*> d_tup, d_sgl;  // split-evaluation tuple representatives and singles
   uint32_t* d_shift = nullptr;       // q^3-byte step table of the dense translates, or nullptr
+  // matrix-core path (VPlanDesc): used for counting when vpath is set
+  bool vpath = false;
+  hwc::VPlanDesc vdesc{};
+  hwc::VPlanDesc* d_vdesc = nullptr;
+  void* d_vimage = nullptr;
+  uint32_t vgrid = 0, vblock = 256;
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
   uint32_t block = 256, grid = 0, wpe = 1;
@@ -252,6 +264,11 @@ void free_plan(DevPlan* P) {
     if (t) (void)hipFree(t);
   if (P->d_shift) (void)hipFree(P->d_shift);
   P->d_shift = nullptr;
+  if (P->d_vimage) (void)hipFree(P->d_vimage);
+  if (P->d_vdesc) (void)hipFree(P->d_vdesc);
+  P->d_vimage = nullptr;
+  P->d_vdesc = nullptr;
+  P->vpath = false;
   P->d_tup.clear();
   P->d_sgl.clear();
   P->d_image = nullptr;
@@ -298,6 +315,90 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask)
     if ((device_mask >> j) & 1u) form[j] = hwc::kFormD;
   for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
   return form;
+}
+
+// floor(v / div) = (v * m) >> s for every v <= vmax, with v, m 24-bit operands
+// and the product below 2^31 (so that a signed or unsigned shift agree):
+// m = ceil(2^s / div) and vmax (m div - 2^s) < 2^s.
+bool div_magic(uint64_t vmax, uint32_t div, uint32_t* m, uint32_t* s) {
+  if (vmax >= (1u << 24)) return false;
+  for (int sh = 31; sh >= 1; --sh) {
+    const uint64_t mm = ((1ull << sh) + div - 1) / div;
+    if (mm >= (1u << 24) || vmax * mm >= (1ull << 31)) continue;
+    if (vmax * (mm * div - (1ull << sh)) >= (1ull << sh)) continue;
+    *m = (uint32_t)mm;
+    *s = (uint32_t)sh;
+    return true;
+  }
+  return false;
+}
+
+// The image of the matrix-core path (plan.h, VPlanDesc) for prime q <= 31:
+// per level the swept points' coordinate blocks, then the character table.
+// Returns false (path not used) when q is not such a prime or the image does
+// not fit LDS.
+int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint32_t orbit, bool* ok) {
+  *ok = false;
+  if (e != 1 || p > hwc::kVMaxP) return HWC_OK;
+  const uint32_t NC = 2 * g + 3;
+  hwc::VPlanDesc V{};
+  V.p = p; V.g = g; V.ncoef = NC; V.orbit = orbit;
+  std::vector<uint8_t> img;
+  auto align16 = [&]() { while (img.size() % 16) img.push_back(0); };
+  for (uint32_t j = 0; j < g; ++j) {
+    const hwc::Field& F = P->fields[j]->F;
+    const uint32_t KC = j + 1, M = (uint32_t)F.M;
+    std::vector<uint32_t> xs;
+    if (orbit) xs = F.prim_reps;
+    else for (uint32_t L = 0; L < M; ++L) xs.push_back(L);
+    hwc::VLevel& L = V.lv[j];
+    L.pts = (uint32_t)xs.size();
+    L.nblk = (L.pts + 31) / 32;
+    align16();
+    L.vo = (uint32_t)img.size();
+    if (L.vo + (uint64_t)L.nblk * KC * 512 > hwc::kLdsImageLimit) return HWC_OK;
+    img.resize(L.vo + (size_t)L.nblk * KC * 512, 0);
+    for (uint32_t pi = 0; pi < L.pts; ++pi) {
+      const uint32_t bb = pi / 32, row = pi % 32;
+      for (uint32_t i = 0; i < NC; ++i) {
+        uint32_t el = F.exp[(uint64_t)i * xs[pi] % M];   // x^i, packed coordinates
+        for (uint32_t d = 0; d < KC; ++d, el /= p) {
+          const uint32_t digit = el % p;
+          img[L.vo + ((size_t)(bb * KC + d) * 32 + row) * 16 + i] = (uint8_t)(d == 0 ? 4 * digit : digit);
+        }
+      }
+    }
+    align16();
+    L.to = (uint32_t)img.size();
+    uint64_t Q = 1;
+    for (uint32_t d = 0; d < KC; ++d) Q *= p;
+    if (L.to + 4 * Q > hwc::kLdsImageLimit) return HWC_OK;
+    for (uint64_t el = 0; el < Q; ++el) {
+      const uint32_t v = el == 0 ? hwc::kVZero : (F.log[el] & 1u);
+      for (int b = 0; b < 4; ++b) img.push_back((uint8_t)(v >> (8 * b)));
+    }
+    const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
+    if (!div_magic(4 * vmax1, 4 * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return HWC_OK;
+  }
+  align16();
+  if (img.size() > hwc::kLdsImageLimit) return HWC_OK;
+  V.image_bytes = (uint32_t)img.size();
+  HIPX(c, hipMalloc(&P->d_vimage, img.size()));
+  HIPX(c, hipMemcpy(P->d_vimage, img.data(), img.size(), hipMemcpyHostToDevice));
+  V.image = static_cast<const uint32_t*>(P->d_vimage);
+  HIPX(c, hipMalloc(&P->d_vdesc, sizeof(hwc::VPlanDesc)));
+  HIPX(c, hipMemcpy(P->d_vdesc, &V, sizeof(V), hipMemcpyHostToDevice));
+  P->vdesc = V;
+  P->dev_bytes += img.size() + sizeof(V);
+  c->table_bytes += img.size() + sizeof(V);
+  // enough waves per CU to cover the matrix-core and LDS latencies
+  int bpc = 0;
+  P->vblock = V.image_bytes > 40 * 1024 ? 1024 : 256;
+  HIPX(c, hwc::occupancy_vcount(g, P->vblock, V.image_bytes, &bpc));
+  if (bpc < 1) return HWC_OK;
+  P->vgrid = (uint32_t)(c->cus * bpc);
+  *ok = true;
+  return HWC_OK;
 }
 
 // Build (or fetch) the device plan for (q, g, orbit).
@@ -507,6 +608,12 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   if (bpc < 1) bpc = 1;
   if (T.wg_per_cu && (int)T.wg_per_cu < bpc) bpc = (int)T.wg_per_cu;
   P->grid = (uint32_t)(c->cus * bpc);
+  if (T.mfma) {
+    bool ok = false;
+    int rv = build_vplan(c, P.get(), p, e, g, orbit, &ok);
+    if (rv) return rv;
+    P->vpath = ok;
+  }
   // relative cost of one tile, for ordering mixed batches (longest first)
   P->tile_cost = 0;
   for (uint32_t j = 0; j < g; ++j)
@@ -577,6 +684,30 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
       if (rc) return rc;
     }
     HIPX(c, hipEventRecord(ev[0], s));
+  }
+  if (P->vpath) {
+    // matrix-core path: rows in input order, no bucketing
+    if (record) HIPX(c, hipEventRecord(ev[1], s));
+    if (n > 0) {
+      if (flags & HWC_PLAIN) {
+        for (uint32_t j = 0; j < g; ++j)
+          HIPX(c, hwc::launch_vcount(P->vdesc, P->d_vdesc, cb, codes, n, j, j, nullptr, S.lv, c->d_err, P->vgrid,
+                                     P->vblock, s));
+        HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
+      } else {
+        HIPX(c, hwc::launch_vcount(P->vdesc, P->d_vdesc, cb, codes, n, 0, g - 1, N, lam ? S.lv : nullptr, c->d_err,
+                                   P->vgrid, P->vblock, s));
+      }
+      if (lam)
+        HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, (flags & kFlagSqf) ? 1u : 0u, s));
+    }
+    if (record) HIPX(c, hipEventRecord(ev[2], s));
+    if (hk) HIPX(c, hwc::hist_run(N, lam, n, g, P->q, S.hist, hk, hc, hcap, hlen, c->d_err, s));
+    if (record) {
+      HIPX(c, hipEventRecord(ev[3], s));
+      c->prof.push_back(ev);
+    }
+    return HWC_OK;
   }
   if (P->d_shift && n > 0) {
     HIPX(c, hwc::launch_shift(cb, g, codes, n, P->q, P->d_shift, S.tcodes, s));
@@ -950,6 +1081,10 @@ int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
       if (value < 0 || value > 64) return fail(c, HWC_ERR_ARG, "workgroups per CU must be in 0..64");
       T.wg_per_cu = (uint32_t)value;
       break;
+    case HWC_OPT_MFMA:
+      if (value != 0 && value != 1) return fail(c, HWC_ERR_ARG, "mfma must be 0 or 1");
+      T.mfma = value != 0;
+      break;
     case HWC_OPT_SHIFT:
       if (value != 0 && value != 1) return fail(c, HWC_ERR_ARG, "shift must be 0 or 1");
       T.shift = value != 0;
@@ -1312,6 +1447,7 @@ int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out) {
     if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return create_fail(e, "hipGetDeviceProperties");
     c->cus = prop.multiProcessorCount;
     if ((e = hwc::prepare_kernels()) != hipSuccess) return create_fail(e, "kernel attributes");
+    if ((e = hwc::prepare_vcount()) != hipSuccess) return create_fail(e, "kernel attributes");
     if ((e = hipMalloc(reinterpret_cast<void**>(&c->d_err), 256)) != hipSuccess) return create_fail(e, "hipMalloc");
     if ((e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming)) != hipSuccess)
       return create_fail(e, "hipEventCreate");
@@ -1661,7 +1797,8 @@ int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_
     levels[j].msplit = L.msplit;
     levels[j].nt = L.nt;
     levels[j].ns = L.ns;
-    levels[j].lds_bytes = P->desc.image_bytes;
+    levels[j].lds_bytes = P->vpath ? P->vdesc.image_bytes : P->desc.image_bytes;
+    levels[j].mfma = P->vpath ? 1u : 0u;
   }
   return HWC_OK;
 }

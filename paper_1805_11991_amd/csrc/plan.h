@@ -79,6 +79,30 @@ struct SingleDesc {
   uint32_t d, M;
 };
 
+// Counting by F_p-linear algebra (prime q = p): with F_{p^j} = F_p[t]/(P) and
+// x^i = sum_d a_{i,d} t^d, f(x) = sum_i c_i x^i has coordinates
+// D_d = sum_i c_i a_{i,d} mod p, i.e. the codes times a Vandermonde matrix of
+// coordinates -- an int8 matrix product for the matrix cores.  The image holds,
+// per level, the swept points in blocks of 32 as the A operand of
+// v_mfma_i32_32x32x16_i8 ([block][d][row][16 bytes]; coordinate 0 times 4, so
+// its residue mod 4p is four times the residue mod p), then a u32 table of the
+// quadratic character over packed elements (byte offset 4 sum_d r_d p^d):
+// 0 square, 1 nonsquare, kVZero for zero.  Needs 4(p-1) <= 127: p <= 31.
+constexpr uint32_t kVZero = 1u << 15;
+constexpr uint32_t kVMaxP = 31;
+struct VLevel {
+  uint32_t pts, nblk;     // swept points and 32-point blocks (padding rows are zero)
+  uint32_t vo, to;        // byte offsets of the blocks and of the character table
+  uint32_t m0, s0;        // floor(v / 4p) = (v * m0) >> s0 for every value coordinate 0 reaches
+  uint32_t m1, s1;        // floor(v / p) = (v * m1) >> s1 for the other coordinates
+};
+struct VPlanDesc {
+  uint32_t p, g, ncoef, orbit;
+  uint32_t image_bytes;
+  const uint32_t* image;
+  VLevel lv[kMaxG];
+};
+
 // One request of a multi-plan launch (device memory).
 struct JobDesc {
   const PlanDesc* plan;   // device copy of the job's plan

@@ -40,6 +40,7 @@ HWC_OPT_DEVICE_TABLES = 4
 HWC_OPT_WAVES_PER_SIMD = 5
 HWC_OPT_SPLIT_MIN_M = 6
 HWC_OPT_SHIFT = 7
+HWC_OPT_MFMA = 8
 
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
@@ -68,7 +69,7 @@ class hwc_hist(ctypes.Structure):
 
 
 class hwc_level_desc(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_uint32) for n in ("M", "form", "nx", "weight", "msplit", "nt", "ns", "lds_bytes")]
+    _fields_ = [(n, ctypes.c_uint32) for n in ("M", "form", "nx", "weight", "msplit", "nt", "ns", "lds_bytes", "mfma")]
 
 
 class hwc_job(ctypes.Structure):

@@ -324,17 +324,22 @@ OPTION_SETS = [
     {"block": 1024, "waves_per_simd": 8},
     {"block": 512, "waves_per_simd": 6, "split": 0},
     {"split_min_m": 0},            # every level split, down to F_q itself (vanishing bases everywhere)
+    {"mfma": 0},                   # Zech logarithms where the matrix-core path would run
+    {"mfma": 0, "split": 0},
+    {"mfma": 0, "block": 1024, "waves_per_simd": 6},
 ]
 
 
 @pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000)])
 @pytest.mark.parametrize("opts", range(len(OPTION_SETS)))
 def test_tuning_options_keep_results(gctx, oracle_mod, curvegen_mod, q, g, n, opts):
-    """Every tunable (split and its threshold, device-memory placement of any
-    level's table, block size, register budget) gives the oracle's counts."""
+    """Every tunable (matrix-core or Zech path, split and its threshold,
+    device-memory placement of any level's table, block size, register
+    budget) gives the oracle's counts."""
     from paper_1805_11991_amd import hwcount as hw
     ids = {"split": hw.HWC_OPT_SPLIT, "block": hw.HWC_OPT_BLOCK, "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD,
-           "device_tables": hw.HWC_OPT_DEVICE_TABLES, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M}
+           "device_tables": hw.HWC_OPT_DEVICE_TABLES, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M,
+           "mfma": hw.HWC_OPT_MFMA}
     ctx = hw.Context(device=0, autotune_db=None)
     try:
         for k, v in OPTION_SETS[opts].items():

@@ -33,6 +33,8 @@ def _sparse_rows(curvegen_mod, q, g, n, seed, frac=0.35):
 def _count(ctx, q, g, rows, shift, flags=0):
     import torch
     from paper_1805_11991_amd import hwcount as hw
+    # translates serve the Zech-logarithm path; the matrix-core path needs none
+    ctx.set_plan_option(q, g, hw.HWC_OPT_MFMA, 0, flags & hw.HWC_FULL_SWEEP)
     ctx.set_plan_option(q, g, hw.HWC_OPT_SHIFT, shift, flags & hw.HWC_FULL_SWEEP)
     n = len(rows)
     d = torch.from_numpy(rows).cuda()
