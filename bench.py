@@ -30,8 +30,12 @@ LDS_BANKS_PER_CU = 32          # u16 gathers served per clock per CU without con
 NUM_CU = 256
 CLOCK_HZ = 2.4e9
 LDS_PEAK_LOOKUPS = LDS_BANKS_PER_CU * NUM_CU * CLOCK_HZ
+# one wave64 vector ALU instruction per CU per clock (four SIMDs of 16 lanes)
+VALU_PEAK_OPS = 64 * NUM_CU * CLOCK_HZ
+MFMA_INT8_PEAK_OPS = 5.0e15   # dense int8 matrix-core peak
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "count_kernel_g3_q13_2p24_hbm_traffic.md")
-KERNEL_SOURCES = ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
+KERNEL_SOURCES = ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/vcount.hip",
+                  "paper_1805_11991_amd/csrc/plan.h",
                   "paper_1805_11991_amd/autotune/gfx950.json")
 
 
@@ -67,6 +71,24 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
         cost = np.where(ok, L["nt"] * per_tuple + L["ns"] * horner, L["nx"] * horner)
         total += int(cost.sum())
     return total, plain
+
+
+def mfma_work(n: int, levels: list[dict]) -> dict:
+    """Work of the matrix-core count kernel for n curves.  Every level j
+    (k = j coordinates) evaluates each curve at its swept points, padded to
+    blocks of 32: one int8 product of K = 16 per coordinate and point (the
+    matrix cores), and per (curve, point) pair 4k + 1 vector ALU operations
+    -- per coordinate the residue (multiply and shift for the quotient, two
+    multiply-adds) and one add of the character read."""
+    tiles = (n + 31) // 32
+    pairs = valu = mfma = 0
+    for j, L in enumerate(levels, start=1):
+        pts = (L["nx"] + 31) // 32 * 32
+        pr = tiles * 32 * pts
+        pairs += pr
+        valu += pr * (4 * j + 1)
+        mfma += pr * j * 16 * 2
+    return {"pairs": pairs, "valu_ops": valu, "mfma_ops": mfma}
 
 
 def evaluated_rows(ctx, q: int, g: int, d_rows):
@@ -197,35 +219,62 @@ def main():
     count_ms = prof["count_ms"] / prof["calls"]
     levels = ctx.plan_info(q, g)
     nx = [L["nx"] for L in levels]
-    # the rows the kernel evaluates: zero-coefficient rows become dense translates
-    lookups, plain_lookups = lookups_per_batch(evaluated_rows(ctx, q, g, bufs[1]), levels)
-    achieved = lookups / (count_ms * 1e-3)
     traffic = measured_traffic()
-    roofline = {
-        "bound": "lds",
-        "achieved": round(achieved / 1e9, 2),
-        "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
-        "unit": "Glookup/s",
-        "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
+    common = {
         "traffic": None if traffic is None else traffic["fetch"] + traffic["write"],
         "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
         "traffic_detail": traffic,
-        "kernel": "count_kernel<3,int8>",
         "kernel_ms": round(count_ms, 4),
-        "lookups_per_launch": lookups,
-        "plain_horner_lookups": plain_lookups,
-        "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit", "nt", "ns")} for L in levels],
         "prep_ms": round(prof["prep_ms"] / prof["calls"], 4),
         "hist_ms": round(prof["hist_ms"] / prof["calls"], 4),
     }
-    # the practical ceiling of that bound on this device: a kernel doing
-    # nothing but dependent random reads of a table the size of the top level's
-    ceiling = ctx.lds_gather_rate(2 * (q ** g - 1), chains=4)
-    roofline["gather_ceiling"] = round(ceiling / 1e9, 2)
-    roofline["frac_of_gather_ceiling"] = round(achieved / ceiling, 4)
-    log(f"roofline: count kernel {count_ms:.3f} ms, {achieved / 1e9:.1f} Glookup/s "
-        f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak, {achieved / ceiling:.3f} of the "
-        f"measured gather ceiling {ceiling / 1e9:.0f} Glookup/s)")
+    if levels[0]["mfma"]:
+        # matrix-core path: bound by the vector ALU work on the products
+        work = mfma_work(n, levels)
+        achieved = work["valu_ops"] / (count_ms * 1e-3)
+        mfma_rate = work["mfma_ops"] / (count_ms * 1e-3)
+        roofline = {
+            "bound": "alu",
+            "achieved": round(achieved / 1e9, 1),
+            "peak": round(VALU_PEAK_OPS / 1e9, 1),
+            "unit": "G int32 lane-ops/s",
+            "frac": round(achieved / VALU_PEAK_OPS, 4),
+            **common,
+            "kernel": "vcount_kernel<3,int8>",
+            "pairs_per_launch": work["pairs"],
+            "valu_ops_per_launch": work["valu_ops"],
+            "mfma_int8_ops_per_launch": work["mfma_ops"],
+            "mfma_int8_tops": round(mfma_rate / 1e12, 2),
+            "mfma_frac": round(mfma_rate / MFMA_INT8_PEAK_OPS, 4),
+            "levels": [{"M": L["M"], "nx": L["nx"], "pts_padded": (L["nx"] + 31) // 32 * 32} for L in levels],
+        }
+        log(f"roofline: count kernel {count_ms:.3f} ms, {work['pairs'] / (count_ms * 1e-3) / 1e9:.0f} G "
+            f"(curve, point) pairs/s, {achieved / 1e12:.2f} T lane-ops/s ({achieved / VALU_PEAK_OPS:.3f} of "
+            f"the vector ALU peak), int8 MFMA {mfma_rate / 1e12:.1f} TOPS ({mfma_rate / MFMA_INT8_PEAK_OPS:.4f})")
+    else:
+        # the rows the kernel evaluates: zero-coefficient rows become dense translates
+        lookups, plain_lookups = lookups_per_batch(evaluated_rows(ctx, q, g, bufs[1]), levels)
+        achieved = lookups / (count_ms * 1e-3)
+        roofline = {
+            "bound": "lds",
+            "achieved": round(achieved / 1e9, 2),
+            "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
+            "unit": "Glookup/s",
+            "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
+            **common,
+            "kernel": "count_kernel<3,int8>",
+            "lookups_per_launch": lookups,
+            "plain_horner_lookups": plain_lookups,
+            "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit", "nt", "ns")} for L in levels],
+        }
+        # the practical ceiling of that bound on this device: a kernel doing
+        # nothing but dependent random reads of a table the size of the top level's
+        ceiling = ctx.lds_gather_rate(2 * (q ** g - 1), chains=4)
+        roofline["gather_ceiling"] = round(ceiling / 1e9, 2)
+        roofline["frac_of_gather_ceiling"] = round(achieved / ceiling, 4)
+        log(f"roofline: count kernel {count_ms:.3f} ms, {achieved / 1e9:.1f} Glookup/s "
+            f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak, {achieved / ceiling:.3f} of the "
+            f"measured gather ceiling {ceiling / 1e9:.0f} Glookup/s)")
 
     extra = {}
     if not args.quick:

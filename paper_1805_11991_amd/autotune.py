@@ -10,6 +10,7 @@ the database's entries as per-plan options when it is created.
     python -m paper_1805_11991_amd.autotune --qg 13,3 --qg 13,4 [--n 1048576] [--out path]
 
 Search space (library options, see include/hwcount.h):
+  mfma            int8 matrix-product counting (prime q <= 31, image in LDS) or Zech logarithms
   split           split evaluation over m-th roots of unity on LDS levels (on/off)
   split_min_m     smallest level (nonzero elements) that is split
   block           threads per workgroup of the count kernel (256, 512, 1024)
@@ -31,6 +32,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DB_DIR = os.path.join(HERE, "autotune")
 
 SPACE = {
+    "mfma": [1, 0],
     "split": [1, 0],
     "split_min_m": [64, 2048],
     "block": [256, 512, 1024],
@@ -45,7 +47,8 @@ def _device_mask(choice, g: int) -> int:
 
 def _opt_ids():
     from . import hwcount as hw
-    return {"split": hw.HWC_OPT_SPLIT, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M, "block": hw.HWC_OPT_BLOCK,
+    return {"mfma": hw.HWC_OPT_MFMA, "split": hw.HWC_OPT_SPLIT, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M,
+            "block": hw.HWC_OPT_BLOCK,
             "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD, "device_tables": hw.HWC_OPT_DEVICE_TABLES}
 
 
@@ -103,6 +106,8 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
         cand = dict(zip(names, values))
         if cand.get("split") == 0 and cand.get("split_min_m", 0) != space.get("split_min_m", [0])[0]:
             continue                      # the threshold means nothing without the split
+        if cand.get("mfma") == 1 and any(cand[k] != space[k][0] for k in cand if k != "mfma"):
+            continue                      # the other options tune the Zech-logarithm kernel only
         try:
             for k, v in cand.items():
                 ctx.set_plan_option(q, g, ids[k], _device_mask(v, g) if k == "device_tables" else v, flags)
