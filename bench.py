@@ -77,16 +77,18 @@ def mfma_work(n: int, levels: list[dict]) -> dict:
     """Work of the matrix-core count kernel for n curves.  Every level j
     (k = j coordinates) evaluates each curve at its swept points, padded to
     blocks of 32: one int8 product of K = 16 per coordinate and point (the
-    matrix cores), and per (curve, point) pair 4k + 1 vector ALU operations
-    -- per coordinate the residue (multiply and shift for the quotient, two
-    multiply-adds) and one add of the character read."""
+    matrix cores), and per (curve, point) pair 4k vector ALU operations: for
+    each coordinate its residue (multiply and shift for the quotient, then
+    multiply-adds into the table index; coordinate 0 arrives with the table
+    offset already added, one multiply-add fewer) and one add of the
+    character read."""
     tiles = (n + 31) // 32
     pairs = valu = mfma = 0
     for j, L in enumerate(levels, start=1):
         pts = (L["nx"] + 31) // 32 * 32
         pr = tiles * 32 * pts
         pairs += pr
-        valu += pr * (4 * j + 1)
+        valu += pr * 4 * j
         mfma += pr * j * 16 * 2
     return {"pairs": pairs, "valu_ops": valu, "mfma_ops": mfma}
 

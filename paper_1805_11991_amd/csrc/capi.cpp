@@ -356,8 +356,21 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
     L.nblk = (L.pts + 31) / 32;
     align16();
     L.vo = (uint32_t)img.size();
+    // the character table's offset: after the blocks, a multiple of 4 * 127
+    const uint64_t vend = L.vo + (uint64_t)L.nblk * KC * 512;
+    const uint64_t unit = 4ull * hwc::kVSlotUnit;
+    L.to = (uint32_t)((vend + unit - 1) / unit * unit);
+    if (L.to / hwc::kVSlotUnit > (uint64_t)(16 - NC) * 127) return HWC_OK;   // spare slots cannot reach it
     if (L.vo + (uint64_t)L.nblk * KC * 512 > hwc::kLdsImageLimit) return HWC_OK;
     img.resize(L.vo + (size_t)L.nblk * KC * 512, 0);
+    for (uint32_t pi = 0; pi < L.nblk * 32; ++pi) {   // spare slots of coordinate 0: sum to / 127
+      uint32_t rest = L.to / hwc::kVSlotUnit;
+      for (uint32_t k = NC; k < 16; ++k) {
+        const uint32_t a = rest < 127 ? rest : 127;
+        img[L.vo + ((size_t)(pi / 32) * KC * 32 + pi % 32) * 16 + k] = (uint8_t)a;
+        rest -= a;
+      }
+    }
     for (uint32_t pi = 0; pi < L.pts; ++pi) {
       const uint32_t bb = pi / 32, row = pi % 32;
       for (uint32_t i = 0; i < NC; ++i) {
@@ -368,8 +381,7 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
         }
       }
     }
-    align16();
-    L.to = (uint32_t)img.size();
+    img.resize(L.to, 0);
     uint64_t Q = 1;
     for (uint32_t d = 0; d < KC; ++d) Q *= p;
     if (L.to + 4 * Q > hwc::kLdsImageLimit) return HWC_OK;
@@ -379,6 +391,8 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
     }
     const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
     if (!div_magic(4 * vmax1, 4 * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return HWC_OK;
+    if (4 * vmax1 + L.to >= (1u << 24)) return HWC_OK;   // coordinate 0 with the offset stays a 24-bit operand
+    L.nbm0 = (uint32_t)(0u - (uint32_t)((uint64_t)L.to * L.m0));
   }
   align16();
   if (img.size() > hwc::kLdsImageLimit) return HWC_OK;

@@ -88,12 +88,17 @@ struct SingleDesc {
 // its residue mod 4p is four times the residue mod p), then a u32 table of the
 // quadratic character over packed elements (byte offset 4 sum_d r_d p^d):
 // 0 square, 1 nonsquare, kVZero for zero.  Needs 4(p-1) <= 127: p <= 31.
+// The K slots past the coefficients hold 127 on the curve side and, in the
+// coordinate-0 rows, values summing to to / 127, so the product adds the
+// table's byte offset (a multiple of 508) to coordinate 0 by itself.
+constexpr uint32_t kVSlotUnit = 127;
 constexpr uint32_t kVZero = 1u << 15;
 constexpr uint32_t kVMaxP = 31;
 struct VLevel {
   uint32_t pts, nblk;     // swept points and 32-point blocks (padding rows are zero)
   uint32_t vo, to;        // byte offsets of the blocks and of the character table
   uint32_t m0, s0;        // floor(v / 4p) = (v * m0) >> s0 for every value coordinate 0 reaches
+  uint32_t nbm0;          // -to * m0 mod 2^32: coordinate 0 arrives with the table offset added
   uint32_t m1, s1;        // floor(v / p) = (v * m1) >> s1 for the other coordinates
 };
 struct VPlanDesc {

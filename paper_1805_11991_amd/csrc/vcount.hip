@@ -31,10 +31,13 @@ __device__ __forceinline__ uint32_t vlds32(uint32_t a) { return *(vlds32_ptr)(si
 __device__ __forceinline__ long vlds64(uint32_t a) { return (long)*(vlds64_ptr)(size_t)a; }
 
 // c + a * b on 24-bit operands with b uniform, one instruction each (the
-// compiler otherwise splits these into a multiply and a three-way add)
-__device__ __forceinline__ uint32_t mad_u24(uint32_t a, uint32_t b, uint32_t c) {
+// compiler otherwise splits these into a multiply and a three-way add).  The
+// hazard checks do not see into inline assembly, so no matrix-core result is
+// read here first: every value is read by compiled code (its quotient) before,
+// and the quotient is an input of these instructions, which orders them after.
+__device__ __forceinline__ uint32_t mad_u24_after(uint32_t a, uint32_t b, uint32_t c, uint32_t after) {
   uint32_t r;
-  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+  asm("v_mad_u32_u24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c), "v"(after));
   return r;
 }
 __device__ __forceinline__ uint32_t mad_i24(uint32_t a, int32_t b, uint32_t c) {
@@ -42,7 +45,9 @@ __device__ __forceinline__ uint32_t mad_i24(uint32_t a, int32_t b, uint32_t c) {
   asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
   return r;
 }
-__device__ __forceinline__ uint32_t quot(uint32_t v, uint32_t m, uint32_t s) { return __umul24(v, m) >> s; }
+__device__ __forceinline__ uint32_t quot(uint32_t v, uint32_t m, uint32_t s) {
+  return (uint32_t)__umul24(v, m) >> s;
+}
 
 // One level with KC coordinates: the lane's zeros and nonsquares over its rows.
 // The character table has u32 entries; coordinate 0 comes scaled by 4 from the
@@ -66,19 +71,21 @@ __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lan
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
+      // v0 = table offset + 4 (coordinate 0); its quotient by 4p without the offset
       const uint32_t v0 = (uint32_t)D[0][i];
-      uint32_t idx = mad_i24(quot(v0, L.m0, L.s0), neg0, v0 + L.to);
+      const uint32_t q0 = ((uint32_t)__umul24(v0, L.m0) + L.nbm0) >> L.s0;
+      uint32_t idx = mad_i24(q0, neg0, v0);
       if (KC > 1) {
-        const uint32_t v = (uint32_t)D[1][i];
-        idx = mad_i24(quot(v, L.m1, L.s1), neg1, mad_u24(v, mult1, idx));
+        const uint32_t v = (uint32_t)D[1][i], q = quot(v, L.m1, L.s1);
+        idx = mad_i24(q, neg1, mad_u24_after(v, mult1, idx, q));
       }
       if (KC > 2) {
-        const uint32_t v = (uint32_t)D[2][i];
-        idx = mad_i24(quot(v, L.m1, L.s1), neg2, mad_u24(v, mult2, idx));
+        const uint32_t v = (uint32_t)D[2][i], q = quot(v, L.m1, L.s1);
+        idx = mad_i24(q, neg2, mad_u24_after(v, mult2, idx, q));
       }
       if (KC > 3) {
-        const uint32_t v = (uint32_t)D[3][i];
-        idx = mad_i24(quot(v, L.m1, L.s1), neg3, mad_u24(v, mult3, idx));
+        const uint32_t v = (uint32_t)D[3][i], q = quot(v, L.m1, L.s1);
+        idx = mad_i24(q, neg3, mad_u24_after(v, mult3, idx, q));
       }
       acc += vlds32(idx);
     }
@@ -133,7 +140,8 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
     long b = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const uint32_t lo = c[j], hi = (8 + j < NC) ? c[(8 + j < NC) ? 8 + j : 0] : 0u;
+      const uint32_t lo = j < NC ? c[j < NC ? j : 0] : kVSlotUnit;
+      const uint32_t hi = 8 + j < NC ? c[8 + j < NC ? 8 + j : 0] : kVSlotUnit;
       b |= (long)(half ? hi : lo) << (8 * j);
     }
     uint32_t lv[G];
