@@ -106,8 +106,8 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
         cand = dict(zip(names, values))
         if cand.get("split") == 0 and cand.get("split_min_m", 0) != space.get("split_min_m", [0])[0]:
             continue                      # the threshold means nothing without the split
-        if cand.get("mfma") == 1 and any(cand[k] != space[k][0] for k in cand if k != "mfma"):
-            continue                      # the other options tune the Zech-logarithm kernel only
+        if cand.get("mfma") == 1 and any(cand[k] != space[k][0] for k in cand if k not in ("mfma", "block")):
+            continue                      # only the block size applies to the matrix-core kernel
         try:
             for k, v in cand.items():
                 ctx.set_plan_option(q, g, ids[k], _device_mask(v, g) if k == "device_tables" else v, flags)

@@ -337,7 +337,8 @@ bool div_magic(uint64_t vmax, uint32_t div, uint32_t* m, uint32_t* s) {
 // per level the swept points' coordinate blocks, then the character table.
 // Returns false (path not used) when q is not such a prime or the image does
 // not fit LDS.
-int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint32_t orbit, bool* ok) {
+int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint32_t orbit, uint32_t block_opt,
+                bool* ok) {
   *ok = false;
   if (e != 1 || p > hwc::kVMaxP) return HWC_OK;
   const uint32_t NC = 2 * g + 3;
@@ -405,12 +406,20 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
   P->vdesc = V;
   P->dev_bytes += img.size() + sizeof(V);
   c->table_bytes += img.size() + sizeof(V);
-  // enough waves per CU to cover the matrix-core and LDS latencies
-  int bpc = 0;
-  P->vblock = V.image_bytes > 40 * 1024 ? 1024 : 256;
-  HIPX(c, hwc::occupancy_vcount(g, P->vblock, V.image_bytes, &bpc));
-  if (bpc < 1) return HWC_OK;
-  P->vgrid = (uint32_t)(c->cus * bpc);
+  // the block size that keeps the most waves per CU resident (LDS holds one
+  // image per workgroup), unless a block size is set
+  int best_waves = 0;
+  for (uint32_t blk : {256u, 512u, 1024u}) {
+    if (block_opt && blk != block_opt) continue;
+    int bpc = 0;
+    HIPX(c, hwc::occupancy_vcount(g, blk, V.image_bytes, &bpc));
+    if (bpc * (int)blk > best_waves * 64) {
+      best_waves = bpc * (int)blk / 64;
+      P->vblock = blk;
+      P->vgrid = (uint32_t)(c->cus * bpc);
+    }
+  }
+  if (best_waves < 1) return HWC_OK;
   *ok = true;
   return HWC_OK;
 }
@@ -624,7 +633,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   P->grid = (uint32_t)(c->cus * bpc);
   if (T.mfma) {
     bool ok = false;
-    int rv = build_vplan(c, P.get(), p, e, g, orbit, &ok);
+    int rv = build_vplan(c, P.get(), p, e, g, orbit, T.block, &ok);
     if (rv) return rv;
     P->vpath = ok;
   }
