@@ -102,24 +102,45 @@ __global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ s
 }
 
 // in and out may be the same array: each thread reads its own run before writing it
+// Each thread owns 16 consecutive values, moved as four 16-byte vectors when
+// the tile is whole (tiles start at multiples of 4096 values, so 16-byte aligned).
 __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uint64_t n,
                                                          const uint32_t* __restrict__ offs, uint32_t* out) {
   __shared__ uint32_t sh[256];
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
   constexpr uint32_t per = kScanTile / 256;
+  const bool whole = base + kScanTile <= n;
   uint32_t v[per];
   uint32_t s = 0;
-  for (uint32_t j = 0; j < per; ++j) {
-    const uint64_t i = base + threadIdx.x * per + j;
-    v[j] = i < n ? in[i] : 0u;
-    s += v[j];
+  const uint64_t first = base + threadIdx.x * per;
+  if (whole) {
+#pragma unroll
+    for (uint32_t j = 0; j < per / 4; ++j) {
+      const uint4 w = reinterpret_cast<const uint4*>(in + first)[j];
+      v[4 * j] = w.x; v[4 * j + 1] = w.y; v[4 * j + 2] = w.z; v[4 * j + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < per; ++j) v[j] = first + j < n ? in[first + j] : 0u;
   }
+#pragma unroll
+  for (uint32_t j = 0; j < per; ++j) s += v[j];
   uint32_t tot;
   uint32_t off = block_exclusive_scan(s, sh, &tot) + offs[blockIdx.x];
+#pragma unroll
   for (uint32_t j = 0; j < per; ++j) {
-    const uint64_t i = base + threadIdx.x * per + j;
-    if (i < n) out[i] = off;
-    off += v[j];
+    const uint32_t x = v[j];
+    v[j] = off;
+    off += x;
+  }
+  if (whole) {
+#pragma unroll
+    for (uint32_t j = 0; j < per / 4; ++j)
+      reinterpret_cast<uint4*>(out + first)[j] = make_uint4(v[4 * j], v[4 * j + 1], v[4 * j + 2], v[4 * j + 3]);
+  } else {
+#pragma unroll
+    for (uint32_t j = 0; j < per; ++j)
+      if (first + j < n) out[first + j] = v[j];
   }
 }
 
@@ -144,7 +165,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __res
 
 // Keys of a block are ranked in 16 rounds of 256 (round-major = index order).
 // Within a round: lanes with equal digits are found by bit ballots, waves are
-// ordered through per-wave digit counts in LDS.
+// ordered through per-wave digit counts in LDS.  Each key first goes to its
+// place in the block's digit-sorted tile in LDS; the tile is then written out
+// in that order, so neighbouring threads store to neighbouring addresses of
+// one digit's run instead of scattering single keys.
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __restrict__ in, uint64_t n,
                                                                      uint32_t shift, uint32_t nblocks,
@@ -152,11 +176,46 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
                                                                      K* __restrict__ out) {
   constexpr int kWaves = kSortThreads / 64;
   constexpr uint32_t kRadixBins = 1u << RB;
-  __shared__ uint32_t running[kRadixBins];
+  __shared__ uint32_t gstart[kRadixBins];   // the block's first global position per digit
+  __shared__ uint32_t lstart[kRadixBins];   // its first position per digit within the tile
+  __shared__ uint32_t running[kRadixBins];  // keys of the digit placed so far
   __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ K tile[kSortTile];
+  __shared__ uint32_t scan_sh[kSortThreads];
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  for (uint32_t d = t; d < kRadixBins; d += blockDim.x) running[d] = bh_scanned[(uint64_t)d * nblocks + blockIdx.x];
   const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const uint64_t nbh = (uint64_t)nblocks * kRadixBins;
+  // digit counts of this block from the scanned histogram (differences of
+  // consecutive entries of the [digit][block] order), then their prefix
+  constexpr uint32_t kPer = kRadixBins / kSortThreads;
+  uint32_t cnt[kPer], csum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    const uint32_t d = t * kPer + k;
+    const uint64_t idx = (uint64_t)d * nblocks + blockIdx.x;
+    const uint32_t a = bh_scanned[idx];
+    const uint32_t b = idx + 1 < nbh ? bh_scanned[idx + 1] : (uint32_t)n;
+    gstart[d] = a;
+    running[d] = 0;
+    cnt[k] = b - a;
+    csum += cnt[k];
+  }
+  {
+    scan_sh[t] = csum;
+    __syncthreads();
+    for (uint32_t off = 1; off < kSortThreads; off <<= 1) {
+      const uint32_t a = t >= off ? scan_sh[t - off] : 0u;
+      __syncthreads();
+      scan_sh[t] += a;
+      __syncthreads();
+    }
+    uint32_t acc = scan_sh[t] - csum;
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+      lstart[t * kPer + k] = acc;
+      acc += cnt[k];
+    }
+  }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int r = 0; r < kSortItems; ++r) {
     const uint64_t i = base + (uint64_t)r * kSortThreads + t;
@@ -176,9 +235,9 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
     if (valid && rank_w == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t pos = running[dig] + rank_w;
+      uint32_t pos = lstart[dig] + running[dig] + rank_w;
       for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][dig];
-      out[pos] = key;
+      tile[pos] = key;
     }
     __syncthreads();
     for (uint32_t d = t; d < kRadixBins; d += blockDim.x) {
@@ -187,6 +246,12 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
       running[d] += s;
     }
     __syncthreads();
+  }
+  const uint32_t nin = (uint32_t)((n - base) < (uint64_t)kSortTile ? (n - base) : (uint64_t)kSortTile);
+  for (uint32_t j = t; j < nin; j += blockDim.x) {
+    const K key = tile[j];
+    const uint32_t dig = (uint32_t)((key >> shift) & (kRadixBins - 1));
+    out[gstart[dig] + (j - lstart[dig])] = key;
   }
 }
 
@@ -254,7 +319,8 @@ uint64_t hist_scratch_bytes(uint64_t n) {
          + nbh * 4                 // block histograms
          + 2 * n * 4               // flags, pos
          + n * 8                   // run starts
-         + nsums * 4 + 64;         // scan block sums, totals
+         + nsums * 4 + 64          // scan block sums, totals
+         + 8 * 256;                // every part starts 256-byte aligned
 }
 
 static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, uint32_t* sums, uint32_t* total,
@@ -329,14 +395,19 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
   const uint64_t nbh = nb_sort * (1u << rb);
   const uint64_t big = (n > nbh ? n : nbh);
   const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
-  uint64_t* keysA = reinterpret_cast<uint64_t*>(p); p += n * 8;
-  uint64_t* keysB = reinterpret_cast<uint64_t*>(p); p += n * 8;
-  uint64_t* starts = reinterpret_cast<uint64_t*>(p); p += n * 8;
-  uint32_t* bh = reinterpret_cast<uint32_t*>(p); p += nbh * 4;
-  uint32_t* flags = reinterpret_cast<uint32_t*>(p); p += n * 4;
-  uint32_t* pos = reinterpret_cast<uint32_t*>(p); p += n * 4;
-  uint32_t* sums = reinterpret_cast<uint32_t*>(p); p += nsums * 4;
-  uint32_t* totals = reinterpret_cast<uint32_t*>(p);
+  auto take = [&](uint64_t bytes) {   // 256-byte aligned parts (vector loads in the scans)
+    uint8_t* q = p;
+    p += (bytes + 255) / 256 * 256;
+    return q;
+  };
+  uint64_t* keysA = reinterpret_cast<uint64_t*>(take(n * 8));
+  uint64_t* keysB = reinterpret_cast<uint64_t*>(take(n * 8));
+  uint64_t* starts = reinterpret_cast<uint64_t*>(take(n * 8));
+  uint32_t* bh = reinterpret_cast<uint32_t*>(take(nbh * 4));
+  uint32_t* flags = reinterpret_cast<uint32_t*>(take(n * 4));
+  uint32_t* pos = reinterpret_cast<uint32_t*>(take(n * 4));
+  uint32_t* sums = reinterpret_cast<uint32_t*>(take(nsums * 4));
+  uint32_t* totals = reinterpret_cast<uint32_t*>(take(64));
   if (n == 0) {
     if (out_len) hipLaunchKernelGGL(hist_empty_kernel, dim3(1), dim3(64), 0, s, out_len);
     return hipGetLastError();
