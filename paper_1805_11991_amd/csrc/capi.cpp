@@ -34,8 +34,8 @@ hipError_t prepare_kernels();
 hipError_t prepare_vcount();
 hipError_t occupancy_vcount(uint32_t g, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 hipError_t launch_vcount(const VPlanDesc& V, const VPlanDesc* dV, int coeff_bytes, const void* codes, uint64_t n,
-                         uint32_t lvl_lo, uint32_t lvl_hi, int32_t* outN, uint32_t* outLv, uint32_t* err,
-                         uint32_t grid, uint32_t block, hipStream_t s);
+                         uint32_t lvl_lo, uint32_t lvl_hi, uint32_t tw, bool acc, int32_t* outN, uint32_t* outLv,
+                         uint32_t* err, uint32_t grid, uint32_t block, hipStream_t s);
 hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes, uint64_t n, const uint32_t* lv,
                            int32_t* outN, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
@@ -102,12 +102,18 @@ struct DevPlan {
   std::vector<uint32_t*> d_gtab;     // form D tables
   std::vector<uint32_t*> d_tup, d_sgl;  // split-evaluation tuple representatives and singles
   uint32_t* d_shift = nullptr;       // q^3-byte step table of the dense translates, or nullptr
-  // matrix-core path (VPlanDesc): used for counting when vpath is set
+  // matrix-core path: used for counting when vpath is set.  One pass holds
+  // every level; otherwise the lower levels come first and the top level's
+  // points are split over the following passes, which add their counts.
+  struct VPass {
+    hwc::VPlanDesc desc{};
+    hwc::VPlanDesc* d_desc = nullptr;
+    void* d_image = nullptr;
+    uint32_t lo = 0, hi = 0, tw = 4;
+    uint32_t grid = 0, block = 256;
+  };
   bool vpath = false;
-  hwc::VPlanDesc vdesc{};
-  hwc::VPlanDesc* d_vdesc = nullptr;
-  void* d_vimage = nullptr;
-  uint32_t vgrid = 0, vblock = 256;
+  std::vector<VPass> vpasses;
   uint64_t dev_bytes = 0;
   uint64_t last_use = 0;
   uint32_t block = 256, grid = 0, wpe = 1;
@@ -264,10 +270,11 @@ void free_plan(DevPlan* P) {
     if (t) (void)hipFree(t);
   if (P->d_shift) (void)hipFree(P->d_shift);
   P->d_shift = nullptr;
-  if (P->d_vimage) (void)hipFree(P->d_vimage);
-  if (P->d_vdesc) (void)hipFree(P->d_vdesc);
-  P->d_vimage = nullptr;
-  P->d_vdesc = nullptr;
+  for (auto& v : P->vpasses) {
+    if (v.d_image) (void)hipFree(v.d_image);
+    if (v.d_desc) (void)hipFree(v.d_desc);
+  }
+  P->vpasses.clear();
   P->vpath = false;
   P->d_tup.clear();
   P->d_sgl.clear();
@@ -333,93 +340,152 @@ bool div_magic(uint64_t vmax, uint32_t div, uint32_t* m, uint32_t* s) {
   return false;
 }
 
-// The image of the matrix-core path (plan.h, VPlanDesc) for prime q <= 31:
-// per level the swept points' coordinate blocks, then the character table.
-// Returns false (path not used) when q is not such a prime or the image does
-// not fit LDS.
+// Appends the points pts[i0, i1) of level j (j + 1 coordinates) to an image
+// of the matrix-core path: their coordinate blocks and the character table
+// with tw-byte entries (plan.h, VPlanDesc) -- the table after the blocks, or
+// first when the image is empty (offset 0: nothing to fold into the product,
+// which keeps large blocks of a split level reachable).  False when the image
+// would pass `limit` or the quotient constants do not exist.
+bool append_vlevel(std::vector<uint8_t>& img, const hwc::Field& F, uint32_t j, const std::vector<uint32_t>& xs,
+                   size_t i0, size_t i1, uint32_t p, uint32_t NC, uint32_t tw, uint64_t limit, hwc::VLevel* out) {
+  const uint32_t KC = j + 1, M = (uint32_t)F.M;
+  hwc::VLevel L{};
+  L.pts = (uint32_t)(i1 - i0);
+  L.nblk = (L.pts + 31) / 32;
+  L.pad = L.nblk * 32 - L.pts;
+  uint64_t Q = 1;
+  for (uint32_t d = 0; d < KC; ++d) Q *= p;
+  const bool table_first = img.empty();
+  const uint64_t unit = (uint64_t)tw * hwc::kVSlotUnit;
+  uint64_t to, vo;
+  if (table_first) {
+    to = 0;
+    vo = (tw * Q + 15) / 16 * 16;
+  } else {
+    while (img.size() % 16) img.push_back(0);
+    vo = img.size();
+    // the table's offset: after the blocks, a multiple of tw * 127
+    to = (vo + (uint64_t)L.nblk * KC * 512 + unit - 1) / unit * unit;
+  }
+  const uint64_t vend = vo + (uint64_t)L.nblk * KC * 512;
+  if (std::max(vend, to + tw * Q) > limit || to / hwc::kVSlotUnit > (uint64_t)(16 - NC) * 127) return false;
+  L.vo = (uint32_t)vo;
+  L.to = (uint32_t)to;
+  const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
+  if (!div_magic(tw * vmax1, tw * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return false;
+  if (tw * vmax1 + L.to >= (1u << 24)) return false;   // coordinate 0 with the offset stays a 24-bit operand
+  L.nbm0 = (uint32_t)(0u - (uint32_t)((uint64_t)L.to * L.m0));
+  if (img.size() < vend) img.resize(vend, 0);
+  for (uint32_t pi = 0; pi < L.nblk * 32; ++pi) {   // spare slots of coordinate 0: sum to / 127
+    uint32_t rest = L.to / hwc::kVSlotUnit;
+    for (uint32_t k = NC; k < 16; ++k) {
+      const uint32_t a = rest < 127 ? rest : 127;
+      img[L.vo + ((size_t)(pi / 32) * KC * 32 + pi % 32) * 16 + k] = (uint8_t)a;
+      rest -= a;
+    }
+  }
+  for (uint32_t pi = 0; pi < L.pts; ++pi) {
+    const uint32_t bb = pi / 32, row = pi % 32;
+    for (uint32_t i = 0; i < NC; ++i) {
+      uint32_t el = F.exp[(uint64_t)i * xs[i0 + pi] % M];   // x^i, packed coordinates
+      for (uint32_t d = 0; d < KC; ++d, el /= p) {
+        const uint32_t digit = el % p;
+        img[L.vo + ((size_t)(bb * KC + d) * 32 + row) * 16 + i] = (uint8_t)(d == 0 ? tw * digit : digit);
+      }
+    }
+  }
+  if (img.size() < L.to + tw * Q) img.resize(L.to + tw * Q, 0);
+  for (uint64_t el = 0; el < Q; ++el) {
+    const uint32_t v = el == 0 ? hwc::kVZero : (F.log[el] & 1u);
+    for (uint32_t b = 0; b < tw; ++b) img[L.to + el * tw + b] = (uint8_t)(v >> (8 * b));
+  }
+  while (img.size() % 16) img.push_back(0);
+  *out = L;
+  return true;
+}
+
+// The passes of the matrix-core path for prime q <= 31 (plan.h, VPlanDesc).
+// Leaves vpath unset when q is not such a prime or the levels do not fit.
 int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint32_t orbit, uint32_t block_opt,
                 bool* ok) {
   *ok = false;
   if (e != 1 || p > hwc::kVMaxP) return HWC_OK;
   const uint32_t NC = 2 * g + 3;
-  hwc::VPlanDesc V{};
-  V.p = p; V.g = g; V.ncoef = NC; V.orbit = orbit;
-  std::vector<uint8_t> img;
-  auto align16 = [&]() { while (img.size() % 16) img.push_back(0); };
+  std::vector<std::vector<uint32_t>> xs(g);
   for (uint32_t j = 0; j < g; ++j) {
     const hwc::Field& F = P->fields[j]->F;
-    const uint32_t KC = j + 1, M = (uint32_t)F.M;
-    std::vector<uint32_t> xs;
-    if (orbit) xs = F.prim_reps;
-    else for (uint32_t L = 0; L < M; ++L) xs.push_back(L);
-    hwc::VLevel& L = V.lv[j];
-    L.pts = (uint32_t)xs.size();
-    L.nblk = (L.pts + 31) / 32;
-    align16();
-    L.vo = (uint32_t)img.size();
-    // the character table's offset: after the blocks, a multiple of 4 * 127
-    const uint64_t vend = L.vo + (uint64_t)L.nblk * KC * 512;
-    const uint64_t unit = 4ull * hwc::kVSlotUnit;
-    L.to = (uint32_t)((vend + unit - 1) / unit * unit);
-    if (L.to / hwc::kVSlotUnit > (uint64_t)(16 - NC) * 127) return HWC_OK;   // spare slots cannot reach it
-    if (L.vo + (uint64_t)L.nblk * KC * 512 > hwc::kLdsImageLimit) return HWC_OK;
-    img.resize(L.vo + (size_t)L.nblk * KC * 512, 0);
-    for (uint32_t pi = 0; pi < L.nblk * 32; ++pi) {   // spare slots of coordinate 0: sum to / 127
-      uint32_t rest = L.to / hwc::kVSlotUnit;
-      for (uint32_t k = NC; k < 16; ++k) {
-        const uint32_t a = rest < 127 ? rest : 127;
-        img[L.vo + ((size_t)(pi / 32) * KC * 32 + pi % 32) * 16 + k] = (uint8_t)a;
-        rest -= a;
-      }
+    if (orbit) xs[j] = F.prim_reps;
+    else for (uint32_t L = 0; L < (uint32_t)F.M; ++L) xs[j].push_back(L);
+  }
+  struct Built { std::vector<uint8_t> img; hwc::VPlanDesc d{}; uint32_t lo, hi, tw; };
+  std::vector<Built> passes;
+  auto start_pass = [&](uint32_t lo, uint32_t hi, uint32_t tw) {
+    Built b;
+    b.d.p = p; b.d.g = g; b.d.ncoef = NC; b.d.orbit = orbit;
+    b.lo = lo; b.hi = hi; b.tw = tw;
+    return b;
+  };
+  const uint64_t limit = hwc::kLdsImageLimit;
+  {   // every level in one image
+    Built b = start_pass(0, g - 1, 4);
+    bool fits = true;
+    for (uint32_t j = 0; j < g && fits; ++j)
+      fits = append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, limit, &b.d.lv[j]);
+    if (fits) passes.push_back(std::move(b));
+  }
+  if (passes.empty()) {
+    // the lower levels in one image, the top level's points over several
+    const uint32_t top = g - 1;
+    if (g > 1) {
+      Built b = start_pass(0, top - 1, 4);
+      for (uint32_t j = 0; j < top; ++j)
+        if (!append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, limit, &b.d.lv[j]))
+          return HWC_OK;
+      passes.push_back(std::move(b));
     }
-    for (uint32_t pi = 0; pi < L.pts; ++pi) {
-      const uint32_t bb = pi / 32, row = pi % 32;
-      for (uint32_t i = 0; i < NC; ++i) {
-        uint32_t el = F.exp[(uint64_t)i * xs[pi] % M];   // x^i, packed coordinates
-        for (uint32_t d = 0; d < KC; ++d, el /= p) {
-          const uint32_t digit = el % p;
-          img[L.vo + ((size_t)(bb * KC + d) * 32 + row) * 16 + i] = (uint8_t)(d == 0 ? 4 * digit : digit);
-        }
-      }
-    }
-    img.resize(L.to, 0);
     uint64_t Q = 1;
-    for (uint32_t d = 0; d < KC; ++d) Q *= p;
-    if (L.to + 4 * Q > hwc::kLdsImageLimit) return HWC_OK;
-    for (uint64_t el = 0; el < Q; ++el) {
-      const uint32_t v = el == 0 ? hwc::kVZero : (F.log[el] & 1u);
-      for (int b = 0; b < 4; ++b) img.push_back((uint8_t)(v >> (8 * b)));
-    }
-    const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
-    if (!div_magic(4 * vmax1, 4 * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return HWC_OK;
-    if (4 * vmax1 + L.to >= (1u << 24)) return HWC_OK;   // coordinate 0 with the offset stays a 24-bit operand
-    L.nbm0 = (uint32_t)(0u - (uint32_t)((uint64_t)L.to * L.m0));
-  }
-  align16();
-  if (img.size() > hwc::kLdsImageLimit) return HWC_OK;
-  V.image_bytes = (uint32_t)img.size();
-  HIPX(c, hipMalloc(&P->d_vimage, img.size()));
-  HIPX(c, hipMemcpy(P->d_vimage, img.data(), img.size(), hipMemcpyHostToDevice));
-  V.image = static_cast<const uint32_t*>(P->d_vimage);
-  HIPX(c, hipMalloc(&P->d_vdesc, sizeof(hwc::VPlanDesc)));
-  HIPX(c, hipMemcpy(P->d_vdesc, &V, sizeof(V), hipMemcpyHostToDevice));
-  P->vdesc = V;
-  P->dev_bytes += img.size() + sizeof(V);
-  c->table_bytes += img.size() + sizeof(V);
-  // the block size that keeps the most waves per CU resident (LDS holds one
-  // image per workgroup), unless a block size is set
-  int best_waves = 0;
-  for (uint32_t blk : {256u, 512u, 1024u}) {
-    if (block_opt && blk != block_opt) continue;
-    int bpc = 0;
-    HIPX(c, hwc::occupancy_vcount(g, blk, V.image_bytes, &bpc));
-    if (bpc * (int)blk > best_waves * 64) {
-      best_waves = bpc * (int)blk / 64;
-      P->vblock = blk;
-      P->vgrid = (uint32_t)(c->cus * bpc);
+    for (uint32_t d = 0; d <= top; ++d) Q *= p;
+    const uint32_t tw = 4 * Q <= 48 * 1024 ? 4 : 2;
+    if (tw == 2 && 2 * (p - 1) > 127) return HWC_OK;
+    const uint64_t blk_bytes = (uint64_t)(top + 1) * 512, room = limit - 1024 - tw * Q;
+    if (tw * Q + 1024 >= limit || room < blk_bytes) return HWC_OK;
+    const size_t per = (size_t)(room / blk_bytes) * 32;
+    for (size_t i0 = 0; i0 < xs[top].size(); i0 += per) {
+      Built b = start_pass(top, top, tw);
+      const size_t i1 = std::min(xs[top].size(), i0 + per);
+      if (!append_vlevel(b.img, P->fields[top]->F, top, xs[top], i0, i1, p, NC, tw, limit, &b.d.lv[top]))
+        return HWC_OK;
+      passes.push_back(std::move(b));
     }
   }
-  if (best_waves < 1) return HWC_OK;
+  for (auto& b : passes) {
+    DevPlan::VPass v;
+    v.lo = b.lo; v.hi = b.hi; v.tw = b.tw;
+    v.desc = b.d;
+    v.desc.image_bytes = (uint32_t)b.img.size();
+    HIPX(c, hipMalloc(&v.d_image, b.img.size()));
+    HIPX(c, hipMemcpy(v.d_image, b.img.data(), b.img.size(), hipMemcpyHostToDevice));
+    v.desc.image = static_cast<const uint32_t*>(v.d_image);
+    HIPX(c, hipMalloc(&v.d_desc, sizeof(hwc::VPlanDesc)));
+    HIPX(c, hipMemcpy(v.d_desc, &v.desc, sizeof(v.desc), hipMemcpyHostToDevice));
+    P->dev_bytes += b.img.size() + sizeof(v.desc);
+    c->table_bytes += b.img.size() + sizeof(v.desc);
+    // the block size that keeps the most waves per CU resident (LDS holds one
+    // image per workgroup), unless a block size is set
+    int best_waves = 0;
+    for (uint32_t blk : {256u, 512u, 1024u}) {
+      if (block_opt && blk != block_opt) continue;
+      int bpc = 0;
+      HIPX(c, hwc::occupancy_vcount(g, blk, v.desc.image_bytes, &bpc));
+      if (bpc * (int)blk > best_waves * 64) {
+        best_waves = bpc * (int)blk / 64;
+        v.block = blk;
+        v.grid = (uint32_t)(c->cus * bpc);
+      }
+    }
+    P->vpasses.push_back(v);
+    if (best_waves < 1) return HWC_OK;
+  }
   *ok = true;
   return HWC_OK;
 }
@@ -712,14 +778,21 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
     // matrix-core path: rows in input order, no bucketing
     if (record) HIPX(c, hipEventRecord(ev[1], s));
     if (n > 0) {
-      if (flags & HWC_PLAIN) {
-        for (uint32_t j = 0; j < g; ++j)
-          HIPX(c, hwc::launch_vcount(P->vdesc, P->d_vdesc, cb, codes, n, j, j, nullptr, S.lv, c->d_err, P->vgrid,
-                                     P->vblock, s));
-        HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
+      const auto& V = P->vpasses;
+      if (V.size() == 1 && !(flags & HWC_PLAIN)) {
+        HIPX(c, hwc::launch_vcount(V[0].desc, V[0].d_desc, cb, codes, n, 0, g - 1, 4, false, N, lam ? S.lv : nullptr,
+                                   c->d_err, V[0].grid, V[0].block, s));
       } else {
-        HIPX(c, hwc::launch_vcount(P->vdesc, P->d_vdesc, cb, codes, n, 0, g - 1, N, lam ? S.lv : nullptr, c->d_err,
-                                   P->vgrid, P->vblock, s));
+        // one launch per level (plain form) or per pass, counts added up per curve
+        HIPX(c, hwc::launch_fill(S.lv, 0, n * g, s));
+        for (const auto& v : V)
+          for (uint32_t j = v.lo; j <= v.hi; ++j) {
+            if (!(flags & HWC_PLAIN) && j != v.lo) break;
+            const uint32_t hi = (flags & HWC_PLAIN) ? j : v.hi;
+            HIPX(c, hwc::launch_vcount(v.desc, v.d_desc, cb, codes, n, j, hi, v.tw, true, nullptr, S.lv, c->d_err,
+                                       v.grid, v.block, s));
+          }
+        HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
       }
       if (lam)
         HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, (flags & kFlagSqf) ? 1u : 0u, s));
@@ -793,7 +866,8 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
     if (bits > 63.0) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "histogram key wider than 63 bits for this (q, g)");
   }
   Scratch S;
-  if ((rc = get_scratch(c, n, g, (flags & HWC_PLAIN) != 0 || lam != nullptr, hk != nullptr, &S))) return rc;
+  const bool need_lv = (flags & HWC_PLAIN) != 0 || lam != nullptr || (P->vpath && P->vpasses.size() > 1);
+  if ((rc = get_scratch(c, n, g, need_lv, hk != nullptr, &S))) return rc;
   if (P->d_shift) {
     if ((rc = ensure(c, c->tcodes, std::max<uint64_t>(n, 1) * (2 * g + 3) * cb))) return rc;
     S.tcodes = c->tcodes.p;
@@ -1820,7 +1894,9 @@ int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_
     levels[j].msplit = L.msplit;
     levels[j].nt = L.nt;
     levels[j].ns = L.ns;
-    levels[j].lds_bytes = P->vpath ? P->vdesc.image_bytes : P->desc.image_bytes;
+    uint32_t vmax = 0;
+    for (const auto& v : P->vpasses) vmax = std::max(vmax, v.desc.image_bytes);
+    levels[j].lds_bytes = P->vpath ? vmax : P->desc.image_bytes;
     levels[j].mfma = P->vpath ? 1u : 0u;
   }
   return HWC_OK;

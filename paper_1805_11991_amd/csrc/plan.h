@@ -88,6 +88,9 @@ struct SingleDesc {
 // its residue mod 4p is four times the residue mod p), then a u32 table of the
 // quadratic character over packed elements (byte offset 4 sum_d r_d p^d):
 // 0 square, 1 nonsquare, kVZero for zero.  Needs 4(p-1) <= 127: p <= 31.
+// When a level's blocks do not fit one image, its points are split over
+// several images (passes) that add their counts per curve; such a level may
+// use a u16 table (byte offset 2 sum_d r_d p^d, coordinate 0 doubled).
 // The K slots past the coefficients hold 127 on the curve side and, in the
 // coordinate-0 rows, values summing to to / 127, so the product adds the
 // table's byte offset (a multiple of 508) to coordinate 0 by itself.
@@ -95,7 +98,8 @@ constexpr uint32_t kVSlotUnit = 127;
 constexpr uint32_t kVZero = 1u << 15;
 constexpr uint32_t kVMaxP = 31;
 struct VLevel {
-  uint32_t pts, nblk;     // swept points and 32-point blocks (padding rows are zero)
+  uint32_t pts, nblk;     // swept points in the image and their 32-point blocks
+  uint32_t pad;           // padding rows of the blocks (zero points, subtracted)
   uint32_t vo, to;        // byte offsets of the blocks and of the character table
   uint32_t m0, s0;        // floor(v / 4p) = (v * m0) >> s0 for every value coordinate 0 reaches
   uint32_t nbm0;          // -to * m0 mod 2^32: coordinate 0 arrives with the table offset added

@@ -24,10 +24,12 @@ namespace hwc {
 namespace {
 
 typedef int v16i __attribute__((ext_vector_type(16)));
+typedef const __attribute__((address_space(3))) uint16_t* vlds16_ptr;
 typedef const __attribute__((address_space(3))) uint32_t* vlds32_ptr;
 typedef const __attribute__((address_space(3))) uint64_t* vlds64_ptr;
 
 __device__ __forceinline__ uint32_t vlds32(uint32_t a) { return *(vlds32_ptr)(size_t)a; }
+__device__ __forceinline__ uint32_t vlds16(uint32_t a) { return *(vlds16_ptr)(size_t)a; }
 __device__ __forceinline__ long vlds64(uint32_t a) { return (long)*(vlds64_ptr)(size_t)a; }
 
 // c + a * b on 24-bit operands with b uniform, one instruction each (the
@@ -50,14 +52,15 @@ __device__ __forceinline__ uint32_t quot(uint32_t v, uint32_t m, uint32_t s) {
 }
 
 // One level with KC coordinates: the lane's zeros and nonsquares over its rows.
-// The character table has u32 entries; coordinate 0 comes scaled by 4 from the
-// matrix product, so its residue mod 4p is already 4 r_0 (a byte offset).
-template <int KC>
+// The character table has TW-byte entries; coordinate 0 comes scaled by TW
+// from the matrix product, so its residue mod TW p is already TW r_0 (a byte
+// offset).
+template <int KC, int TW>
 __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lane, long b, uint32_t& zs,
                                        uint32_t& ns) {
   const uint32_t vrow = L.vo + (lane & 31u) * 16u + (lane >> 5) * 8u;
-  const uint32_t mult1 = 4 * p, mult2 = 4 * p * p, mult3 = 4 * p * p * p;
-  const int32_t neg0 = -(int32_t)(4 * p), neg1 = -(int32_t)(mult1 * p), neg2 = -(int32_t)(mult2 * p),
+  const uint32_t mult1 = TW * p, mult2 = TW * p * p, mult3 = TW * p * p * p;
+  const int32_t neg0 = -(int32_t)(TW * p), neg1 = -(int32_t)(mult1 * p), neg2 = -(int32_t)(mult2 * p),
                 neg3 = -(int32_t)(mult3 * p);
   const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t acc = 0;
@@ -87,7 +90,7 @@ __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lan
         const uint32_t v = (uint32_t)D[3][i], q = quot(v, L.m1, L.s1);
         idx = mad_i24(q, neg3, mad_u24_after(v, mult3, idx, q));
       }
-      acc += vlds32(idx);
+      acc += TW == 4 ? vlds32(idx) : vlds16(idx);
     }
   }
   zs = acc >> 15;
@@ -96,22 +99,25 @@ __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lan
 
 // Level J (J + 1 coordinates) of a curve: lv[J] = zeros | nonsquares << 8,
 // summed over the two lanes that hold the curve.
-template <int J, int G>
+template <int J, int G, int TW>
 __device__ __forceinline__ void level_counts(const VPlanDesc& V, uint32_t p, uint32_t lane, long b, uint32_t lvl_lo,
                                              uint32_t lvl_hi, uint32_t (&lv)[G]) {
   if constexpr (J < G) {
     if ((uint32_t)J < lvl_lo || (uint32_t)J > lvl_hi) return;
     const VLevel& L = V.lv[J];
     uint32_t zs, ns;
-    vlevel<J + 1>(L, p, lane, b, zs, ns);
+    vlevel<J + 1, TW>(L, p, lane, b, zs, ns);
     zs += __shfl_xor(zs, 32);
     ns += __shfl_xor(ns, 32);
-    zs -= L.nblk * 32u - L.pts;   // padding rows are zero points
+    zs -= L.pad;   // padding rows are zero points
     lv[J] = zs | (ns << 8);
   }
 }
 
-template <int G, typename CT>
+// ACC: the image holds part of the points (one pass of several); the counts
+// are added to outLv (zeros | nonsquares << 8 per curve and level, which the
+// assembly turns into N afterwards) and outN is not written.
+template <int G, typename CT, int TW, bool ACC>
 __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restrict__ Vd, const CT* __restrict__ codes,
                                                       uint64_t n, uint32_t lvl_lo, uint32_t lvl_hi,
                                                       int32_t* __restrict__ outN, uint32_t* __restrict__ outLv,
@@ -147,11 +153,17 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
     uint32_t lv[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) lv[j] = 0;
-    level_counts<0, G>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<1, G>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<2, G>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<3, G>(V, p, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<0, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<1, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<2, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<3, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
     if (!valid || half) continue;
+    if (ACC) {
+#pragma unroll
+      for (int j = 0; j < G; ++j)
+        if ((uint32_t)j >= lvl_lo && (uint32_t)j <= lvl_hi) outLv[row * G + j] += lv[j];
+      continue;
+    }
     if (outLv) {
 #pragma unroll
       for (int j = 0; j < G; ++j)
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
       // x = 0 and the points at infinity (Sec. 1.1), then the levels
       const uint32_t to1 = V.lv[0].to;
       const uint32_t c0 = c[0], ct = c[NC - 1];
-      const bool ns0 = vlds32(to1 + 4 * c0) == 1u, nst = vlds32(to1 + 4 * ct) == 1u;
+      const bool ns0 = vlds32(to1 + 4 * c0) == 1u, nst = vlds32(to1 + 4 * ct) == 1u;   // TW = 4 here
 #pragma unroll
       for (int k = 1; k <= G; ++k) {
         const bool odd = k & 1;
@@ -188,53 +200,75 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
 
 }  // namespace
 
+// tw: table entry bytes of the image (4, or 2 for a pass of a split level);
+// acc: add the counts to outLv (a pass of several) instead of writing N.
 hipError_t launch_vcount(const VPlanDesc& V, const VPlanDesc* dV, int coeff_bytes, const void* codes, uint64_t n,
-                         uint32_t lvl_lo, uint32_t lvl_hi, int32_t* outN, uint32_t* outLv, uint32_t* err,
-                         uint32_t grid, uint32_t block, hipStream_t s) {
+                         uint32_t lvl_lo, uint32_t lvl_hi, uint32_t tw, bool acc, int32_t* outN, uint32_t* outLv,
+                         uint32_t* err, uint32_t grid, uint32_t block, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (V.image_bytes > kLdsImageLimit || lvl_hi >= V.g || lvl_lo > lvl_hi) return hipErrorInvalidValue;
-#define HWC_V(GG)                                                                                               \
-  case GG:                                                                                                      \
-    if (coeff_bytes == 1)                                                                                       \
-      hipLaunchKernelGGL((vcount_kernel<GG, int8_t>), dim3(grid), dim3(block), V.image_bytes, s, dV,            \
-                         static_cast<const int8_t*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err);              \
-    else                                                                                                        \
-      hipLaunchKernelGGL((vcount_kernel<GG, int16_t>), dim3(grid), dim3(block), V.image_bytes, s, dV,           \
-                         static_cast<const int16_t*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err);             \
+  if ((tw != 4 && tw != 2) || (tw == 2 && !acc) || (acc && !outLv)) return hipErrorInvalidValue;
+#define HWC_VK(GG, CTT, TWV, ACCV)                                                                                \
+  hipLaunchKernelGGL((vcount_kernel<GG, CTT, TWV, ACCV>), dim3(grid), dim3(block), V.image_bytes, s, dV,         \
+                     static_cast<const CTT*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err)
+#define HWC_V(GG)                                                                                                 \
+  case GG:                                                                                                        \
+    if (coeff_bytes == 1) {                                                                                       \
+      if (!acc) HWC_VK(GG, int8_t, 4, false);                                                                     \
+      else if (tw == 4) HWC_VK(GG, int8_t, 4, true);                                                              \
+      else HWC_VK(GG, int8_t, 2, true);                                                                           \
+    } else {                                                                                                      \
+      if (!acc) HWC_VK(GG, int16_t, 4, false);                                                                    \
+      else if (tw == 4) HWC_VK(GG, int16_t, 4, true);                                                             \
+      else HWC_VK(GG, int16_t, 2, true);                                                                          \
+    }                                                                                                             \
     break;
   switch (V.g) {
     HWC_V(1) HWC_V(2) HWC_V(3) HWC_V(4)
     default: return hipErrorInvalidValue;
   }
 #undef HWC_V
+#undef HWC_VK
   return hipGetLastError();
 }
 
-// Largest dynamic LDS for every instantiation, and the blocks per CU of one.
+// Largest dynamic LDS for every instantiation (none may declare static LDS:
+// the image starts at address 0).
+template <int G, typename CT, int TW, bool ACC>
+hipError_t prepare_one() {
+  const void* f = reinterpret_cast<const void*>(&vcount_kernel<G, CT, TW, ACC>);
+  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsImageLimit);
+  hipFuncAttributes fa;
+  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, f);
+  if (e == hipSuccess && fa.sharedSizeBytes != 0) e = hipErrorInvalidKernelFile;
+  return e;
+}
+
+template <int G>
+hipError_t prepare_g() {
+  hipError_t e = prepare_one<G, int8_t, 4, false>();
+  if (e == hipSuccess) e = prepare_one<G, int8_t, 4, true>();
+  if (e == hipSuccess) e = prepare_one<G, int8_t, 2, true>();
+  if (e == hipSuccess) e = prepare_one<G, int16_t, 4, false>();
+  if (e == hipSuccess) e = prepare_one<G, int16_t, 4, true>();
+  if (e == hipSuccess) e = prepare_one<G, int16_t, 2, true>();
+  return e;
+}
+
 hipError_t prepare_vcount() {
-  hipError_t e = hipSuccess;
-  for (const void* f : {reinterpret_cast<const void*>(&vcount_kernel<1, int8_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<2, int8_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<3, int8_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<4, int8_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<1, int16_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<2, int16_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<3, int16_t>),
-                        reinterpret_cast<const void*>(&vcount_kernel<4, int16_t>)}) {
-    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsImageLimit);
-    hipFuncAttributes fa;
-    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, f);
-    if (e == hipSuccess && fa.sharedSizeBytes != 0) e = hipErrorInvalidKernelFile;   // image must start at 0
-  }
+  hipError_t e = prepare_g<1>();
+  if (e == hipSuccess) e = prepare_g<2>();
+  if (e == hipSuccess) e = prepare_g<3>();
+  if (e == hipSuccess) e = prepare_g<4>();
   return e;
 }
 
 hipError_t occupancy_vcount(uint32_t g, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
   switch (g) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<1, int8_t>, block, lds_bytes);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<2, int8_t>, block, lds_bytes);
-    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<3, int8_t>, block, lds_bytes);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<4, int8_t>, block, lds_bytes);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<1, int8_t, 4, true>, block, lds_bytes);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<2, int8_t, 4, true>, block, lds_bytes);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<3, int8_t, 4, true>, block, lds_bytes);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<4, int8_t, 4, true>, block, lds_bytes);
     default: return hipErrorInvalidValue;
   }
 }
