@@ -334,10 +334,18 @@ def main():
         runner(13, 4, bufs4, 0)()
         p4 = ctx.profile_read()
         ctx.profile(False)
-        lk4, _ = lookups_per_batch(evaluated_rows(ctx, 13, 4, bufs4[1]), ctx.plan_info(13, 4))
+        lv4 = ctx.plan_info(13, 4)
         g4["count_kernel_ms"] = round(p4["count_ms"], 3)
-        g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
-        g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)
+        if lv4[0]["mfma"]:
+            w4 = mfma_work(n4, lv4)
+            g4["path"] = "matrix cores (top level over several passes)"
+            g4["valu_ops_per_s"] = round(w4["valu_ops"] / (p4["count_ms"] * 1e-3), 1)
+            g4["valu_frac"] = round(w4["valu_ops"] / (p4["count_ms"] * 1e-3) / VALU_PEAK_OPS, 4)
+        else:
+            lk4, _ = lookups_per_batch(evaluated_rows(ctx, 13, 4, bufs4[1]), lv4)
+            g4["path"] = "Zech logarithms"
+            g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
+            g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)
         g4["curves"] = n4
         extra["g4_q13"] = g4
         del bufs4
