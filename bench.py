@@ -81,14 +81,15 @@ def mfma_work(n: int, levels: list[dict]) -> dict:
     each coordinate its residue (multiply and shift for the quotient, then
     multiply-adds into the table index; coordinate 0 arrives with the table
     offset already added, one multiply-add fewer) and one add of the
-    character read."""
+    character read.  In the balanced form (mfma = 2) the quotient of every
+    coordinate but the first is one multiply-high: 3k + 1 operations."""
     tiles = (n + 31) // 32
     pairs = valu = mfma = 0
     for j, L in enumerate(levels, start=1):
         pts = (L["nx"] + 31) // 32 * 32
         pr = tiles * 32 * pts
         pairs += pr
-        valu += pr * 4 * j
+        valu += pr * ((3 * j + 1) if L["mfma"] == 2 else 4 * j)
         mfma += pr * j * 16 * 2
     return {"pairs": pairs, "valu_ops": valu, "mfma_ops": mfma}
 

@@ -261,7 +261,8 @@ int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags
  * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
  * x^m, plus ns single points), the LDS bytes of the plan, and mfma = 1 when
  * the plan counts by int8 matrix products (HWC_OPT_MFMA) instead of Zech
- * logarithms. */
+ * logarithms, 2 when it does so in the balanced form (p = 11, 13: one
+ * 24-bit multiply-high per coordinate for the quotients). */
 typedef struct {
   uint32_t M, form, nx, weight, msplit, nt, ns, lds_bytes, mfma;
 } hwc_level_desc;

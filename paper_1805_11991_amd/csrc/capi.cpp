@@ -347,7 +347,8 @@ bool div_magic(uint64_t vmax, uint32_t div, uint32_t* m, uint32_t* s) {
 // which keeps large blocks of a split level reachable).  False when the image
 // would pass `limit` or the quotient constants do not exist.
 bool append_vlevel(std::vector<uint8_t>& img, const hwc::Field& F, uint32_t j, const std::vector<uint32_t>& xs,
-                   size_t i0, size_t i1, uint32_t p, uint32_t NC, uint32_t tw, uint64_t limit, hwc::VLevel* out) {
+                   size_t i0, size_t i1, uint32_t p, uint32_t NC, uint32_t tw, bool bal, uint32_t sb, uint64_t limit,
+                   hwc::VLevel* out) {
   const uint32_t KC = j + 1, M = (uint32_t)F.M;
   hwc::VLevel L{};
   L.pts = (uint32_t)(i1 - i0);
@@ -368,20 +369,38 @@ bool append_vlevel(std::vector<uint8_t>& img, const hwc::Field& F, uint32_t j, c
     to = (vo + (uint64_t)L.nblk * KC * 512 + unit - 1) / unit * unit;
   }
   const uint64_t vend = vo + (uint64_t)L.nblk * KC * 512;
-  if (std::max(vend, to + tw * Q) > limit || to / hwc::kVSlotUnit > (uint64_t)(16 - NC) * 127) return false;
+  const uint64_t cap = (uint64_t)(16 - NC) * 127;   // what the spare slots can add, in units of 127
+  // balanced form: coordinate 0 offset by 127 tw p, the others by 127 sb p^2
+  const uint64_t h = (p - 1) / 2, off0 = bal ? 127ull * tw * p : 0, offd = 127ull * sb * p * p;
+  if (std::max(vend, to + tw * Q) > limit || (off0 + to) / hwc::kVSlotUnit > cap) return false;
   L.vo = (uint32_t)vo;
   L.to = (uint32_t)to;
-  const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
-  if (!div_magic(tw * vmax1, tw * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return false;
-  if (tw * vmax1 + L.to >= (1u << 24)) return false;   // coordinate 0 with the offset stays a 24-bit operand
+  if (bal) {
+    const uint64_t span0 = (uint64_t)tw * NC * h * h, spand = (uint64_t)sb * p * NC * h * h;
+    if (tw % sb || off0 < span0 || offd < spand || sb * p * p > cap || sb * p * p < 256) return false;
+    if (!div_magic(off0 + span0, tw * p, &L.m0, &L.s0)) return false;
+    if (off0 + span0 + L.to >= (1u << 24) || offd + spand >= (1u << 24)) return false;
+    const uint64_t div = (uint64_t)sb * p * p, m = ((1ull << 32) + div - 1) / div;
+    if (m >= (1u << 24) || (offd + spand) * (m * div - (1ull << 32)) >= (1ull << 32)) return false;
+    L.m1 = (uint32_t)m;
+    L.s1 = 32;
+  } else {
+    const uint64_t vmax1 = (uint64_t)NC * (p - 1) * (p - 1);
+    if (!div_magic(tw * vmax1, tw * p, &L.m0, &L.s0) || !div_magic(vmax1, p, &L.m1, &L.s1)) return false;
+    if (tw * vmax1 + L.to >= (1u << 24)) return false;   // coordinate 0 with the offset stays a 24-bit operand
+  }
   L.nbm0 = (uint32_t)(0u - (uint32_t)((uint64_t)L.to * L.m0));
   if (img.size() < vend) img.resize(vend, 0);
-  for (uint32_t pi = 0; pi < L.nblk * 32; ++pi) {   // spare slots of coordinate 0: sum to / 127
-    uint32_t rest = L.to / hwc::kVSlotUnit;
-    for (uint32_t k = NC; k < 16; ++k) {
-      const uint32_t a = rest < 127 ? rest : 127;
-      img[L.vo + ((size_t)(pi / 32) * KC * 32 + pi % 32) * 16 + k] = (uint8_t)a;
-      rest -= a;
+  // spare slots: coordinate 0 rows sum to (off0 + to) / 127, the others
+  // (balanced form) to sb p^2; the curve side holds 127 there
+  for (uint32_t pi = 0; pi < L.nblk * 32; ++pi) {
+    for (uint32_t d = 0; d < (bal ? KC : 1u); ++d) {
+      uint32_t rest = (uint32_t)(d == 0 ? (off0 + L.to) / hwc::kVSlotUnit : offd / hwc::kVSlotUnit);
+      for (uint32_t k = NC; k < 16; ++k) {
+        const uint32_t a = rest < 127 ? rest : 127;
+        img[L.vo + ((size_t)((pi / 32) * KC + d) * 32 + pi % 32) * 16 + k] = (uint8_t)a;
+        rest -= a;
+      }
     }
   }
   for (uint32_t pi = 0; pi < L.pts; ++pi) {
@@ -390,7 +409,14 @@ bool append_vlevel(std::vector<uint8_t>& img, const hwc::Field& F, uint32_t j, c
       uint32_t el = F.exp[(uint64_t)i * xs[i0 + pi] % M];   // x^i, packed coordinates
       for (uint32_t d = 0; d < KC; ++d, el /= p) {
         const uint32_t digit = el % p;
-        img[L.vo + ((size_t)(bb * KC + d) * 32 + row) * 16 + i] = (uint8_t)(d == 0 ? tw * digit : digit);
+        int32_t a;
+        if (bal) {
+          const int32_t db = 2 * digit > p ? (int32_t)digit - (int32_t)p : (int32_t)digit;
+          a = d == 0 ? (int32_t)(tw / sb) * db : (int32_t)p * db;
+        } else {
+          a = (int32_t)(d == 0 ? tw * digit : digit);
+        }
+        img[L.vo + ((size_t)(bb * KC + d) * 32 + row) * 16 + i] = (uint8_t)(int8_t)a;
       }
     }
   }
@@ -419,9 +445,14 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
   }
   struct Built { std::vector<uint8_t> img; hwc::VPlanDesc d{}; uint32_t lo, hi, tw; };
   std::vector<Built> passes;
+  // the balanced form where its constants exist (p = 11, 13; plan.h)
+  const uint32_t sb = p == 13 ? 2u : 4u;
+  auto use_bal = [&](uint32_t tw) { return (p == 13 || p == 11) && tw % sb == 0; };
   auto start_pass = [&](uint32_t lo, uint32_t hi, uint32_t tw) {
     Built b;
     b.d.p = p; b.d.g = g; b.d.ncoef = NC; b.d.orbit = orbit;
+    b.d.bal = use_bal(tw) ? 1u : 0u;
+    b.d.sb = sb;
     b.lo = lo; b.hi = hi; b.tw = tw;
     return b;
   };
@@ -430,7 +461,8 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
     Built b = start_pass(0, g - 1, 4);
     bool fits = true;
     for (uint32_t j = 0; j < g && fits; ++j)
-      fits = append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, limit, &b.d.lv[j]);
+      fits = append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, b.d.bal, sb, limit,
+                           &b.d.lv[j]);
     if (fits) passes.push_back(std::move(b));
   }
   if (passes.empty()) {
@@ -439,7 +471,8 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
     if (g > 1) {
       Built b = start_pass(0, top - 1, 4);
       for (uint32_t j = 0; j < top; ++j)
-        if (!append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, limit, &b.d.lv[j]))
+        if (!append_vlevel(b.img, P->fields[j]->F, j, xs[j], 0, xs[j].size(), p, NC, 4, b.d.bal, sb, limit,
+                           &b.d.lv[j]))
           return HWC_OK;
       passes.push_back(std::move(b));
     }
@@ -453,7 +486,8 @@ int build_vplan(hwc_ctx* c, DevPlan* P, uint32_t p, uint32_t e, uint32_t g, uint
     for (size_t i0 = 0; i0 < xs[top].size(); i0 += per) {
       Built b = start_pass(top, top, tw);
       const size_t i1 = std::min(xs[top].size(), i0 + per);
-      if (!append_vlevel(b.img, P->fields[top]->F, top, xs[top], i0, i1, p, NC, tw, limit, &b.d.lv[top]))
+      if (!append_vlevel(b.img, P->fields[top]->F, top, xs[top], i0, i1, p, NC, tw, b.d.bal, sb, limit,
+                         &b.d.lv[top]))
         return HWC_OK;
       passes.push_back(std::move(b));
     }
@@ -1897,7 +1931,7 @@ int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_
     uint32_t vmax = 0;
     for (const auto& v : P->vpasses) vmax = std::max(vmax, v.desc.image_bytes);
     levels[j].lds_bytes = P->vpath ? vmax : P->desc.image_bytes;
-    levels[j].mfma = P->vpath ? 1u : 0u;
+    levels[j].mfma = P->vpath ? (P->vpasses.back().desc.bal ? 2u : 1u) : 0u;
   }
   return HWC_OK;
 }

@@ -105,8 +105,15 @@ struct VLevel {
   uint32_t nbm0;          // -to * m0 mod 2^32: coordinate 0 arrives with the table offset added
   uint32_t m1, s1;        // floor(v / p) = (v * m1) >> s1 for the other coordinates
 };
+// Balanced form (p = 11, 13): digits and coefficients in -(p-1)/2 .. (p-1)/2,
+// coefficients times sb, coordinates d >= 1 times p, coordinate 0 times tw/sb,
+// and constants in the spare K slots that make every value nonnegative and
+// a multiple of the divisor where it must vanish; then coordinate d >= 1 is
+// sb p D_d + 127 sb p^2 and its quotient by sb p^2 (>= 256) is one 24-bit
+// multiply-high by m1.
 struct VPlanDesc {
   uint32_t p, g, ncoef, orbit;
+  uint32_t bal, sb;       // balanced form and the coefficient scale
   uint32_t image_bytes;
   const uint32_t* image;
   VLevel lv[kMaxG];

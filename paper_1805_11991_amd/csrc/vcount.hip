@@ -50,18 +50,25 @@ __device__ __forceinline__ uint32_t mad_i24(uint32_t a, int32_t b, uint32_t c) {
 __device__ __forceinline__ uint32_t quot(uint32_t v, uint32_t m, uint32_t s) {
   return (uint32_t)__umul24(v, m) >> s;
 }
+// floor(v m / 2^32) on 24-bit operands (v_mul_hi_u32_u24)
+__device__ __forceinline__ uint32_t mulhi24(uint32_t v, uint32_t m) {
+  return (uint32_t)(((uint64_t)(v & 0xFFFFFFu) * (m & 0xFFFFFFu)) >> 32);
+}
 
 // One level with KC coordinates: the lane's zeros and nonsquares over its rows.
 // The character table has TW-byte entries; coordinate 0 comes scaled by TW
 // from the matrix product, so its residue mod TW p is already TW r_0 (a byte
 // offset).
-template <int KC, int TW>
-__device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lane, long b, uint32_t& zs,
-                                       uint32_t& ns) {
+template <int KC, int TW, bool BAL>
+__device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t sb, uint32_t lane, long b,
+                                       uint32_t& zs, uint32_t& ns) {
   const uint32_t vrow = L.vo + (lane & 31u) * 16u + (lane >> 5) * 8u;
-  const uint32_t mult1 = TW * p, mult2 = TW * p * p, mult3 = TW * p * p * p;
-  const int32_t neg0 = -(int32_t)(TW * p), neg1 = -(int32_t)(mult1 * p), neg2 = -(int32_t)(mult2 * p),
-                neg3 = -(int32_t)(mult3 * p);
+  // coordinate d >= 1 adds mult_d D_d - TW p^(d+1) q_d; in the balanced form
+  // D_d carries a factor sb p, so its multiplier is TW p^(d-1) / sb
+  const uint32_t mult1 = BAL ? TW / sb : TW * p, mult2 = BAL ? TW * p / sb : TW * p * p,
+                 mult3 = BAL ? TW * p * p / sb : TW * p * p * p;
+  const int32_t neg0 = -(int32_t)(TW * p), neg1 = -(int32_t)(TW * p * p), neg2 = -(int32_t)(TW * p * p * p),
+                neg3 = -(int32_t)(TW * p * p * p * p);
   const v16i zero = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   uint32_t acc = 0;
 #pragma unroll 1
@@ -79,15 +86,15 @@ __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lan
       const uint32_t q0 = ((uint32_t)__umul24(v0, L.m0) + L.nbm0) >> L.s0;
       uint32_t idx = mad_i24(q0, neg0, v0);
       if (KC > 1) {
-        const uint32_t v = (uint32_t)D[1][i], q = quot(v, L.m1, L.s1);
+        const uint32_t v = (uint32_t)D[1][i], q = BAL ? mulhi24(v, L.m1) : quot(v, L.m1, L.s1);
         idx = mad_i24(q, neg1, mad_u24_after(v, mult1, idx, q));
       }
       if (KC > 2) {
-        const uint32_t v = (uint32_t)D[2][i], q = quot(v, L.m1, L.s1);
+        const uint32_t v = (uint32_t)D[2][i], q = BAL ? mulhi24(v, L.m1) : quot(v, L.m1, L.s1);
         idx = mad_i24(q, neg2, mad_u24_after(v, mult2, idx, q));
       }
       if (KC > 3) {
-        const uint32_t v = (uint32_t)D[3][i], q = quot(v, L.m1, L.s1);
+        const uint32_t v = (uint32_t)D[3][i], q = BAL ? mulhi24(v, L.m1) : quot(v, L.m1, L.s1);
         idx = mad_i24(q, neg3, mad_u24_after(v, mult3, idx, q));
       }
       acc += TW == 4 ? vlds32(idx) : vlds16(idx);
@@ -99,14 +106,14 @@ __device__ __forceinline__ void vlevel(const VLevel& L, uint32_t p, uint32_t lan
 
 // Level J (J + 1 coordinates) of a curve: lv[J] = zeros | nonsquares << 8,
 // summed over the two lanes that hold the curve.
-template <int J, int G, int TW>
-__device__ __forceinline__ void level_counts(const VPlanDesc& V, uint32_t p, uint32_t lane, long b, uint32_t lvl_lo,
-                                             uint32_t lvl_hi, uint32_t (&lv)[G]) {
+template <int J, int G, int TW, bool BAL>
+__device__ __forceinline__ void level_counts(const VPlanDesc& V, uint32_t p, uint32_t sb, uint32_t lane, long b,
+                                             uint32_t lvl_lo, uint32_t lvl_hi, uint32_t (&lv)[G]) {
   if constexpr (J < G) {
     if ((uint32_t)J < lvl_lo || (uint32_t)J > lvl_hi) return;
     const VLevel& L = V.lv[J];
     uint32_t zs, ns;
-    vlevel<J + 1, TW>(L, p, lane, b, zs, ns);
+    vlevel<J + 1, TW, BAL>(L, p, sb, lane, b, zs, ns);
     zs += __shfl_xor(zs, 32);
     ns += __shfl_xor(ns, 32);
     zs -= L.pad;   // padding rows are zero points
@@ -117,7 +124,7 @@ __device__ __forceinline__ void level_counts(const VPlanDesc& V, uint32_t p, uin
 // ACC: the image holds part of the points (one pass of several); the counts
 // are added to outLv (zeros | nonsquares << 8 per curve and level, which the
 // assembly turns into N afterwards) and outN is not written.
-template <int G, typename CT, int TW, bool ACC>
+template <int G, typename CT, int TW, bool ACC, bool BAL>
 __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restrict__ Vd, const CT* __restrict__ codes,
                                                       uint64_t n, uint32_t lvl_lo, uint32_t lvl_hi,
                                                       int32_t* __restrict__ outN, uint32_t* __restrict__ outLv,
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
   for (uint32_t i = threadIdx.x; i < V.image_bytes / 4; i += blockDim.x) vl32[i] = V.image[i];
   __syncthreads();
   const uint32_t lane = threadIdx.x & 63u, half = lane >> 5;
-  const uint32_t p = __builtin_amdgcn_readfirstlane(V.p);
+  const uint32_t p = __builtin_amdgcn_readfirstlane(V.p), sb = __builtin_amdgcn_readfirstlane(V.sb);
   const uint64_t ntiles = (n + 31) / 32;
   const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   uint32_t bad = 0;
@@ -143,20 +150,26 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
       c[i] = (v < 0 || v >= (int)p) ? 0u : (uint32_t)v;
     }
     if (valid && c[NC - 1] == 0 && c[NC - 2] == 0) bad |= 2u;
+    // the B operand: codes, or sb times the balanced codes (as int8)
+    uint32_t cb[NC];
+#pragma unroll
+    for (int i = 0; i < NC; ++i)
+      cb[i] = BAL ? (uint32_t)(sb * (int32_t)(2 * c[i] > p ? (int32_t)c[i] - (int32_t)p : (int32_t)c[i])) & 0xFFu
+                  : c[i];
     long b = 0;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const uint32_t lo = j < NC ? c[j < NC ? j : 0] : kVSlotUnit;
-      const uint32_t hi = 8 + j < NC ? c[8 + j < NC ? 8 + j : 0] : kVSlotUnit;
+      const uint32_t lo = j < NC ? cb[j < NC ? j : 0] : kVSlotUnit;
+      const uint32_t hi = 8 + j < NC ? cb[8 + j < NC ? 8 + j : 0] : kVSlotUnit;
       b |= (long)(half ? hi : lo) << (8 * j);
     }
     uint32_t lv[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) lv[j] = 0;
-    level_counts<0, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<1, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<2, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
-    level_counts<3, G, TW>(V, p, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<0, G, TW, BAL>(V, p, sb, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<1, G, TW, BAL>(V, p, sb, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<2, G, TW, BAL>(V, p, sb, lane, b, lvl_lo, lvl_hi, lv);
+    level_counts<3, G, TW, BAL>(V, p, sb, lane, b, lvl_lo, lvl_hi, lv);
     if (!valid || half) continue;
     if (ACC) {
 #pragma unroll
@@ -205,12 +218,19 @@ __global__ __launch_bounds__(1024) void vcount_kernel(const VPlanDesc* __restric
 hipError_t launch_vcount(const VPlanDesc& V, const VPlanDesc* dV, int coeff_bytes, const void* codes, uint64_t n,
                          uint32_t lvl_lo, uint32_t lvl_hi, uint32_t tw, bool acc, int32_t* outN, uint32_t* outLv,
                          uint32_t* err, uint32_t grid, uint32_t block, hipStream_t s) {
+  const bool bal = V.bal != 0;
   if (n == 0) return hipSuccess;
   if (V.image_bytes > kLdsImageLimit || lvl_hi >= V.g || lvl_lo > lvl_hi) return hipErrorInvalidValue;
   if ((tw != 4 && tw != 2) || (tw == 2 && !acc) || (acc && !outLv)) return hipErrorInvalidValue;
 #define HWC_VK(GG, CTT, TWV, ACCV)                                                                                \
-  hipLaunchKernelGGL((vcount_kernel<GG, CTT, TWV, ACCV>), dim3(grid), dim3(block), V.image_bytes, s, dV,         \
-                     static_cast<const CTT*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err)
+  do {                                                                                                            \
+    if (bal)                                                                                                      \
+      hipLaunchKernelGGL((vcount_kernel<GG, CTT, TWV, ACCV, true>), dim3(grid), dim3(block), V.image_bytes, s, dV, \
+                         static_cast<const CTT*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err);                   \
+    else                                                                                                          \
+      hipLaunchKernelGGL((vcount_kernel<GG, CTT, TWV, ACCV, false>), dim3(grid), dim3(block), V.image_bytes, s,  \
+                         dV, static_cast<const CTT*>(codes), n, lvl_lo, lvl_hi, outN, outLv, err);               \
+  } while (0)
 #define HWC_V(GG)                                                                                                 \
   case GG:                                                                                                        \
     if (coeff_bytes == 1) {                                                                                       \
@@ -236,11 +256,14 @@ hipError_t launch_vcount(const VPlanDesc& V, const VPlanDesc* dV, int coeff_byte
 // the image starts at address 0).
 template <int G, typename CT, int TW, bool ACC>
 hipError_t prepare_one() {
-  const void* f = reinterpret_cast<const void*>(&vcount_kernel<G, CT, TW, ACC>);
-  hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsImageLimit);
-  hipFuncAttributes fa;
-  if (e == hipSuccess) e = hipFuncGetAttributes(&fa, f);
-  if (e == hipSuccess && fa.sharedSizeBytes != 0) e = hipErrorInvalidKernelFile;
+  hipError_t e = hipSuccess;
+  for (const void* f : {reinterpret_cast<const void*>(&vcount_kernel<G, CT, TW, ACC, false>),
+                        reinterpret_cast<const void*>(&vcount_kernel<G, CT, TW, ACC, true>)}) {
+    if (e == hipSuccess) e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsImageLimit);
+    hipFuncAttributes fa;
+    if (e == hipSuccess) e = hipFuncGetAttributes(&fa, f);
+    if (e == hipSuccess && fa.sharedSizeBytes != 0) e = hipErrorInvalidKernelFile;
+  }
   return e;
 }
 
@@ -265,10 +288,10 @@ hipError_t prepare_vcount() {
 
 hipError_t occupancy_vcount(uint32_t g, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
   switch (g) {
-    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<1, int8_t, 4, true>, block, lds_bytes);
-    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<2, int8_t, 4, true>, block, lds_bytes);
-    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<3, int8_t, 4, true>, block, lds_bytes);
-    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<4, int8_t, 4, true>, block, lds_bytes);
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<1, int8_t, 4, true, true>, block, lds_bytes);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<2, int8_t, 4, true, true>, block, lds_bytes);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<3, int8_t, 4, true, true>, block, lds_bytes);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, vcount_kernel<4, int8_t, 4, true, true>, block, lds_bytes);
     default: return hipErrorInvalidValue;
   }
 }
