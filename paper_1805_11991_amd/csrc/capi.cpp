@@ -1931,7 +1931,9 @@ int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_
     uint32_t vmax = 0;
     for (const auto& v : P->vpasses) vmax = std::max(vmax, v.desc.image_bytes);
     levels[j].lds_bytes = P->vpath ? vmax : P->desc.image_bytes;
-    levels[j].mfma = P->vpath ? (P->vpasses.back().desc.bal ? 2u : 1u) : 0u;
+    levels[j].mfma = 0;
+    for (const auto& v : P->vpasses)
+      if (P->vpath && v.lo <= j && j <= v.hi) levels[j].mfma = v.desc.bal ? 2u : 1u;
   }
   return HWC_OK;
 }
