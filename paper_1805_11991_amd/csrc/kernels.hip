@@ -1322,66 +1322,128 @@ __device__ __forceinline__ uint32_t fq_add(const uint16_t* __restrict__ ztab, ui
   return s >= M ? s - M : s;
 }
 
+// fq_add without branches (the table read always issues, at index 0 when an
+// operand is zero), so the reads of one quotient step go out together.
+__device__ __forceinline__ uint32_t fq_add_sel(const uint16_t* __restrict__ zl, uint32_t M, uint32_t a,
+                                               uint32_t b) {
+  const bool az = a == M, bz = b == M;
+  uint32_t d = b >= a ? b - a : b + M - a;
+  d = (az || bz) ? 0u : d;
+  const uint32_t v = zl[d];
+  uint32_t s = a + (v >> 1);
+  s = s >= M ? s - M : s;
+  s = v == 6 * M ? M : s;
+  return az ? b : (bz ? a : s);
+}
+
 // Parity of log disc(f) over F_q (1: disc is a nonsquare), f given by its
-// codes with deg f = NC-1 (top code nonzero); nsf is set when f and f' share
-// a factor (the remainder sequence hits zero before a constant).
+// codes (leading zero codes allowed); nsf is set when f and f' share a factor
+// (the remainder sequence hits zero before a constant). The Euclidean
+// remainder sequence of (f, f') runs as one quotient step, one leading-zero
+// strip or one swap per iteration on left-aligned coefficient arrays (entry 0
+// is the leading coefficient), so every array index is a compile-time
+// constant and the arrays stay in registers. The parity of Res(f, f') follows
+// Res(A, B) = (-1)^(deg A deg B) lc(B)^(deg A - deg R) Res(B, R), R = A mod B;
+// disc f = (-1)^(n(n-1)/2) Res(f, f') / lc(f).
 template <int NC>
-__device__ uint32_t disc_parity(const uint32_t (&code)[NC], const uint16_t* __restrict__ ztab,
+__device__ uint32_t disc_parity(const uint32_t (&code)[NC], const uint16_t* __restrict__ zl,
                                 const uint32_t* __restrict__ emb, uint32_t M, uint32_t p, uint32_t chim1,
                                 bool& nsf) {
   constexpr int D = NC - 1;
-  int top = D;
-  while (top > 0 && code[top] == 0) --top;                   // actual degree (2g+1 rows too)
-  uint32_t A[NC], B[NC];
+  constexpr int T = 3 * D;                                  // steps: <= deg f + deg f' + stages
+  uint32_t a[NC], b[NC];                                    // logs, M = the zero element
 #pragma unroll
-  for (int k = 0; k < NC; ++k) A[k] = emb[code[k]];
+  for (int k = 0; k < NC; ++k) a[D - k] = emb[code[k]];    // a[s]: coefficient of X^(D - s)
 #pragma unroll
-  for (int k = 0; k + 1 < NC; ++k) {                         // f' = sum (k+1) c_{k+1} X^k
-    const uint32_t li = emb[(uint32_t)(k + 1) % p];          // log of the integer k+1 in F_q
-    B[k] = (A[k + 1] == M || li == M) ? M : (A[k + 1] + li) % M;
+  for (int s = 0; s < D; ++s) {                             // f': (D - s) c_(D - s) X^(D - 1 - s)
+    const uint32_t li = emb[(uint32_t)(D - s) % p];         // log of the integer D - s in F_q
+    b[s] = (a[s] == M || li == M) ? M : addmod(a[s], li, M);
   }
-  B[NC - 1] = M;
-  int dA = top, dB = top - 1;
-  while (dB >= 0 && B[dB] == M) --dB;
+  b[D] = M;
+  int dA = D, dB = D - 1;
+#pragma unroll
+  for (int r = 0; r < D; ++r) {                             // strip leading zeros of f and f'
+    if (a[0] == M && dA > 0) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) a[s] = a[s + 1];
+      a[D] = M;
+      --dA;
+    }
+    if (b[0] == M && dB >= 0) {
+#pragma unroll
+      for (int s = 0; s < D; ++s) b[s] = b[s + 1];
+      b[D] = M;
+      --dB;
+    }
+  }
+  const int top = dA;
+  const uint32_t lcf = a[0];
   // f' shorter than deg f - 1 (p | deg f): Res with the formal degree
   // deg f - 1 carries lc(f)^(deg f - 1 - deg f') in front
-  uint32_t par = dB >= 0 ? (A[top] & (uint32_t)(top - 1 - dB) & 1u) : 0u;
-  bool bad = dB < 0;
-  while (!bad && dB > 0) {
-    for (int t = dA; t >= dB; --t) {                         // A <- A mod B
-      if (A[t] == M) continue;
-      const uint32_t fac = submod(A[t], B[dB], M);
-      for (int k = 0; k < dB; ++k) {
-        if (B[k] == M) continue;
-        const uint32_t neg = addmod(addmod(fac, B[k], M), M / 2, M);
-        A[t - dB + k] = fq_add(ztab, M, A[t - dB + k], neg);
-      }
-      A[t] = M;
-    }
-    int dR = dB - 1;
-    while (dR >= 0 && A[dR] == M) --dR;
-    if (dR < 0) { bad = true; break; }                       // common factor: not square-free
-    par ^= ((uint32_t)(dA * dB) & 1u) & chim1;
-    par ^= B[dB] & (uint32_t)(dA - dR) & 1u;
+  uint32_t par = dB >= 0 ? (lcf & (uint32_t)(top - 1 - dB) & 1u) : 0u;
+  bool bad = dB < 0 || lcf == M;
+  bool done = bad || dB == 0;
+  int dA0 = dA;                                             // deg A at the start of the stage
+#pragma unroll 1
+  for (int it = 0; it < T; ++it) {
+    if (done) break;
+    if (dA >= dB) {                                         // A -= (lc A / lc B) X^(dA - dB) B
+      const bool z = a[0] == M;                             // quotient digit 0: A unchanged
+      const uint32_t fac = addmod(submod(z ? 0u : a[0], b[0], M), M / 2, M);   // log of -(lc A / lc B)
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      const uint32_t t = A[k];
-      A[k] = B[k];
-      B[k] = t;
+      for (int s = 1; s < NC; ++s)
+        a[s] = fq_add_sel(zl, M, a[s], (z || b[s] == M) ? M : addmod(fac, b[s], M));
+#pragma unroll
+      for (int s = 0; s < D; ++s) a[s] = a[s + 1];
+      a[D] = M;
+      --dA;
+    } else if (dA >= 0 && a[0] == M) {                      // a leading zero of the remainder
+#pragma unroll
+      for (int s = 0; s < D; ++s) a[s] = a[s + 1];
+      a[D] = M;
+      --dA;
+    } else if (dA < 0) {                                    // zero remainder: common factor
+      bad = true;
+      done = true;
+    } else {                                                // (A, B) <- (B, A mod B)
+      par ^= ((uint32_t)(dA0 * dB) & 1u) & chim1;
+      par ^= b[0] & (uint32_t)(dA0 - dA) & 1u;
+#pragma unroll
+      for (int s = 0; s < NC; ++s) {
+        const uint32_t t = a[s];
+        a[s] = b[s];
+        b[s] = t;
+      }
+      const int t = dA;
+      dA = dB;
+      dB = t;
+      dA0 = dA;
+      done = dB == 0;
     }
-    dA = dB;
-    dB = dR;
   }
   nsf = bad;
-  if (!bad) par ^= B[0] & (uint32_t)dA & 1u;
-  return par ^ ((uint32_t)((top * (top - 1) / 2) & 1) & chim1) ^ (emb[code[top]] & 1u);
+  if (!bad) par ^= b[0] & (uint32_t)dA & 1u;                // Res(A, c) = c^deg A
+  return par ^ ((uint32_t)((top * (top - 1) / 2) & 1) & chim1) ^ (lcf & 1u);
 }
 
+// Rows per block pass of lambda_kernel (four per thread).
+constexpr uint32_t kLamTile = 1024;
+
+// The partition from the root counts r_j = #{x in F_(q^j) : f(x) = 0} (the
+// zeros in lv), one block pass per kLamTile rows: the rows whose partition the
+// counts leave open (deg f = 2g+2 with no factor of degree <= g: (2g+2) or
+// (g+1, g+1)), or every row when sqf asks for the square-free test, are listed
+// in LDS and then take the discriminant on full waves (Stickelberger: the two
+// shapes differ in the character of disc f).
 template <int G, typename CT>
 __global__ __launch_bounds__(256) void lambda_kernel(const PlanDesc* __restrict__ Pd, const CT* __restrict__ codes,
                                                      uint64_t n, const uint32_t* __restrict__ lv,
                                                      uint32_t* __restrict__ lam, uint32_t sqf) {
   constexpr int NC = 2 * G + 3, D2 = 2 * G + 2;
+  constexpr uint32_t kOpen = 1u << 30, kBad = 1u << 31;     // flags beside the partial code
+  extern __shared__ uint16_t zl[];                           // the Zech table of F_q
+  __shared__ uint32_t lrow[kLamTile], lpre[kLamTile];
+  __shared__ uint32_t lcnt;
   const PlanDesc& P = *Pd;
   const uint32_t q = P.q, p = P.p, M = P.lv[0].M;           // level 1 is F_q
   const uint8_t* img = reinterpret_cast<const uint8_t*>(P.image);
@@ -1389,65 +1451,101 @@ __global__ __launch_bounds__(256) void lambda_kernel(const PlanDesc* __restrict_
   const uint32_t* emb = reinterpret_cast<const uint32_t*>(img + P.lv[0].emb_off);
   const uint32_t chim1 = (M / 2) & 1u;                      // parity of log(-1)
   const bool orbit = P.orbit != 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const CT* row = codes + i * NC;
-    uint32_t code[NC];
+  for (uint32_t k = threadIdx.x; k < M; k += blockDim.x) zl[k] = ztab[k];
+  const uint32_t lane = threadIdx.x & 63u;
+  for (uint64_t base = blockIdx.x * (uint64_t)kLamTile; base < n; base += (uint64_t)gridDim.x * kLamTile) {
+    if (threadIdx.x == 0) lcnt = 0;
+    __syncthreads();
+    for (uint32_t off = 0; off < kLamTile; off += blockDim.x) {
+      const uint64_t i = base + off + threadIdx.x;
+      bool later = false;
+      uint32_t pre = 0;
+      if (i < n) {
+        const CT* row = codes + i * NC;
+        uint32_t code[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      int v = (int)row[k];
-      code[k] = (uint32_t)(v < 0 ? 0 : (v >= (int)q ? (int)q - 1 : v));
-    }
-    const uint32_t x0 = code[0] == 0 ? 1u : 0u;               // X divides f
-    const bool top = code[NC - 1] != 0;
-    uint32_t r[G + 1], nj[G + 1];
-#pragma unroll
-    for (int j = 1; j <= G; ++j) r[j] = (lv[i * G + j - 1] & 0xFFu) + (orbit ? 0u : x0);
-    bool ok = true;
-#pragma unroll
-    for (int j = 1; j <= G; ++j) {
-      if (orbit) {
-        nj[j] = r[j] + (j == 1 ? x0 : 0u);
-      } else {
-        // j n_j = sum_{d | j} mu(j / d) r_d
-        int s = 0;
-#pragma unroll
-        for (int d = 1; d <= j; ++d) {
-          if (j % d) continue;
-          const int m = j / d;
-          const int mu = m == 1 ? 1 : (m == 2 || m == 3) ? -1 : 0;   // j <= 4
-          s += mu * (int)r[d];
+        for (int k = 0; k < NC; ++k) {
+          int v = (int)row[k];
+          code[k] = (uint32_t)(v < 0 ? 0 : (v >= (int)q ? (int)q - 1 : v));
         }
-        ok &= s >= 0 && s % j == 0;
-        nj[j] = s >= 0 ? (uint32_t)(s / j) : 0u;
+        const uint32_t x0 = code[0] == 0 ? 1u : 0u;               // X divides f
+        const bool top = code[NC - 1] != 0;
+        uint32_t r[G + 1], nj[G + 1];
+#pragma unroll
+        for (int j = 1; j <= G; ++j) r[j] = (lv[i * G + j - 1] & 0xFFu) + (orbit ? 0u : x0);
+        bool ok = true;
+#pragma unroll
+        for (int j = 1; j <= G; ++j) {
+          if (orbit) {
+            nj[j] = r[j] + (j == 1 ? x0 : 0u);
+          } else {
+            // j n_j = sum_{d | j} mu(j / d) r_d
+            int s = 0;
+#pragma unroll
+            for (int d = 1; d <= j; ++d) {
+              if (j % d) continue;
+              const int m = j / d;
+              const int mu = m == 1 ? 1 : (m == 2 || m == 3) ? -1 : 0;   // j <= 4
+              s += mu * (int)r[d];
+            }
+            ok &= s >= 0 && s % j == 0;
+            nj[j] = s >= 0 ? (uint32_t)(s / j) : 0u;
+          }
+        }
+        uint32_t c = 0, deg = 0;
+        const uint32_t m1 = nj[1] + (top ? 0u : 1u);             // the part at infinity of odd degree
+        c |= m1;
+        deg += m1;
+#pragma unroll
+        for (int j = 2; j <= G; ++j) {
+          c |= nj[j] << lam_shift(j);
+          deg += (uint32_t)j * nj[j];
+        }
+        ok &= deg <= (uint32_t)D2;
+        const uint32_t R = ok ? (uint32_t)D2 - deg : 0u;
+        if (R > 0 && R < (uint32_t)D2) {
+          ok &= R > (uint32_t)G;
+          c |= 1u << lam_shift(R);
+        }
+        later = sqf || R == (uint32_t)D2;
+        pre = c | (R == (uint32_t)D2 ? kOpen : 0u) | (ok ? 0u : kBad);
+        if (!later) lam[i] = ok ? c : kLamInvalid;
+      }
+      const uint64_t mask = __ballot(later);                 // one LDS atomic per wave
+      if (mask) {
+        const uint32_t lead = (uint32_t)__builtin_ctzll(mask);
+        uint32_t slot = 0;
+        if (lane == lead) slot = atomicAdd(&lcnt, (uint32_t)__popcll(mask));
+        slot = (uint32_t)__shfl((int)slot, (int)lead) + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+        if (later) {
+          lrow[slot] = (uint32_t)(i - base);
+          lpre[slot] = pre;
+        }
       }
     }
-    uint32_t c = 0, deg = 0;
-    const uint32_t m1 = nj[1] + (top ? 0u : 1u);             // the part at infinity of odd degree
-    c |= m1;
-    deg += m1;
+    __syncthreads();
+    const uint32_t nl = lcnt;
+    for (uint32_t k = threadIdx.x; k < nl; k += blockDim.x) {
+      const uint64_t i = base + lrow[k];
+      const uint32_t pr = lpre[k];
+      const CT* row = codes + i * NC;
+      uint32_t code[NC];
 #pragma unroll
-    for (int j = 2; j <= G; ++j) {
-      c |= nj[j] << lam_shift(j);
-      deg += (uint32_t)j * nj[j];
+      for (int t = 0; t < NC; ++t) {
+        int v = (int)row[t];
+        code[t] = (uint32_t)(v < 0 ? 0 : (v >= (int)q ? (int)q - 1 : v));
+      }
+      bool nsf = false;                                      // common factor with f'
+      const uint32_t pd = disc_parity<NC>(code, zl, emb, M, p, chim1, nsf);
+      bool ok = !(pr & kBad);
+      uint32_t c = pr & ~(kOpen | kBad);
+      if (pr & kOpen) {
+        ok &= !nsf;
+        c |= pd ? (1u << lam_shift(D2)) : (2u << lam_shift(G + 1));
+      }
+      lam[i] = (sqf && nsf) ? 0u : (ok ? c : kLamInvalid);  // sqf: 0 marks a row with a square factor
     }
-    ok &= deg <= (uint32_t)D2;
-    const uint32_t R = ok ? (uint32_t)D2 - deg : 0u;
-    if (R > 0 && R < (uint32_t)D2) {
-      ok &= R > (uint32_t)G;
-      c |= 1u << lam_shift(R);
-    }
-    bool nsf = false;                                        // common factor with f'
-    uint32_t pd = 0;
-    if (R == (uint32_t)D2 || sqf) pd = disc_parity<NC>(code, ztab, emb, M, p, chim1, nsf);
-    if (R == (uint32_t)D2) {
-      ok &= !nsf;
-      c |= pd ? (1u << lam_shift(D2)) : (2u << lam_shift(G + 1));
-    }
-    if (sqf && nsf) {
-      lam[i] = 0;                                            // not square-free: no partition
-      continue;
-    }
-    lam[i] = ok ? c : kLamInvalid;
+    __syncthreads();
   }
 }
 
@@ -1739,14 +1837,15 @@ hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_
 hipError_t launch_lambda(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, uint64_t n,
                          const uint32_t* lv, uint32_t* lam, uint32_t sqf, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536);
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((n + kLamTile - 1) / kLamTile, 65536);
+  const size_t lds = ((size_t)P.lv[0].M * 2 + 3) & ~size_t(3);
 #define HWC_LAM(GG)                                                                                        \
   case GG:                                                                                                 \
     if (coeff_bytes == 1)                                                                                  \
-      hipLaunchKernelGGL((lambda_kernel<GG, int8_t>), dim3(grid), dim3(256), 0, s, dP,                      \
+      hipLaunchKernelGGL((lambda_kernel<GG, int8_t>), dim3(grid), dim3(256), lds, s, dP,                    \
                          static_cast<const int8_t*>(codes), n, lv, lam, sqf);                             \
     else                                                                                                   \
-      hipLaunchKernelGGL((lambda_kernel<GG, int16_t>), dim3(grid), dim3(256), 0, s, dP,                     \
+      hipLaunchKernelGGL((lambda_kernel<GG, int16_t>), dim3(grid), dim3(256), lds, s, dP,                   \
                          static_cast<const int16_t*>(codes), n, lv, lam, sqf);                            \
     break;
   switch (P.g) {
