@@ -891,8 +891,8 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   if ((rc = get_plan(c, q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u, &P))) return rc;
   if (lam && P->desc.lv[0].form != hwc::kFormA)
     return fail(c, HWC_ERR_FIELD_TOO_LARGE, "the factorization partition needs q <= 10923");
-  if (hk) {   // the histogram key (mixed radix 2q^k+3, plus the partition code) must fit 63 bits
-    double bits = lam ? hwc::kLamBits : 0.0, qk = 1;
+  if (hk) {   // the histogram key (mixed radix 2q^k+3, plus the partition's rank) must fit 63 bits
+    double bits = lam ? std::log2((double)hwc::lam_code_list(g, nullptr)) : 0.0, qk = 1;
     for (uint32_t k = 0; k < g; ++k) {
       qk *= q;
       bits += std::log2(2 * qk + 3);

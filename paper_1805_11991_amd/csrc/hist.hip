@@ -6,7 +6,9 @@
 //
 // Radix R_k = 2 q^k + 3 covers every possible N_k (at most two affine points
 // per x and two at infinity), so the key needs no Weil bound and stays valid
-// for any input row.
+// for any input row.  With the partition as last column, its digit is the
+// code's rank among the partition codes of 2g+2 (a few dozen values), so the
+// key keeps to 32 bits where the counts leave room.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -23,13 +25,18 @@ constexpr int kScanTile = 4096;
 struct KeyRadix {
   uint32_t g;          // columns taken from N
   uint32_t width;      // g, or g + 1 with the factorization code as last column
-  uint64_t radix[5];   // R_k, then 2^18 for the code
+  uint64_t radix[5];   // R_k, then the number of partition codes
+  uint32_t nlam;       // partition codes (ascending): the code's digit is its rank
+  uint32_t lam_codes[kLamCodesMax];
 };
 
 template <typename K>
 __global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N,
                                                         const uint32_t* __restrict__ lam, uint64_t n, KeyRadix kr,
                                                         K* __restrict__ keys, uint32_t* __restrict__ err) {
+  __shared__ uint32_t codes[kLamCodesMax];
+  for (uint32_t t = threadIdx.x; t < kr.nlam; t += blockDim.x) codes[t] = kr.lam_codes[t];
+  __syncthreads();
   uint32_t bad = 0;
   for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
     uint64_t key = 0;
@@ -39,9 +46,12 @@ __global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restric
       key = key * kr.radix[k] + (uint64_t)v;
     }
     if (lam) {
-      uint32_t v = lam[i];
-      if ((uint64_t)v >= kr.radix[kr.g]) { bad = 1; v = 0; }
-      key = key * kr.radix[kr.g] + v;
+      const uint32_t v = lam[i];
+      uint32_t lo = 0;                                 // first rank whose code is >= v
+      for (uint32_t step = 32; step; step >>= 1)
+        if (lo + step <= kr.nlam && codes[lo + step - 1] < v) lo += step;
+      if (lo >= kr.nlam || codes[lo] != v) { bad = 1; lo = 0; }
+      key = key * kr.radix[kr.g] + lo;
     }
     keys[i] = (K)key;
   }
@@ -278,7 +288,8 @@ __global__ __launch_bounds__(256) void runs_kernel(const K* __restrict__ keys, u
     if (j < cap) {
       uint64_t key = (uint64_t)keys[i];
       for (int k = (int)kr.width - 1; k >= 0; --k) {
-        out_keys[j * kr.width + k] = (int32_t)(key % kr.radix[k]);
+        const uint32_t d = (uint32_t)(key % kr.radix[k]);
+        out_keys[j * kr.width + k] = (int32_t)(k == (int)kr.g ? kr.lam_codes[d] : d);
         key /= kr.radix[k];
       }
     }
@@ -365,7 +376,7 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
 // lam[n] as a last column) into out_keys[cap][width] / out_counts[cap];
 // *out_len gets the number of distinct tuples (which may exceed cap: then only
 // the first cap are written).  scratch: hist_scratch_bytes(n) bytes.  err |= 4
-// when a value lies outside its radix.
+// when a value lies outside its radix (or a code is no partition of 2g+2).
 hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t g, uint32_t q, void* scratch,
                     int32_t* out_keys, uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err,
                     hipStream_t s) {
@@ -380,9 +391,10 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
     kr.radix[k] = (k < g) ? 2 * qk + 3 : 1;
     if (k < g) bits += __builtin_log2((double)kr.radix[k]);
   }
+  kr.nlam = lam ? lam_code_list(g, kr.lam_codes) : 0u;
   if (lam) {
-    kr.radix[g] = 1ull << kLamBits;
-    bits += kLamBits;
+    kr.radix[g] = kr.nlam;
+    bits += __builtin_log2((double)kr.nlam);
   }
   if (bits > 63.0) return hipErrorInvalidValue;
   const uint32_t nbits = (uint32_t)bits + 1;

@@ -72,6 +72,40 @@ __host__ __device__ constexpr uint32_t lam_shift(uint32_t j) {
   return j == 1 ? 0u : j == 2 ? 4u : j == 3 ? 7u : j == 4 ? 9u : j == 5 ? 11u : 7u + j;
 }
 
+// The partition codes a histogram column can hold for genus g: 0 (the mark of
+// a row with a square factor) and the code of every partition of 2g+2, in
+// ascending order, so a code's rank there is a dense digit (at most 43 values,
+// p(10) = 42) that sorts like the code. Writes them to out (room for
+// kLamCodesMax, or nullptr) and returns how many there are.
+constexpr uint32_t kLamCodesMax = 48;
+inline uint32_t lam_code_list(uint32_t g, uint32_t* out) {
+  uint32_t buf[kLamCodesMax];
+  uint32_t n = 0;
+  buf[n++] = 0;
+  // parts in non-increasing order: stack of (remaining degree, largest part, code)
+  struct Frame { uint32_t rem, maxp, code; };
+  Frame st[64];                          // pending siblings along one path: <= 10 + 9 + .. + 1
+  uint32_t top = 0;
+  st[top++] = {2 * g + 2, 2 * g + 2, 0};
+  while (top) {
+    const Frame f = st[--top];
+    if (f.rem == 0) {
+      if (n < kLamCodesMax) buf[n++] = f.code;
+      continue;
+    }
+    for (uint32_t j = 1; j <= f.maxp && j <= f.rem; ++j) st[top++] = {f.rem - j, j, f.code + (1u << lam_shift(j))};
+  }
+  for (uint32_t i = 1; i < n; ++i)   // insertion sort (n <= 43)
+    for (uint32_t k = i; k > 0 && buf[k - 1] > buf[k]; --k) {
+      const uint32_t t = buf[k];
+      buf[k] = buf[k - 1];
+      buf[k - 1] = t;
+    }
+  if (out)
+    for (uint32_t i = 0; i < n; ++i) out[i] = buf[i];
+  return n;
+}
+
 // One curve for the lane-per-x kernel: coefficient logs in F_{q^k} (M where
 // the coefficient is zero), degree d, M = q^k - 1.
 struct SingleDesc {
