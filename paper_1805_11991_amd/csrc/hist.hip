@@ -156,6 +156,27 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uin
 
 // ---- stable LSD radix sort of u32 or u64 keys (u32 when the key fits) ----
 
+// The tile of workgroup b among nb: workgroups go to the 8 XCDs in turn, so
+// this gives each XCD a contiguous range of tiles, and the [digit][tile]
+// entries that neighbouring tiles read and write share that XCD's L2 lines.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  const uint32_t x = b & 7u, per = nb >> 3, rem = nb & 7u;
+  return x * per + (x < rem ? x : rem) + (b >> 3);
+}
+
+// The valid lanes of the wave whose digit equals this lane's (one ballot per
+// digit bit).
+template <int RB>
+__device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t dig) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < RB; ++b) {
+    const uint64_t ones = __ballot(((dig >> b) & 1u) != 0);
+    peers &= ((dig >> b) & 1u) ? ones : ~ones;
+  }
+  return peers;
+}
+
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __restrict__ keys, uint64_t n,
                                                                   uint32_t shift, uint32_t nblocks,
@@ -164,21 +185,24 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __res
   __shared__ uint32_t cnt[kRadixBins];
   for (uint32_t i = threadIdx.x; i < kRadixBins; i += blockDim.x) cnt[i] = 0;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
+  const uint64_t base = (uint64_t)tile * kSortTile;
   for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile; j += blockDim.x) {
     const uint64_t i = base + j;
     if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
   }
   __syncthreads();
-  for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + blockIdx.x] = cnt[d];
+  for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + tile] = cnt[d];
 }
 
-// Keys of a block are ranked in 16 rounds of 256 (round-major = index order).
-// Within a round: lanes with equal digits are found by bit ballots, waves are
-// ordered through per-wave digit counts in LDS.  Each key first goes to its
-// place in the block's digit-sorted tile in LDS; the tile is then written out
-// in that order, so neighbouring threads store to neighbouring addresses of
-// one digit's run instead of scattering single keys.
+// Wave w of a block ranks the keys w*1024 .. w*1024+1023 of the block's tile
+// in 16 rounds of 64 (index order within the wave): lanes with equal digits
+// are found by bit ballots, and the wave keeps its own running count per digit
+// in LDS, so the rounds need no block barrier.  The waves' counts then give
+// each wave its start per digit, each key goes to its place in the block's
+// digit-sorted tile in LDS, and the tile is written out in that order, so
+// neighbouring threads store to neighbouring addresses of one digit's run
+// instead of scattering single keys.
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __restrict__ in, uint64_t n,
                                                                      uint32_t shift, uint32_t nblocks,
@@ -186,15 +210,17 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
                                                                      K* __restrict__ out) {
   constexpr int kWaves = kSortThreads / 64;
   constexpr uint32_t kRadixBins = 1u << RB;
+  constexpr uint32_t kNone = ~0u;
   __shared__ uint32_t gstart[kRadixBins];   // the block's first global position per digit
   __shared__ uint32_t lstart[kRadixBins];   // its first position per digit within the tile
-  __shared__ uint32_t running[kRadixBins];  // keys of the digit placed so far
-  __shared__ uint32_t wcnt[kWaves][kRadixBins];
+  __shared__ uint32_t wrun[kWaves][kRadixBins];   // a wave's count per digit, then its start
   __shared__ K tile[kSortTile];
   __shared__ uint32_t scan_sh[kSortThreads];
   const uint32_t t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * kSortTile;
+  const uint32_t tb = xcd_tile(blockIdx.x, nblocks);
+  const uint64_t base = (uint64_t)tb * kSortTile;
   const uint64_t nbh = (uint64_t)nblocks * kRadixBins;
+  for (uint32_t d = t; d < (uint32_t)(kWaves * kRadixBins); d += blockDim.x) (&wrun[0][0])[d] = 0;
   // digit counts of this block from the scanned histogram (differences of
   // consecutive entries of the [digit][block] order), then their prefix
   constexpr uint32_t kPer = kRadixBins / kSortThreads;
@@ -202,11 +228,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     const uint32_t d = t * kPer + k;
-    const uint64_t idx = (uint64_t)d * nblocks + blockIdx.x;
+    const uint64_t idx = (uint64_t)d * nblocks + tb;
     const uint32_t a = bh_scanned[idx];
     const uint32_t b = idx + 1 < nbh ? bh_scanned[idx + 1] : (uint32_t)n;
     gstart[d] = a;
-    running[d] = 0;
     cnt[k] = b - a;
     csum += cnt[k];
   }
@@ -227,36 +252,43 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
     }
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int r = 0; r < kSortItems; ++r) {
-    const uint64_t i = base + (uint64_t)r * kSortThreads + t;
-    const bool valid = i < n;
-    const K key = valid ? in[i] : (K)0;
-    const uint32_t dig = (uint32_t)((key >> shift) & (kRadixBins - 1));
-    for (uint32_t d = t; d < (uint32_t)(kWaves * kRadixBins); d += blockDim.x) (&wcnt[0][0])[d] = 0;
-    __syncthreads();
-    // peers: valid lanes of this wave with the same digit
-    uint64_t peers = __ballot(valid);
+  const uint64_t wfirst = base + (uint64_t)wave * (kSortTile / kWaves);
+  K key[kSortItems];
+  uint32_t rank[kSortItems];
 #pragma unroll
-    for (int b = 0; b < RB; ++b) {
-      const uint64_t ones = __ballot(((dig >> b) & 1u) != 0);
-      peers &= ((dig >> b) & 1u) ? ones : ~ones;
-    }
-    const uint32_t rank_w = (uint32_t)__popcll(peers & lt);
-    if (valid && rank_w == 0) wcnt[wave][dig] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = lstart[dig] + running[dig] + rank_w;
-      for (uint32_t w = 0; w < wave; ++w) pos += wcnt[w][dig];
-      tile[pos] = key;
-    }
-    __syncthreads();
-    for (uint32_t d = t; d < kRadixBins; d += blockDim.x) {
-      uint32_t s = 0;
-      for (int w = 0; w < kWaves; ++w) s += wcnt[w][d];
-      running[d] += s;
-    }
-    __syncthreads();
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = wfirst + (uint64_t)r * 64 + lane;
+    const bool valid = i < n;
+    key[r] = valid ? in[i] : (K)0;
+    const uint32_t dig = (uint32_t)((key[r] >> shift) & (kRadixBins - 1));
+    const uint64_t peers = digit_peers<RB>(valid, dig);
+    // every lane reads the wave's count before its leader adds the round's
+    // keys (one wave: LDS operations complete in issue order)
+    const uint32_t before = valid ? wrun[wave][dig] : 0u;
+    const uint32_t below = (uint32_t)__popcll(peers & lt);
+    __builtin_amdgcn_wave_barrier();
+    if (valid && below == 0) wrun[wave][dig] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+    rank[r] = valid ? before + below : kNone;
   }
+  __syncthreads();
+  for (uint32_t d = t; d < kRadixBins; d += blockDim.x) {   // wave starts per digit
+    uint32_t acc = lstart[d];
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const uint32_t c = wrun[w][d];
+      wrun[w][d] = acc;
+      acc += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (rank[r] == kNone) continue;
+    const uint32_t dig = (uint32_t)((key[r] >> shift) & (kRadixBins - 1));
+    tile[wrun[wave][dig] + rank[r]] = key[r];
+  }
+  __syncthreads();
   const uint32_t nin = (uint32_t)((n - base) < (uint64_t)kSortTile ? (n - base) : (uint64_t)kSortTile);
   for (uint32_t j = t; j < nin; j += blockDim.x) {
     const K key = tile[j];
