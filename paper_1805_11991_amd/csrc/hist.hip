@@ -30,34 +30,6 @@ struct KeyRadix {
   uint32_t lam_codes[kLamCodesMax];
 };
 
-template <typename K>
-__global__ __launch_bounds__(256) void make_keys_kernel(const int32_t* __restrict__ N,
-                                                        const uint32_t* __restrict__ lam, uint64_t n, KeyRadix kr,
-                                                        K* __restrict__ keys, uint32_t* __restrict__ err) {
-  __shared__ uint32_t codes[kLamCodesMax];
-  for (uint32_t t = threadIdx.x; t < kr.nlam; t += blockDim.x) codes[t] = kr.lam_codes[t];
-  __syncthreads();
-  uint32_t bad = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    uint64_t key = 0;
-    for (uint32_t k = 0; k < kr.g; ++k) {
-      int32_t v = N[i * kr.g + k];
-      if (v < 0 || (uint64_t)v >= kr.radix[k]) { bad = 1; v = 0; }
-      key = key * kr.radix[k] + (uint64_t)v;
-    }
-    if (lam) {
-      const uint32_t v = lam[i];
-      uint32_t lo = 0;                                 // first rank whose code is >= v
-      for (uint32_t step = 32; step; step >>= 1)
-        if (lo + step <= kr.nlam && codes[lo + step - 1] < v) lo += step;
-      if (lo >= kr.nlam || codes[lo] != v) { bad = 1; lo = 0; }
-      key = key * kr.radix[kr.g] + lo;
-    }
-    keys[i] = (K)key;
-  }
-  if (bad) atomicOr(err, 4u);
-}
-
 // ---- device-wide exclusive scan of u32 (chunks of kScanTile) ----
 
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
@@ -187,12 +159,72 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __res
   __syncthreads();
   const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
   const uint64_t base = (uint64_t)tile * kSortTile;
-  for (uint32_t j = threadIdx.x; j < (uint32_t)kSortTile; j += blockDim.x) {
-    const uint64_t i = base + j;
-    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (kRadixBins - 1)], 1u);
+  K v[kSortItems];                                   // all loads in flight before the adds
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    v[r] = i < n ? keys[i] : (K)0;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r)
+    if (base + (uint64_t)r * kSortThreads + threadIdx.x < n) atomicAdd(&cnt[(v[r] >> shift) & (kRadixBins - 1)], 1u);
+  __syncthreads();
+  for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + tile] = cnt[d];
+}
+
+// Keys of one sort tile (the tile of this workgroup, as in radix_hist_kernel),
+// with the tile's counts of the first digit (bits 0..RB-1) into bh, so the
+// first pass needs no histogram kernel.  K = u32 keys take u32 arithmetic
+// (every partial key is at most the final one).  G = kr.g.
+template <typename K, int RB, int G>
+__global__ __launch_bounds__(kSortThreads) void make_keys_kernel(const int32_t* __restrict__ N,
+                                                                 const uint32_t* __restrict__ lam, uint64_t n,
+                                                                 KeyRadix kr, K* __restrict__ keys,
+                                                                 uint32_t* __restrict__ err, uint32_t nblocks,
+                                                                 uint32_t* __restrict__ bh) {
+  constexpr uint32_t kRadixBins = 1u << RB;
+  __shared__ uint32_t codes[kLamCodesMax];
+  __shared__ uint32_t cnt[kRadixBins];
+  for (uint32_t t = threadIdx.x; t < kr.nlam; t += blockDim.x) codes[t] = kr.lam_codes[t];
+  for (uint32_t t = threadIdx.x; t < kRadixBins; t += blockDim.x) cnt[t] = 0;
+  __syncthreads();
+  const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
+  const uint64_t base = (uint64_t)tile * kSortTile;
+  uint32_t bad = 0;
+  K kv[kSortItems];                                  // every row's loads before the stores and adds
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    K key = 0;
+    if (i < n) {
+#pragma unroll
+      for (int k = 0; k < G; ++k) {
+        int32_t v = N[i * G + k];
+        if (v < 0 || (uint64_t)v >= kr.radix[k]) { bad = 1; v = 0; }
+        key = key * (K)kr.radix[k] + (K)v;
+      }
+      if (lam) {
+        const uint32_t v = lam[i];
+        uint32_t lo = 0;                             // first rank whose code is >= v
+        for (uint32_t step = 32; step; step >>= 1)
+          if (lo + step <= kr.nlam && codes[lo + step - 1] < v) lo += step;
+        if (lo >= kr.nlam || codes[lo] != v) { bad = 1; lo = 0; }
+        key = key * (K)kr.radix[kr.g] + (K)lo;
+      }
+    }
+    kv[r] = key;
+  }
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
+    if (i < n) {
+      keys[i] = kv[r];
+      atomicAdd(&cnt[(uint32_t)kv[r] & (kRadixBins - 1)], 1u);
+    }
   }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + tile] = cnt[d];
+  if (bad) atomicOr(err, 4u);
 }
 
 // Wave w of a block ranks the keys w*1024 .. w*1024+1023 of the block's tile
@@ -383,11 +415,21 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
                                  uint64_t* starts, uint32_t* bh, uint32_t* flags, uint32_t* pos, uint32_t* sums,
                                  uint32_t* totals, int32_t* out_keys, uint64_t* out_counts, uint64_t cap,
                                  uint64_t* out_len, uint32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(make_keys_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, N, lam, n, kr, keysA, err);
+  switch (kr.g) {
+#define HWC_KEYS(GG)                                                                                      \
+  case GG:                                                                                                \
+    hipLaunchKernelGGL((make_keys_kernel<K, RB, GG>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, N, lam, n, \
+                       kr, keysA, err, (uint32_t)nb_sort, bh);                                           \
+    break;
+    HWC_KEYS(1) HWC_KEYS(2) HWC_KEYS(3) HWC_KEYS(4)
+#undef HWC_KEYS
+    default: return hipErrorInvalidValue;
+  }
   for (uint32_t pass = 0; pass < npass; ++pass) {
     const uint32_t shift = pass * RB;
-    hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
-                       (uint32_t)nb_sort, bh);
+    if (pass > 0)   // the first digit's counts come from make_keys_kernel
+      hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n,
+                         shift, (uint32_t)nb_sort, bh);
     hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
