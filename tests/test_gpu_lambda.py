@@ -63,6 +63,21 @@ def test_lambda_matches_oracle(lctx, oracle_mod, curvegen_mod, q, g, n, flags):
     assert np.array_equal(hc, c.astype(np.uint64))
 
 
+@pytest.mark.parametrize("q,g,n", [(13, 3, 5000), (5, 4, 2600), (3, 2, 4097), (7, 1, 1025)])
+def test_lambda_several_tiles(lctx, oracle_mod, curvegen_mod, q, g, n):
+    # the partition kernel works in passes of 1024 rows per workgroup and the
+    # histogram in sort tiles of 4096 keys: several of each, ragged last ones
+    curves = curvegen_mod.sample(q, g, n, seed=900 + q + 10 * g)
+    N, lam, hk, hc = _run(lctx, q, g, curves)
+    assert np.array_equal(N, oracle_mod.count_curves(q, g, curves))
+    want = _codes_from_oracle(oracle_mod.factor_degrees(q, g, curves))
+    assert np.array_equal(lam, want)
+    rows = np.concatenate([N.astype(np.int64), lam.astype(np.int64)[:, None]], axis=1)
+    k, c = np.unique(rows, axis=0, return_counts=True)
+    assert np.array_equal(hk.astype(np.int64), k)
+    assert np.array_equal(hc, c.astype(np.uint64))
+
+
 def test_lambda_full_enumeration_g2_q5(lctx, oracle_mod, curvegen_mod):
     curves = curvegen_mod.enumerate_all(5, 2)
     N, lam, hk, hc = _run(lctx, 5, 2, curves)
