@@ -330,33 +330,83 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
 }
 
 // ---- run-length encoding of sorted keys ----
+// Tiles of kRunTile keys, kRunItems consecutive keys per thread; a key is a
+// run head when it is the first key or differs from its predecessor.
 
+constexpr int kRunItems = 16;
+constexpr int kRunTile = 256 * kRunItems;
+
+// The thread's keys first .. first + kRunItems - 1 (16-byte loads when all
+// are in range; first is a multiple of kRunItems, the buffer 256-aligned) and
+// the key before them (0 at the start: key 0 is a head by its index).
 template <typename K>
-__global__ __launch_bounds__(256) void head_flags_kernel(const K* __restrict__ keys, uint64_t n,
-                                                         uint32_t* __restrict__ flags) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1u : 0u;
+__device__ __forceinline__ K load_run(const K* __restrict__ keys, uint64_t first, uint64_t n, K (&v)[kRunItems]) {
+  if (first + kRunItems <= n) {
+    constexpr int kVec = kRunItems * (int)sizeof(K) / 16;
+    const uint4* p = reinterpret_cast<const uint4*>(keys + first);
+    uint4 w[kVec];
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) w[k] = p[k];
+    __builtin_memcpy(v, w, sizeof(v));
+  } else {
+#pragma unroll
+    for (int j = 0; j < kRunItems; ++j) v[j] = first + j < n ? keys[first + j] : (K)0;
+  }
+  return (first > 0 && first <= n) ? keys[first - 1] : (K)0;
 }
 
-// For each run head i (pos = its run index): decode key into the tuple and
-// store the run start; counts are finished by runs_count_kernel.
+template <typename K>
+__device__ __forceinline__ uint32_t run_heads(const K (&v)[kRunItems], K prev, uint64_t first, uint64_t n) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < kRunItems; ++j) {
+    const uint64_t i = first + j;
+    c += (i < n && (i == 0 || v[j] != (j ? v[j - 1] : prev))) ? 1u : 0u;
+  }
+  return c;
+}
+
+// Run heads per tile.
+template <typename K>
+__global__ __launch_bounds__(256) void run_heads_kernel(const K* __restrict__ keys, uint64_t n,
+                                                        uint32_t* __restrict__ tile_heads) {
+  __shared__ uint32_t sh[256];
+  const uint64_t first = (uint64_t)blockIdx.x * kRunTile + (uint64_t)threadIdx.x * kRunItems;
+  K v[kRunItems];
+  const K prev = load_run(keys, first, n, v);
+  uint32_t tot;
+  block_exclusive_scan(run_heads(v, prev, first, n), sh, &tot);
+  if (threadIdx.x == 0) tile_heads[blockIdx.x] = tot;
+}
+
+// Each run head i gets its run index j (the tile's offset plus the heads
+// before it in the tile): starts[j] = i, and the key decoded into the tuple
+// when j < cap; counts are finished by runs_count_kernel.
 template <typename K>
 __global__ __launch_bounds__(256) void runs_kernel(const K* __restrict__ keys, uint64_t n,
-                                                   const uint32_t* __restrict__ flags,
-                                                   const uint32_t* __restrict__ pos, KeyRadix kr, uint64_t cap,
+                                                   const uint32_t* __restrict__ tile_off, KeyRadix kr, uint64_t cap,
                                                    int32_t* __restrict__ out_keys, uint64_t* __restrict__ starts) {
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    if (!flags[i]) continue;
-    const uint64_t j = pos[i];
+  __shared__ uint32_t sh[256];
+  const uint64_t first = (uint64_t)blockIdx.x * kRunTile + (uint64_t)threadIdx.x * kRunItems;
+  K v[kRunItems];
+  const K prev = load_run(keys, first, n, v);
+  uint32_t tot;
+  uint64_t j = (uint64_t)tile_off[blockIdx.x] + block_exclusive_scan(run_heads(v, prev, first, n), sh, &tot);
+#pragma unroll
+  for (int t = 0; t < kRunItems; ++t) {
+    const uint64_t i = first + t;
+    if (i >= n || (i > 0 && v[t] == (t ? v[t - 1] : prev))) continue;
     starts[j] = i;
     if (j < cap) {
-      uint64_t key = (uint64_t)keys[i];
+      K key = v[t];                                  // u32 keys: 32-bit divisions (every radix fits)
       for (int k = (int)kr.width - 1; k >= 0; --k) {
-        const uint32_t d = (uint32_t)(key % kr.radix[k]);
+        const K r = (K)kr.radix[k];
+        const uint32_t d = (uint32_t)(key % r);
         out_keys[j * kr.width + k] = (int32_t)(k == (int)kr.g ? kr.lam_codes[d] : d);
-        key /= kr.radix[k];
+        key /= r;
       }
     }
+    ++j;
   }
 }
 
@@ -436,11 +486,11 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
                        (uint32_t)nb_sort, bh, keysB);
     K* tmp = keysA; keysA = keysB; keysB = tmp;
   }
-  hipLaunchKernelGGL(head_flags_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags);
-  hipError_t e = scan_exclusive(flags, n, pos, sums, totals, s);
+  const uint32_t nt = (uint32_t)((n + kRunTile - 1) / kRunTile);
+  hipLaunchKernelGGL(run_heads_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, flags);
+  hipError_t e = scan_exclusive(flags, nt, pos, sums, totals, s);   // tile offsets, total runs
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(runs_kernel<K>, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, keysA, n, flags, pos, kr, cap,
-                     out_keys, starts);
+  hipLaunchKernelGGL(runs_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, pos, kr, cap, out_keys, starts);
   hipLaunchKernelGGL(runs_count_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, starts, totals, n, cap,
                      out_counts, out_len);
   return hipGetLastError();
