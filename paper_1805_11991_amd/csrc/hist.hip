@@ -253,6 +253,15 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
   const uint64_t base = (uint64_t)tb * kSortTile;
   const uint64_t nbh = (uint64_t)nblocks * kRadixBins;
   for (uint32_t d = t; d < (uint32_t)(kWaves * kRadixBins); d += blockDim.x) (&wrun[0][0])[d] = 0;
+  // the wave's keys: loads issued first, so they overlap the offset reads and
+  // the scan below
+  const uint64_t wfirst = base + (uint64_t)wave * (kSortTile / kWaves);
+  K key[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint64_t i = wfirst + (uint64_t)r * 64 + lane;
+    key[r] = i < n ? in[i] : (K)0;
+  }
   // digit counts of this block from the scanned histogram (differences of
   // consecutive entries of the [digit][block] order), then their prefix
   constexpr uint32_t kPer = kRadixBins / kSortThreads;
@@ -284,14 +293,11 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
     }
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t wfirst = base + (uint64_t)wave * (kSortTile / kWaves);
-  K key[kSortItems];
   uint32_t rank[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
     const uint64_t i = wfirst + (uint64_t)r * 64 + lane;
     const bool valid = i < n;
-    key[r] = valid ? in[i] : (K)0;
     const uint32_t dig = (uint32_t)((key[r] >> shift) & (kRadixBins - 1));
     const uint64_t peers = digit_peers<RB>(valid, dig);
     // every lane reads the wave's count before its leader adds the round's
@@ -322,7 +328,10 @@ __global__ __launch_bounds__(kSortThreads) void radix_scatter_kernel(const K* __
   }
   __syncthreads();
   const uint32_t nin = (uint32_t)((n - base) < (uint64_t)kSortTile ? (n - base) : (uint64_t)kSortTile);
-  for (uint32_t j = t; j < nin; j += blockDim.x) {
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const uint32_t j = (uint32_t)r * kSortThreads + t;
+    if (j >= nin) break;
     const K key = tile[j];
     const uint32_t dig = (uint32_t)((key >> shift) & (kRadixBins - 1));
     out[gstart[dig] + (j - lstart[dig])] = key;
