@@ -449,9 +449,10 @@ uint64_t hist_scratch_bytes(uint64_t n) {
   const uint64_t nbh = nb_sort * 512;   // digits of up to 9 bits
   const uint64_t big = (n > nbh ? n : nbh);
   const uint64_t nsums = (big + kScanTile - 1) / kScanTile + 1;
+  const uint64_t nt = (n + kRunTile - 1) / kRunTile;
   return 2 * n * 8                 // keys ping-pong
          + nbh * 4                 // block histograms
-         + 2 * n * 4               // flags, pos
+         + 2 * nt * 4              // run heads and offsets per run-length tile
          + n * 8                   // run starts
          + nsums * 4 + 64          // scan block sums, totals
          + 8 * 256;                // every part starts 256-byte aligned
@@ -471,7 +472,7 @@ static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, 
 template <typename K, int RB>
 static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t n, const KeyRadix& kr,
                                  uint32_t npass, uint64_t nb_sort, uint64_t nbh, K* keysA, K* keysB,
-                                 uint64_t* starts, uint32_t* bh, uint32_t* flags, uint32_t* pos, uint32_t* sums,
+                                 uint64_t* starts, uint32_t* bh, uint32_t* tile_heads, uint32_t* tile_off, uint32_t* sums,
                                  uint32_t* totals, int32_t* out_keys, uint64_t* out_counts, uint64_t cap,
                                  uint64_t* out_len, uint32_t* err, hipStream_t s) {
   switch (kr.g) {
@@ -496,10 +497,10 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
     K* tmp = keysA; keysA = keysB; keysB = tmp;
   }
   const uint32_t nt = (uint32_t)((n + kRunTile - 1) / kRunTile);
-  hipLaunchKernelGGL(run_heads_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, flags);
-  hipError_t e = scan_exclusive(flags, nt, pos, sums, totals, s);   // tile offsets, total runs
+  hipLaunchKernelGGL(run_heads_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, tile_heads);
+  hipError_t e = scan_exclusive(tile_heads, nt, tile_off, sums, totals, s);   // tile offsets, total runs
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(runs_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, pos, kr, cap, out_keys, starts);
+  hipLaunchKernelGGL(runs_kernel<K>, dim3(nt), dim3(256), 0, s, keysA, n, tile_off, kr, cap, out_keys, starts);
   hipLaunchKernelGGL(runs_count_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, s, starts, totals, n, cap,
                      out_counts, out_len);
   return hipGetLastError();
@@ -549,8 +550,9 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
   uint64_t* keysB = reinterpret_cast<uint64_t*>(take(n * 8));
   uint64_t* starts = reinterpret_cast<uint64_t*>(take(n * 8));
   uint32_t* bh = reinterpret_cast<uint32_t*>(take(nbh * 4));
-  uint32_t* flags = reinterpret_cast<uint32_t*>(take(n * 4));
-  uint32_t* pos = reinterpret_cast<uint32_t*>(take(n * 4));
+  const uint64_t nt = (n + kRunTile - 1) / kRunTile;
+  uint32_t* tile_heads = reinterpret_cast<uint32_t*>(take(nt * 4));
+  uint32_t* tile_off = reinterpret_cast<uint32_t*>(take(nt * 4));
   uint32_t* sums = reinterpret_cast<uint32_t*>(take(nsums * 4));
   uint32_t* totals = reinterpret_cast<uint32_t*>(take(64));
   if (n == 0) {
@@ -560,7 +562,7 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
   uint32_t* keysA32 = reinterpret_cast<uint32_t*>(keysA);
   uint32_t* keysB32 = reinterpret_cast<uint32_t*>(keysB);
 #define HWC_SORT(KT, RBV, A, B)                                                                                \
-  return sort_and_count<KT, RBV>(N, lam, n, kr, npass, nb_sort, nbh, A, B, starts, bh, flags, pos, sums, totals, \
+  return sort_and_count<KT, RBV>(N, lam, n, kr, npass, nb_sort, nbh, A, B, starts, bh, tile_heads, tile_off, sums, totals, \
                                  out_keys, out_counts, cap, out_len, err, s)
   if (nbits <= 32) {
     if (rb == 9) HWC_SORT(uint32_t, 9, keysA32, keysB32);
