@@ -63,33 +63,23 @@ __global__ __launch_bounds__(256) void scan_reduce_kernel(const uint32_t* __rest
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-// exclusive scan of sums[0..nb) in place (one block, nb <= 1024*64); total to *total
-__global__ __launch_bounds__(1024) void scan_top_kernel(uint32_t* __restrict__ sums, uint32_t nb,
-                                                        uint32_t* __restrict__ total) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t per = (nb + blockDim.x - 1) / blockDim.x;
-  const uint32_t lo = threadIdx.x * per;
-  uint32_t s = 0;
-  for (uint32_t j = 0; j < per; ++j)
-    if (lo + j < nb) s += sums[lo + j];
-  uint32_t tot;
-  uint32_t off = block_exclusive_scan(s, sh, &tot);
-  for (uint32_t j = 0; j < per; ++j)
-    if (lo + j < nb) {
-      const uint32_t v = sums[lo + j];
-      sums[lo + j] = off;
-      off += v;
-    }
-  if (threadIdx.x == 0 && total) *total = tot;
-}
-
 // in and out may be the same array: each thread reads its own run before writing it
 // Each thread owns 16 consecutive values, moved as four 16-byte vectors when
 // the tile is whole (tiles start at multiples of 4096 values, so 16-byte aligned).
+// A tile's offset is the sum of the tile sums before it (sums: one per tile,
+// from scan_reduce_kernel; nullptr for a single tile); the last tile writes
+// the grand total to *total when given.
 __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uint64_t n,
-                                                         const uint32_t* __restrict__ offs, uint32_t* out) {
+                                                         const uint32_t* __restrict__ sums, uint32_t* out,
+                                                         uint32_t* __restrict__ total) {
   __shared__ uint32_t sh[256];
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  uint32_t before = 0;
+  if (sums) {
+    uint32_t p = 0;
+    for (uint32_t k = threadIdx.x; k < blockIdx.x; k += blockDim.x) p += sums[k];
+    block_exclusive_scan(p, sh, &before);
+  }
   constexpr uint32_t per = kScanTile / 256;
   const bool whole = base + kScanTile <= n;
   uint32_t v[per];
@@ -108,7 +98,8 @@ __global__ __launch_bounds__(256) void scan_apply_kernel(const uint32_t* in, uin
 #pragma unroll
   for (uint32_t j = 0; j < per; ++j) s += v[j];
   uint32_t tot;
-  uint32_t off = block_exclusive_scan(s, sh, &tot) + offs[blockIdx.x];
+  uint32_t off = block_exclusive_scan(s, sh, &tot) + before;
+  if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = before + tot;
 #pragma unroll
   for (uint32_t j = 0; j < per; ++j) {
     const uint32_t x = v[j];
@@ -462,9 +453,8 @@ static hipError_t scan_exclusive(const uint32_t* in, uint64_t n, uint32_t* out, 
                                  hipStream_t s) {
   const uint32_t nb = (uint32_t)((n + kScanTile - 1) / kScanTile);
   if (nb == 0) return hipSuccess;
-  hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, in, n, sums);
-  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, sums, nb, total);
-  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(256), 0, s, in, n, sums, out);
+  if (nb > 1) hipLaunchKernelGGL(scan_reduce_kernel, dim3(nb), dim3(256), 0, s, in, n, sums);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(nb), dim3(256), 0, s, in, n, nb > 1 ? sums : nullptr, out, total);
   return hipGetLastError();
 }
 
