@@ -28,6 +28,8 @@ struct KeyRadix {
   uint64_t radix[5];   // R_k, then the number of partition codes
   uint32_t nlam;       // partition codes (ascending): the code's digit is its rank
   uint32_t lam_codes[kLamCodesMax];
+  uint32_t lam_mul;    // slot (c * lam_mul) >> 24 is distinct for every code c
+  uint8_t lam_slot[256];   // rank + 1 of the code in that slot, 0 for none
 };
 
 // ---- device-wide exclusive scan of u32 (chunks of kScanTile) ----
@@ -175,8 +177,10 @@ __global__ __launch_bounds__(kSortThreads) void make_keys_kernel(const int32_t* 
                                                                  uint32_t* __restrict__ bh) {
   constexpr uint32_t kRadixBins = 1u << RB;
   __shared__ uint32_t codes[kLamCodesMax];
+  __shared__ uint8_t slots[256];
   __shared__ uint32_t cnt[kRadixBins];
   for (uint32_t t = threadIdx.x; t < kr.nlam; t += blockDim.x) codes[t] = kr.lam_codes[t];
+  for (uint32_t t = threadIdx.x; t < 256; t += blockDim.x) slots[t] = kr.lam_slot[t];
   for (uint32_t t = threadIdx.x; t < kRadixBins; t += blockDim.x) cnt[t] = 0;
   __syncthreads();
   const uint32_t tile = xcd_tile(blockIdx.x, nblocks);
@@ -196,11 +200,9 @@ __global__ __launch_bounds__(kSortThreads) void make_keys_kernel(const int32_t* 
       }
       if (lam) {
         const uint32_t v = lam[i];
-        uint32_t lo = 0;                             // first rank whose code is >= v
-        for (uint32_t step = 32; step; step >>= 1)
-          if (lo + step <= kr.nlam && codes[lo + step - 1] < v) lo += step;
-        if (lo >= kr.nlam || codes[lo] != v) { bad = 1; lo = 0; }
-        key = key * (K)kr.radix[kr.g] + (K)lo;
+        uint32_t rk = slots[(v * kr.lam_mul) >> 24];  // rank + 1 of the code in v's slot
+        if (rk == 0 || codes[rk - 1] != v) { bad = 1; rk = 1; }
+        key = key * (K)kr.radix[kr.g] + (K)(rk - 1);
       }
     }
     kv[r] = key;
@@ -516,6 +518,24 @@ hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t 
     if (k < g) bits += __builtin_log2((double)kr.radix[k]);
   }
   kr.nlam = lam ? lam_code_list(g, kr.lam_codes) : 0u;
+  kr.lam_mul = 0;
+  for (uint32_t t = 0; t < 256; ++t) kr.lam_slot[t] = 0;
+  if (lam) {   // an odd multiplier that puts the codes in distinct slots (the first one tried does for g <= 4)
+    for (uint32_t m = 0x9E3779B1u, tries = 0; kr.lam_mul == 0; m += 2) {
+      if (++tries > (1u << 16)) return hipErrorInvalidValue;
+      bool clash = false;
+      for (uint32_t t = 0; t < 256; ++t) kr.lam_slot[t] = 0;
+      for (uint32_t r = 0; r < kr.nlam && !clash; ++r) {
+        uint8_t& sl = kr.lam_slot[(kr.lam_codes[r] * m) >> 24];
+        clash = sl != 0;
+        sl = (uint8_t)(r + 1);
+      }
+      if (!clash) {
+        kr.lam_mul = m;
+        break;
+      }
+    }
+  }
   if (lam) {
     kr.radix[g] = kr.nlam;
     bits += __builtin_log2((double)kr.nlam);
