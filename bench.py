@@ -1,19 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the Hasse-Weil curve counter on one MI355X.
 
-One step = one pass of the whole path over one batch resident in HBM: curve
-bucketing by zero pattern, the count of N_1..N_g for every curve (Zech-table
-kernel, persistent and fused over all levels), and the sorted histogram of the
-tuples.  Workload of `value`: g = 3 over F_13, 2^24 seeded square-free curves
-(the set the metric is quoted on), Frobenius-orbit sweep, graph replay.
+One step = one pass of the whole path over one batch resident in HBM: the
+count of N_1..N_g for every curve and the sorted histogram of the tuples.
+The headline (`value`) is the paper's method: f evaluated at every swept x
+with Zech-logarithm arithmetic (Sec. 2.3, table (3.2)), g = 3 over F_13,
+2^24 seeded square-free curves, Frobenius-orbit sweep, persistent batched
+kernel replayed from a captured graph.
 
-Also measured in the same run: the plain form (one launch per level plus a
-separate assembly, no graph) on the same set, both forms with the full sweep,
-the g = 4 / F_13 set of 2^26 curves in both forms, a profiled loop that times
-the count kernel with HIP events on its launch stream (roofline), and the CPU
-oracle on a bounded sample (cpu_baseline).
+Also measured in the same run, each as its own object of the JSON line:
+  zech_path        the Zech path at g=3 and g=4 over F_13: batched and plain
+                   (one launch per level, no graph) with per-step spread,
+                   lookups/s against the LDS peak and the measured gather ceiling
+  matrix_core_path the opt-in int8 matrix-product formulation on the same sets
+                   (vector ALU and LDS-read fractions, unpadded pairs)
+  cfg2_batched     g = 2 over all 71 odd prime powers q < 300, 2^16 curves each,
+                   one multi-plan launch against per-q plain launches
+  cfg3_batched     g = 4 over q in {3, 5, 7, 9, 11, 13} (q = 3 fully enumerated,
+                   2^26 curves for the others) in one launch, and per q
+  serving          continuous batching of Poisson request streams of mixed (q, g)
+  cpu_baseline     the CPU oracle on a bounded sample, on the host's cores and on one
+plus the host-buffer entry point, the factorization partition, the map
+N_{3,13} by Algorithm 1 and Table 1's single curve.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--path zech|mfma]
 """
 from __future__ import annotations
 
@@ -33,10 +43,12 @@ LDS_PEAK_LOOKUPS = LDS_BANKS_PER_CU * NUM_CU * CLOCK_HZ
 # one wave64 vector ALU instruction per CU per clock (four SIMDs of 16 lanes)
 VALU_PEAK_OPS = 64 * NUM_CU * CLOCK_HZ
 MFMA_INT8_PEAK_OPS = 5.0e15   # dense int8 matrix-core peak
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "count_kernel_g3_q13_2p24_hbm_traffic.md")
-KERNEL_SOURCES = ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/vcount.hip",
-                  "paper_1805_11991_amd/csrc/plan.h",
-                  "paper_1805_11991_amd/autotune/gfx950.json")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_SUMMARY = {"zech": os.path.join(PROFILES, "count_kernel_g3_q13_2p24_hbm_traffic.md"),
+                   "mfma": os.path.join(PROFILES, "vcount_kernel_g3_q13_2p24_hbm_traffic.md")}
+KERNEL_SOURCES = {"zech": ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
+                           "paper_1805_11991_amd/autotune/gfx950.json"),
+                  "mfma": ("paper_1805_11991_amd/csrc/vcount.hip", "paper_1805_11991_amd/csrc/plan.h")}
 
 
 def log(msg: str):
@@ -44,8 +56,8 @@ def log(msg: str):
 
 
 def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
-    """Table reads the count kernel's algorithm needs for a batch, and the
-    plain-Horner count for reference.
+    """Table reads the Zech count kernel's algorithm needs for a batch, and
+    the plain-Horner count for reference.
 
     Plain Horner: one read per nonzero term below the leading one, for every
     swept x.  Split evaluation (levels with msplit = m): a tuple of m points
@@ -74,28 +86,26 @@ def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
 
 
 def mfma_work(n: int, levels: list[dict]) -> dict:
-    """Work of the matrix-core count kernel for n curves.  Every level j
-    (k = j coordinates) evaluates each curve at its swept points, padded to
-    blocks of 32: one int8 product of K = 16 per coordinate and point (the
-    matrix cores), and per (curve, point) pair 4k vector ALU operations: for
-    each coordinate its residue (multiply and shift for the quotient, then
-    multiply-adds into the table index; coordinate 0 arrives with the table
-    offset already added, one multiply-add fewer) and one add of the
-    character read.  In the balanced form (mfma = 2) the quotient of every
-    coordinate but the first is one multiply-high: 3k + 1 operations."""
-    tiles = (n + 31) // 32
-    pairs = valu = mfma = 0
+    """Work of the matrix-product count kernel for n curves.  Every level j
+    (j coordinates) evaluates each curve at its swept points: per (curve,
+    point) pair 3j + 1 vector ALU operations in the balanced form (mfma = 2:
+    a multiply-high and two multiply-adds per coordinate but the first, which
+    arrives with the table offset added; one add of the character read), 4j
+    otherwise, and one random 32-bit read of the character table from LDS.
+    Work is counted on the real points only; the kernel also sweeps the
+    padding of each level's last 32-point block (reported beside)."""
+    pairs = padded = valu = mfma = 0
     for j, L in enumerate(levels, start=1):
-        pts = (L["nx"] + 31) // 32 * 32
-        pr = tiles * 32 * pts
+        pr = n * L["nx"]
         pairs += pr
+        padded += n * ((L["nx"] + 31) // 32 * 32)
         valu += pr * ((3 * j + 1) if L["mfma"] == 2 else 4 * j)
-        mfma += pr * j * 16 * 2
-    return {"pairs": pairs, "valu_ops": valu, "mfma_ops": mfma}
+        mfma += ((n + 31) // 32 * 32) * ((L["nx"] + 31) // 32 * 32) * j * 16 * 2
+    return {"pairs": pairs, "pairs_padded": padded, "valu_ops": valu, "mfma_ops": mfma}
 
 
 def evaluated_rows(ctx, q: int, g: int, d_rows):
-    """The rows the count kernel evaluates for d_rows (rows with zero
+    """The rows the Zech count kernel evaluates for d_rows (rows with zero
     coefficients replaced by their dense translates), on the host."""
     import torch
     out = torch.empty_like(d_rows)
@@ -104,31 +114,31 @@ def evaluated_rows(ctx, q: int, g: int, d_rows):
     return out.cpu().numpy()
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(path: str) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        path = os.path.join(ROOT, rel)
-        if os.path.exists(path):
-            with open(path, "rb") as fh:
+    for rel in KERNEL_SOURCES[path]:
+        p = os.path.join(ROOT, rel)
+        if os.path.exists(p):
+            with open(p, "rb") as fh:
                 h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic() -> dict | None:
-    """HBM bytes per launch of the count kernel from the committed counter
-    summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same counter's
-    reading for a copy of known size); None when the kernel sources have
-    changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_SUMMARY):
+def measured_traffic(path: str) -> dict | None:
+    """HBM bytes per launch of the count kernel of `path` from the committed
+    counter summary; None when the kernel sources have changed since the
+    counters were taken (or there is no summary)."""
+    fn = TRAFFIC_SUMMARY[path]
+    if not os.path.exists(fn):
         return None
     vals = {}
-    with open(TRAFFIC_SUMMARY) as fh:
+    with open(fn) as fh:
         for line in fh:
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("source_sha256_16") != kernel_source_hash():
+    if vals.get("source_sha256_16") != kernel_source_hash(path):
         return None
     try:
         return {"fetch": int(vals["fetch_bytes_per_launch"]), "write": int(vals["write_bytes_per_launch"])}
@@ -138,7 +148,7 @@ def measured_traffic() -> dict | None:
 
 def calibration_copy(torch, dev, nbytes: int = 1 << 30, reps: int = 3):
     """A plain copy kernel of known size (nbytes read, nbytes written) whose
-    FETCH_SIZE / WRITE_SIZE readings scale the count kernel's."""
+    counter readings scale the count kernel's."""
     a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     for _ in range(reps):
@@ -147,30 +157,56 @@ def calibration_copy(torch, dev, nbytes: int = 1 << 30, reps: int = 3):
     log(f"calibration copy: {reps} x {nbytes} bytes read and written")
 
 
-def time_loop(fn, steps: int, warmup: int, sync) -> float:
+def timed_steps(torch, stream, fn, steps: int, warmup: int) -> dict:
+    """Mean step time over `steps` steps issued back to back (synchronized on
+    both sides), plus per-step times from events on the launch stream."""
     for _ in range(warmup):
         fn()
-    sync()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         fn()
-    sync()
-    return (time.perf_counter() - t0) / steps
+    torch.cuda.synchronize()
+    mean = (time.perf_counter() - t0) / steps * 1e3
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for i in range(steps):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    per.sort()
+    return {"ms_per_step": round(mean, 4), "min_ms": round(per[0], 4), "median_ms": round(per[len(per) // 2], 4),
+            "max_ms": round(per[-1], 4), "steps": steps}
+
+
+def ratio(plain: dict, batched: dict) -> dict:
+    """batched-vs-plain speedup from the means, and its range from the
+    per-step extremes (slowest batched against fastest plain and back)."""
+    return {"mean": round(plain["ms_per_step"] / batched["ms_per_step"], 4),
+            "min": round(plain["min_ms"] / batched["max_ms"], 4),
+            "max": round(plain["max_ms"] / batched["min_ms"], 4)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--quick", action="store_true", help="skip the secondary measurements")
+    ap.add_argument("--quick", action="store_true", help="the headline only (profiling runs)")
+    ap.add_argument("--path", choices=("zech", "mfma"), default="zech",
+                    help="with --quick: which counting path the headline runs")
+    ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB copy kernel (scale for the traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the counter has no multi-GPU path (asked for --gpus {args.gpus})",
               file=sys.stderr)
+        sys.exit(2)
+    if args.path != "zech" and not args.quick:
+        print("--path mfma is for --quick profiling runs; the full run measures both paths", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -181,134 +217,174 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    sync = torch.cuda.synchronize
-    ctx = hwcount.Context(device=0)
+    ctx = hwcount.Context(device=0)                 # Zech logarithms (the default)
+    mctx = hwcount.Context(device=0, mfma=True)     # the opt-in matrix-product path
+    head_ctx = mctx if args.path == "mfma" else ctx
 
-    def setup(q, g, n, seed):
+    def setup(q, g, n, seed, hist=True):
         t0 = time.perf_counter()
         curves = curvegen.sample(q, g, n, seed=seed)
         log(f"generated q={q} g={g} n={n} in {time.perf_counter() - t0:.1f}s")
         d = torch.from_numpy(curves).to(dev)
         N = torch.empty((n, g), dtype=torch.int32, device=dev)
+        if not hist:
+            return curves, d, N, None, None, None
         hk = torch.empty((n, g), dtype=torch.int32, device=dev)
         hc = torch.empty(n, dtype=torch.int64, device=dev)
         hl = torch.zeros(1, dtype=torch.int64, device=dev)
         return curves, d, N, hk, hc, hl
 
-    def runner(q, g, bufs, flags):
+    def runner(c, q, g, bufs, flags):
         _, d, N, hk, hc, hl = bufs
-        return lambda: ctx.count_curves_dev(q, g, d, N, hk, hc, hl, flags=flags, stream=stream)
+        return lambda: c.count_curves_dev(q, g, d, N, hk, hc, hl, flags=flags, stream=stream)
 
-    # ---------------- headline: g = 3, q = 13, 2^24 curves ----------------
-    q, g, n = 13, 3, 1 << 24
-    bufs = setup(q, g, n, curvegen.BASE_SEED + 1)
-    curves = bufs[0]
-    batched = runner(q, g, bufs, 0)
-    ms = time_loop(batched, args.steps, args.warmup, sync) * 1e3
-    ctx.status()
-    value = n / (ms * 1e-3)
-    log(f"g3 q13 batched orbit: {ms:.3f} ms/step, {value:.4g} curves/s")
-    Nref = bufs[2].cpu().numpy()
-    nhist = int(bufs[5].item())
+    def kernel_ms(c, fn, reps):
+        """Count-kernel time per call from the library's HIP events on the
+        launch stream (direct launches while profiling)."""
+        c.profile(True)
+        for _ in range(reps):
+            fn()
+        prof = c.profile_read()
+        c.profile(False)
+        c.status()
+        k = max(prof["calls"], 1)
+        return {"count_ms": prof["count_ms"] / k, "prep_ms": prof["prep_ms"] / k, "hist_ms": prof["hist_ms"] / k}
 
-    # roofline: the count kernel timed with HIP events on its launch stream
-    ctx.profile(True)
-    for _ in range(args.steps):
-        batched()
-    prof = ctx.profile_read()
-    ctx.profile(False)
-    ctx.status()
-    assert np.array_equal(bufs[2].cpu().numpy(), Nref), "profiled run differs from the graph run"
-    count_ms = prof["count_ms"] / prof["calls"]
-    levels = ctx.plan_info(q, g)
-    nx = [L["nx"] for L in levels]
-    traffic = measured_traffic()
-    common = {
-        "traffic": None if traffic is None else traffic["fetch"] + traffic["write"],
-        "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-        "traffic_detail": traffic,
-        "kernel_ms": round(count_ms, 4),
-        "prep_ms": round(prof["prep_ms"] / prof["calls"], 4),
-        "hist_ms": round(prof["hist_ms"] / prof["calls"], 4),
-    }
-    if levels[0]["mfma"]:
-        # matrix-core path: bound by the vector ALU work on the products
-        work = mfma_work(n, levels)
-        achieved = work["valu_ops"] / (count_ms * 1e-3)
-        mfma_rate = work["mfma_ops"] / (count_ms * 1e-3)
-        roofline = {
-            "bound": "alu",
-            "achieved": round(achieved / 1e9, 1),
-            "peak": round(VALU_PEAK_OPS / 1e9, 1),
-            "unit": "G int32 lane-ops/s",
-            "frac": round(achieved / VALU_PEAK_OPS, 4),
-            **common,
-            "kernel": "vcount_kernel<3,int8>",
-            "pairs_per_launch": work["pairs"],
-            "valu_ops_per_launch": work["valu_ops"],
-            "mfma_int8_ops_per_launch": work["mfma_ops"],
-            "mfma_int8_tops": round(mfma_rate / 1e12, 2),
-            "mfma_frac": round(mfma_rate / MFMA_INT8_PEAK_OPS, 4),
-            "levels": [{"M": L["M"], "nx": L["nx"], "pts_padded": (L["nx"] + 31) // 32 * 32} for L in levels],
-        }
-        log(f"roofline: count kernel {count_ms:.3f} ms, {work['pairs'] / (count_ms * 1e-3) / 1e9:.0f} G "
-            f"(curve, point) pairs/s, {achieved / 1e12:.2f} T lane-ops/s ({achieved / VALU_PEAK_OPS:.3f} of "
-            f"the vector ALU peak), int8 MFMA {mfma_rate / 1e12:.1f} TOPS ({mfma_rate / MFMA_INT8_PEAK_OPS:.4f})")
-    else:
-        # the rows the kernel evaluates: zero-coefficient rows become dense translates
-        lookups, plain_lookups = lookups_per_batch(evaluated_rows(ctx, q, g, bufs[1]), levels)
-        achieved = lookups / (count_ms * 1e-3)
-        roofline = {
+    def zech_roofline(c, q, g, bufs, kms, ceiling=None):
+        levels = c.plan_info(q, g)
+        lookups, plain_lookups = lookups_per_batch(evaluated_rows(c, q, g, bufs[1]), levels)
+        achieved = lookups / (kms * 1e-3)
+        if ceiling is None:
+            # the practical ceiling of that bound on this device: a kernel doing
+            # nothing but dependent random reads of a table the size of the top level's
+            ceiling = c.lds_gather_rate(min(2 * (q ** g - 1), 80000), chains=4)
+        return {
             "bound": "lds",
             "achieved": round(achieved / 1e9, 2),
             "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
             "unit": "Glookup/s",
             "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
-            **common,
-            "kernel": "count_kernel<3,int8>",
+            "gather_ceiling": round(ceiling / 1e9, 2),
+            "frac_of_gather_ceiling": round(achieved / ceiling, 4),
+            "kernel_ms": round(kms, 4),
             "lookups_per_launch": lookups,
+            "lookups_per_curve": round(lookups / len(bufs[0]), 1),
             "plain_horner_lookups": plain_lookups,
             "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit", "nt", "ns")} for L in levels],
         }
-        # the practical ceiling of that bound on this device: a kernel doing
-        # nothing but dependent random reads of a table the size of the top level's
-        ceiling = ctx.lds_gather_rate(2 * (q ** g - 1), chains=4)
-        roofline["gather_ceiling"] = round(ceiling / 1e9, 2)
-        roofline["frac_of_gather_ceiling"] = round(achieved / ceiling, 4)
-        log(f"roofline: count kernel {count_ms:.3f} ms, {achieved / 1e9:.1f} Glookup/s "
-            f"({achieved / LDS_PEAK_LOOKUPS:.3f} of LDS peak, {achieved / ceiling:.3f} of the "
-            f"measured gather ceiling {ceiling / 1e9:.0f} Glookup/s)")
+
+    def mfma_roofline(c, q, g, n, kms, ceiling):
+        levels = c.plan_info(q, g)
+        w = mfma_work(n, levels)
+        s = kms * 1e-3
+        return {
+            "bound": "alu",
+            "achieved": round(w["valu_ops"] / s / 1e9, 1),
+            "peak": round(VALU_PEAK_OPS / 1e9, 1),
+            "unit": "G int32 lane-ops/s",
+            "frac": round(w["valu_ops"] / s / VALU_PEAK_OPS, 4),
+            "kernel_ms": round(kms, 4),
+            "pairs_per_launch": w["pairs"],
+            "pairs_per_s": round(w["pairs"] / s, 1),
+            "pairs_padded_per_launch": w["pairs_padded"],
+            "valu_ops_per_launch": w["valu_ops"],
+            "lds_table_reads_per_s": round(w["pairs_padded"] / s, 1),
+            "lds_read_frac": round(w["pairs_padded"] / s / LDS_PEAK_LOOKUPS, 4),
+            "lds_read_frac_of_gather_ceiling": round(w["pairs_padded"] / s / ceiling, 4),
+            "mfma_int8_tops": round(w["mfma_ops"] / s / 1e12, 2),
+            "mfma_frac": round(w["mfma_ops"] / s / MFMA_INT8_PEAK_OPS, 4),
+            "levels": [{"M": L["M"], "nx": L["nx"], "balanced": L["mfma"] == 2} for L in levels],
+        }
+
+    # ---------------- headline: g = 3, q = 13, 2^24 curves, Zech path ----------------
+    q, g, n = 13, 3, 1 << 24
+    bufs = setup(q, g, n, curvegen.BASE_SEED + 1)
+    curves = bufs[0]
+    batched = runner(head_ctx, q, g, bufs, 0)
+    for _ in range(args.warmup):
+        batched()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / args.steps * 1e3
+    head_ctx.status()
+    value = n / (ms * 1e-3)
+    log(f"g3 q13 batched orbit ({args.path}): {ms:.3f} ms/step, {value:.4g} curves/s")
+    Nref = bufs[2].cpu().numpy()
+    nhist = int(bufs[5].item())
+
+    km = kernel_ms(head_ctx, batched, args.steps)
+    assert np.array_equal(bufs[2].cpu().numpy(), Nref), "profiled run differs from the graph run"
+    ceiling3 = ctx.lds_gather_rate(2 * (q ** g - 1), chains=4)
+    if args.path == "zech":
+        roofline = zech_roofline(ctx, q, g, bufs, km["count_ms"], ceiling3)
+        roofline["kernel"] = "count_kernel<3,int8>"
+    else:
+        roofline = mfma_roofline(mctx, q, g, n, km["count_ms"], ceiling3)
+        roofline["kernel"] = "vcount_kernel<3,int8>"
+    traffic = measured_traffic(args.path)
+    roofline["traffic"] = None if traffic is None else traffic["fetch"] + traffic["write"]
+    roofline["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
+    roofline["traffic_detail"] = traffic
+    roofline["prep_ms"] = round(km["prep_ms"], 4)
+    roofline["hist_ms"] = round(km["hist_ms"], 4)
+    log(f"roofline: {roofline['kernel']} {km['count_ms']:.3f} ms, {roofline['achieved']} {roofline['unit']} "
+        f"({roofline['frac']} of peak)")
 
     extra = {}
     if not args.quick:
-        for name, flags in (("plain_orbit", hwcount.HWC_PLAIN), ("batched_full", hwcount.HWC_FULL_SWEEP),
+        zp = {}
+        # the Zech path, g = 3: batched (graph) against plain (launch per level)
+        head = timed_steps(torch, stream, batched, args.steps, 1)
+        plain = timed_steps(torch, stream, runner(ctx, q, g, bufs, hwcount.HWC_PLAIN), args.steps, 1)
+        ctx.status()
+        assert np.array_equal(bufs[2].cpu().numpy(), Nref), "plain form differs from batched"
+        assert int(bufs[5].item()) == nhist
+        zp["g3_q13"] = {"curves": n, "batched": head, "plain": plain, "batched_vs_plain": ratio(plain, head),
+                        "curves_per_s": round(n / (head["ms_per_step"] * 1e-3), 1),
+                        "roofline": {k: v for k, v in roofline.items() if not k.startswith("traffic")}}
+        log(f"zech g3: batched {head['ms_per_step']} ms, plain {plain['ms_per_step']} ms")
+        for name, flags in (("batched_full", hwcount.HWC_FULL_SWEEP),
                             ("plain_full", hwcount.HWC_PLAIN | hwcount.HWC_FULL_SWEEP)):
-            fn = runner(q, g, bufs, flags)
-            m = time_loop(fn, max(1, min(args.steps, 3)), 1, sync) * 1e3
+            t = timed_steps(torch, stream, runner(ctx, q, g, bufs, flags), 3, 1)
             ctx.status()
             assert np.array_equal(bufs[2].cpu().numpy(), Nref), f"{name} differs from batched"
-            assert int(bufs[5].item()) == nhist
-            extra[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n / (m * 1e-3), 1)}
-            log(f"g3 q13 {name}: {m:.3f} ms/step")
-        extra["batched_vs_plain"] = round(extra["plain_orbit"]["ms_per_step"] / ms, 3)
+            zp["g3_q13"][name] = t
+
+        # the matrix-product path on the same set
+        mp = {}
+        mb = timed_steps(torch, stream, runner(mctx, q, g, bufs, 0), args.steps, 2)
+        mpl = timed_steps(torch, stream, runner(mctx, q, g, bufs, hwcount.HWC_PLAIN), args.steps, 1)
+        mctx.status()
+        assert np.array_equal(bufs[2].cpu().numpy(), Nref), "matrix-product path differs from the Zech path"
+        assert int(bufs[5].item()) == nhist
+        mk = kernel_ms(mctx, runner(mctx, q, g, bufs, 0), args.steps)
+        mroof = mfma_roofline(mctx, q, g, n, mk["count_ms"], ceiling3)
+        mtraffic = measured_traffic("mfma")
+        mroof["traffic"] = None if mtraffic is None else mtraffic["fetch"] + mtraffic["write"]
+        mroof["kernel"] = "vcount_kernel<3,int8>"
+        mp["g3_q13"] = {"curves": n, "batched": mb, "plain": mpl, "batched_vs_plain": ratio(mpl, mb),
+                        "curves_per_s": round(n / (mb["ms_per_step"] * 1e-3), 1), "roofline": mroof,
+                        "vs_zech_path": round(head["ms_per_step"] / mb["ms_per_step"], 3)}
+        log(f"mfma g3: batched {mb['ms_per_step']} ms, plain {mpl['ms_per_step']} ms, kernel "
+            f"{mk['count_ms']:.3f} ms ({mroof['frac']} of VALU peak)")
+
         # counts plus the factorization partition lambda and the (N, lambda)
-        # histogram (the full map of eq. 1.2)
+        # histogram (the full map of eq. 1.2), Zech path
         lam = torch.empty(n, dtype=torch.int32, device=dev)
         hk1 = torch.empty((n, g + 1), dtype=torch.int32, device=dev)
         _, d, N, _, hc, hl = bufs
-
-        def with_lambda():
-            ctx.count_lambda_dev(q, g, d, N, lam, hk1, hc, hl, stream=stream)
-        ml = time_loop(with_lambda, max(1, min(args.steps, 3)), 1, sync) * 1e3
+        wl = timed_steps(torch, stream, lambda: ctx.count_lambda_dev(q, g, d, N, lam, hk1, hc, hl, stream=stream),
+                         3, 1)
         ctx.status()
         assert np.array_equal(N.cpu().numpy(), Nref), "lambda mode changed N"
-        extra["with_lambda"] = {"ms_per_step": round(ml, 3), "curves_per_s": round(n / (ml * 1e-3), 1),
+        extra["with_lambda"] = {**wl, "curves_per_s": round(n / (wl["ms_per_step"] * 1e-3), 1),
                                 "histogram_distinct": int(hl.item())}
-        log(f"g3 q13 with lambda: {ml:.3f} ms/step ({int(hl.item())} distinct (N, lambda))")
         del lam, hk1
         # host buffers through the synchronous entry point: PCIe copies of the
         # codes, N and the histogram included (never the headline value)
-        Nh = None
         curves16 = curves.astype(np.int16)          # the host entry point takes int16 codes
         t0 = time.perf_counter()
         for _ in range(2):
@@ -317,53 +393,108 @@ def main():
         assert np.array_equal(Nh, Nref), "host-buffer path differs"
         extra["host_buffers"] = {"ms_per_step": round(mh, 3), "curves_per_s": round(n / (mh * 1e-3), 1)}
         log(f"g3 q13 host buffers (PCIe included): {mh:.3f} ms/step")
-        del bufs
+        del bufs, curves16
         torch.cuda.empty_cache()
+
         # ---------------- g = 4, q = 13, 2^26 curves ----------------
         n4 = 1 << 26
         bufs4 = setup(13, 4, n4, curvegen.BASE_SEED + 3)
-        g4 = {}
-        steps4 = max(1, min(args.steps, 3))
-        for name, flags in (("batched_orbit", 0), ("plain_orbit", hwcount.HWC_PLAIN)):
-            fn = runner(13, 4, bufs4, flags)
-            m = time_loop(fn, steps4, 1, sync) * 1e3
-            ctx.status()
-            g4[name] = {"ms_per_step": round(m, 3), "curves_per_s": round(n4 / (m * 1e-3), 1)}
-            log(f"g4 q13 {name}: {m:.3f} ms/step")
-        g4["batched_vs_plain"] = round(g4["plain_orbit"]["ms_per_step"] / g4["batched_orbit"]["ms_per_step"], 3)
-        ctx.profile(True)
-        runner(13, 4, bufs4, 0)()
-        p4 = ctx.profile_read()
-        ctx.profile(False)
-        lv4 = ctx.plan_info(13, 4)
-        g4["count_kernel_ms"] = round(p4["count_ms"], 3)
-        if lv4[0]["mfma"]:
-            w4 = mfma_work(n4, lv4)
-            g4["path"] = "matrix cores (top level over several passes)"
-            g4["valu_ops_per_s"] = round(w4["valu_ops"] / (p4["count_ms"] * 1e-3), 1)
-            g4["valu_frac"] = round(w4["valu_ops"] / (p4["count_ms"] * 1e-3) / VALU_PEAK_OPS, 4)
-        else:
-            lk4, _ = lookups_per_batch(evaluated_rows(ctx, 13, 4, bufs4[1]), lv4)
-            g4["path"] = "Zech logarithms"
-            g4["glookup_per_s"] = round(lk4 / (p4["count_ms"] * 1e-3) / 1e9, 2)
-            g4["lds_frac"] = round(lk4 / (p4["count_ms"] * 1e-3) / LDS_PEAK_LOOKUPS, 4)
-        g4["curves"] = n4
-        extra["g4_q13"] = g4
-        del bufs4
+        steps4 = max(5, min(args.steps, 5))
+        zb = timed_steps(torch, stream, runner(ctx, 13, 4, bufs4, 0), steps4, 1)
+        zpl = timed_steps(torch, stream, runner(ctx, 13, 4, bufs4, hwcount.HWC_PLAIN), steps4, 1)
+        ctx.status()
+        N4 = bufs4[2].cpu().numpy()
+        k4 = kernel_ms(ctx, runner(ctx, 13, 4, bufs4, 0), 2)
+        ceiling4 = ctx.lds_gather_rate(2 * (13 ** 4 - 1), chains=4)
+        zr4 = zech_roofline(ctx, 13, 4, bufs4, k4["count_ms"], ceiling4)
+        zr4["kernel"] = "count_kernel<4,int8>"
+        zp["g4_q13"] = {"curves": n4, "batched": zb, "plain": zpl, "batched_vs_plain": ratio(zpl, zb),
+                        "curves_per_s": round(n4 / (zb["ms_per_step"] * 1e-3), 1), "roofline": zr4}
+        log(f"zech g4: batched {zb['ms_per_step']} ms, plain {zpl['ms_per_step']} ms, "
+            f"{zr4['achieved']} Glookup/s")
+        mb4 = timed_steps(torch, stream, runner(mctx, 13, 4, bufs4, 0), steps4, 1)
+        mpl4 = timed_steps(torch, stream, runner(mctx, 13, 4, bufs4, hwcount.HWC_PLAIN), steps4, 1)
+        mctx.status()
+        assert np.array_equal(bufs4[2].cpu().numpy(), N4), "g=4: matrix-product path differs from the Zech path"
+        mk4 = kernel_ms(mctx, runner(mctx, 13, 4, bufs4, 0), 2)
+        mr4 = mfma_roofline(mctx, 13, 4, n4, mk4["count_ms"], ceiling4)
+        mr4["kernel"] = "vcount_kernel<4,int8> (level 4 over several passes)"
+        mp["g4_q13"] = {"curves": n4, "batched": mb4, "plain": mpl4, "batched_vs_plain": ratio(mpl4, mb4),
+                        "curves_per_s": round(n4 / (mb4["ms_per_step"] * 1e-3), 1), "roofline": mr4,
+                        "vs_zech_path": round(zb["ms_per_step"] / mb4["ms_per_step"], 3)}
+        log(f"mfma g4: batched {mb4['ms_per_step']} ms, plain {mpl4['ms_per_step']} ms")
+        extra["zech_path"] = zp
+        extra["matrix_core_path"] = mp
+        del bufs4, N4
         torch.cuda.empty_cache()
 
-    if not args.quick:
+        # ---------------- batched sets over many fields ----------------
+        def multi(c, specs, steps, label):
+            """One multi-plan launch over every job against one plain launch
+            sequence per job; N equal between the two."""
+            jobs = []
+            for qq, gg, cc in specs:
+                m = len(cc)
+                jobs.append(dict(q=qq, g=gg, d_coeffs=torch.from_numpy(cc).to(dev),
+                                 d_out_N=torch.empty((m, gg), dtype=torch.int32, device=dev),
+                                 d_hist_keys=torch.empty((max(m, 1), gg), dtype=torch.int32, device=dev),
+                                 d_hist_counts=torch.empty(max(m, 1), dtype=torch.int64, device=dev),
+                                 d_hist_len=torch.zeros(1, dtype=torch.int64, device=dev)))
+            total = sum(len(cc) for _, _, cc in specs)
+            tb = timed_steps(torch, stream, lambda: c.count_batch(jobs, stream=stream), steps, 1)
+            c.status()
+            Nb = [j["d_out_N"].cpu().numpy() for j in jobs]
+
+            def plain_all():
+                for j in jobs:
+                    c.count_curves_dev(j["q"], j["g"], j["d_coeffs"], j["d_out_N"], j["d_hist_keys"],
+                                       j["d_hist_counts"], j["d_hist_len"], flags=hwcount.HWC_PLAIN, stream=stream)
+            tp = timed_steps(torch, stream, plain_all, steps, 1)
+            c.status()
+            for j, nb in zip(jobs, Nb):
+                assert np.array_equal(j["d_out_N"].cpu().numpy(), nb), f"{label}: plain differs for q={j['q']}"
+            per_q = []
+            for j in jobs:      # each field alone: batched form and plain form
+                one = timed_steps(torch, stream, lambda j=j: c.count_batch([j], stream=stream), 2, 1)
+                onep = timed_steps(torch, stream, lambda j=j: c.count_batch([j], flags=hwcount.HWC_PLAIN,
+                                                                              stream=stream), 2, 1)
+                m = int(j["d_coeffs"].shape[0])
+                per_q.append({"q": j["q"], "g": j["g"], "curves": m, "batched_ms": one["ms_per_step"],
+                              "plain_ms": onep["ms_per_step"],
+                              "curves_per_s": round(m / (one["ms_per_step"] * 1e-3), 1),
+                              "batched_vs_plain": round(onep["ms_per_step"] / one["ms_per_step"], 3)})
+            c.status()
+            del jobs
+            torch.cuda.empty_cache()
+            return {"jobs": len(specs), "curves": total, "batched": tb, "plain": tp,
+                    "batched_vs_plain": ratio(tp, tb), "curves_per_s": round(total / (tb["ms_per_step"] * 1e-3), 1),
+                    "plain_curves_per_s": round(total / (tp["ms_per_step"] * 1e-3), 1), "per_q_alone": per_q}
+
+        from paper_1805_11991_amd.serving import odd_prime_power
+        qs2 = [x for x in range(3, 300) if odd_prime_power(x)]
+        specs2 = [(x, 2, curvegen.sample(x, 2, 1 << 16, seed=curvegen.BASE_SEED + 2 + x)) for x in qs2]
+        extra["cfg2_batched"] = multi(ctx, specs2, 5, "cfg2")
+        log(f"cfg2 (71 fields, g=2): batched {extra['cfg2_batched']['batched']['ms_per_step']} ms, plain "
+            f"{extra['cfg2_batched']['plain']['ms_per_step']} ms")
+        del specs2
+        specs3 = [(3, 4, curvegen.enumerate_all(3, 4))]
+        for x in (5, 7, 9, 11, 13):
+            specs3.append((x, 4, curvegen.sample(x, 4, 1 << 26, seed=curvegen.BASE_SEED + 3 + x)))
+        extra["cfg3_batched"] = multi(ctx, specs3, 3, "cfg3")
+        log(f"cfg3 (g=4, q<=13): batched {extra['cfg3_batched']['batched']['ms_per_step']} ms, plain "
+            f"{extra['cfg3_batched']['plain']['ms_per_step']} ms")
+        del specs3
+
         # the whole map N_{3,13} of eq. (1.2) by Algorithm 1 (reduced representatives)
         t0 = time.perf_counter()
-        mk, mc, mreps = ctx.count_map(13, 3)
+        mk_, mc_, mreps = ctx.count_map(13, 3)
         mt = time.perf_counter() - t0
         total = 12 * (13 ** 8 - 13 ** 7) + 12 * (13 ** 7 - 13 ** 6)
-        assert int(mc.sum()) == total
+        assert int(mc_.sum()) == total
         extra["map_g3_q13"] = {"seconds": round(mt, 3), "representatives": mreps, "curves_covered": total,
-                               "entries": int(len(mk)), "curves_covered_per_s": round(total / mt, 1)}
-        log(f"map N_(3,13): {mt:.3f} s, {mreps} representatives for {total} curves, {len(mk)} entries")
+                               "entries": int(len(mk_)), "curves_covered_per_s": round(total / mt, 1)}
+        log(f"map N_(3,13): {mt:.3f} s, {mreps} representatives for {total} curves, {len(mk_)} entries")
 
-    if not args.quick:
         # Table 1 (Sec. 4): one curve over F_{p^2}, lane per x; the paper's K80
         # evaluation times are printed beside for context only
         k80_eval_ms = {101: 0.36, 211: 1.47, 307: 3.11, 401: 0.95, 503: 1.25, 1009: 2.93, 1511: 394.0,
@@ -371,7 +502,7 @@ def main():
         curve = [17, 12, 16, 11, 10, 13, 12]
         rows = []
         for p, k80 in k80_eval_ms.items():
-            row = np.array([c % p for c in curve], dtype=np.int16)
+            row = np.array([cc % p for cc in curve], dtype=np.int16)
             t0 = time.perf_counter()
             Nf, tf = ctx.count_single(p, 2, row, 2, flags=hwcount.HWC_FULL_SWEEP)   # builds the tables
             first = (time.perf_counter() - t0) * 1e3
@@ -379,11 +510,17 @@ def main():
             No, to = ctx.count_single(p, 2, row, 2)
             assert Nf.tolist() == No.tolist()
             rows.append({"p": p, "N1": int(Nf[0]), "N2": int(Nf[1]), "first_call_ms": round(first, 2),
+                         "tables_ms": round(tf["tables_ms"], 3),
                          "kernel_ms_full_sweep": round(tf["kernel_ms"], 4),
                          "kernel_ms_orbit_sweep": round(to["kernel_ms"], 4), "paper_k80_eval_ms": k80})
-            log(f"table 1 p={p}: N2={int(Nf[1])} kernels {tf['kernel_ms']:.3f} ms full, "
-                f"{to['kernel_ms']:.3f} ms orbits (first call {first:.0f} ms with tables)")
         extra["table1_single_curve"] = rows
+        log("table 1 curves done")
+
+        if not args.no_serving:
+            from paper_1805_11991_amd import serving
+            sctx = hwcount.Context(device=0, hbm_budget_bytes=256 << 20)
+            extra["serving"] = serving.serve_bench(sctx, log=log)
+            sctx.close()
 
     if args.calib_copy:
         calibration_copy(torch, dev)
@@ -391,15 +528,30 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        threads = min(os.cpu_count() or 1, 16)
+        host_cores = os.cpu_count() or 1
+        try:
+            usable = len(os.sched_getaffinity(0))
+        except AttributeError:
+            usable = host_cores
+        # the box allots 16 CPUs to a one-GPU job, whatever the host has
+        threads = max(1, min(usable, 16))
         sample = 1 << 18
         t0 = time.perf_counter()
         ref = oracle.count_curves(q, g, curves[:sample], threads=threads)
         dt = time.perf_counter() - t0
         assert np.array_equal(ref, Nref[:sample]), "oracle disagrees with the GPU on the CPU sample"
+        one = 1 << 14
+        t0 = time.perf_counter()
+        ref1 = oracle.count_curves(q, g, curves[:one], threads=1)
+        dt1 = time.perf_counter() - t0
+        assert np.array_equal(ref1, Nref[:one])
         cpu = {"value": round(sample / dt, 1), "unit": "curves/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {sample} curves of the g=3 q=13 set, all k=1..3 ({dt:.1f} s)"}
-        log(f"cpu oracle: {sample / dt:.1f} curves/s on {threads} threads")
+               "sample": f"first {sample} curves of the g=3 q=13 set, all k=1..3 ({dt:.1f} s on {threads} threads)",
+               "threads": threads, "host_cores": host_cores, "usable_cores": usable,
+               "one_core_curves_per_s": round(one / dt1, 1),
+               "one_core_sample": f"first {one} curves of the same set ({dt1:.1f} s)"}
+        log(f"cpu oracle: {sample / dt:.1f} curves/s on {threads} threads ({host_cores} host cores, "
+            f"{usable} usable); {one / dt1:.1f} curves/s on one")
 
     out = {
         "metric": "curves/s (all k) at g=3 q=13 and g=4 q=13; batched vs plain, bit-exact",
@@ -412,16 +564,20 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "int32",
+        "dtype": ("u16 Zech-log table lookups, int32 counts (exact integer)" if args.path == "zech"
+                  else "int8 MFMA operands, int32 accumulate (exact integer)"),
         "data": "synthetic: seeded uniform square-free curves (SplitMix64/Lemire rejection), no dataset",
-        "config": {"workload": "g3_q13_2^24_curves_batched_orbit_sweep", "q": q, "g": g, "curves": n,
-                   "levels_nx": nx, "histogram_distinct": nhist},
+        "config": {"workload": f"g3_q13_2^24_curves_batched_orbit_sweep_{args.path}", "q": q, "g": g, "curves": n,
+                   "path": "Zech logarithms" if args.path == "zech" else "int8 matrix products",
+                   "histogram_distinct": nhist},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
     ctx.close()
+    mctx.close()
+
 
 
 if __name__ == "__main__":

@@ -268,10 +268,23 @@ typedef struct {
 } hwc_level_desc;
 int hwc_plan_info(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags, hwc_level_desc* levels);
 
-/* Cache statistics: fields built, plans resident, device bytes of tables,
- * hits and misses of the table cache.  Any pointer may be NULL. */
+/* Table-cache statistics: plans resident, device bytes of their tables, hits
+ * and misses of the cache, plans evicted (least recently used first) to stay
+ * within the HBM budget, and bytes released but not yet freed (memory that
+ * work still in flight may read; it is freed once that work is complete and
+ * counts against the budget until then).  Any pointer may be NULL. */
 int hwc_ctx_stats(const hwc_ctx* ctx, uint64_t* plans_resident, uint64_t* table_bytes, uint64_t* cache_hits,
-                  uint64_t* cache_misses);
+                  uint64_t* cache_misses, uint64_t* evictions, uint64_t* pending_free_bytes);
+
+/* Preallocates the scratch of the calls enqueued on `stream` (NULL = the
+ * context's stream) for requests and batches of up to max_curves rows in
+ * total over at most max_jobs jobs (any g, int8 or int16 codes), so that
+ * such calls never grow a buffer while earlier work is in flight -- a
+ * serving loop calls it once per stream before it starts.  Calls on
+ * different streams use different scratch (up to four streams; more share),
+ * so their kernels overlap on the device.  Synchronous; HWC_ERR_ARG for
+ * max_curves >= 2^31 or max_jobs outside 1..65535. */
+int hwc_ctx_reserve(hwc_ctx* ctx, uint64_t max_curves, uint32_t max_jobs, void* stream);
 
 #ifdef __cplusplus
 }

@@ -10,7 +10,9 @@ the database's entries as per-plan options when it is created.
     python -m paper_1805_11991_amd.autotune --qg 13,3 --qg 13,4 [--n 1048576] [--out path]
 
 Search space (library options, see include/hwcount.h):
-  mfma            int8 matrix-product counting (prime q <= 31, image in LDS) or Zech logarithms
+  mfma            only with --with-mfma: the opt-in int8 matrix-product counting (prime
+                  q <= 31, image in LDS) against Zech logarithms; without it the
+                  database keeps the Zech-logarithm path and sets no mfma option
   split           split evaluation over m-th roots of unity on LDS levels (on/off)
   split_min_m     smallest level (nonzero elements) that is split
   block           threads per workgroup of the count kernel (256, 512, 1024)
@@ -32,12 +34,17 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DB_DIR = os.path.join(HERE, "autotune")
 
 SPACE = {
-    "mfma": [1, 0],
     "split": [1, 0],
     "split_min_m": [64, 2048],
     "block": [256, 512, 1024],
     "waves_per_simd": [1, 6],
     "device_tables": ["none", "top"],
+}
+
+
+SMALL_SPACE = {
+    "split": [1, 0],
+    "block": [256, 512, 1024],
 }
 
 
@@ -106,7 +113,8 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
         cand = dict(zip(names, values))
         if cand.get("split") == 0 and cand.get("split_min_m", 0) != space.get("split_min_m", [0])[0]:
             continue                      # the threshold means nothing without the split
-        if cand.get("mfma") == 1 and any(cand[k] != space[k][0] for k in cand if k not in ("mfma", "block")):
+        if cand.get("mfma") == 1 and any(cand[k] != space[k][0] for k in cand
+                                         if k in space and k not in ("mfma", "block")):
             continue                      # only the block size applies to the matrix-core kernel
         try:
             for k, v in cand.items():
@@ -146,6 +154,9 @@ def main(argv=None):
     ap.add_argument("--full-sweep", action="store_true")
     ap.add_argument("--out", default=None)
     ap.add_argument("--arch", default="gfx950")
+    ap.add_argument("--with-mfma", action="store_true", help="also try the matrix-product path")
+    ap.add_argument("--small", action="store_true",
+                    help="reduced space (split, block) for the many small plans of the batched sets")
     args = ap.parse_args(argv)
     sys.path.insert(0, os.path.dirname(HERE))
     from . import hwcount as hw
@@ -160,7 +171,10 @@ def main(argv=None):
         q, g = (int(v) for v in qg.split(","))
         t0 = time.time()
         print(f"tuning q={q} g={g} on {args.n} curves", flush=True)
-        res = tune(ctx, q, g, n=args.n, flags=flags)
+        space = dict(SMALL_SPACE if args.small else SPACE)
+        if args.with_mfma:
+            space = {"mfma": [1, 0], **space}
+        res = tune(ctx, q, g, n=args.n, flags=flags, space=space)
         print(f"best {res['options']}: {res['count_ms']} ms ({time.time() - t0:.0f} s)", flush=True)
         db[db_key(q, g, flags)] = res
     os.makedirs(os.path.dirname(out), exist_ok=True)

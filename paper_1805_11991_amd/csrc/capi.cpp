@@ -84,7 +84,7 @@ struct Tuning {
   bool split = true;            // split evaluation over mu_m cosets on form A levels
   uint32_t split_min_m = 64;    // ... of at least this many nonzero elements
   bool shift = true;            // count rows with zero coefficients as dense translates f(x + t)
-  bool mfma = true;             // prime q <= 31: count by int8 matrix products where the image fits LDS
+  bool mfma = false;            // prime q <= 31: count by int8 matrix products where the image fits LDS (opt-in)
   uint32_t block = 0;           // threads per workgroup, 0: automatic
   uint32_t wg_per_cu = 0;       // cap on workgroups per CU, 0: occupancy limit
   uint32_t wpe = 0;             // minimum waves per SIMD of the kernel build, 0: none
@@ -139,10 +139,13 @@ struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   void* jobs = nullptr;   // job descriptors owned by a multi-plan graph
+  int set = 0;            // scratch set whose buffers the graph uses
+  std::vector<const DevPlan*> plans;   // plans whose tables it reads
 };
 
 struct JobSlot {          // job descriptors of a direct multi-plan launch
-  void* p = nullptr;
+  void* p = nullptr;      // device copy
+  void* h = nullptr;      // pinned host staging, copied asynchronously
   size_t bytes = 0;
   hipEvent_t done = nullptr;
   bool used = false;
@@ -150,6 +153,22 @@ struct JobSlot {          // job descriptors of a direct multi-plan launch
 
 constexpr uint32_t kSmallStride = 4 * 2048 + 16;   // per-job bucketing words (u32)
 constexpr int kJobSlots = 4;
+
+// Scratch of the work enqueued on one stream.  Calls on different streams
+// use different sets, so their kernels can overlap on the device; calls that
+// share a set are ordered by its event (a stream waits for the set's previous
+// work when that work went to another stream), so every set's work forms one
+// chain and its event, once complete, means all of it is.
+struct ScratchSet {
+  Buf pid, small, tiles, perm, lv, hist, tcodes;                     // one request
+  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords, btcodes;   // multi-plan launches
+  JobSlot slots[kJobSlots];
+  int next_slot = 0;
+  hipStream_t last = nullptr;
+  hipEvent_t ev = nullptr;
+  bool ev_valid = false;
+};
+constexpr int kSets = 4;           // sets for streams
 
 }  // namespace
 
@@ -167,19 +186,20 @@ struct hwc_ctx {
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, std::unique_ptr<DevPlan>> plans;
   uint64_t table_bytes = 0, hits = 0, misses = 0, tick = 0, evictions = 0;
   int cus = 0;
-  // scratch
-  Buf pid, small, tiles, perm, lv, N, hist, codes, hout, tcodes;
+  // scratch of the synchronous host-buffer, map, single-curve and diagnostic calls
+  Buf N, codes, hout;
   Buf mcodes, mN, mlam, mhk, mhc, mcj;   // map of eq. (1.2): one chunk of representatives
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, SingleTabs> single;   // one-curve tables
   uint32_t* d_err = nullptr;
   std::list<GraphEntry> graphs;
-  // multi-plan scratch
-  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords, btcodes;
-  JobSlot slots[kJobSlots];
-  int next_slot = 0;
-  // every call's work is ordered after the previous call's, whatever the stream
-  hipEvent_t order_ev = nullptr;
-  bool order_valid = false;
+  // scratch of the asynchronous calls, one set per stream (round robin past kSets)
+  ScratchSet sets[kSets];
+  std::vector<std::pair<hipStream_t, int>> set_of;
+  int next_set = 0;
+  // device memory released while work may still read it: freed once every
+  // set's work is complete (hipFree would otherwise wait for the whole device)
+  std::vector<void*> grave;
+  uint64_t grave_bytes = 0;
   // profiling: events around the phases of each direct (non-graph) call
   bool profile = false;
   Tuning defaults;
@@ -201,39 +221,117 @@ int fail(hwc_ctx* c, int code, const std::string& msg) {
     if (_e != hipSuccess) return fail((ctx), HWC_ERR_DEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
   } while (0)
 
-void destroy_graph(GraphEntry& g) {
+// Device memory that queued work may still read is not freed at once: it is
+// kept until every set's work is complete (reap), so releasing it never
+// waits for the device in the middle of a stream.
+void defer_free(hwc_ctx* c, void* p, uint64_t bytes) {
+  if (!p) return;
+  c->grave.push_back(p);
+  c->grave_bytes += bytes;
+}
+
+// Frees the deferred memory once no set has work in flight (wait: wait for
+// that work first).  Returns false when something was still running.
+bool reap(hwc_ctx* c, bool wait) {
+  if (c->grave.empty()) return true;
+  for (auto& st : c->sets) {
+    if (!st.ev_valid) continue;
+    if (wait) {
+      if (hipEventSynchronize(st.ev) != hipSuccess) return false;
+    } else if (hipEventQuery(st.ev) != hipSuccess) {
+      return false;
+    }
+  }
+  for (void* p : c->grave) (void)hipFree(p);
+  c->grave.clear();
+  c->grave_bytes = 0;
+  return true;
+}
+
+void wait_set(hwc_ctx* c, int set) {
+  ScratchSet& st = c->sets[set];
+  if (st.ev_valid) (void)hipEventSynchronize(st.ev);
+}
+
+void destroy_graph(hwc_ctx* c, GraphEntry& g) {
+  wait_set(c, g.set);   // a replay may still run
   if (g.exec) (void)hipGraphExecDestroy(g.exec);
   if (g.graph) (void)hipGraphDestroy(g.graph);
-  if (g.jobs) (void)hipFree(g.jobs);
+  defer_free(c, g.jobs, 0);
   g.exec = nullptr;
   g.graph = nullptr;
   g.jobs = nullptr;
 }
 
-void drop_graphs(hwc_ctx* c) {
-  if (!c->graphs.empty()) (void)hipDeviceSynchronize();
-  for (auto& g : c->graphs) destroy_graph(g);
-  c->graphs.clear();
-}
-
-// order this call's work on s after everything the context enqueued before
-int order_begin(hwc_ctx* c, hipStream_t s) {
-  if (c->order_valid) HIPX(c, hipStreamWaitEvent(s, c->order_ev, 0));
-  return HWC_OK;
-}
-int order_end(hwc_ctx* c, hipStream_t s) {
-  HIPX(c, hipEventRecord(c->order_ev, s));
-  c->order_valid = true;
-  return HWC_OK;
-}
-
-int ensure(hwc_ctx* c, Buf& b, size_t bytes) {
-  if (b.bytes >= bytes && b.p) return HWC_OK;
-  drop_graphs(c);  // captured graphs may hold the old pointer
-  if (b.p) {
-    HIPX(c, hipDeviceSynchronize());  // queued work may still use the old buffer
-    HIPX(c, hipFree(b.p));
+// drop the graphs that use scratch set `set` (-1: every graph)
+void drop_graphs(hwc_ctx* c, int set = -1) {
+  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+    if (set < 0 || it->set == set) {
+      destroy_graph(c, *it);
+      it = c->graphs.erase(it);
+    } else {
+      ++it;
+    }
   }
+}
+
+// drop the graphs that read the tables of plan P
+void drop_graphs_of_plan(hwc_ctx* c, const DevPlan* P) {
+  for (auto it = c->graphs.begin(); it != c->graphs.end();) {
+    if (std::find(it->plans.begin(), it->plans.end(), P) != it->plans.end()) {
+      destroy_graph(c, *it);
+      it = c->graphs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
+// The scratch set of stream s: its own while there are free sets, then
+// shared round robin.
+int set_for(hwc_ctx* c, hipStream_t s) {
+  for (const auto& kv : c->set_of)
+    if (kv.first == s) return kv.second;
+  const int k = c->next_set % kSets;
+  c->next_set++;
+  c->set_of.emplace_back(s, k);
+  return k;
+}
+
+// order this call's work on s after the previous work of its set
+int order_begin(hwc_ctx* c, int set, hipStream_t s) {
+  ScratchSet& st = c->sets[set];
+  if (st.ev_valid && st.last != s) HIPX(c, hipStreamWaitEvent(s, st.ev, 0));
+  return HWC_OK;
+}
+int order_end(hwc_ctx* c, int set, hipStream_t s) {
+  ScratchSet& st = c->sets[set];
+  HIPX(c, hipEventRecord(st.ev, s));
+  st.last = s;
+  st.ev_valid = true;
+  return HWC_OK;
+}
+
+// grow a scratch buffer of set `set` (never shrinks)
+int ensure(hwc_ctx* c, int set, Buf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return HWC_OK;
+  if (b.p) {
+    drop_graphs(c, set);   // captured graphs may hold the old pointer
+    defer_free(c, b.p, b.bytes);
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+  size_t want = std::max<size_t>(bytes, 256);
+  want = (want + 4095) & ~size_t(4095);
+  HIPX(c, hipMalloc(&b.p, want));
+  b.bytes = want;
+  return HWC_OK;
+}
+
+// buffers of the synchronous calls (their work is complete when they return)
+int ensure_sync(hwc_ctx* c, Buf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return HWC_OK;
+  if (b.p) HIPX(c, hipFree(b.p));
   b.p = nullptr;
   b.bytes = 0;
   size_t want = std::max<size_t>(bytes, 256);
@@ -257,23 +355,22 @@ std::shared_ptr<FieldEntry> get_field(hwc_ctx* c, uint32_t p, uint32_t e, uint32
   return fe;
 }
 
-void free_plan(DevPlan* P) {
-  if (P->d_image) (void)hipFree(P->d_image);
-  if (P->d_desc) (void)hipFree(P->d_desc);
-  for (auto* r : P->d_reps)
-    if (r) (void)hipFree(r);
-  for (auto* t : P->d_gtab)
-    if (t) (void)hipFree(t);
-  for (auto* t : P->d_tup)
-    if (t) (void)hipFree(t);
-  for (auto* t : P->d_sgl)
-    if (t) (void)hipFree(t);
-  if (P->d_shift) (void)hipFree(P->d_shift);
-  P->d_shift = nullptr;
+// Releases the plan's device memory (deferred: queued work may still read it).
+void free_plan(hwc_ctx* c, DevPlan* P) {
+  drop_graphs_of_plan(c, P);
+  defer_free(c, P->d_image, 0);
+  defer_free(c, P->d_desc, 0);
+  for (auto* r : P->d_reps) defer_free(c, r, 0);
+  for (auto* t : P->d_gtab) defer_free(c, t, 0);
+  for (auto* t : P->d_tup) defer_free(c, t, 0);
+  for (auto* t : P->d_sgl) defer_free(c, t, 0);
+  defer_free(c, P->d_shift, 0);
   for (auto& v : P->vpasses) {
-    if (v.d_image) (void)hipFree(v.d_image);
-    if (v.d_desc) (void)hipFree(v.d_desc);
+    defer_free(c, v.d_image, 0);
+    defer_free(c, v.d_desc, 0);
   }
+  c->grave_bytes += P->dev_bytes;
+  P->d_shift = nullptr;
   P->vpasses.clear();
   P->vpath = false;
   P->d_tup.clear();
@@ -630,23 +727,8 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     if (orbit) bytes += P->fields[j]->F.prim_reps.size() * 4;
     bytes += gtabs[j].size() * 4;
   }
-  if (c->budget) {
-    while (c->table_bytes + bytes > c->budget) {
-      auto victim = c->plans.end();
-      for (auto i2 = c->plans.begin(); i2 != c->plans.end(); ++i2)
-        if (i2->second->pins == 0 && (victim == c->plans.end() || i2->second->last_use < victim->second->last_use))
-          victim = i2;
-      if (victim == c->plans.end()) break;
-      drop_graphs(c);
-      HIPX(c, hipDeviceSynchronize());
-      c->table_bytes -= victim->second->dev_bytes;
-      free_plan(victim->second.get());
-      c->plans.erase(victim);
-      c->evictions++;
-    }
-    if (c->table_bytes + bytes > c->budget)
-      return fail(c, HWC_ERR_OOM_BUDGET, "tables exceed the context's HBM budget");
-  }
+  if (c->budget && bytes > c->budget)
+    return fail(c, HWC_ERR_OOM_BUDGET, "tables exceed the context's HBM budget");
   HIPX(c, hipMalloc(&P->d_image, D.image_bytes));
   HIPX(c, hipMemcpy(P->d_image, P->image.data(), D.image_bytes, hipMemcpyHostToDevice));
   D.image = static_cast<const uint32_t*>(P->d_image);
@@ -737,6 +819,31 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     if (rv) return rv;
     P->vpath = ok;
   }
+  if (c->budget) {
+    // admission by the HBM budget: least recently used plans make room; their
+    // memory counts against the budget until it is actually freed (once the
+    // work reading it is done)
+    (void)reap(c, false);
+    while (c->table_bytes + c->grave_bytes > c->budget) {
+      auto victim = c->plans.end();
+      for (auto i2 = c->plans.begin(); i2 != c->plans.end(); ++i2)
+        if (i2->second->pins == 0 && (victim == c->plans.end() || i2->second->last_use < victim->second->last_use))
+          victim = i2;
+      if (victim == c->plans.end()) break;
+      c->table_bytes -= victim->second->dev_bytes;
+      free_plan(c, victim->second.get());
+      c->plans.erase(victim);
+      c->evictions++;
+      (void)reap(c, false);
+    }
+    if (c->table_bytes + c->grave_bytes > c->budget && c->grave_bytes) (void)reap(c, true);
+    if (c->table_bytes + c->grave_bytes > c->budget) {
+      c->table_bytes -= P->dev_bytes;
+      free_plan(c, P.get());
+      (void)reap(c, false);
+      return fail(c, HWC_ERR_OOM_BUDGET, "tables exceed the context's HBM budget");
+    }
+  }
   // relative cost of one tile, for ordering mixed batches (longest first)
   P->tile_cost = 0;
   for (uint32_t j = 0; j < g; ++j)
@@ -758,30 +865,80 @@ struct Scratch {
   uint64_t max_tiles;
 };
 
-int get_scratch(hwc_ctx* c, uint64_t n, uint32_t g, bool plain, bool hist, Scratch* s) {
-  // plain: per-level results (also needed for the factorization partition)
+// Byte sizes of the scratch parts of one request of n rows (plain: per-level
+// results, also needed for the factorization partition and the passes of the
+// matrix-product path; tcodes: dense translates of the rows).
+struct ScratchSizes {
+  uint64_t pid, small, tiles, perm, lv, hist, tcodes;
+  uint64_t max_tiles;
+};
+ScratchSizes scratch_sizes(uint64_t n, uint32_t g, int cb, bool plain, bool hist, bool tcodes) {
   const uint32_t npat = hwc::pattern_count(g);
-  s->max_tiles = n / hwc::kWave + npat + 1;
+  ScratchSizes z{};
+  z.max_tiles = n / hwc::kWave + npat + 1;
+  z.pid = std::max<uint64_t>(n, 1) * 2;
+  z.small = (uint64_t)(4 * npat + 16) * 4;
+  z.tiles = z.max_tiles * 8;
+  z.perm = std::max<uint64_t>(n, 1) * 4;
+  z.lv = plain ? std::max<uint64_t>(n, 1) * g * 4 : 0;
+  z.hist = hist ? hwc::hist_scratch_bytes(n) : 0;
+  z.tcodes = tcodes ? std::max<uint64_t>(n, 1) * (2 * g + 3) * (uint64_t)cb : 0;
+  return z;
+}
+
+// Points the parts of S at base + offsets (256-byte aligned); returns the bytes used.
+uint64_t carve_scratch(const ScratchSizes& z, uint32_t g, uint8_t* base, Scratch* s) {
+  const uint32_t npat = hwc::pattern_count(g);
+  uint64_t off = 0;
+  auto take = [&](uint64_t bytes) -> void* {
+    void* p = base ? static_cast<void*>(base + off) : nullptr;
+    off += (bytes + 255) / 256 * 256;
+    return bytes ? p : nullptr;
+  };
+  s->max_tiles = z.max_tiles;
+  s->pid = static_cast<uint16_t*>(take(z.pid));
+  uint32_t* sm = static_cast<uint32_t*>(take(z.small));
+  s->counts = sm;
+  s->bucket_start = sm ? sm + npat : nullptr;
+  s->tile_start = sm ? sm + 2 * npat : nullptr;
+  s->cursor = sm ? sm + 3 * npat : nullptr;
+  s->ntiles = sm ? sm + 4 * npat : nullptr;
+  s->queue = sm ? sm + 4 * npat + 4 : nullptr;
+  s->tiles = static_cast<uint64_t*>(take(z.tiles));
+  s->perm = static_cast<uint32_t*>(take(z.perm));
+  s->lv = static_cast<uint32_t*>(take(z.lv));
+  s->hist = take(z.hist);
+  s->tcodes = take(z.tcodes);
+  return off;
+}
+
+int get_scratch(hwc_ctx* c, int set, uint64_t n, uint32_t g, int cb, bool plain, bool hist, bool tcodes,
+                Scratch* s) {
+  const ScratchSizes z = scratch_sizes(n, g, cb, plain, hist, tcodes);
+  ScratchSet& st = c->sets[set];
   int rc;
-  if ((rc = ensure(c, c->pid, std::max<uint64_t>(n, 1) * 2))) return rc;
-  if ((rc = ensure(c, c->small, (size_t)(4 * npat + 16) * 4))) return rc;
-  if ((rc = ensure(c, c->tiles, s->max_tiles * 8))) return rc;
-  if ((rc = ensure(c, c->perm, std::max<uint64_t>(n, 1) * 4))) return rc;
-  if (plain && (rc = ensure(c, c->lv, std::max<uint64_t>(n, 1) * g * 4))) return rc;
-  if (hist && (rc = ensure(c, c->hist, hwc::hist_scratch_bytes(n)))) return rc;
-  s->pid = static_cast<uint16_t*>(c->pid.p);
-  uint32_t* sm = static_cast<uint32_t*>(c->small.p);
+  if ((rc = ensure(c, set, st.pid, z.pid))) return rc;
+  if ((rc = ensure(c, set, st.small, z.small))) return rc;
+  if ((rc = ensure(c, set, st.tiles, z.tiles))) return rc;
+  if ((rc = ensure(c, set, st.perm, z.perm))) return rc;
+  if (plain && (rc = ensure(c, set, st.lv, z.lv))) return rc;
+  if (hist && (rc = ensure(c, set, st.hist, z.hist))) return rc;
+  if (tcodes && (rc = ensure(c, set, st.tcodes, z.tcodes))) return rc;
+  const uint32_t npat = hwc::pattern_count(g);
+  s->max_tiles = z.max_tiles;
+  s->pid = static_cast<uint16_t*>(st.pid.p);
+  uint32_t* sm = static_cast<uint32_t*>(st.small.p);
   s->counts = sm;
   s->bucket_start = sm + npat;
   s->tile_start = sm + 2 * npat;
   s->cursor = sm + 3 * npat;
   s->ntiles = sm + 4 * npat;
   s->queue = sm + 4 * npat + 4;
-  s->tiles = static_cast<uint64_t*>(c->tiles.p);
-  s->perm = static_cast<uint32_t*>(c->perm.p);
-  s->lv = plain ? static_cast<uint32_t*>(c->lv.p) : nullptr;
-  s->hist = hist ? c->hist.p : nullptr;
-  s->tcodes = nullptr;
+  s->tiles = static_cast<uint64_t*>(st.tiles.p);
+  s->perm = static_cast<uint32_t*>(st.perm.p);
+  s->lv = plain ? static_cast<uint32_t*>(st.lv.p) : nullptr;
+  s->hist = hist ? st.hist.p : nullptr;
+  s->tcodes = tcodes ? st.tcodes.p : nullptr;
   return HWC_OK;
 }
 
@@ -877,8 +1034,9 @@ int check_args(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags) {
   return HWC_OK;
 }
 
-int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N, int32_t* hk,
-            uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s, uint32_t* lam = nullptr) {
+// Argument checks and the plan of one device-pointer request.
+int prepare_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N, int32_t* hk,
+                uint64_t* hc, uint64_t* hlen, uint32_t flags, uint32_t* lam, bool build, DevPlan** out) {
   int rc = check_args(c, q, g, flags & ~kFlagSqf);
   if (rc) return rc;
   if (cb != 1 && cb != 2) return fail(c, HWC_ERR_ARG, "coeff_bytes must be 1 or 2");
@@ -888,7 +1046,16 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   if (n >= (1ull << 31)) return fail(c, HWC_ERR_ARG, "n too large");
   HIPX(c, hipSetDevice(c->device));
   DevPlan* P = nullptr;
-  if ((rc = get_plan(c, q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u, &P))) return rc;
+  const auto key = std::make_tuple(q, g, (flags & HWC_FULL_SWEEP) ? 0u : 1u);
+  if (build) {
+    if ((rc = get_plan(c, q, g, std::get<2>(key), &P))) return rc;
+  } else {
+    auto it = c->plans.find(key);
+    if (it == c->plans.end())
+      return fail(c, HWC_ERR_ARG, "the plan of (q, g) is not resident: build it first (hwc_plan_info or a count)");
+    P = it->second.get();
+    P->last_use = ++c->tick;
+  }
   if (lam && P->desc.lv[0].form != hwc::kFormA)
     return fail(c, HWC_ERR_FIELD_TOO_LARGE, "the factorization partition needs q <= 10923");
   if (hk) {   // the histogram key (mixed radix 2q^k+3, plus the partition's rank) must fit 63 bits
@@ -899,34 +1066,47 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
     }
     if (bits > 63.0) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "histogram key wider than 63 bits for this (q, g)");
   }
+  *out = P;
+  return HWC_OK;
+}
+
+bool needs_lv(const DevPlan* P, uint32_t flags, const uint32_t* lam) {
+  return (flags & HWC_PLAIN) != 0 || lam != nullptr || (P->vpath && P->vpasses.size() > 1);
+}
+bool needs_tcodes(const DevPlan* P) { return P->d_shift != nullptr && !P->vpath; }
+
+int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N, int32_t* hk,
+            uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s, uint32_t* lam = nullptr) {
+  DevPlan* P = nullptr;
+  int rc = prepare_dev(c, q, g, codes, cb, n, N, hk, hc, hlen, flags, lam, true, &P);
+  if (rc) return rc;
+  const int set = set_for(c, s);
+  (void)reap(c, false);
   Scratch S;
-  const bool need_lv = (flags & HWC_PLAIN) != 0 || lam != nullptr || (P->vpath && P->vpasses.size() > 1);
-  if ((rc = get_scratch(c, n, g, need_lv, hk != nullptr, &S))) return rc;
-  if (P->d_shift) {
-    if ((rc = ensure(c, c->tcodes, std::max<uint64_t>(n, 1) * (2 * g + 3) * cb))) return rc;
-    S.tcodes = c->tcodes.p;
-  }
+  if ((rc = get_scratch(c, set, n, g, cb, needs_lv(P, flags, lam), hk != nullptr, needs_tcodes(P), &S))) return rc;
   const bool use_graph = !(flags & (HWC_PLAIN | HWC_NO_GRAPH)) && n > 0 && !c->profile;
-  if ((rc = order_begin(c, s))) return rc;
+  if ((rc = order_begin(c, set, s))) return rc;
   if (!use_graph) {
     rc = enqueue(c, P, S, codes, cb, n, N, lam, hk, hc, hcap, hlen, flags, s, c->profile);
     if (rc) return rc;
-    return order_end(c, s);
+    return order_end(c, set, s);
   }
   std::vector<uint64_t> key = {1, (uint64_t)(uintptr_t)P, n, (uint64_t)cb, (uint64_t)(uintptr_t)codes,
                                (uint64_t)(uintptr_t)N, (uint64_t)(uintptr_t)hk, (uint64_t)(uintptr_t)hc, hcap,
-                               (uint64_t)(uintptr_t)hlen, flags, (uint64_t)(uintptr_t)lam};
+                               (uint64_t)(uintptr_t)hlen, flags, (uint64_t)(uintptr_t)lam, (uint64_t)set};
   for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
     if (it->key == key) {
       c->graphs.splice(c->graphs.begin(), c->graphs, it);
       HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
-      return order_end(c, s);
+      return order_end(c, set, s);
     }
   }
   // capture on the context stream, replay on s
   if (s != c->stream) HIPX(c, hipStreamSynchronize(c->stream));
   GraphEntry ge;
   ge.key = key;
+  ge.set = set;
+  ge.plans = {P};
   HIPX(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   rc = enqueue(c, P, S, codes, cb, n, N, lam, hk, hc, hcap, hlen, flags, c->stream);
   hipGraph_t graph = nullptr;
@@ -940,61 +1120,79 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   HIPX(c, hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0));
   c->graphs.push_front(ge);
   while (c->graphs.size() > kMaxGraphs) {
-    destroy_graph(c->graphs.back());
+    destroy_graph(c, c->graphs.back());
     c->graphs.pop_back();
   }
   HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
-  return order_end(c, s);
+  return order_end(c, set, s);
 }
 
 // ---- several requests in one persistent launch ----
 
 struct BatchPlan {
-  std::vector<size_t> order;        // jobs, most expensive tiles first
+  std::vector<size_t> order;        // Zech-path jobs, most expensive tiles first
+  std::vector<size_t> vjobs;        // matrix-product jobs (input order), launched after the batch kernel
   std::vector<DevPlan*> plans;      // per job (input order)
   std::vector<uint64_t> off, toff;  // row and tile offsets (sorted order)
   std::vector<uint64_t> max_tiles;
   std::vector<uint64_t> tco;        // byte offset of the job's dense translates, or kNoShift
-  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0, tbytes = 0;
-  uint32_t lds = 0, block = 256, grid = 0, per = 8;
+  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0, tbytes = 0, nlv = 0;
+  uint32_t lds = 0, block = 256, grid = 0, per = 8, gmax = 1;
 };
 
 constexpr uint64_t kNoShift = ~0ull;
 
 // Rows the batch kernel reads for sorted job r: the dense translates when its
 // plan has a step table, else the caller's rows.
-const void* batch_rows(hwc_ctx* c, const hwc_job& J, const BatchPlan& B, size_t r) {
-  return B.tco[r] == kNoShift ? J.d_coeffs : static_cast<const void*>(static_cast<char*>(c->btcodes.p) + B.tco[r]);
+const void* batch_rows(const ScratchSet& st, const hwc_job& J, const BatchPlan& B, size_t r) {
+  return B.tco[r] == kNoShift ? J.d_coeffs : static_cast<const void*>(static_cast<char*>(st.btcodes.p) + B.tco[r]);
 }
 
-int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, const BatchPlan& B, const hwc::JobDesc* d_jobs,
-                  hipStream_t s) {
-  uint16_t* pid = static_cast<uint16_t*>(c->bpid.p);
-  uint32_t* perm = static_cast<uint32_t*>(c->bperm.p);
-  uint64_t* tiles = static_cast<uint64_t*>(c->btiles.p);
-  uint32_t* small = static_cast<uint32_t*>(c->bsmall.p);
-  uint32_t* words = static_cast<uint32_t*>(c->bwords.p);
-  for (size_t r = 0; r < njobs; ++r) {
-    const hwc_job& J = jobs[B.order[r]];
-    const DevPlan* P = B.plans[B.order[r]];
-    uint32_t* sm = small + r * kSmallStride;
-    const void* rows = batch_rows(c, J, B, r);
-    if (rows != J.d_coeffs)
-      HIPX(c, hwc::launch_shift(J.coeff_bytes, J.g, J.d_coeffs, J.n, P->q, P->d_shift, const_cast<void*>(rows), s));
-    HIPX(c, hwc::launch_bucket(J.coeff_bytes, rows, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
-                               sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
-                               B.max_tiles[r], s));
+// Every job of a batch on stream s: the Zech-path jobs in one persistent
+// multi-plan launch (after their bucketing), their histograms, then each
+// matrix-product job as its own launches (ordered on the same stream; in a
+// captured graph they are nodes of the same graph).
+int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, const BatchPlan& B, const hwc::JobDesc* d_jobs, int set,
+                  uint32_t flags, hipStream_t s) {
+  const ScratchSet& st = c->sets[set];
+  const size_t nz = B.order.size();
+  if (nz) {
+    uint16_t* pid = static_cast<uint16_t*>(st.bpid.p);
+    uint32_t* perm = static_cast<uint32_t*>(st.bperm.p);
+    uint64_t* tiles = static_cast<uint64_t*>(st.btiles.p);
+    uint32_t* small = static_cast<uint32_t*>(st.bsmall.p);
+    uint32_t* words = static_cast<uint32_t*>(st.bwords.p);
+    for (size_t r = 0; r < nz; ++r) {
+      const hwc_job& J = jobs[B.order[r]];
+      const DevPlan* P = B.plans[B.order[r]];
+      uint32_t* sm = small + r * kSmallStride;
+      const void* rows = batch_rows(st, J, B, r);
+      if (rows != J.d_coeffs)
+        HIPX(c, hwc::launch_shift(J.coeff_bytes, J.g, J.d_coeffs, J.n, P->q, P->d_shift, const_cast<void*>(rows), s));
+      HIPX(c, hwc::launch_bucket(J.coeff_bytes, rows, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
+                                 sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
+                                 B.max_tiles[r], s));
+    }
+    HIPX(c, hwc::launch_chunk_build(small + 8192, kSmallStride, (uint32_t)nz, B.per,
+                                    static_cast<uint32_t*>(st.bcstart.p), static_cast<uint64_t*>(st.bchunks.p),
+                                    B.chunks_max, words, words + 1, s));
+    HIPX(c, hwc::launch_batch(d_jobs, static_cast<uint64_t*>(st.bchunks.p), words, words + 1, B.lds, B.grid, B.block,
+                              s));
+    for (size_t r = 0; r < nz; ++r) {
+      const hwc_job& J = jobs[B.order[r]];
+      if (!J.d_hist_keys) continue;
+      HIPX(c, hwc::hist_run(J.d_out_N, nullptr, J.n, J.g, J.q, st.hist.p, J.d_hist_keys, J.d_hist_counts,
+                            J.hist_capacity, J.d_hist_len, c->d_err, s));
+    }
   }
-  HIPX(c, hwc::launch_chunk_build(small + 8192, kSmallStride, (uint32_t)njobs, B.per,
-                                  static_cast<uint32_t*>(c->bcstart.p), static_cast<uint64_t*>(c->bchunks.p),
-                                  B.chunks_max, words, words + 1, s));
-  HIPX(c, hwc::launch_batch(d_jobs, static_cast<uint64_t*>(c->bchunks.p), words, words + 1, B.lds, B.grid, B.block,
-                            s));
-  for (size_t r = 0; r < njobs; ++r) {
-    const hwc_job& J = jobs[B.order[r]];
-    if (!J.d_hist_keys) continue;
-    HIPX(c, hwc::hist_run(J.d_out_N, nullptr, J.n, J.g, J.q, c->hist.p, J.d_hist_keys, J.d_hist_counts, J.hist_capacity,
-                          J.d_hist_len, c->d_err, s));
+  for (size_t i : B.vjobs) {
+    const hwc_job& J = jobs[i];
+    Scratch S{};
+    S.lv = static_cast<uint32_t*>(st.lv.p);
+    S.hist = st.hist.p;
+    int rc = enqueue(c, B.plans[i], S, J.d_coeffs, J.coeff_bytes, J.n, J.d_out_N, nullptr, J.d_hist_keys,
+                     J.d_hist_counts, J.hist_capacity, J.d_hist_len, flags, s);
+    if (rc) return rc;
   }
   return HWC_OK;
 }
@@ -1037,17 +1235,43 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     BatchPlan& b;
     ~Unpin() { for (auto* p : b.plans) if (p) p->pins--; }
   } unpin{B};
-  B.order.resize(njobs);
-  for (size_t i = 0; i < njobs; ++i) B.order[i] = i;
+  const int set = set_for(c, s);
+  (void)reap(c, false);
+  ScratchSet& st = c->sets[set];
+  for (size_t i = 0; i < njobs; ++i) {
+    if (B.plans[i]->vpath) {
+      B.vjobs.push_back(i);
+      const hwc_job& J = jobs[i];
+      if (B.plans[i]->vpasses.size() > 1) B.nlv = std::max<uint64_t>(B.nlv, J.n * J.g);
+      if (J.d_hist_keys) B.nhist = std::max<uint64_t>(B.nhist, J.n);
+    } else {
+      B.order.push_back(i);
+    }
+  }
   std::stable_sort(B.order.begin(), B.order.end(),
                    [&](size_t a, size_t b) { return B.plans[a]->tile_cost > B.plans[b]->tile_cost; });
-  for (size_t r = 0; r < njobs; ++r) B.lds = std::max(B.lds, B.plans[B.order[r]]->desc.image_bytes);
-  B.block = B.lds > 80 * 1024 ? 1024 : 256;
+  const size_t nz = B.order.size();
+  // launch shape of the multi-plan kernel: the block size of the plan with the
+  // most work (its tuned choice, or the automatic rule), at most one image of
+  // the largest plan per workgroup
+  double wmax = -1;
+  for (size_t r = 0; r < nz; ++r) {
+    const DevPlan* P = B.plans[B.order[r]];
+    B.lds = std::max(B.lds, P->desc.image_bytes);
+    const double w = P->tile_cost * (double)jobs[B.order[r]].n;
+    if (w > wmax) {
+      wmax = w;
+      B.block = P->block;
+    }
+  }
+  if (B.lds > 80 * 1024) B.block = 1024;   // one workgroup per CU: all of it
   B.per = 2 * (B.block / hwc::kWave);
-  int bpc = 0;
-  HIPX(c, hwc::occupancy_batch(B.block, B.lds, &bpc));
-  B.grid = (uint32_t)(c->cus * std::max(bpc, 1));
-  for (size_t r = 0; r < njobs; ++r) {
+  if (nz) {
+    int bpc = 0;
+    HIPX(c, hwc::occupancy_batch(B.block, B.lds, &bpc));
+    B.grid = (uint32_t)(c->cus * std::max(bpc, 1));
+  }
+  for (size_t r = 0; r < nz; ++r) {
     const hwc_job& J = jobs[B.order[r]];
     const uint64_t mt = J.n / hwc::kWave + hwc::pattern_count(J.g) + 1;
     B.off.push_back(B.ntot);
@@ -1064,66 +1288,77 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     B.chunks_max += mt / B.per + 1;
     if (J.d_hist_keys) B.nhist = std::max<uint64_t>(B.nhist, J.n);
   }
-  if ((rc = ensure(c, c->bpid, std::max<uint64_t>(B.ntot, 1) * 2))) return rc;
-  if ((rc = ensure(c, c->bperm, std::max<uint64_t>(B.ntot, 1) * 4))) return rc;
-  if ((rc = ensure(c, c->btiles, B.tiles_tot * 8))) return rc;
-  if ((rc = ensure(c, c->bsmall, njobs * kSmallStride * 4))) return rc;
-  if ((rc = ensure(c, c->bchunks, B.chunks_max * 8))) return rc;
-  if ((rc = ensure(c, c->bcstart, (njobs + 1) * 4))) return rc;
-  if ((rc = ensure(c, c->bwords, 64))) return rc;
-  if (B.tbytes && (rc = ensure(c, c->btcodes, B.tbytes))) return rc;
-  if (B.nhist && (rc = ensure(c, c->hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
-  std::vector<hwc::JobDesc> hj(njobs);
-  for (size_t r = 0; r < njobs; ++r) {
+  if (nz) {
+    if ((rc = ensure(c, set, st.bpid, std::max<uint64_t>(B.ntot, 1) * 2))) return rc;
+    if ((rc = ensure(c, set, st.bperm, std::max<uint64_t>(B.ntot, 1) * 4))) return rc;
+    if ((rc = ensure(c, set, st.btiles, B.tiles_tot * 8))) return rc;
+    if ((rc = ensure(c, set, st.bsmall, nz * kSmallStride * 4))) return rc;
+    if ((rc = ensure(c, set, st.bchunks, B.chunks_max * 8))) return rc;
+    if ((rc = ensure(c, set, st.bcstart, (nz + 1) * 4))) return rc;
+    if ((rc = ensure(c, set, st.bwords, 64))) return rc;
+    if (B.tbytes && (rc = ensure(c, set, st.btcodes, B.tbytes))) return rc;
+  }
+  if (B.nhist && (rc = ensure(c, set, st.hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
+  if (B.nlv && (rc = ensure(c, set, st.lv, B.nlv * 4))) return rc;
+  std::vector<hwc::JobDesc> hj(std::max<size_t>(nz, 1));
+  for (size_t r = 0; r < nz; ++r) {
     const hwc_job& J = jobs[B.order[r]];
     hj[r].plan = B.plans[B.order[r]]->d_desc;
-    hj[r].codes = batch_rows(c, J, B, r);
-    hj[r].perm = static_cast<uint32_t*>(c->bperm.p) + B.off[r];
-    hj[r].tiles = static_cast<uint64_t*>(c->btiles.p) + B.toff[r];
+    hj[r].codes = batch_rows(st, J, B, r);
+    hj[r].perm = static_cast<uint32_t*>(st.bperm.p) + B.off[r];
+    hj[r].tiles = static_cast<uint64_t*>(st.btiles.p) + B.toff[r];
     hj[r].outN = J.d_out_N;
     hj[r].cb = (uint32_t)J.coeff_bytes;
     hj[r].g = J.g;
   }
-  const size_t jbytes = njobs * sizeof(hwc::JobDesc);
-  if ((rc = order_begin(c, s))) return rc;
+  const size_t jbytes = std::max<size_t>(nz, 1) * sizeof(hwc::JobDesc);
+  if ((rc = order_begin(c, set, s))) return rc;
   const bool use_graph = !(flags & HWC_NO_GRAPH) && !c->profile;
   if (!use_graph) {
-    JobSlot& sl = c->slots[c->next_slot];
-    c->next_slot = (c->next_slot + 1) % kJobSlots;
+    // job descriptors through a ring of pinned staging buffers, copied on s
+    JobSlot& sl = st.slots[st.next_slot];
+    st.next_slot = (st.next_slot + 1) % kJobSlots;
     if (sl.used) HIPX(c, hipEventSynchronize(sl.done));
     if (!sl.done) HIPX(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
     if (sl.bytes < jbytes) {
-      if (sl.p) HIPX(c, hipFree(sl.p));
-      sl.p = nullptr;
-      HIPX(c, hipMalloc(&sl.p, jbytes));
-      sl.bytes = jbytes;
+      defer_free(c, sl.p, sl.bytes);
+      if (sl.h) HIPX(c, hipHostFree(sl.h));
+      sl.p = sl.h = nullptr;
+      sl.bytes = 0;
+      const size_t want = std::max<size_t>(jbytes, 64 * sizeof(hwc::JobDesc));
+      HIPX(c, hipMalloc(&sl.p, want));
+      HIPX(c, hipHostMalloc(&sl.h, want, hipHostMallocDefault));
+      sl.bytes = want;
     }
-    HIPX(c, hipMemcpy(sl.p, hj.data(), jbytes, hipMemcpyHostToDevice));
-    rc = enqueue_batch(c, jobs, njobs, B, static_cast<const hwc::JobDesc*>(sl.p), s);
+    std::memcpy(sl.h, hj.data(), jbytes);
+    HIPX(c, hipMemcpyAsync(sl.p, sl.h, jbytes, hipMemcpyHostToDevice, s));
+    rc = enqueue_batch(c, jobs, B, static_cast<const hwc::JobDesc*>(sl.p), set, flags, s);
     if (rc) return rc;
     HIPX(c, hipEventRecord(sl.done, s));
     sl.used = true;
-    return order_end(c, s);
+    return order_end(c, set, s);
   }
-  std::vector<uint64_t> key = {2, njobs, flags};
+  std::vector<uint64_t> key = {2, njobs, flags, (uint64_t)set};
   for (size_t i = 0; i < njobs; ++i) {
     const hwc_job& J = jobs[i];
     for (uint64_t v : {(uint64_t)J.q, (uint64_t)J.g, (uint64_t)(uintptr_t)J.d_coeffs, (uint64_t)J.coeff_bytes, J.n,
                        (uint64_t)(uintptr_t)J.d_out_N, (uint64_t)(uintptr_t)J.d_hist_keys,
                        (uint64_t)(uintptr_t)J.d_hist_counts, J.hist_capacity, (uint64_t)(uintptr_t)J.d_hist_len,
-                       (uint64_t)(uintptr_t)B.plans[i]->d_desc})
+                       (uint64_t)(uintptr_t)B.plans[i]})
       key.push_back(v);
   }
   for (auto it = c->graphs.begin(); it != c->graphs.end(); ++it) {
     if (it->key == key) {
       c->graphs.splice(c->graphs.begin(), c->graphs, it);
       HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
-      return order_end(c, s);
+      return order_end(c, set, s);
     }
   }
   if (s != c->stream) HIPX(c, hipStreamSynchronize(c->stream));
   GraphEntry ge;
   ge.key = key;
+  ge.set = set;
+  ge.plans.assign(B.plans.begin(), B.plans.end());
   HIPX(c, hipMalloc(&ge.jobs, jbytes));
   hipError_t me = hipMemcpy(ge.jobs, hj.data(), jbytes, hipMemcpyHostToDevice);
   if (me != hipSuccess) {
@@ -1131,26 +1366,26 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     return fail(c, HWC_ERR_DEVICE, std::string("job copy: ") + hipGetErrorString(me));
   }
   HIPX(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  rc = enqueue_batch(c, jobs, njobs, B, static_cast<const hwc::JobDesc*>(ge.jobs), c->stream);
+  rc = enqueue_batch(c, jobs, B, static_cast<const hwc::JobDesc*>(ge.jobs), set, flags, c->stream);
   hipGraph_t graph = nullptr;
   hipError_t ee = hipStreamEndCapture(c->stream, &graph);
   ge.graph = graph;
   if (rc || ee != hipSuccess) {
-    destroy_graph(ge);
+    destroy_graph(c, ge);
     return rc ? rc : fail(c, HWC_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(ee));
   }
   hipError_t ie = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
   if (ie != hipSuccess) {
-    destroy_graph(ge);
+    destroy_graph(c, ge);
     return fail(c, HWC_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(ie));
   }
   c->graphs.push_front(ge);
   while (c->graphs.size() > kMaxGraphs) {
-    destroy_graph(c->graphs.back());
+    destroy_graph(c, c->graphs.back());
     c->graphs.pop_back();
   }
   HIPX(c, hipGraphLaunch(c->graphs.front().exec, s));
-  return order_end(c, s);
+  return order_end(c, set, s);
 }
 
 // square-free test over F_q with the level-1 tables (codes are packed values)
@@ -1241,12 +1476,10 @@ int set_tuning_field(hwc_ctx* c, Tuning& T, int opt, int64_t value) {
 // drop cached plans (all, or the one of key) and every graph
 int drop_plans(hwc_ctx* c, const std::tuple<uint32_t, uint32_t, uint32_t>* key) {
   if (c->device < 0) return HWC_OK;
-  drop_graphs(c);
-  HIPX(c, hipDeviceSynchronize());
   for (auto it = c->plans.begin(); it != c->plans.end();) {
     if (!key || it->first == *key) {
       c->table_bytes -= it->second->dev_bytes;
-      free_plan(it->second.get());
+      free_plan(c, it->second.get());
       it = c->plans.erase(it);
     } else {
       ++it;
@@ -1335,12 +1568,12 @@ int run_map(hwc_ctx* c, uint32_t q, uint32_t g, int32_t* keys, uint64_t* counts,
   radix[g] = 1ull << hwc::kLamBits;
   if (bits > 63.0) return fail(c, HWC_ERR_FIELD_TOO_LARGE, "map key wider than 63 bits");
   const uint64_t kChunk = 1ull << 22;
-  if ((rc = ensure(c, c->mcodes, kChunk * nc * cb))) return rc;
-  if ((rc = ensure(c, c->mN, kChunk * g * 4))) return rc;
-  if ((rc = ensure(c, c->mlam, kChunk * 4))) return rc;
-  if ((rc = ensure(c, c->mhk, kChunk * (g + 1) * 4))) return rc;
-  if ((rc = ensure(c, c->mhc, kChunk * 8 + 64))) return rc;
-  if ((rc = ensure(c, c->mcj, 4096 * 4))) return rc;
+  if ((rc = ensure_sync(c, c->mcodes, kChunk * nc * cb))) return rc;
+  if ((rc = ensure_sync(c, c->mN, kChunk * g * 4))) return rc;
+  if ((rc = ensure_sync(c, c->mlam, kChunk * 4))) return rc;
+  if ((rc = ensure_sync(c, c->mhk, kChunk * (g + 1) * 4))) return rc;
+  if ((rc = ensure_sync(c, c->mhc, kChunk * 8 + 64))) return rc;
+  if ((rc = ensure_sync(c, c->mcj, 4096 * 4))) return rc;
   const std::vector<RepClass> classes = rep_classes(fe->F, q, p, g);
   std::unordered_map<uint64_t, uint64_t> acc;
   std::vector<int32_t> hk;
@@ -1482,7 +1715,7 @@ int run_single(hwc_ctx* c, uint32_t q, uint32_t g, const int16_t* coeffs, uint32
   HIPX(c, hipSetDevice(c->device));
   const bool orbit = !(flags & HWC_FULL_SWEEP);
   const uint32_t d = coeffs[nc - 1] ? nc - 1 : nc - 2;
-  if ((rc = ensure(c, c->hout, 64))) return rc;
+  if ((rc = ensure_sync(c, c->hout, 64))) return rc;
   unsigned long long* d_cnt = static_cast<unsigned long long*>(c->hout.p);
   std::vector<uint64_t> z(kmax + 1), ns(kmax + 1), nx(kmax + 1);
   double build_ms = 0, upload_ms = 0, eval_ms = 0;
@@ -1580,8 +1813,9 @@ int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out) {
     if ((e = hwc::prepare_kernels()) != hipSuccess) return create_fail(e, "kernel attributes");
     if ((e = hwc::prepare_vcount()) != hipSuccess) return create_fail(e, "kernel attributes");
     if ((e = hipMalloc(reinterpret_cast<void**>(&c->d_err), 256)) != hipSuccess) return create_fail(e, "hipMalloc");
-    if ((e = hipEventCreateWithFlags(&c->order_ev, hipEventDisableTiming)) != hipSuccess)
-      return create_fail(e, "hipEventCreate");
+    for (auto& st : c->sets)
+      if ((e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming)) != hipSuccess)
+        return create_fail(e, "hipEventCreate");
     if ((e = hipMemset(c->d_err, 0, 256)) != hipSuccess) return create_fail(e, "hipMemset");
   }
   *out = c.release();
@@ -1593,21 +1827,27 @@ void hwc_ctx_destroy(hwc_ctx* c) {
   if (c->device >= 0) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < kSets; ++k) wait_set(c, k);
     drop_graphs(c);
-    for (auto& kv : c->plans) free_plan(kv.second.get());
-    for (Buf* b : {&c->pid, &c->small, &c->tiles, &c->perm, &c->lv, &c->N, &c->hist, &c->codes, &c->hout, &c->bpid,
-                   &c->bperm, &c->btiles, &c->bsmall, &c->bchunks, &c->bcstart, &c->bwords, &c->mcodes, &c->mN,
-                   &c->mlam, &c->mhk, &c->mhc, &c->mcj, &c->tcodes, &c->btcodes})
+    for (auto& kv : c->plans) free_plan(c, kv.second.get());
+    (void)reap(c, true);
+    for (Buf* b : {&c->N, &c->codes, &c->hout, &c->mcodes, &c->mN, &c->mlam, &c->mhk, &c->mhc, &c->mcj})
       if (b->p) (void)hipFree(b->p);
-    for (auto& sl : c->slots) {
-      if (sl.p) (void)hipFree(sl.p);
-      if (sl.done) (void)hipEventDestroy(sl.done);
+    for (auto& st : c->sets) {
+      for (Buf* b : {&st.pid, &st.small, &st.tiles, &st.perm, &st.lv, &st.hist, &st.tcodes, &st.bpid, &st.bperm,
+                     &st.btiles, &st.bsmall, &st.bchunks, &st.bcstart, &st.bwords, &st.btcodes})
+        if (b->p) (void)hipFree(b->p);
+      for (auto& sl : st.slots) {
+        if (sl.p) (void)hipFree(sl.p);
+        if (sl.h) (void)hipHostFree(sl.h);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+      }
+      if (st.ev) (void)hipEventDestroy(st.ev);
     }
     for (auto& kv : c->single) {
       if (kv.second.d_zech) (void)hipFree(kv.second.d_zech);
       if (kv.second.d_reps) (void)hipFree(kv.second.d_reps);
     }
-    if (c->order_ev) (void)hipEventDestroy(c->order_ev);
     if (c->d_err) (void)hipFree(c->d_err);
     for (auto& ev : c->prof)
       for (auto e : ev) (void)hipEventDestroy(e);
@@ -1688,14 +1928,14 @@ int hwc_count_curves(hwc_ctx* c, uint32_t q, uint32_t g, const int16_t* coeffs, 
     for (uint64_t i = 0; i < n; ++i)
       if (!squarefree_host(fe->F, coeffs + i * nc, (int)nc)) return fail(c, HWC_ERR_SINGULAR, "row is not square-free");
   }
-  if ((rc = ensure(c, c->codes, std::max<uint64_t>(n, 1) * nc * 2))) return rc;
-  if ((rc = ensure(c, c->N, std::max<uint64_t>(n, 1) * g * 4))) return rc;
+  if ((rc = ensure_sync(c, c->codes, std::max<uint64_t>(n, 1) * nc * 2))) return rc;
+  if ((rc = ensure_sync(c, c->N, std::max<uint64_t>(n, 1) * g * 4))) return rc;
   const bool want_hist = out_hist != nullptr;
   uint64_t cap = want_hist ? out_hist->capacity : 0;
   uint64_t* d_len = nullptr;
   if (want_hist) {
     // device histogram sized to n (the most it can need), copied back up to cap
-    if ((rc = ensure(c, c->hout, std::max<uint64_t>(n, 1) * (g * 4 + 8) + 64))) return rc;
+    if ((rc = ensure_sync(c, c->hout, std::max<uint64_t>(n, 1) * (g * 4 + 8) + 64))) return rc;
   }
   if (n) HIPX(c, hipMemcpyAsync(c->codes.p, coeffs, n * nc * 2, hipMemcpyHostToDevice, c->stream));
   HIPX(c, hwc::launch_fill(c->d_err, 0, 1, c->stream));
@@ -1809,7 +2049,7 @@ int hwc_lds_gather_rate(hwc_ctx* c, uint32_t table_entries, uint32_t chains, dou
   if (chains != 1 && chains != 2 && chains != 4) return fail(c, HWC_ERR_ARG, "chains must be 1, 2 or 4");
   HIPX(c, hipSetDevice(c->device));
   int rc;
-  if ((rc = ensure(c, c->hout, 64))) return rc;
+  if ((rc = ensure_sync(c, c->hout, 64))) return rc;
   int ncu = 0;
   HIPX(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
   const uint32_t grid = (uint32_t)ncu * 32, steps = 4096;
@@ -1939,12 +2179,62 @@ int hwc_plan_info(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t flags, hwc_level_
 }
 
 int hwc_ctx_stats(const hwc_ctx* c, uint64_t* plans_resident, uint64_t* table_bytes, uint64_t* cache_hits,
-                  uint64_t* cache_misses) {
+                  uint64_t* cache_misses, uint64_t* evictions, uint64_t* pending_free_bytes) {
   if (!c) return HWC_ERR_ARG;
   if (plans_resident) *plans_resident = c->plans.size();
   if (table_bytes) *table_bytes = c->table_bytes;
   if (cache_hits) *cache_hits = c->hits;
   if (cache_misses) *cache_misses = c->misses;
+  if (evictions) *evictions = c->evictions;
+  if (pending_free_bytes) *pending_free_bytes = c->grave_bytes;
+  return HWC_OK;
+}
+
+int hwc_ctx_reserve(hwc_ctx* c, uint64_t max_curves, uint32_t max_jobs, void* stream) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (c->device < 0) return fail(c, HWC_ERR_NO_DEVICE, "host-only context");
+  if (max_curves >= (1ull << 31) || max_jobs < 1 || max_jobs > 65535) return fail(c, HWC_ERR_ARG, "reserve sizes");
+  HIPX(c, hipSetDevice(c->device));
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  const int set = set_for(c, s);
+  ScratchSet& st = c->sets[set];
+  const uint64_t N = std::max<uint64_t>(max_curves, 1), J = max_jobs;
+  // one request of N rows at the largest genus and code width, every optional part
+  const ScratchSizes z = scratch_sizes(N, hwc::kMaxG, 2, true, true, true);
+  int rc;
+  if ((rc = ensure(c, set, st.pid, z.pid))) return rc;
+  if ((rc = ensure(c, set, st.small, z.small))) return rc;
+  if ((rc = ensure(c, set, st.tiles, z.tiles))) return rc;
+  if ((rc = ensure(c, set, st.perm, z.perm))) return rc;
+  if ((rc = ensure(c, set, st.lv, z.lv))) return rc;
+  if ((rc = ensure(c, set, st.hist, z.hist))) return rc;
+  if ((rc = ensure(c, set, st.tcodes, z.tcodes))) return rc;
+  // a multi-plan batch of N rows over at most J jobs (run_batch's sizes, bounded
+  // with every job at the largest genus and the smallest chunk size of 8 tiles)
+  const uint64_t tiles = N / hwc::kWave + J * (hwc::pattern_count(hwc::kMaxG) + 1);
+  if ((rc = ensure(c, set, st.bpid, N * 2))) return rc;
+  if ((rc = ensure(c, set, st.bperm, N * 4))) return rc;
+  if ((rc = ensure(c, set, st.btiles, tiles * 8))) return rc;
+  if ((rc = ensure(c, set, st.bsmall, J * kSmallStride * 4))) return rc;
+  if ((rc = ensure(c, set, st.bchunks, (tiles / 8 + J) * 8))) return rc;
+  if ((rc = ensure(c, set, st.bcstart, (J + 1) * 4))) return rc;
+  if ((rc = ensure(c, set, st.bwords, 64))) return rc;
+  if ((rc = ensure(c, set, st.btcodes, N * (2 * hwc::kMaxG + 3) * 2 + J * 256))) return rc;
+  const size_t jbytes = std::max<size_t>(J, 64) * sizeof(hwc::JobDesc);
+  for (auto& sl : st.slots) {
+    if (sl.bytes >= jbytes) continue;
+    if (sl.used) HIPX(c, hipEventSynchronize(sl.done));
+    if (!sl.done) HIPX(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    defer_free(c, sl.p, sl.bytes);
+    if (sl.h) HIPX(c, hipHostFree(sl.h));
+    sl.p = sl.h = nullptr;
+    sl.bytes = 0;
+    HIPX(c, hipMalloc(&sl.p, jbytes));
+    HIPX(c, hipHostMalloc(&sl.h, jbytes, hipHostMallocDefault));
+    sl.bytes = jbytes;
+  }
   return HWC_OK;
 }
 

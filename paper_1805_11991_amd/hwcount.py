@@ -47,7 +47,8 @@ EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_fie
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
            "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate",
            "hwc_translate_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile",
-           "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option")
+           "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option",
+           "hwc_ctx_reserve")
 
 
 class HwcError(RuntimeError):
@@ -118,7 +119,8 @@ def load():
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
         "hwc_ctx_stats": (i32, [vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64),
-                                ctypes.POINTER(u64)]),
+                                ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]),
+        "hwc_ctx_reserve": (i32, [vp, u64, u32, vp]),
         "hwc_ctx_profile": (i32, [vp, i32]),
         "hwc_ctx_set_option": (i32, [vp, i32, ctypes.c_int64]),
         "hwc_ctx_set_plan_option": (i32, [vp, u32, u32, u32, i32, ctypes.c_int64]),
@@ -175,9 +177,13 @@ class Field:
 class Context:
     """hwc_ctx: device -1 gives a host-only context (fields only)."""
 
-    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, autotune_db: str | None = "default"):
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, autotune_db: str | None = "default",
+                 mfma: bool = False):
         """autotune_db: path of a tuning database, "default" for the one of
-        this architecture shipped with the package (if present), or None."""
+        this architecture shipped with the package (if present), or None.
+        mfma: opt in to the int8 matrix-product counting path for prime
+        q <= 31 (HWC_OPT_MFMA) on every plan, tuned or not; the default is
+        Zech-logarithm evaluation."""
         lib = load()
         h = ctypes.c_void_p()
         rc = lib.hwc_ctx_create(device, hbm_budget_bytes, ctypes.byref(h))
@@ -186,6 +192,9 @@ class Context:
         self._h = h
         self.device = device
         self.tuned_entries = 0
+        if mfma:
+            # before the tuning database: its per-plan entries start from the defaults
+            self.set_option(HWC_OPT_MFMA, 1)
         if device >= 0 and autotune_db is not None:
             from . import autotune
             db = autotune.load_db(None if autotune_db == "default" else autotune_db)
@@ -345,9 +354,15 @@ class Context:
         return [{f: getattr(a, f) for f, _ in hwc_level_desc._fields_} for a in arr]
 
     def stats(self) -> dict:
-        v = [ctypes.c_uint64() for _ in range(4)]
+        v = [ctypes.c_uint64() for _ in range(6)]
         self._check(load().hwc_ctx_stats(self._h, *(ctypes.byref(x) for x in v)))
-        return dict(zip(("plans_resident", "table_bytes", "cache_hits", "cache_misses"), (x.value for x in v)))
+        return dict(zip(("plans_resident", "table_bytes", "cache_hits", "cache_misses", "evictions",
+                         "pending_free_bytes"), (x.value for x in v)))
+
+    def reserve(self, max_curves: int, max_jobs: int = 64, stream=None):
+        """Preallocate the scratch of the calls on `stream` (hwc_ctx_reserve)."""
+        s = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+        self._check(load().hwc_ctx_reserve(self._h, max_curves, max_jobs, s))
 
 
 LAMBDA_SHIFT = (0, 4, 7, 9, 11, 13, 14, 15, 16, 17)

@@ -1,14 +1,19 @@
 """Serving loop: continuous batching of curve-count requests of mixed (q, g).
 
 Requests arrive over time.  Pending requests are admitted into the next batch
-while the batch has room (a curve budget); a request larger than the budget is
-split into chunks that ride in successive batches.  Each batch is one call of
-the library's multi-plan persistent launch (``hwc_count_batch``), enqueued on
-one of several streams, so uploads and downloads of one batch overlap the
-counting of another.  Field tables stay resident in the context's device cache,
-which admits plans against an HBM budget (least recently used plans are
-evicted).  A finished batch is detected by an event; results are scattered
-back to their requests and a request completes when its last chunk does.
+while the batch has room: at most `batch_curves` curves and, when the executor
+states one, at most its per-batch device bytes (codes, N and histogram
+buffers); a request larger than that is split into chunks that ride in
+successive batches.  A batch launches as soon as one of the executor's slots
+(a stream with its own preallocated device arena and library scratch) is
+free, so batches in flight overlap on the device: the uploads, kernels and
+downloads of one run beside another's.  Each batch is one call of the
+library's multi-plan persistent launch (``hwc_count_batch``).  Field tables
+stay resident in the context's device cache, which admits plans against its
+HBM budget (least recently used plans are evicted; their memory is freed once
+the work reading it is done).  A finished batch is detected by an event;
+results are scattered back to their requests and a request completes when its
+last chunk does.
 
 A request that cannot be served (bad q or g, bad coefficients, a field too
 large, tables over the HBM budget) fails on its own; the loop keeps serving
@@ -107,10 +112,14 @@ def merge_hist(parts: list[tuple[np.ndarray, np.ndarray]], g: int):
 
 
 class Server:
-    def __init__(self, executor, batch_curves: int = 1 << 22, max_inflight: int = 2, clock=time.perf_counter):
+    def __init__(self, executor, batch_curves: int = 1 << 22, max_inflight: int = 2, clock=time.perf_counter,
+                 max_jobs: int | None = None):
         self.ex = executor
         self.batch_curves = batch_curves
-        self.max_inflight = max_inflight
+        # an executor with slots of its own bounds the batches in flight and their bytes
+        self.max_inflight = min(max_inflight, getattr(executor, "slots", max_inflight))
+        self.batch_bytes = getattr(executor, "batch_bytes", None)
+        self.max_jobs = max_jobs or getattr(executor, "max_jobs", 1 << 16)
         self.clock = clock
         self.pending: deque[Chunk] = deque()
         self.inflight: deque = deque()      # (handle, [chunks])
@@ -130,9 +139,13 @@ class Server:
             req.hist = (np.zeros((0, req.g), np.int32), np.zeros(0, np.uint64))
             self._finish(req)
             return
-        req.chunks_left = math.ceil(n / self.batch_curves)
-        for lo in range(0, n, self.batch_curves):
-            self.pending.append(Chunk(req, lo, min(n, lo + self.batch_curves)))
+        per = self.batch_curves
+        if self.batch_bytes is not None:   # a chunk must fit one batch's device bytes
+            per_curve = -(-self.ex.job_bytes(req.q, req.g, 1024, req.codes.dtype, req.want_hist) // 1024)
+            per = max(1, min(per, (self.batch_bytes - 4096) // per_curve))
+        req.chunks_left = math.ceil(n / per)
+        for lo in range(0, n, per):
+            self.pending.append(Chunk(req, lo, min(n, lo + per)))
 
     # -- the loop
     def step(self) -> int:
@@ -143,13 +156,20 @@ class Server:
             handle, chunks = self.inflight.popleft()
             self._collect(handle, chunks)
         while self.pending and len(self.inflight) < self.max_inflight:
-            batch, room = [], self.batch_curves
-            while self.pending and self.pending[0].hi - self.pending[0].lo <= room:
-                ch = self.pending.popleft()
+            batch, room, room_b = [], self.batch_curves, self.batch_bytes
+            while self.pending and len(batch) < self.max_jobs:
+                ch = self.pending[0]
+                m = ch.hi - ch.lo
+                b = self._bytes(ch)
+                if m > room or (room_b is not None and b > room_b):
+                    break
+                self.pending.popleft()
                 if ch.req.error:          # an earlier chunk of the request failed
                     continue
                 batch.append(ch)
-                room -= ch.hi - ch.lo
+                room -= m
+                if room_b is not None:
+                    room_b -= b
             if not batch:
                 break
             self._launch(batch)
@@ -161,6 +181,11 @@ class Server:
                 self.ex.wait_any([h for h, _ in self.inflight])
 
     # -- internals
+    def _bytes(self, ch: Chunk) -> int:
+        if self.batch_bytes is None:
+            return 0
+        return self.ex.job_bytes(ch.req.q, ch.req.g, ch.hi - ch.lo, ch.req.codes.dtype, ch.req.want_hist)
+
     def _launch(self, batch: list[Chunk]):
         try:
             handle = self.ex.submit([(c.req.q, c.req.g, c.req.codes[c.lo:c.hi], c.req.want_hist) for c in batch])
@@ -169,6 +194,9 @@ class Server:
         except Exception:
             # isolate the failing request(s): run each chunk on its own
             for c in batch:
+                free = getattr(self.ex, "free_slots", None)
+                while free is not None and free() == 0 and self.inflight:
+                    self._collect(*self.inflight.popleft())    # wait for a slot
                 try:
                     handle = self.ex.submit([(c.req.q, c.req.g, c.req.codes[c.lo:c.hi], c.req.want_hist)])
                     self.inflight.append((handle, [c]))
@@ -209,42 +237,108 @@ class Server:
 
 
 class GpuExecutor:
-    """Runs batches with hwc_count_batch on round-robin streams."""
+    """Runs batches with hwc_count_batch, one batch per slot.  A slot is a
+    stream with its own device arena (codes, N and histogram buffers of up
+    to `batch_bytes`), pinned host staging for the uploads and downloads,
+    and library scratch preallocated with hwc_ctx_reserve; nothing is
+    allocated per batch, and batches on different slots overlap."""
 
-    def __init__(self, ctx, streams: int = 2):
+    ALIGN = 256
+
+    def __init__(self, ctx, streams: int = 2, batch_curves: int = 1 << 22, max_jobs: int = 256):
         import torch
         self.torch = torch
         self.ctx = ctx
-        self.streams = [torch.cuda.Stream() for _ in range(streams)]
-        self.k = 0
+        self.max_jobs = max_jobs
+        # worst case per curve: int16 codes at g = 4, N, histogram keys and counts
+        self.batch_bytes = batch_curves * self.job_bytes(13, 4, 1, np.int16, True) + max_jobs * 4 * self.ALIGN
+        self.slots = streams
+        self._free = list(range(streams))
+        self._s = []
+        for _ in range(streams):
+            st = torch.cuda.Stream()
+            ctx.reserve(batch_curves, max_jobs, stream=st)
+            self._s.append({"stream": st,
+                            "dev": torch.empty(self.batch_bytes, dtype=torch.uint8, device="cuda"),
+                            "h_in": torch.empty(self.batch_bytes, dtype=torch.uint8).pin_memory(),
+                            "h_out": torch.empty(self.batch_bytes, dtype=torch.uint8).pin_memory(),
+                            "d_len": torch.zeros(max_jobs, dtype=torch.int64, device="cuda"),
+                            "h_len": torch.zeros(max_jobs, dtype=torch.int64).pin_memory()})
+
+    @classmethod
+    def _al(cls, b: int) -> int:
+        return (b + cls.ALIGN - 1) // cls.ALIGN * cls.ALIGN
+
+    @classmethod
+    def job_bytes(cls, q, g, n, dtype, want_hist) -> int:
+        cb = np.dtype(dtype).itemsize
+        b = cls._al(n * (2 * g + 3) * cb) + cls._al(n * g * 4)
+        if want_hist:
+            b += cls._al(max(n, 1) * g * 4) + cls._al(max(n, 1) * 8)
+        return b
+
+    def free_slots(self) -> int:
+        return len(self._free)
 
     def submit(self, jobs):
         torch = self.torch
-        s = self.streams[self.k % len(self.streams)]
-        self.k += 1
-        bufs = []
-        with torch.cuda.stream(s):
-            for q, g, codes, want_hist in jobs:
-                n = codes.shape[0]
-                d = torch.from_numpy(np.ascontiguousarray(codes)).pin_memory().to("cuda", non_blocking=True)
-                b = {"q": q, "g": g, "d_coeffs": d,
-                     "d_out_N": torch.empty((n, g), dtype=torch.int32, device="cuda")}
-                if want_hist:
-                    b["d_hist_keys"] = torch.empty((max(n, 1), g), dtype=torch.int32, device="cuda")
-                    b["d_hist_counts"] = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
-                    b["d_hist_len"] = torch.zeros(1, dtype=torch.int64, device="cuda")
-                bufs.append(b)
-        self.ctx.count_batch(bufs, stream=s)
-        with torch.cuda.stream(s):
-            outs = []
-            for b in bufs:
-                o = {"N": b["d_out_N"].to("cpu", non_blocking=True)}
-                if "d_hist_len" in b:
-                    o["len"] = b["d_hist_len"].to("cpu", non_blocking=True)
-                outs.append(o)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        return {"event": ev, "bufs": bufs, "outs": outs, "stream": s}
+        if not self._free:
+            raise RuntimeError("no free slot")
+        if len(jobs) > self.max_jobs:
+            raise RuntimeError("too many jobs for one batch")
+        k = self._free.pop(0)
+        sl = self._s[k]
+        s = sl["stream"]
+        dev, h_in, h_out = sl["dev"], sl["h_in"], sl["h_out"]
+        hv_in = h_in.numpy()
+        off = 0
+
+        def take(nbytes):
+            nonlocal off
+            if off + nbytes > self.batch_bytes:
+                raise RuntimeError("batch larger than the slot's arena")
+            o = off
+            off += self._al(nbytes)
+            return o
+
+        try:
+            bufs, views = [], []
+            with torch.cuda.stream(s):
+                for i, (q, g, codes, want_hist) in enumerate(jobs):
+                    n = codes.shape[0]
+                    c = np.ascontiguousarray(codes)
+                    o = take(c.nbytes)
+                    hv_in[o:o + c.nbytes] = c.view(np.uint8).reshape(-1)
+                    d = dev[o:o + c.nbytes]
+                    d.copy_(h_in[o:o + c.nbytes], non_blocking=True)
+                    tdt = torch.int8 if c.dtype == np.int8 else torch.int16
+                    b = {"q": q, "g": g, "d_coeffs": d.view(tdt).view(n, 2 * g + 3)}
+                    on = take(n * g * 4)
+                    b["d_out_N"] = dev[on:on + n * g * 4].view(torch.int32).view(n, g)
+                    view = {"N": (on, n, g)}
+                    if want_hist:
+                        m = max(n, 1)
+                        ok, oc = take(m * g * 4), take(m * 8)
+                        b["d_hist_keys"] = dev[ok:ok + m * g * 4].view(torch.int32).view(m, g)
+                        b["d_hist_counts"] = dev[oc:oc + m * 8].view(torch.int64)
+                        b["d_hist_len"] = sl["d_len"][i:i + 1]
+                        view["hist"] = (ok, oc, g)
+                    bufs.append(b)
+                    views.append(view)
+            from .hwcount import HWC_NO_GRAPH
+            self.ctx.count_batch(bufs, flags=HWC_NO_GRAPH, stream=s)
+            with torch.cuda.stream(s):
+                for i, v in enumerate(views):
+                    on, n, g = v["N"]
+                    h_out[on:on + n * g * 4].copy_(dev[on:on + n * g * 4], non_blocking=True)
+                    if "hist" in v:
+                        sl["h_len"][i:i + 1].copy_(sl["d_len"][i:i + 1], non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(s)
+        except Exception:
+            self._free.insert(0, k)
+            raise
+        return {"event": ev, "slot": k, "views": views, "stream": s}
 
     def poll(self, h) -> bool:
         return h["event"].query()
@@ -254,17 +348,26 @@ class GpuExecutor:
             handles[0]["event"].synchronize()
 
     def collect(self, h):
-        h["event"].synchronize()
-        self.ctx.status(h["stream"])
-        res = []
-        for b, o in zip(h["bufs"], h["outs"]):
-            N = o["N"].numpy()
-            hist = None
-            if "len" in o:
-                L = int(o["len"].item())
-                hist = (b["d_hist_keys"][:L].cpu().numpy(), b["d_hist_counts"][:L].cpu().numpy().astype(np.uint64))
-            res.append((N, hist))
-        return res
+        sl = self._s[h["slot"]]
+        try:
+            h["event"].synchronize()
+            self.ctx.status(h["stream"])
+            h_out = sl["h_out"].numpy()
+            res = []
+            for i, v in enumerate(h["views"]):
+                on, n, g = v["N"]
+                N = h_out[on:on + n * g * 4].view(np.int32).reshape(n, g).copy()
+                hist = None
+                if "hist" in v:
+                    ok, oc, g = v["hist"]
+                    L = int(sl["h_len"][i])
+                    keys = sl["dev"][ok:ok + L * g * 4].view(self.torch.int32).view(L, g).cpu().numpy()
+                    cnt = sl["dev"][oc:oc + L * 8].view(self.torch.int64).cpu().numpy().astype(np.uint64)
+                    hist = (keys, cnt)
+                res.append((N, hist))
+            return res
+        finally:
+            self._free.append(h["slot"])
 
 
 def poisson_requests(rate: float, count: int, seed: int, max_log2: int = 20):
@@ -297,7 +400,7 @@ def serve_bench(ctx, rates=(0.25, 0.5, 0.75, 0.9), requests: int = 120, seed: in
     """Capacity with every request queued at t = 0, then Poisson arrivals at
     fractions of that capacity; curves/s and p50/p99 latency per rate."""
     from . import curvegen
-    ex = GpuExecutor(ctx)
+    ex = GpuExecutor(ctx, batch_curves=batch_curves)
 
     def make(shapes):
         reqs = []

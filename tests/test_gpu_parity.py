@@ -25,6 +25,7 @@ MODES = {
 
 @pytest.fixture(scope="module")
 def gctx():
+    """The default context: Zech-logarithm evaluation on every plan."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -32,6 +33,23 @@ def gctx():
     ctx = hwcount.Context(device=0)
     yield ctx
     ctx.close()
+
+
+@pytest.fixture(scope="module")
+def mctx():
+    """A context with the opt-in matrix-product path (prime q <= 31)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1805_11991_amd import hwcount
+    ctx = hwcount.Context(device=0, mfma=True)
+    yield ctx
+    ctx.close()
+
+
+def _path_of(ctx, q, g):
+    """"mfma" when the plan of (q, g) counts by matrix products, else "zech"."""
+    return "mfma" if ctx.plan_info(q, g)[0]["mfma"] else "zech"
 
 
 def _hist_np(N):
@@ -60,14 +78,26 @@ def test_g2_q5_full_enumeration(gctx, oracle_mod, curvegen_mod):
     _check(gctx, oracle_mod, 5, 2, curves)
 
 
-def test_g3_q13_slice(gctx, oracle_mod, curvegen_mod):
+def test_default_path_is_zech(gctx, mctx):
+    # the default evaluates with Zech logarithms everywhere; the matrix-product
+    # path runs only where it was asked for (and exists: prime q <= 31)
+    for q, g in ((13, 3), (13, 4), (5, 2), (7, 4), (9, 3)):
+        assert _path_of(gctx, q, g) == "zech", (q, g)
+    for q, g in ((13, 3), (13, 4), (5, 2), (7, 4)):
+        assert _path_of(mctx, q, g) == "mfma", (q, g)
+    assert _path_of(mctx, 9, 3) == "zech"      # prime powers have no matrix-product form
+
+
+def test_g3_q13_slice(gctx, mctx, oracle_mod, curvegen_mod):
     curves = curvegen_mod.sample(13, 3, 6000, seed=curvegen_mod.BASE_SEED + 1)
-    _check(gctx, oracle_mod, 13, 3, curves)
+    Nref = _check(gctx, oracle_mod, 13, 3, curves)
+    _check(mctx, oracle_mod, 13, 3, curves, Nref=Nref)
 
 
-def test_g4_q13_slice(gctx, oracle_mod, curvegen_mod):
+def test_g4_q13_slice(gctx, mctx, oracle_mod, curvegen_mod):
     curves = curvegen_mod.sample(13, 4, 400, seed=curvegen_mod.BASE_SEED + 3)
-    _check(gctx, oracle_mod, 13, 4, curves)
+    Nref = _check(gctx, oracle_mod, 13, 4, curves)
+    _check(mctx, oracle_mod, 13, 4, curves, Nref=Nref)
 
 
 def test_g4_q3_full_enumeration(gctx, oracle_mod, curvegen_mod):
@@ -83,15 +113,28 @@ def test_g4_q3_full_enumeration(gctx, oracle_mod, curvegen_mod):
     (3, 3, 500), (5, 3, 400), (7, 3, 300), (9, 3, 200), (11, 3, 200), (17, 3, 60), (25, 3, 30), (31, 3, 20),
     (5, 4, 150), (7, 4, 60), (9, 4, 40), (11, 4, 20),
 ])
-def test_other_fields(gctx, oracle_mod, curvegen_mod, q, g, n):
+def test_other_fields(gctx, mctx, oracle_mod, curvegen_mod, q, g, n):
     curves = curvegen_mod.sample(q, g, n, seed=4242 + q * 10 + g, dtype=np.int16)
-    _check(gctx, oracle_mod, q, g, curves)
+    Nref = _check(gctx, oracle_mod, q, g, curves)
+    if _path_of(mctx, q, g) == "mfma":
+        _check(mctx, oracle_mod, q, g, curves, Nref=Nref)
 
 
-def test_sparse_patterns(gctx, oracle_mod, curvegen_mod):
-    # rows with many zero coefficients exercise the gap path of the Horner sweep
+@pytest.mark.parametrize("path", ["zech", "mfma"])
+def test_sparse_patterns(gctx, mctx, oracle_mod, curvegen_mod, path):
+    # rows with many zero coefficients: on the Zech path the masked (gap)
+    # Horner sweep with translates off, and the dense translates with them on;
+    # on the matrix-product path zeros are zeros of the product
+    from paper_1805_11991_amd import hwcount as hw
+    ctxs = [mctx] if path == "mfma" else [gctx]
+    if path == "zech":
+        noshift = hw.Context(device=0, autotune_db=None)
+        noshift.set_option(hw.HWC_OPT_SHIFT, 0)
+        ctxs.append(noshift)
     rng = np.random.default_rng(5)
     for q, g in ((13, 3), (13, 4), (7, 2)):
+        for ctx in ctxs:
+            assert _path_of(ctx, q, g) == path
         nc = 2 * g + 3
         rows = []
         while len(rows) < 300:
@@ -104,34 +147,40 @@ def test_sparse_patterns(gctx, oracle_mod, curvegen_mod):
         rows.append([1] + [0] * (2 * g) + [1, 0])          # x^{2g+1} + 1
         rows.append([0, 1] + [0] * (2 * g - 1) + [0, 1])   # x^{2g+2} + x
         curves = np.array(rows, dtype=np.int16)
-        _check(gctx, oracle_mod, q, g, curves)
+        Nref = oracle_mod.count_curves(q, g, curves)
+        for ctx in ctxs:
+            _check(ctx, oracle_mod, q, g, curves, Nref=Nref)
+    if path == "zech":
+        ctxs[1].close()
 
 
-def test_int8_and_int16_agree(gctx, curvegen_mod):
+def test_int8_and_int16_agree(gctx, mctx, oracle_mod, curvegen_mod):
     import torch
-    curves = curvegen_mod.sample(13, 3, 5000, seed=77)
-    outs = []
-    for dt in (torch.int8, torch.int16):
-        d = torch.from_numpy(curves.astype(np.int16)).to(dt).cuda()
-        N = torch.empty((len(curves), 3), dtype=torch.int32, device="cuda")
-        gctx.count_curves_dev(13, 3, d, N)
-        gctx.status()
-        outs.append(N.cpu().numpy())
-    assert np.array_equal(outs[0], outs[1])
+    for q, g in ((13, 3), (13, 4)):
+        curves = curvegen_mod.sample(q, g, 5000 if g == 3 else 700, seed=77)
+        ref = oracle_mod.count_curves(q, g, curves)
+        for ctx in (gctx, mctx):
+            for dt in (torch.int8, torch.int16):
+                d = torch.from_numpy(curves.astype(np.int16)).to(dt).cuda()
+                N = torch.empty((len(curves), g), dtype=torch.int32, device="cuda")
+                ctx.count_curves_dev(q, g, d, N)
+                ctx.status()
+                assert np.array_equal(N.cpu().numpy(), ref), (q, g, dt, _path_of(ctx, q, g))
 
 
-def test_edge_sizes(gctx, oracle_mod, curvegen_mod):
-    for n in (0, 1, 63, 64, 65, 129):
-        curves = curvegen_mod.sample(13, 3, n, seed=9 + n, dtype=np.int16)
-        N, H = gctx.count_curves(13, 3, curves, hist_capacity=max(n, 1))
-        assert N.shape == (n, 3)
-        if n:
-            ref = oracle_mod.count_curves(13, 3, curves)
-            assert np.array_equal(N, ref)
-            k, c = oracle_mod.histogram(ref)
-            assert np.array_equal(H[0], k) and np.array_equal(H[1], c)
-        else:
-            assert len(H[0]) == 0
+def test_edge_sizes(gctx, mctx, oracle_mod, curvegen_mod):
+    for ctx in (gctx, mctx):
+        for n in (0, 1, 31, 32, 33, 63, 64, 65, 129):
+            curves = curvegen_mod.sample(13, 3, n, seed=9 + n, dtype=np.int16)
+            N, H = ctx.count_curves(13, 3, curves, hist_capacity=max(n, 1))
+            assert N.shape == (n, 3)
+            if n:
+                ref = oracle_mod.count_curves(13, 3, curves)
+                assert np.array_equal(N, ref), (n, _path_of(ctx, 13, 3))
+                k, c = oracle_mod.histogram(ref)
+                assert np.array_equal(H[0], k) and np.array_equal(H[1], c)
+            else:
+                assert len(H[0]) == 0
 
 
 def test_errors(gctx):
@@ -205,36 +254,43 @@ def test_graph_replays_match_eager(gctx, curvegen_mod):
         assert torch.equal(hk[:L], hk0[:L]) and torch.equal(hc[:L], hc0[:L])
 
 
-def test_full_size_g3_q13_sampled(gctx, oracle_mod, curvegen_mod):
-    """The 2^24-curve g=3 set in the benchmark's launch form (persistent,
-    graph, orbit sweep), checked on a seeded sample of rows, plus histogram
-    invariants (total = n, strictly increasing tuples)."""
+def test_full_size_g3_q13(gctx, mctx, oracle_mod, curvegen_mod):
+    """The 2^24-curve g=3 set over F_13 in the benchmark's launch form
+    (persistent, graph, orbit sweep): every N of the Zech path equals the
+    matrix-product path's (two independent evaluations), the first 2^18 rows
+    and a seeded sample across the whole set equal the oracle's, and the
+    device histogram equals the oracle's histogram of N."""
     import torch
     n = 1 << 24
     curves = curvegen_mod.sample(13, 3, n, seed=curvegen_mod.BASE_SEED + 1)
     d = torch.from_numpy(curves).cuda()
-    N = torch.empty((n, 3), dtype=torch.int32, device="cuda")
-    hk = torch.empty((n, 3), dtype=torch.int32, device="cuda")
-    hc = torch.empty(n, dtype=torch.int64, device="cuda")
-    hl = torch.zeros(1, dtype=torch.int64, device="cuda")
-    gctx.count_curves_dev(13, 3, d, N, hk, hc, hl)
-    gctx.status()
-    Nh = N.cpu().numpy()
+    out = {}
+    for name, ctx in (("zech", gctx), ("mfma", mctx)):
+        assert _path_of(ctx, 13, 3) == name
+        N = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+        hk = torch.empty((n, 3), dtype=torch.int32, device="cuda")
+        hc = torch.empty(n, dtype=torch.int64, device="cuda")
+        hl = torch.zeros(1, dtype=torch.int64, device="cuda")
+        print(f"  full-size g=3 q=13 on the {name} path", flush=True)
+        ctx.count_curves_dev(13, 3, d, N, hk, hc, hl)
+        ctx.status()
+        L = int(hl.item())
+        out[name] = (N.cpu().numpy(), hk[:L].cpu().numpy(), hc[:L].cpu().numpy().astype(np.uint64))
+        del N, hk, hc
+    Nz, kz, cz = out["zech"]
+    Nm, km, cm = out["mfma"]
+    bad = np.flatnonzero((Nz != Nm).any(axis=1))
+    assert bad.size == 0, (bad[:5], Nz[bad[:5]], Nm[bad[:5]])
     rng = np.random.default_rng(2024)
-    idx = np.unique(np.concatenate([rng.integers(0, n, 1500), [0, n - 1]]))
+    idx = np.unique(np.concatenate([np.arange(1 << 18), rng.integers(0, n, 4096), [n - 1]]))
+    print(f"  oracle on {len(idx)} rows", flush=True)
     ref = oracle_mod.count_curves(13, 3, curves[idx])
-    assert np.array_equal(Nh[idx], ref)
-    L = int(hl.item())
-    keys = hk[:L].cpu().numpy()
-    cnt = hc[:L].cpu().numpy()
-    assert int(cnt.sum()) == n
-    assert (np.diff(keys[:, 0]) >= 0).all()
-    kk = keys.astype(np.int64)
-    lin = (kk[:, 0] * 400 + kk[:, 1]) * 5000 + kk[:, 2]
-    assert (np.diff(lin) > 0).all()
-    # the histogram equals the one of the per-curve output
-    k2, c2 = _hist_np(Nh)
-    assert np.array_equal(k2, keys) and np.array_equal(c2, cnt.astype(np.uint64))
+    bad = np.flatnonzero((Nz[idx] != ref).any(axis=1))
+    assert bad.size == 0, (idx[bad[:5]], Nz[idx[bad[:5]]], ref[bad[:5]])
+    kref, cref = oracle_mod.histogram(Nz)
+    for keys, cnt in ((kz, cz), (km, cm)):
+        assert np.array_equal(keys, kref) and np.array_equal(cnt, cref)
+    assert int(cref.sum()) == n
 
 
 @pytest.mark.parametrize("q,g,n", [(191, 2, 30), (211, 2, 24), (293, 2, 16), (37, 3, 6), (41, 3, 5), (43, 3, 4),
@@ -317,66 +373,112 @@ def test_two_streams_are_ordered(gctx, oracle_mod, curvegen_mod):
     assert np.array_equal(Nb.cpu().numpy(), rb)
 
 
-OPTION_SETS = [
-    {"split": 0},
-    {"device_tables": 1},          # lowest level only in device memory
-    {"device_tables": 15},         # every level
-    {"block": 1024, "waves_per_simd": 8},
-    {"block": 512, "waves_per_simd": 6, "split": 0},
-    {"split_min_m": 0},            # every level split, down to F_q itself (vanishing bases everywhere)
-    {"mfma": 0},                   # Zech logarithms where the matrix-core path would run
+# Zech-logarithm options: each set says mfma 0 so that it runs the Zech
+# kernels whatever the default is
+ZECH_OPTION_SETS = [
+    {"mfma": 0},
     {"mfma": 0, "split": 0},
+    {"mfma": 0, "device_tables": 1},          # lowest level only in device memory
+    {"mfma": 0, "device_tables": 15},         # every level
+    {"mfma": 0, "block": 1024, "waves_per_simd": 8},
+    {"mfma": 0, "block": 512, "waves_per_simd": 6, "split": 0},
+    {"mfma": 0, "split_min_m": 0},            # every level split, down to F_q (vanishing bases everywhere)
+    {"mfma": 0, "split_min_m": 2048},
     {"mfma": 0, "block": 1024, "waves_per_simd": 6},
+    {"mfma": 0, "shift": 0},                  # rows counted as given (masked Horner on sparse rows)
+]
+# the matrix-product path's options (only the block size applies)
+MFMA_OPTION_SETS = [
+    {"mfma": 1},
+    {"mfma": 1, "block": 256},
+    {"mfma": 1, "block": 512},
+    {"mfma": 1, "block": 1024},
 ]
 
 
-@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000)])
-@pytest.mark.parametrize("opts", range(len(OPTION_SETS)))
-def test_tuning_options_keep_results(gctx, oracle_mod, curvegen_mod, q, g, n, opts):
-    """Every tunable (matrix-core or Zech path, split and its threshold,
-    device-memory placement of any level's table, block size, register
-    budget) gives the oracle's counts."""
+def _run_option_set(oracle_mod, curvegen_mod, q, g, n, opts, seed, want_path):
     from paper_1805_11991_amd import hwcount as hw
     ids = {"split": hw.HWC_OPT_SPLIT, "block": hw.HWC_OPT_BLOCK, "waves_per_simd": hw.HWC_OPT_WAVES_PER_SIMD,
            "device_tables": hw.HWC_OPT_DEVICE_TABLES, "split_min_m": hw.HWC_OPT_SPLIT_MIN_M,
-           "mfma": hw.HWC_OPT_MFMA}
+           "mfma": hw.HWC_OPT_MFMA, "shift": hw.HWC_OPT_SHIFT}
     ctx = hw.Context(device=0, autotune_db=None)
     try:
-        for k, v in OPTION_SETS[opts].items():
+        for k, v in opts.items():
             ctx.set_plan_option(q, g, ids[k], v)
             ctx.set_plan_option(q, g, ids[k], v, hw.HWC_FULL_SWEEP)
-        curves = curvegen_mod.sample(q, g, n, seed=900 + opts)
-        _check(ctx, oracle_mod, q, g, curves, modes={"batched-orbit": 0, "batched-full": 1, "plain-orbit": 2})
+        assert _path_of(ctx, q, g) == want_path, (q, g, opts)
+        curves = curvegen_mod.sample(q, g, n, seed=seed)
+        Nref = oracle_mod.count_curves(q, g, curves)
+        _check(ctx, oracle_mod, q, g, curves, modes={"batched-orbit": 0, "batched-full": 1, "plain-orbit": 2},
+               Nref=Nref)
+        # the same rows as int16 codes through the device entry point
+        import torch
+        d = torch.from_numpy(curves.astype(np.int16)).cuda()
+        N = torch.empty((n, g), dtype=torch.int32, device="cuda")
+        ctx.count_curves_dev(q, g, d, N)
+        ctx.status()
+        assert np.array_equal(N.cpu().numpy(), Nref)
     finally:
         ctx.close()
 
 
-def test_full_size_g4_q13_sampled(gctx, oracle_mod, curvegen_mod):
-    """The 2^26-curve g=4 set over F_13 in the benchmark's launch form,
-    checked on a seeded sample of rows, plus histogram invariants."""
+@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000)])
+@pytest.mark.parametrize("opts", range(len(ZECH_OPTION_SETS)))
+def test_zech_options_keep_results(oracle_mod, curvegen_mod, q, g, n, opts):
+    """Every tunable of the Zech path (split and its threshold, device-memory
+    placement of any level's table, block size, register budget, dense
+    translates) gives the oracle's counts, and the Zech kernels are what ran."""
+    _run_option_set(oracle_mod, curvegen_mod, q, g, n, ZECH_OPTION_SETS[opts], 900 + opts, "zech")
+
+
+@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (7, 2, 3000), (31, 3, 300)])
+@pytest.mark.parametrize("opts", range(len(MFMA_OPTION_SETS)))
+def test_mfma_options_keep_results(oracle_mod, curvegen_mod, q, g, n, opts):
+    """The matrix-product path at every block size, with one pass holding all
+    levels (g = 3, q = 5 at g = 4) or the top level over several passes
+    (g = 4, q = 13), int8 and int16 codes."""
+    _run_option_set(oracle_mod, curvegen_mod, q, g, n, MFMA_OPTION_SETS[opts], 950 + opts, "mfma")
+
+
+def test_full_size_g4_q13(gctx, mctx, oracle_mod, curvegen_mod):
+    """The 2^26-curve g=4 set over F_13 in the benchmark's launch form: every
+    N of the Zech path equals the matrix-product path's, the first 4096 rows
+    and a seeded sample equal the oracle's, and the device histogram equals
+    the oracle's histogram of N."""
     import torch
     n = 1 << 26
     curves = curvegen_mod.sample(13, 4, n, seed=curvegen_mod.BASE_SEED + 3)
     d = torch.from_numpy(curves).cuda()
-    N = torch.empty((n, 4), dtype=torch.int32, device="cuda")
-    hk = torch.empty((n, 4), dtype=torch.int32, device="cuda")
-    hc = torch.empty(n, dtype=torch.int64, device="cuda")
-    hl = torch.zeros(1, dtype=torch.int64, device="cuda")
-    gctx.count_curves_dev(13, 4, d, N, hk, hc, hl)
-    gctx.status()
-    Nh = N.cpu().numpy()
+    Ns = {}
+    hist = None
+    for name, ctx in (("zech", gctx), ("mfma", mctx)):
+        assert _path_of(ctx, 13, 4) == name
+        N = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+        print(f"  full-size g=4 q=13 on the {name} path", flush=True)
+        if name == "zech":
+            hk = torch.empty((n, 4), dtype=torch.int32, device="cuda")
+            hc = torch.empty(n, dtype=torch.int64, device="cuda")
+            hl = torch.zeros(1, dtype=torch.int64, device="cuda")
+            ctx.count_curves_dev(13, 4, d, N, hk, hc, hl)
+            ctx.status()
+            L = int(hl.item())
+            hist = (hk[:L].cpu().numpy(), hc[:L].cpu().numpy().astype(np.uint64))
+            del hk, hc
+        else:
+            ctx.count_curves_dev(13, 4, d, N)
+            ctx.status()
+        Ns[name] = N.cpu().numpy()
+        del N
+    bad = np.flatnonzero((Ns["zech"] != Ns["mfma"]).any(axis=1))
+    assert bad.size == 0, (bad[:5], Ns["zech"][bad[:5]], Ns["mfma"][bad[:5]])
     rng = np.random.default_rng(4096)
-    idx = np.unique(np.concatenate([rng.integers(0, n, 300), [0, n - 1]]))
+    idx = np.unique(np.concatenate([np.arange(4096), rng.integers(0, n, 512), [n - 1]]))
+    print(f"  oracle on {len(idx)} rows", flush=True)
     ref = oracle_mod.count_curves(13, 4, curves[idx])
-    assert np.array_equal(Nh[idx], ref)
-    L = int(hl.item())
-    cnt = hc[:L].cpu().numpy()
-    assert int(cnt.sum()) == n
-    keys = hk[:L].cpu().numpy().astype(np.int64)
-    # strictly increasing tuples (lexicographic)
-    d01 = np.diff(keys, axis=0)
-    first = np.argmax(d01 != 0, axis=1)
-    assert (d01[np.arange(len(d01)), first] > 0).all()
+    assert np.array_equal(Ns["zech"][idx], ref)
+    kref, cref = oracle_mod.histogram(Ns["zech"])
+    assert np.array_equal(hist[0], kref) and np.array_equal(hist[1], cref)
+    assert int(cref.sum()) == n
 
 
 def _odd_prime_powers_below(bound):
