@@ -55,9 +55,22 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def algorithmic_lookups(curves, levels: list[dict]) -> int:
+    """The path's algorithmic work in gathers: for every curve and every swept
+    x of every level, one Zech-table gather per nonzero coefficient below the
+    leading one (Horner in the log domain; swept x = the orbit
+    representatives, or every nonzero x of the full sweep).  Counted on the
+    input rows."""
+    import numpy as np
+    # every row's leading coefficient is its highest nonzero one, so the
+    # nonzero coefficients below it are all but one
+    below = (curves != 0).sum(axis=1, dtype=np.int64) - 1
+    return int(below.sum()) * sum(L["nx"] for L in levels)
+
+
 def lookups_per_batch(curves, levels: list[dict]) -> tuple[int, int]:
-    """Table reads the Zech count kernel's algorithm needs for a batch, and
-    the plain-Horner count for reference.
+    """Table reads the Zech count kernel performs for a batch, and the
+    plain-Horner count for reference.
 
     Plain Horner: one read per nonzero term below the leading one, for every
     swept x.  Split evaluation (levels with msplit = m): a tuple of m points
@@ -251,32 +264,42 @@ def main():
         return {"count_ms": prof["count_ms"] / k, "prep_ms": prof["prep_ms"] / k, "hist_ms": prof["hist_ms"] / k}
 
     def zech_roofline(c, q, g, bufs, kms, ceiling=None):
+        """achieved: the algorithmic gathers (one per nonzero coefficient below
+        the leading one, per swept x, on the input rows) per second of the
+        count kernel; beside it the gathers the kernel performs (split
+        evaluation over mu_4 cosets on the translated rows: fewer)."""
         levels = c.plan_info(q, g)
-        lookups, plain_lookups = lookups_per_batch(evaluated_rows(c, q, g, bufs[1]), levels)
-        achieved = lookups / (kms * 1e-3)
+        alg = algorithmic_lookups(bufs[0], levels)
+        performed, _ = lookups_per_batch(evaluated_rows(c, q, g, bufs[1]), levels)
+        s = kms * 1e-3
         if ceiling is None:
             # the practical ceiling of that bound on this device: a kernel doing
             # nothing but dependent random reads of a table the size of the top level's
             ceiling = c.lds_gather_rate(min(2 * (q ** g - 1), 80000), chains=4)
         return {
             "bound": "lds",
-            "achieved": round(achieved / 1e9, 2),
+            "achieved": round(alg / s / 1e9, 2),
             "peak": round(LDS_PEAK_LOOKUPS / 1e9, 1),
             "unit": "Glookup/s",
-            "frac": round(achieved / LDS_PEAK_LOOKUPS, 4),
+            "frac": round(alg / s / LDS_PEAK_LOOKUPS, 4),
             "gather_ceiling": round(ceiling / 1e9, 2),
-            "frac_of_gather_ceiling": round(achieved / ceiling, 4),
+            "frac_of_gather_ceiling": round(alg / s / ceiling, 4),
             "kernel_ms": round(kms, 4),
-            "lookups_per_launch": lookups,
-            "lookups_per_curve": round(lookups / len(bufs[0]), 1),
-            "plain_horner_lookups": plain_lookups,
+            "algorithmic_lookups_per_launch": alg,
+            "algorithmic_lookups_per_curve": round(alg / len(bufs[0]), 1),
+            "performed_lookups_per_launch": performed,
+            "performed_lookups_per_s": round(performed / s, 1),
+            "performed_frac": round(performed / s / LDS_PEAK_LOOKUPS, 4),
+            "performed_frac_of_gather_ceiling": round(performed / s / ceiling, 4),
             "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit", "nt", "ns")} for L in levels],
         }
 
-    def mfma_roofline(c, q, g, n, kms, ceiling):
+    def mfma_roofline(c, q, g, curves, kms, ceiling):
         levels = c.plan_info(q, g)
+        n = len(curves)
         w = mfma_work(n, levels)
         s = kms * 1e-3
+        alg = algorithmic_lookups(curves, levels)
         return {
             "bound": "alu",
             "achieved": round(w["valu_ops"] / s / 1e9, 1),
@@ -293,6 +316,9 @@ def main():
             "lds_read_frac_of_gather_ceiling": round(w["pairs_padded"] / s / ceiling, 4),
             "mfma_int8_tops": round(w["mfma_ops"] / s / 1e12, 2),
             "mfma_frac": round(w["mfma_ops"] / s / MFMA_INT8_PEAK_OPS, 4),
+            # the same curves priced in the Zech path's algorithmic gathers
+            "zech_equivalent_lookups_per_s": round(alg / s, 1),
+            "zech_equivalent_frac_of_lds_peak": round(alg / s / LDS_PEAK_LOOKUPS, 4),
             "levels": [{"M": L["M"], "nx": L["nx"], "balanced": L["mfma"] == 2} for L in levels],
         }
 
@@ -322,7 +348,7 @@ def main():
         roofline = zech_roofline(ctx, q, g, bufs, km["count_ms"], ceiling3)
         roofline["kernel"] = "count_kernel<3,int8>"
     else:
-        roofline = mfma_roofline(mctx, q, g, n, km["count_ms"], ceiling3)
+        roofline = mfma_roofline(mctx, q, g, curves, km["count_ms"], ceiling3)
         roofline["kernel"] = "vcount_kernel<3,int8>"
     traffic = measured_traffic(args.path)
     roofline["traffic"] = None if traffic is None else traffic["fetch"] + traffic["write"]
@@ -361,7 +387,7 @@ def main():
         assert np.array_equal(bufs[2].cpu().numpy(), Nref), "matrix-product path differs from the Zech path"
         assert int(bufs[5].item()) == nhist
         mk = kernel_ms(mctx, runner(mctx, q, g, bufs, 0), args.steps)
-        mroof = mfma_roofline(mctx, q, g, n, mk["count_ms"], ceiling3)
+        mroof = mfma_roofline(mctx, q, g, curves, mk["count_ms"], ceiling3)
         mtraffic = measured_traffic("mfma")
         mroof["traffic"] = None if mtraffic is None else mtraffic["fetch"] + mtraffic["write"]
         mroof["kernel"] = "vcount_kernel<3,int8>"
@@ -417,7 +443,7 @@ def main():
         mctx.status()
         assert np.array_equal(bufs4[2].cpu().numpy(), N4), "g=4: matrix-product path differs from the Zech path"
         mk4 = kernel_ms(mctx, runner(mctx, 13, 4, bufs4, 0), 2)
-        mr4 = mfma_roofline(mctx, 13, 4, n4, mk4["count_ms"], ceiling4)
+        mr4 = mfma_roofline(mctx, 13, 4, bufs4[0], mk4["count_ms"], ceiling4)
         mr4["kernel"] = "vcount_kernel<4,int8> (level 4 over several passes)"
         mp["g4_q13"] = {"curves": n4, "batched": mb4, "plain": mpl4, "batched_vs_plain": ratio(mpl4, mb4),
                         "curves_per_s": round(n4 / (mb4["ms_per_step"] * 1e-3), 1), "roofline": mr4,

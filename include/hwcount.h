@@ -17,8 +17,14 @@
  * (N_1..N_g), i.e. the a-tuple part of the map N_{g,q} of eq. (1.2), with
  * every input row counted once.
  *
- * Evaluation uses Zech-logarithm arithmetic (Sec. 2.3, encoding (3.1),
- * table (3.2)) in HIP kernels; every N_k is an exact integer.
+ * Evaluation (default) uses Zech-logarithm arithmetic in HIP kernels:
+ * elements as discrete logarithms to a primitive element with a zero
+ * sentinel, additions through a Zech table (Sec. 2.3, eq. (2.1), encoding
+ * (3.1), table (3.2)), the quadratic character read from the parity of the
+ * logarithm (eq. (3.3)).  As an opt-in (HWC_OPT_MFMA) prime q <= 31 can be
+ * counted instead by int8 matrix products of the coefficients with the
+ * coordinates of the powers x^i over F_q, which gives the same sums.  Every
+ * N_k is an exact integer either way.
  *
  * Coefficient codes.  A coefficient is an integer code c in [0, q).  For
  * q = p^e with e > 1, c = sum_i d_i p^i (0 <= d_i < p) stands for
@@ -30,9 +36,12 @@
  * Ownership.  The caller owns every input and output buffer; the library
  * owns its tables and scratch memory.  Functions return HWC_OK (0) or a
  * negative HWC_ERR_* code; hwc_last_error() gives a message.  Calls on one
- * context are serialised internally.  Supported: 1 <= g <= 4, and fields
- * whose tables fit the 160 KiB LDS of one CU (F_{q^g} with q^g - 1 <= 32767,
- * e.g. q = 13 for g = 4, q = 31 for g = 3, q = 181 for g = 2).
+ * context are serialised internally.  Supported: 1 <= g <= 4, odd prime
+ * powers q with q^g <= 2^24 and q <= 32768.  Level tables of up to 32767
+ * nonzero elements are staged in the 160 KiB LDS of a CU (e.g. q = 13 at
+ * g = 4, q = 31 at g = 3, q = 181 at g = 2); larger levels (q = 191 .. 293
+ * at g = 2, q = 37 .. 49 at g = 3) keep their Zech tables in device memory,
+ * served by L2 and the MALL.  Histogram keys must fit 63 bits.
  */
 #ifndef HWCOUNT_H
 #define HWCOUNT_H
@@ -127,7 +136,9 @@ int hwc_field_tables(const hwc_field* f, uint32_t* exp, uint32_t* log, uint32_t*
                      uint32_t* prim_reps);
 void hwc_field_release(hwc_field* f);
 
-/* Counts n curves from host memory and waits for the result.
+/* Counts n curves from host memory and waits for the result: N_k by the
+ * decomposition of Sec. 1.1 for k = 1..g, and the histogram of the tuples,
+ * the a-tuple part of eq. (1.2) (Algorithm 1's count of curves per tuple).
  * coeffs: [n][2g+3] int16 codes.  out_N: [n][g] int32 or NULL.  out_hist:
  * histogram or NULL (out_hist->g must equal g).  Returns HWC_ERR_COEFF_RANGE
  * / HWC_ERR_DEGREE for a bad row, HWC_ERR_HIST_CAPACITY when out_hist is too
@@ -135,7 +146,8 @@ void hwc_field_release(hwc_field* f);
 int hwc_count_curves(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs, uint64_t n, int32_t* out_N,
                      hwc_hist* out_hist, uint32_t flags);
 
-/* Device-pointer form: enqueues the whole count on `stream` (a hipStream_t;
+/* Device-pointer form of hwc_count_curves (the same N_k of Sec. 1.1 and
+ * histogram of eq. (1.2)): enqueues the whole count on `stream` (a hipStream_t;
  * NULL = the context's stream) and returns without waiting.  Row errors are
  * found on the device and reported by hwc_ctx_status.  The histogram is
  * written when d_hist_keys is not NULL (d_hist_len receives its length; at
@@ -211,8 +223,18 @@ int hwc_count_single(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs
  * best of two timed runs.  Synchronous. */
 int hwc_lds_gather_rate(hwc_ctx* ctx, uint32_t table_entries, uint32_t chains, double* lookups_per_s);
 
-/* Several requests, enqueued on `stream` in order (the persistent batched
- * form; each job is a hwc_count_curves_dev call). */
+/* Several requests (each as hwc_count_curves_dev: N_k of Sec. 1.1 and the
+ * histogram of eq. (1.2)) in the persistent batched form, enqueued on
+ * `stream`: the rows of every Zech-path job are bucketed, then one
+ * multi-plan launch pops tiles of all jobs (most expensive plans first, the
+ * LDS image restaged when a workgroup moves to another plan) -- the loops
+ * over the curves and fields of Algorithm 1 in one launch, where the paper
+ * launches once per curve and field (Sec. 3.3); jobs on the opt-in
+ * matrix-product path follow as their own launches on the same stream.
+ * Without HWC_NO_GRAPH the whole batch is captured once into a HIP graph
+ * (keyed by the jobs' shapes and pointers) and replayed.  Errors as
+ * hwc_count_curves_dev; a plan that cannot fit the HBM budget fails the
+ * call (HWC_ERR_OOM_BUDGET) before anything is enqueued. */
 int hwc_count_batch(hwc_ctx* ctx, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream);
 
 /* Waits for `stream` (NULL = context stream) and returns the first row error
@@ -239,10 +261,11 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
                                     (0 or 1: no constraint) */
 #define HWC_OPT_SPLIT_MIN_M 6     /* split only levels with at least this many nonzero elements (default 64):
                                     on small fields a wave meets vanishing bases too often */
-#define HWC_OPT_MFMA 8            /* 1 (default): for prime q <= 31, when the level images fit LDS, f(x) is
-                                    evaluated as an int8 matrix product of the coefficients with the
-                                    coordinates of the powers x^i over F_q (Sec. 1.1's sums, exact in int32),
-                                    the character read from a table; 0: Zech logarithms for every plan */
+#define HWC_OPT_MFMA 8            /* 0 (default): Zech logarithms for every plan.  1 (opt-in): for prime
+                                    q <= 31, when the level images fit LDS (the top level may be split over
+                                    several passes), f(x) is evaluated as an int8 matrix product of the
+                                    coefficients with the coordinates of the powers x^i over F_q (Sec. 1.1's
+                                    sums, exact in int32), the character read from a table */
 #define HWC_OPT_SHIFT 7           /* 1 (default): for q <= 32, a row with a zero coefficient below its leading
                                     one is counted as f(x + t), t in F_q, when some t (of the first 8 tried)
                                     leaves no such zero -- same N_k, factorization pattern and discriminant

@@ -149,7 +149,9 @@ def tune(ctx, q: int, g: int, n: int = 1 << 20, seed: int = 4711, flags: int = 0
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--qg", action="append", required=True, help="q,g to tune (repeatable)")
+    ap.add_argument("--qg", action="append", default=[], help="q,g to tune (repeatable)")
+    ap.add_argument("--ranges", action="store_true",
+                    help="every (q, g) of the data-production ranges: g=2 q<300, g=3 q<50, g=4 q<15")
     ap.add_argument("--n", type=int, default=1 << 20)
     ap.add_argument("--full-sweep", action="store_true")
     ap.add_argument("--out", default=None)
@@ -167,14 +169,24 @@ def main(argv=None):
         with open(out) as fh:
             db = json.load(fh).get("entries", {})
     ctx = hw.Context(device=0, autotune_db=None)
-    for qg in args.qg:
+    todo = list(args.qg)
+    if args.ranges:
+        from .serving import odd_prime_power
+        for g, bound in ((4, 15), (3, 50), (2, 300)):
+            todo += [f"{q},{g}" for q in range(3, bound) if odd_prime_power(q)]
+    if not todo:
+        ap.error("nothing to tune: give --qg or --ranges")
+    for qg in todo:
         q, g = (int(v) for v in qg.split(","))
         t0 = time.time()
-        print(f"tuning q={q} g={g} on {args.n} curves", flush=True)
-        space = dict(SMALL_SPACE if args.small else SPACE)
+        # big plans get the whole space; the many small ones the reduced one
+        big = q ** g > 20000
+        space = dict(SPACE if big and not args.small else SMALL_SPACE)
         if args.with_mfma:
             space = {"mfma": [1, 0], **space}
-        res = tune(ctx, q, g, n=args.n, flags=flags, space=space)
+        n = args.n if big else min(args.n, 1 << 18)
+        print(f"tuning q={q} g={g} on {n} curves", flush=True)
+        res = tune(ctx, q, g, n=n, flags=flags, space=space)
         print(f"best {res['options']}: {res['count_ms']} ms ({time.time() - t0:.0f} s)", flush=True)
         db[db_key(q, g, flags)] = res
     os.makedirs(os.path.dirname(out), exist_ok=True)
