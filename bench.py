@@ -229,7 +229,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
+    # a stream of torch's own, made current: torch's default stream has handle
+    # 0, which the library reads as "the context's stream", so events recorded
+    # on it would not bracket the library's work
+    stream = torch.cuda.Stream(dev)
+    torch.cuda.set_stream(stream)
     ctx = hwcount.Context(device=0)                 # Zech logarithms (the default)
     mctx = hwcount.Context(device=0, mfma=True)     # the opt-in matrix-product path
     head_ctx = mctx if args.path == "mfma" else ctx
