@@ -157,6 +157,32 @@ int hwc_count_curves_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coe
                          int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts, uint64_t hist_capacity,
                          uint64_t* d_hist_len, uint32_t flags, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * count as hwc_count_curves_dev, with the same arguments, results, errors and
+ * ownership of the caller's buffers, but this call allocates and frees
+ * nothing.  Its scratch is a static device array of HWC_NOALLOC_SCRATCH_BYTES
+ * per GPU (held from the library's load until the process ends), so:
+ *  - the plan of (q, g) and the sweep of `flags` must already be resident,
+ *    made by an earlier call such as hwc_plan_info or a count on this
+ *    context (HWC_ERR_ARG otherwise; a plan can leave the cache under an HBM
+ *    budget);
+ *  - a request whose scratch exceeds the array fails with HWC_ERR_ARG before
+ *    anything is enqueued (the need is about 31 bytes per row with the
+ *    histogram, 6 without, plus (2g+3) * coeff_bytes on the Zech path, which
+ *    counts rows with zero coefficients as dense translates, plus 4g with
+ *    HWC_PLAIN: up to about 1.6 million rows at g = 3 with int8 codes and the
+ *    histogram, about a million at g = 4 with int16 codes and every part);
+ *  - kernels are launched directly on `stream`, never from a graph;
+ *  - every call on one GPU, from any context, uses that GPU's one array and
+ *    leaves its contents behind: calls that overlap on one GPU race, and the
+ *    caller must order them (one stream, or events).
+ * HWC_VALIDATE is rejected (it needs host rows). */
+#define HWC_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int hwc_count_curves_dev_noalloc(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes,
+                                 uint64_t n, int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts,
+                                 uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream);
+
 /* As hwc_count_curves_dev, plus the factorization partition lambda(f) of
  * every row (Sec. 1.1: the partition of 2g+2 by the degrees of the
  * irreducible factors of f over F_q, with an extra part 1 when deg f = 2g+1),

@@ -66,6 +66,42 @@ hipError_t launch_lds_gather(uint32_t entries, uint32_t chains, uint32_t steps, 
                              hipStream_t s);
 }  // namespace hwc
 
+// Device memory of the allocation-free entry point (hwc_count_curves_dev_noalloc):
+// one array per GPU, allocated when the code object is loaded and held until
+// the process ends.  Host code never passes the array's name to a kernel (on
+// the host it is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device, kept per device below.
+constexpr uint64_t kStaticScratchBytes = HWC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// With `device` current: looks up (once per device) the device address of
+// that GPU's copy of `scratch`.
+hipError_t setup_static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* static_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
 namespace {
 
 constexpr uint32_t kLdsLimit = hwc::kLdsImageLimit;
@@ -206,6 +242,10 @@ struct hwc_ctx {
   std::map<std::tuple<uint32_t, uint32_t, uint32_t>, Tuning> tuned;   // per (q, g, orbit)
   std::vector<std::array<hipEvent_t, 4>> prof;
   std::vector<hipEvent_t> event_pool;
+  // completion of the last allocation-free call (its work reads plan tables
+  // that a release must not free while it runs)
+  hipEvent_t static_ev = nullptr;
+  bool static_ev_valid = false;
 };
 
 namespace {
@@ -239,6 +279,13 @@ bool reap(hwc_ctx* c, bool wait) {
     if (wait) {
       if (hipEventSynchronize(st.ev) != hipSuccess) return false;
     } else if (hipEventQuery(st.ev) != hipSuccess) {
+      return false;
+    }
+  }
+  if (c->static_ev_valid) {
+    if (wait) {
+      if (hipEventSynchronize(c->static_ev) != hipSuccess) return false;
+    } else if (hipEventQuery(c->static_ev) != hipSuccess) {
       return false;
     }
   }
@@ -1127,6 +1174,31 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   return order_end(c, set, s);
 }
 
+// The allocation-free form of run_dev: the plan must already be resident
+// (building it allocates), every scratch part is carved out of this GPU's
+// static array, kernels are launched directly (instantiating a graph
+// allocates) and nothing is allocated or freed.  Overlapping calls on one GPU
+// share the array and race; the caller orders them.
+int run_dev_noalloc(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint64_t n, int32_t* N,
+                    int32_t* hk, uint64_t* hc, uint64_t hcap, uint64_t* hlen, uint32_t flags, hipStream_t s) {
+  DevPlan* P = nullptr;
+  int rc = prepare_dev(c, q, g, codes, cb, n, N, hk, hc, hlen, flags, nullptr, false, &P);
+  if (rc) return rc;
+  void* base = static_scratch(c->device);
+  if (!base) return fail(c, HWC_ERR_DEVICE, "the static scratch of this device was not set up");
+  const ScratchSizes z = scratch_sizes(n, g, cb, needs_lv(P, flags, nullptr), hk != nullptr, needs_tcodes(P));
+  Scratch S;
+  const uint64_t need = carve_scratch(z, g, nullptr, &S);
+  if (need > kStaticScratchBytes)
+    return fail(c, HWC_ERR_ARG, "request needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                    std::to_string(kStaticScratchBytes));
+  carve_scratch(z, g, static_cast<uint8_t*>(base), &S);
+  if ((rc = enqueue(c, P, S, codes, cb, n, N, nullptr, hk, hc, hcap, hlen, flags, s, false))) return rc;
+  HIPX(c, hipEventRecord(c->static_ev, s));
+  c->static_ev_valid = true;
+  return HWC_OK;
+}
+
 // ---- several requests in one persistent launch ----
 
 struct BatchPlan {
@@ -1817,6 +1889,9 @@ int hwc_ctx_create(int device, uint64_t hbm_budget_bytes, hwc_ctx** out) {
       if ((e = hipEventCreateWithFlags(&st.ev, hipEventDisableTiming)) != hipSuccess)
         return create_fail(e, "hipEventCreate");
     if ((e = hipMemset(c->d_err, 0, 256)) != hipSuccess) return create_fail(e, "hipMemset");
+    if ((e = hipEventCreateWithFlags(&c->static_ev, hipEventDisableTiming)) != hipSuccess)
+      return create_fail(e, "hipEventCreate");
+    if ((e = setup_static_scratch(device)) != hipSuccess) return create_fail(e, "hipGetSymbolAddress(scratch)");
   }
   *out = c.release();
   return HWC_OK;
@@ -1828,6 +1903,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < kSets; ++k) wait_set(c, k);
+    if (c->static_ev_valid) (void)hipEventSynchronize(c->static_ev);
     drop_graphs(c);
     for (auto& kv : c->plans) free_plan(c, kv.second.get());
     (void)reap(c, true);
@@ -1852,6 +1928,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     for (auto& ev : c->prof)
       for (auto e : ev) (void)hipEventDestroy(e);
     for (auto e : c->event_pool) (void)hipEventDestroy(e);
+    if (c->static_ev) (void)hipEventDestroy(c->static_ev);
     (void)hipStreamDestroy(c->stream);
   }
   delete c;
@@ -1983,6 +2060,18 @@ int hwc_count_curves_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeff
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
   return run_dev(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity, d_hist_len,
                  flags, s);
+}
+
+int hwc_count_curves_dev_noalloc(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes,
+                                 uint64_t n, int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts,
+                                 uint64_t hist_capacity, uint64_t* d_hist_len, uint32_t flags, void* stream) {
+  if (!c) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (flags & HWC_VALIDATE) return fail(c, HWC_ERR_ARG, "HWC_VALIDATE needs host rows");
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
+  return run_dev_noalloc(c, q, g, d_coeffs, coeff_bytes, n, d_out_N, d_hist_keys, d_hist_counts, hist_capacity,
+                         d_hist_len, flags, s);
 }
 
 int hwc_count_lambda_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,

@@ -48,7 +48,10 @@ EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_fie
            "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate",
            "hwc_translate_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile",
            "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option",
-           "hwc_ctx_reserve")
+           "hwc_ctx_reserve", "hwc_count_curves_dev_noalloc")
+
+#: bytes of the static scratch array of hwc_count_curves_dev_noalloc (per GPU)
+HWC_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class HwcError(RuntimeError):
@@ -111,6 +114,7 @@ def load():
         "hwc_field_release": (None, [vp]),
         "hwc_count_curves": (i32, [vp, u32, u32, vp, u64, vp, ctypes.POINTER(hwc_hist), u32]),
         "hwc_count_curves_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, u64, vp, u32, vp]),
+        "hwc_count_curves_dev_noalloc": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, u64, vp, u32, vp]),
         "hwc_count_lambda_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp, vp, vp, u64, vp, u32, vp]),
         "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_single": (i32, [vp, u32, u32, vp, u32, vp, vp, u32]),
@@ -263,6 +267,18 @@ class Context:
         self._check(load().hwc_count_curves_dev(self._h, q, g, _ptr(d_coeffs), cb, n, _ptr(d_out_N),
                                                 _ptr(d_hist_keys), _ptr(d_hist_counts), cap, _ptr(d_hist_len),
                                                 flags, s))
+
+    def count_curves_dev_noalloc(self, q: int, g: int, d_coeffs, d_out_N, d_hist_keys=None, d_hist_counts=None,
+                                 d_hist_len=None, flags: int = 0, stream=None):
+        """hwc_count_curves_dev_noalloc: as count_curves_dev, allocating nothing
+        (the plan of (q, g) must be resident; scratch is the GPU's static array)."""
+        cb = d_coeffs.element_size()
+        n = d_coeffs.shape[0]
+        cap = 0 if d_hist_keys is None else d_hist_keys.shape[0]
+        s = None if stream is None else ctypes.c_void_p(int(stream.cuda_stream))
+        self._check(load().hwc_count_curves_dev_noalloc(self._h, q, g, _ptr(d_coeffs), cb, n, _ptr(d_out_N),
+                                                        _ptr(d_hist_keys), _ptr(d_hist_counts), cap,
+                                                        _ptr(d_hist_len), flags, s))
 
     def count_lambda_dev(self, q: int, g: int, d_coeffs, d_out_N, d_out_lambda, d_hist_keys=None,
                          d_hist_counts=None, d_hist_len=None, flags: int = 0, stream=None):
