@@ -46,6 +46,8 @@ MFMA_INT8_PEAK_OPS = 5.0e15   # dense int8 matrix-core peak
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_SUMMARY = {"zech": os.path.join(PROFILES, "count_kernel_g3_q13_2p24_hbm_traffic.md"),
                    "mfma": os.path.join(PROFILES, "vcount_kernel_g3_q13_2p24_hbm_traffic.md")}
+COUNTER_SUMMARY = {"zech": os.path.join(PROFILES, "count_kernel_g3_q13_2p24_counters.md"),
+                   "mfma": os.path.join(PROFILES, "vcount_kernel_g3_q13_2p24_counters.md")}
 KERNEL_SOURCES = {"zech": ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
                            "paper_1805_11991_amd/autotune/gfx950.json"),
                   "mfma": ("paper_1805_11991_amd/csrc/vcount.hip", "paper_1805_11991_amd/csrc/plan.h")}
@@ -138,11 +140,10 @@ def kernel_source_hash(path: str) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path: str) -> dict | None:
-    """HBM bytes per launch of the count kernel of `path` from the committed
-    counter summary; None when the kernel sources have changed since the
-    counters were taken (or there is no summary)."""
-    fn = TRAFFIC_SUMMARY[path]
+def summary_values(fn: str, path: str) -> dict | None:
+    """The `- key: value` lines of a committed profile summary; None when
+    the kernel sources of `path` have changed since the counters were taken
+    (or there is no summary)."""
     if not os.path.exists(fn):
         return None
     vals = {}
@@ -153,8 +154,31 @@ def measured_traffic(path: str) -> dict | None:
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("source_sha256_16") != kernel_source_hash(path):
         return None
+    return vals
+
+
+def measured_traffic(path: str) -> dict | None:
+    """HBM bytes per launch of the count kernel of `path` (copy-calibrated
+    FETCH_SIZE and WRITE_SIZE) and its algorithmic bytes, from the committed
+    traffic summary."""
+    vals = summary_values(TRAFFIC_SUMMARY[path], path)
     try:
-        return {"fetch": int(vals["fetch_bytes_per_launch"]), "write": int(vals["write_bytes_per_launch"])}
+        return {"fetch": int(vals["fetch_bytes_per_launch"]), "write": int(vals["write_bytes_per_launch"]),
+                "algorithmic": int(vals["algorithmic_bytes_per_launch"])}
+    except (KeyError, ValueError, TypeError):
+        return None
+
+
+def measured_counters(path: str) -> dict | None:
+    """Issue and LDS utilisation of the count kernel of `path` per CU and
+    clock, from the committed counter summary."""
+    vals = summary_values(COUNTER_SUMMARY[path], path)
+    if vals is None:
+        return None
+    keys = ("valu_insts_per_cu_clock", "salu_insts_per_cu_clock", "lds_active_frac", "lds_bank_conflict_frac",
+            "valu_per_lds_inst", "mfma_busy_frac")
+    try:
+        return {k: float(vals[k]) for k in keys}
     except (KeyError, ValueError):
         return None
 
@@ -358,6 +382,7 @@ def main():
     roofline["traffic"] = None if traffic is None else traffic["fetch"] + traffic["write"]
     roofline["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roofline["traffic_detail"] = traffic
+    roofline["counters"] = measured_counters(args.path)
     roofline["prep_ms"] = round(km["prep_ms"], 4)
     roofline["hist_ms"] = round(km["hist_ms"], 4)
     log(f"roofline: {roofline['kernel']} {km['count_ms']:.3f} ms, {roofline['achieved']} {roofline['unit']} "
@@ -394,6 +419,8 @@ def main():
         mroof = mfma_roofline(mctx, q, g, curves, mk["count_ms"], ceiling3)
         mtraffic = measured_traffic("mfma")
         mroof["traffic"] = None if mtraffic is None else mtraffic["fetch"] + mtraffic["write"]
+        mroof["traffic_detail"] = mtraffic
+        mroof["counters"] = measured_counters("mfma")
         mroof["kernel"] = "vcount_kernel<3,int8>"
         mp["g3_q13"] = {"curves": n, "batched": mb, "plain": mpl, "batched_vs_plain": ratio(mpl, mb),
                         "curves_per_s": round(n / (mb["ms_per_step"] * 1e-3), 1), "roofline": mroof,
