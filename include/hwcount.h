@@ -277,8 +277,10 @@ int hwc_ctx_profile_read(hwc_ctx* ctx, double* prep_ms, double* count_ms, double
 
 /* Launch and layout options of a context (the autotuner's search space).
  * Setting one drops the cached plans and graphs. */
-#define HWC_OPT_SPLIT 1         /* 1 (default): split evaluation over m-th roots of unity on LDS byte-unit
-                                   levels; 0: plain Horner at every x */
+#define HWC_OPT_SPLIT 1         /* 1 (default): split evaluation over the m-th roots of unity of F_q on
+                                   every level with at least HWC_OPT_SPLIT_MIN_M elements: m = 4 when
+                                   4 | q-1, else 3 on byte-unit levels when 3 | q-1, else 2; 0: plain
+                                   Horner at every x */
 #define HWC_OPT_BLOCK 2         /* threads per workgroup of the count kernel: 0 (auto), 256, 512, 1024 */
 #define HWC_OPT_WG_PER_CU 3     /* cap on workgroups per CU of the persistent grid; 0: occupancy limit */
 #define HWC_OPT_DEVICE_TABLES 4 /* bit mask over levels: bit j-1 set puts level j's Zech table in device

@@ -437,13 +437,13 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
   return 0;
 }
 
-// Split factor of a level: m = 4 when 4 | q-1, else (form A levels only) 3
-// when 3 | q-1, else 2; 0 when the level is not split.
+// Split factor of a level: m = 4 when 4 | q-1, else 3 when 3 | q-1 (form A
+// levels only), else 2; 0 when the level is not split.
 uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
   if (!T.split || M < T.split_min_m) return 0;
-  const uint32_t m = ((q - 1) % 4 == 0) ? 4u : (((q - 1) % 3 == 0) ? 3u : 2u);
-  if (form != hwc::kFormA && m != 4) return 0;   // forms C/D split over mu_4 only
-  return m;
+  if ((q - 1) % 4 == 0) return 4;
+  if (form == hwc::kFormA && (q - 1) % 3 == 0) return 3;
+  return 2;                                      // forms C/D: mu_4 or mu_2
 }
 
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;

@@ -749,9 +749,9 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
   return a;
 }
 
-// The four sub-polynomials of a sparse row on a form C/D level in one pass
+// The MS sub-polynomials of a sparse row on a form C/D level in one pass
 // (as horner_classes_a); not EXACT: a vanishing partial sum sets hit.
-template <int NC, bool EXACT, bool GLOBAL>
+template <int NC, int MS, bool EXACT, bool GLOBAL>
 __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* __restrict__ gtab,
                                                  const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
                                                  uint32_t Y, uint32_t (&a)[4], uint32_t (&pend)[4], bool& hit) {
@@ -761,7 +761,7 @@ __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* _
   for (int r = 0; r < 4; ++r) a[r] = 0;
 #pragma unroll
   for (int i = NC - 1; i >= 0; --i) {
-    const int r = i % 4;
+    const int r = i % MS;
     if ((uint32_t)i > d) continue;
     const bool present = (sup >> i) & 1u;
     if (st[r]) p[r] = addmod(p[r], Y, M);
@@ -840,8 +840,8 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
       }
     } else {
       uint32_t av[4], pv[4];
-      horner_classes_c<NC, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
-      if (__ballot(hit)) horner_classes_c<NC, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      horner_classes_c<NC, 4, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      if (__ballot(hit)) horner_classes_c<NC, 4, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
       a0 = av[0]; a1 = av[1]; a2 = av[2]; a3 = av[3];
       p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3];
     }
@@ -910,6 +910,80 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
   }
 }
 
+// Split over mu_2 = {1, -1} on a form C/D level (every odd q; used where 4
+// does not divide q - 1): f(x) = E(x^2) + x O(x^2), so the points x and -x
+// share the two sub-polynomial values at Y = x^2 and take one Zech addition
+// each, f(+-x) = E (1 + (+-x) O / E).  Byte units as sweep_split_c; a
+// vanishing E or O sends the wave through the zero-safe addition on
+// absolute logs, a vanishing point value is recounted exactly.
+template <int NC, bool FULL, int D, bool GLOBAL>
+__device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_t (&sdel_e)[NC], uint32_t d,
+                                               uint32_t mask, const SplitConst& Ke, LevelCounts& c) {
+  uint32_t sdel[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) sdel[i] = 2 * sdel_e[i];
+  SplitConst K = Ke;
+  K.ll[0] = 2 * Ke.ll[0];
+  K.ll[1] = 2 * Ke.ll[1];
+  const uint32_t M = 2 * L.M, tab = L.tab_off, h = M / 2;
+  const uint32_t* gtab = L.gtab;
+  const uint32_t K1 = M + submod(K.ll[1], K.ll[0], M);             // [M, 2M)
+  const uint32_t fix = ((K.ll[0] >> 1) ^ K.blane) & 1u;
+  const uint32_t sup = mask | (1u << d);
+  const uint32_t nt = L.nt;
+  const uint32_t* xt = L.xs_t;
+  uint32_t xnext = (xt && nt) ? sload(xt, 0) : 0u;
+  for (uint32_t it = 0; it < nt; ++it) {
+    const uint32_t x = 2 * xnext;
+    if (it + 1 < nt) xnext = xt ? sload(xt, it + 1) : it + 1;
+    const uint32_t Y = addmod(x, x, M);
+    uint32_t p0, p1, a0, a1;
+    bool hit = false;
+    if (FULL) {
+      a0 = horner_class_c<NC, 2, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+      a1 = horner_class_c<NC, 2, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      if (__ballot(hit)) {
+        a0 = horner_class_c<NC, 2, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+        a1 = horner_class_c<NC, 2, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      }
+    } else {
+      uint32_t av[4], pv[4];
+      horner_classes_c<NC, 2, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      if (__ballot(hit)) horner_classes_c<NC, 2, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      a0 = av[0]; a1 = av[1];
+      p0 = pv[0]; p1 = pv[1];
+    }
+    const uint32_t cls = FULL ? 0u : ((p0 >> 1) & 1u);
+    // log(x O / E) relative to the class logs: x + t_1 Y - t_0 Y
+    const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
+    uint32_t zs = 0, odd;
+    if (!__ballot((a0 == M) | (a1 == M))) {
+      // a1 < M, F1 < M and the power < M: every index stays under 3M
+      const uint32_t F1 = fold(K1 - a0, M);                            // [0, M)
+      const uint32_t rp = tab_c<GLOBAL>(tab, gtab, fold(a1 + F1 + vf, M));
+      const uint32_t rm = tab_c<GLOBAL>(tab, gtab, fold(a1 + F1 + addmod(vf, h, M), M));
+      uint32_t u = ((rp >> 1) & 1u) + ((rm >> 1) & 1u);
+      if (__ballot((rp == M) | (rm == M))) {
+        zs = (rp == M) + (rm == M);
+        u = (rp == M ? 0u : ((rp >> 1) & 1u)) + (rm == M ? 0u : ((rm >> 1) & 1u));
+      }
+      odd = (((a0 >> 1) ^ fix) & 1u) ? (2 - zs) - u : u;
+    } else {
+      const uint32_t v0 = zmul_c(a0, addmod(K.ll[0], p0, M), M);
+      const uint32_t v1 = zmul_c(a1, addmod(K.ll[1], p1, M), M);
+      odd = 0;
+#pragma unroll
+      for (uint32_t s = 0; s < 2; ++s) {
+        const uint32_t f = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v1, addmod(x, s * h, M), M));
+        const bool z = f == M;
+        zs += z;
+        odd += z ? 0u : (((f >> 1) ^ K.blane ^ cls) & 1u);
+      }
+    }
+    c.add_n(cls, 2, zs, odd);
+  }
+}
+
 // Counts for one level: returns z | ns << 8 (roots and non-squares among the
 // swept x; squares are nx - z - ns).
 template <int G>
@@ -948,7 +1022,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
   // split evaluation: needs every class to hold a term (forms C/D: m = 4)
   const uint32_t sup = mask | (1u << d);
   uint32_t ms = L.msplit;
-  if (L.form != kFormA && ms != 4) ms = 0;
+  if (L.form != kFormA && ms != 4 && ms != 2) ms = 0;
   if (ms) {
     uint32_t cls_mask = 0;
 #pragma unroll
@@ -1019,12 +1093,20 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
     L.tab_off = lb;
 #define HWC_FORM_C(GL)                                                                   \
   do {                                                                                   \
-    if (ms) {                                                                            \
+    if (ms == 4) {                                                                       \
       if (full) {                                                                        \
         if (top) sweep_split_c<NC, true, NC - 1, GL>(L, sdel, d, mask, K, c);            \
         else sweep_split_c<NC, true, NC - 2, GL>(L, sdel, d, mask, K, c);                \
       } else {                                                                           \
         sweep_split_c<NC, false, 0, GL>(L, sdel, d, mask, K, c);                         \
+      }                                                                                  \
+      sweep_form_c<NC, GL>(L, L.xs_s, L.ns, del, d, mask, c);                            \
+    } else if (ms == 2) {                                                                \
+      if (full) {                                                                        \
+        if (top) sweep_split2_c<NC, true, NC - 1, GL>(L, sdel, d, mask, K, c);           \
+        else sweep_split2_c<NC, true, NC - 2, GL>(L, sdel, d, mask, K, c);               \
+      } else {                                                                           \
+        sweep_split2_c<NC, false, 0, GL>(L, sdel, d, mask, K, c);                        \
       }                                                                                  \
       sweep_form_c<NC, GL>(L, L.xs_s, L.ns, del, d, mask, c);                            \
     } else {                                                                             \

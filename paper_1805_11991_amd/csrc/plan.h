@@ -46,7 +46,7 @@ struct LevelDesc {
   uint32_t weight;    // points of F_{q^j} each swept x stands for (orbit size, or 1)
   const uint32_t* xs; // x logs (device), nullptr: x runs over 0..M-1
   const uint32_t* gtab;  // form D: 2M entries in device memory
-  // split evaluation over mu_m cosets (form A levels): nt tuple
+  // split evaluation over mu_m cosets (m = 4, 3 or 2; forms C/D: 4 or 2): nt tuple
   // representatives (points L + s M/m, s < m) and ns single points; together
   // they are the same nx points.  msplit = 0 turns it off.
   uint32_t msplit, nt, ns;

@@ -112,6 +112,8 @@ def test_g4_q3_full_enumeration(gctx, oracle_mod, curvegen_mod):
     (169, 2, 60), (181, 2, 60),
     (3, 3, 500), (5, 3, 400), (7, 3, 300), (9, 3, 200), (11, 3, 200), (17, 3, 60), (25, 3, 30), (31, 3, 20),
     (5, 4, 150), (7, 4, 60), (9, 4, 40), (11, 4, 20),
+    # q = 3 mod 4 with top levels in element units or device memory: split over mu_2
+    (107, 2, 200), (179, 2, 100), (23, 3, 80), (27, 3, 60), (31, 3, 130), (43, 3, 8), (47, 3, 6), (11, 4, 300),
 ])
 def test_other_fields(gctx, mctx, oracle_mod, curvegen_mod, q, g, n):
     curves = curvegen_mod.sample(q, g, n, seed=4242 + q * 10 + g, dtype=np.int16)
@@ -422,7 +424,8 @@ def _run_option_set(oracle_mod, curvegen_mod, q, g, n, opts, seed, want_path):
         ctx.close()
 
 
-@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000)])
+@pytest.mark.parametrize("q,g,n", [(13, 3, 3000), (13, 4, 1500), (5, 4, 3000), (9, 3, 2000), (11, 3, 1500),
+                                   (7, 3, 2000)])
 @pytest.mark.parametrize("opts", range(len(ZECH_OPTION_SETS)))
 def test_zech_options_keep_results(oracle_mod, curvegen_mod, q, g, n, opts):
     """Every tunable of the Zech path (split and its threshold, device-memory
