@@ -249,14 +249,25 @@ int hwc_count_single(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs
  * best of two timed runs.  Synchronous. */
 int hwc_lds_gather_rate(hwc_ctx* ctx, uint32_t table_entries, uint32_t chains, double* lookups_per_s);
 
+/* Diagnostic: the rate of dependent random u32 gathers from a table of
+ * table_entries entries (64 .. 2^26) in device memory -- the placement of
+ * Zech tables too large for LDS (Sec. 3.2 tables read at random, served by
+ * L2 and the MALL) -- with `chains` (1, 2 or 4) independent chains per lane
+ * on a grid of 32 workgroups of 256 lanes per CU.  *lookups_per_s receives
+ * the best of two timed runs.  Uses the context's synchronous scratch for
+ * the table; synchronous. */
+int hwc_device_gather_rate(hwc_ctx* ctx, uint64_t table_entries, uint32_t chains, double* lookups_per_s);
+
 /* Several requests (each as hwc_count_curves_dev: N_k of Sec. 1.1 and the
  * histogram of eq. (1.2)) in the persistent batched form, enqueued on
- * `stream`: the rows of every Zech-path job are bucketed, then one
- * multi-plan launch pops tiles of all jobs (most expensive plans first, the
- * LDS image restaged when a workgroup moves to another plan) -- the loops
- * over the curves and fields of Algorithm 1 in one launch, where the paper
- * launches once per curve and field (Sec. 3.3); jobs on the opt-in
- * matrix-product path follow as their own launches on the same stream.
+ * `stream`: the rows of every Zech-path job are bucketed, then a persistent
+ * multi-plan launch takes the jobs one after another, most expensive tiles
+ * first, every wave popping tiles from the current job's queue (the LDS
+ * image restaged only when a workgroup moves to a job of another plan) --
+ * the loops over the curves and fields of Algorithm 1 in one launch, where
+ * the paper launches once per curve and field (Sec. 3.3); jobs on the
+ * opt-in matrix-product path follow as their own launches on the same
+ * stream.
  * Without HWC_NO_GRAPH the whole batch is captured once into a HIP graph
  * (keyed by the jobs' shapes and pointers) and replayed.  Errors as
  * hwc_count_curves_dev; a plan that cannot fit the HBM budget fails the

@@ -45,12 +45,9 @@ hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_
                          uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
                          uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
                          uint64_t max_tiles, hipStream_t s);
-hipError_t launch_batch(const JobDesc* jobs, const uint64_t* chunks, const uint32_t* nchunks, uint32_t* queue,
-                        uint32_t lds_bytes, uint32_t grid, uint32_t block, hipStream_t s);
-hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint32_t njobs, uint32_t per,
-                              uint32_t* chunk_start, uint64_t* chunks, uint64_t max_chunks, uint32_t* nchunks,
-                              uint32_t* queue, hipStream_t s);
-hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
+hipError_t launch_batch(const JobDesc* jobs, uint32_t njobs, uint32_t gmax, uint32_t lds_bytes, uint32_t grid,
+                        uint32_t block, hipStream_t s);
+hipError_t occupancy_batch(uint32_t gmax, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
 uint64_t hist_scratch_bytes(uint64_t n);
 hipError_t hist_run(const int32_t* N, const uint32_t* lam, uint64_t n, uint32_t g, uint32_t q, void* scratch,
                     int32_t* out_keys, uint64_t* out_counts, uint64_t cap, uint64_t* out_len, uint32_t* err,
@@ -62,6 +59,9 @@ hipError_t launch_gen_reps(int coeff_bytes, uint32_t q, uint32_t ncoef, uint32_t
                            hipStream_t s);
 hipError_t launch_single(const uint32_t* zech, const uint32_t* xs, uint64_t nx, const SingleDesc& f,
                          unsigned long long* out, hipStream_t s);
+hipError_t launch_dev_table_fill(uint32_t* tab, uint32_t entries, hipStream_t s);
+hipError_t launch_dev_gather(const uint32_t* tab, uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid,
+                             uint32_t* sink, hipStream_t s);
 hipError_t launch_lds_gather(uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid, uint32_t* sink,
                              hipStream_t s);
 }  // namespace hwc
@@ -197,7 +197,7 @@ constexpr int kJobSlots = 4;
 // chain and its event, once complete, means all of it is.
 struct ScratchSet {
   Buf pid, small, tiles, perm, lv, hist, tcodes;                     // one request
-  Buf bpid, bperm, btiles, bsmall, bchunks, bcstart, bwords, btcodes;   // multi-plan launches
+  Buf bpid, bperm, btiles, bsmall, btcodes;   // multi-plan launches
   JobSlot slots[kJobSlots];
   int next_slot = 0;
   hipStream_t last = nullptr;
@@ -852,10 +852,25 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   HIPX(c, hipMemcpy(P->d_desc, &D, sizeof(hwc::PlanDesc), hipMemcpyHostToDevice));
   P->dev_bytes += bytes;
   c->table_bytes += bytes;
-  // launch shape: many waves per CU; one large block when the tables fill LDS
-  P->block = T.block ? T.block : (D.image_bytes > 80 * 1024 ? 1024 : 256);
+  // launch shape: the block size that keeps the most waves resident per CU
+  // (the image limits the workgroups per CU through LDS, the kernel's
+  // registers limit the waves), the smaller block on a tie
   int bpc = 0;
   P->wpe = T.wpe ? T.wpe : 1;
+  if (T.block) {
+    P->block = T.block;
+  } else {
+    int best = -1;
+    for (uint32_t b : {256u, 512u, 1024u}) {
+      int n = 0;
+      HIPX(c, hwc::occupancy_count(g, 1, b, D.image_bytes, P->wpe, &n));
+      const int waves = n * (int)(b / hwc::kWave);
+      if (waves > best) {
+        best = waves;
+        P->block = b;
+      }
+    }
+  }
   HIPX(c, hwc::occupancy_count(g, 1, P->block, D.image_bytes, P->wpe, &bpc));
   if (bpc < 1) bpc = 1;
   if (T.wg_per_cu && (int)T.wg_per_cu < bpc) bpc = (int)T.wg_per_cu;
@@ -989,6 +1004,17 @@ int get_scratch(hwc_ctx* c, int set, uint64_t n, uint32_t g, int cb, bool plain,
   return HWC_OK;
 }
 
+// Workgroups of a persistent launch over about `tiles` tiles: at most the
+// resident grid, and no more than the tiles need, so that a small request's
+// tiles land one workgroup per CU (the dispatcher spreads workgroups over
+// the CUs) instead of on whichever waves win the queue first, which can put
+// several of them on one CU while others idle.
+uint32_t persistent_grid(uint32_t resident, uint32_t block, uint64_t tiles) {
+  const uint64_t per = std::max<uint32_t>(block / hwc::kWave, 1);
+  const uint64_t need = (tiles + per - 1) / per;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(resident, need));
+}
+
 // Enqueue the whole count of one request on stream s.
 int take_event(hwc_ctx* c, hipEvent_t* ev) {
   if (!c->event_pool.empty()) {
@@ -1057,8 +1083,11 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
                                   P->grid, P->block, P->wpe, s));
       HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
     } else {
+      // a tile per bucket's ragged end besides the full ones (translated rows
+      // fall in a few buckets; more tiles are still all counted)
+      const uint32_t grid = persistent_grid(P->grid, P->block, (n + hwc::kWave - 1) / hwc::kWave + 4);
       HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N,
-                                lam ? S.lv : nullptr, P->grid, P->block, P->wpe, s));
+                                lam ? S.lv : nullptr, grid, P->block, P->wpe, s));
     }
     if (lam) HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, (flags & kFlagSqf) ? 1u : 0u, s));
   }
@@ -1201,6 +1230,12 @@ int run_dev_noalloc(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int c
 
 // ---- several requests in one persistent launch ----
 
+// One persistent launch of a batch: sorted jobs [begin, end) and its shape.
+struct BatchSeg {
+  size_t begin = 0, end = 0;
+  uint32_t lds = 0, block = 256, grid = 0, gmax = 1;
+};
+
 struct BatchPlan {
   std::vector<size_t> order;        // Zech-path jobs, most expensive tiles first
   std::vector<size_t> vjobs;        // matrix-product jobs (input order), launched after the batch kernel
@@ -1208,9 +1243,10 @@ struct BatchPlan {
   std::vector<uint64_t> off, toff;  // row and tile offsets (sorted order)
   std::vector<uint64_t> max_tiles;
   std::vector<uint64_t> tco;        // byte offset of the job's dense translates, or kNoShift
-  uint64_t ntot = 0, tiles_tot = 0, chunks_max = 0, nhist = 0, tbytes = 0, nlv = 0;
-  uint32_t lds = 0, block = 256, grid = 0, per = 8, gmax = 1;
+  std::vector<BatchSeg> segs;       // launches over `order`
+  uint64_t ntot = 0, tiles_tot = 0, nhist = 0, tbytes = 0, nlv = 0;
 };
+
 
 constexpr uint64_t kNoShift = ~0ull;
 
@@ -1233,7 +1269,6 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, const BatchPlan& B, const hwc
     uint32_t* perm = static_cast<uint32_t*>(st.bperm.p);
     uint64_t* tiles = static_cast<uint64_t*>(st.btiles.p);
     uint32_t* small = static_cast<uint32_t*>(st.bsmall.p);
-    uint32_t* words = static_cast<uint32_t*>(st.bwords.p);
     for (size_t r = 0; r < nz; ++r) {
       const hwc_job& J = jobs[B.order[r]];
       const DevPlan* P = B.plans[B.order[r]];
@@ -1245,11 +1280,8 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, const BatchPlan& B, const hwc
                                  sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
                                  B.max_tiles[r], s));
     }
-    HIPX(c, hwc::launch_chunk_build(small + 8192, kSmallStride, (uint32_t)nz, B.per,
-                                    static_cast<uint32_t*>(st.bcstart.p), static_cast<uint64_t*>(st.bchunks.p),
-                                    B.chunks_max, words, words + 1, s));
-    HIPX(c, hwc::launch_batch(d_jobs, static_cast<uint64_t*>(st.bchunks.p), words, words + 1, B.lds, B.grid, B.block,
-                              s));
+    for (const BatchSeg& G : B.segs)
+      HIPX(c, hwc::launch_batch(d_jobs + G.begin, (uint32_t)(G.end - G.begin), G.gmax, G.lds, G.grid, G.block, s));
     for (size_t r = 0; r < nz; ++r) {
       const hwc_job& J = jobs[B.order[r]];
       if (!J.d_hist_keys) continue;
@@ -1323,25 +1355,35 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
   std::stable_sort(B.order.begin(), B.order.end(),
                    [&](size_t a, size_t b) { return B.plans[a]->tile_cost > B.plans[b]->tile_cost; });
   const size_t nz = B.order.size();
-  // launch shape of the multi-plan kernel: the block size of the plan with the
-  // most work (its tuned choice, or the automatic rule), at most one image of
-  // the largest plan per workgroup
-  double wmax = -1;
-  for (size_t r = 0; r < nz; ++r) {
-    const DevPlan* P = B.plans[B.order[r]];
-    B.lds = std::max(B.lds, P->desc.image_bytes);
-    const double w = P->tile_cost * (double)jobs[B.order[r]].n;
-    if (w > wmax) {
-      wmax = w;
-      B.block = P->block;
-    }
-  }
-  if (B.lds > 80 * 1024) B.block = 1024;   // one workgroup per CU: all of it
-  B.per = 2 * (B.block / hwc::kWave);
+  // one launch over every job: the workgroup holds the largest image, the
+  // kernel the largest genus, and the block size is the one that keeps the
+  // most waves resident (the smaller on a tie).  (One launch per LDS size
+  // class, so that small plans keep more workgroups per CU, measured slower
+  // on the 71 fields below 300: each launch costs at least one tile's
+  // latency, and the classes' tiles no longer share the CUs.)
   if (nz) {
-    int bpc = 0;
-    HIPX(c, hwc::occupancy_batch(B.block, B.lds, &bpc));
-    B.grid = (uint32_t)(c->cus * std::max(bpc, 1));
+    BatchSeg G;
+    G.begin = 0;
+    G.end = nz;
+    for (size_t r = 0; r < nz; ++r) {
+      const DevPlan* P = B.plans[B.order[r]];
+      G.lds = std::max(G.lds, P->desc.image_bytes);
+      G.gmax = std::max(G.gmax, P->g);
+    }
+    uint64_t tiles = 0;
+    for (size_t k = G.begin; k < G.end; ++k) tiles += (jobs[B.order[k]].n + hwc::kWave - 1) / hwc::kWave + 4;
+    int best = -1, bpc_best = 1;
+    for (uint32_t b : {256u, 512u, 1024u}) {
+      int n = 0;
+      HIPX(c, hwc::occupancy_batch(G.gmax, b, G.lds, &n));
+      if (n * (int)(b / hwc::kWave) > best) {
+        best = n * (int)(b / hwc::kWave);
+        G.block = b;
+        bpc_best = std::max(n, 1);
+      }
+    }
+    G.grid = persistent_grid((uint32_t)(c->cus * bpc_best), G.block, tiles);
+    B.segs.push_back(G);
   }
   for (size_t r = 0; r < nz; ++r) {
     const hwc_job& J = jobs[B.order[r]];
@@ -1357,7 +1399,6 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     } else {
       B.tco.push_back(kNoShift);
     }
-    B.chunks_max += mt / B.per + 1;
     if (J.d_hist_keys) B.nhist = std::max<uint64_t>(B.nhist, J.n);
   }
   if (nz) {
@@ -1365,9 +1406,6 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     if ((rc = ensure(c, set, st.bperm, std::max<uint64_t>(B.ntot, 1) * 4))) return rc;
     if ((rc = ensure(c, set, st.btiles, B.tiles_tot * 8))) return rc;
     if ((rc = ensure(c, set, st.bsmall, nz * kSmallStride * 4))) return rc;
-    if ((rc = ensure(c, set, st.bchunks, B.chunks_max * 8))) return rc;
-    if ((rc = ensure(c, set, st.bcstart, (nz + 1) * 4))) return rc;
-    if ((rc = ensure(c, set, st.bwords, 64))) return rc;
     if (B.tbytes && (rc = ensure(c, set, st.btcodes, B.tbytes))) return rc;
   }
   if (B.nhist && (rc = ensure(c, set, st.hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
@@ -1379,6 +1417,10 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     hj[r].codes = batch_rows(st, J, B, r);
     hj[r].perm = static_cast<uint32_t*>(st.bperm.p) + B.off[r];
     hj[r].tiles = static_cast<uint64_t*>(st.btiles.p) + B.toff[r];
+    // the bucketing of sorted job r writes its tile count and clears its queue
+    // in its words of the small scratch (launch_bucket in enqueue_batch)
+    hj[r].ntiles = static_cast<uint32_t*>(st.bsmall.p) + r * kSmallStride + 8192;
+    hj[r].queue = static_cast<uint32_t*>(st.bsmall.p) + r * kSmallStride + 8196;
     hj[r].outN = J.d_out_N;
     hj[r].cb = (uint32_t)J.coeff_bytes;
     hj[r].g = J.g;
@@ -1911,7 +1953,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
       if (b->p) (void)hipFree(b->p);
     for (auto& st : c->sets) {
       for (Buf* b : {&st.pid, &st.small, &st.tiles, &st.perm, &st.lv, &st.hist, &st.tcodes, &st.bpid, &st.bperm,
-                     &st.btiles, &st.bsmall, &st.bchunks, &st.bcstart, &st.bwords, &st.btcodes})
+                     &st.btiles, &st.bsmall, &st.btcodes})
         if (b->p) (void)hipFree(b->p);
       for (auto& sl : st.slots) {
         if (sl.p) (void)hipFree(sl.p);
@@ -2165,6 +2207,45 @@ int hwc_lds_gather_rate(hwc_ctx* c, uint32_t table_entries, uint32_t chains, dou
   return HWC_OK;
 }
 
+int hwc_device_gather_rate(hwc_ctx* c, uint64_t table_entries, uint32_t chains, double* lookups_per_s) {
+  if (!c || !lookups_per_s) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (c->device < 0) return fail(c, HWC_ERR_NO_DEVICE, "host-only context");
+  if (table_entries < 64 || table_entries > (1ull << 26)) return fail(c, HWC_ERR_ARG, "table size");
+  if (chains != 1 && chains != 2 && chains != 4) return fail(c, HWC_ERR_ARG, "chains must be 1, 2 or 4");
+  HIPX(c, hipSetDevice(c->device));
+  int rc;
+  if ((rc = ensure_sync(c, c->hout, 64))) return rc;
+  if ((rc = ensure_sync(c, c->N, table_entries * 4))) return rc;
+  int ncu = 0;
+  HIPX(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const uint32_t grid = (uint32_t)ncu * 32, steps = 256, n = (uint32_t)table_entries;
+  uint32_t* tab = static_cast<uint32_t*>(c->N.p);
+  uint32_t* sink = static_cast<uint32_t*>(c->hout.p);
+  HIPX(c, hwc::launch_dev_table_fill(tab, n, c->stream));
+  hipEvent_t e0, e1;
+  HIPX(c, hipEventCreate(&e0));
+  HIPX(c, hipEventCreate(&e1));
+  float best = 0;
+  for (int rep = 0; rep < 3; ++rep) {   // warm-up, then the best of two
+    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+        hwc::launch_dev_gather(tab, n, chains, steps, grid, sink, c->stream) != hipSuccess ||
+        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(c, HWC_ERR_DEVICE, "gather benchmark failed");
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0 && (best == 0 || ms < best)) best = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *lookups_per_s = (double)grid * 256.0 * steps * chains / (best * 1e-3);
+  return HWC_OK;
+}
+
 int hwc_count_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, void* stream) {
   if (!c || (njobs && !jobs)) return HWC_ERR_ARG;
   std::lock_guard<std::mutex> lk(c->mu);
@@ -2301,15 +2382,12 @@ int hwc_ctx_reserve(hwc_ctx* c, uint64_t max_curves, uint32_t max_jobs, void* st
   if ((rc = ensure(c, set, st.hist, z.hist))) return rc;
   if ((rc = ensure(c, set, st.tcodes, z.tcodes))) return rc;
   // a multi-plan batch of N rows over at most J jobs (run_batch's sizes, bounded
-  // with every job at the largest genus and the smallest chunk size of 8 tiles)
+  // with every job at the largest genus)
   const uint64_t tiles = N / hwc::kWave + J * (hwc::pattern_count(hwc::kMaxG) + 1);
   if ((rc = ensure(c, set, st.bpid, N * 2))) return rc;
   if ((rc = ensure(c, set, st.bperm, N * 4))) return rc;
   if ((rc = ensure(c, set, st.btiles, tiles * 8))) return rc;
   if ((rc = ensure(c, set, st.bsmall, J * kSmallStride * 4))) return rc;
-  if ((rc = ensure(c, set, st.bchunks, (tiles / 8 + J) * 8))) return rc;
-  if ((rc = ensure(c, set, st.bcstart, (J + 1) * 4))) return rc;
-  if ((rc = ensure(c, set, st.bwords, 64))) return rc;
   if ((rc = ensure(c, set, st.btcodes, N * (2 * hwc::kMaxG + 3) * 2 + J * 256))) return rc;
   const size_t jbytes = std::max<size_t>(J, 64) * sizeof(hwc::JobDesc);
   for (auto& sl : st.slots) {

@@ -6,6 +6,8 @@
 // pseudo-random entry, walked by CH independent dependent chains per lane on
 // every lane of a full grid.  The rate it reaches is the practical ceiling
 // the count kernel is compared against beside the HBM and MFMA peaks.
+// dev_gather_kernel does the same over a u32 table in device memory, the
+// placement of Zech tables too large for LDS.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -64,7 +66,62 @@ hipError_t launch_ch(uint32_t entries, uint32_t steps, uint32_t grid, uint32_t b
   return hipGetLastError();
 }
 
+// The same walk over a u32 table in device memory (the placement of Zech
+// tables too large for LDS, served by L2 and the MALL): entry i holds the
+// index of another pseudo-random entry.
+__global__ __launch_bounds__(256) void dev_table_fill_kernel(uint32_t* __restrict__ tab, uint32_t entries,
+                                                             uint32_t seed) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < entries; i += gridDim.x * blockDim.x)
+    tab[i] = mix32(i ^ seed) % entries;
+}
+
+template <int CH>
+__global__ __launch_bounds__(256) void dev_gather_kernel(const uint32_t* __restrict__ tab, uint32_t entries,
+                                                         uint32_t steps, uint32_t seed, uint32_t odd,
+                                                         uint32_t* __restrict__ sink) {
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t a[CH];
+#pragma unroll
+  for (int c = 0; c < CH; ++c) a[c] = mix32(gid * CH + c + seed) % entries;
+  for (uint32_t s = 0; s < steps; ++s) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c) a[c] = tab[a[c]];
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int c = 0; c < CH; ++c) x += a[c];
+  // x < CH * entries <= 2^28 < odd (never true), which the compiler cannot see
+  if (x == odd) sink[0] = gid;
+}
+
+template <int CH>
+hipError_t launch_dev_ch(const uint32_t* tab, uint32_t entries, uint32_t steps, uint32_t grid, uint32_t* sink,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(dev_gather_kernel<CH>, dim3(grid), dim3(256), 0, s, tab, entries, steps, 12345u, 0xFFFFFFFFu,
+                     sink);
+  return hipGetLastError();
+}
+
 }  // namespace
+
+// tab: `entries` u32 of device memory, entries in [64, 2^26]
+hipError_t launch_dev_table_fill(uint32_t* tab, uint32_t entries, hipStream_t s) {
+  if (entries < 64 || entries > (1u << 26)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dev_table_fill_kernel, dim3(1024), dim3(256), 0, s, tab, entries, 54321u);
+  return hipGetLastError();
+}
+
+// chains 1, 2 or 4 over the table filled by launch_dev_table_fill; sink: one device u32
+hipError_t launch_dev_gather(const uint32_t* tab, uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid,
+                             uint32_t* sink, hipStream_t s) {
+  if (entries < 64 || entries > (1u << 26) || grid == 0) return hipErrorInvalidValue;
+  switch (chains) {
+    case 1: return launch_dev_ch<1>(tab, entries, steps, grid, sink, s);
+    case 2: return launch_dev_ch<2>(tab, entries, steps, grid, sink, s);
+    case 4: return launch_dev_ch<4>(tab, entries, steps, grid, sink, s);
+    default: return hipErrorInvalidValue;
+  }
+}
 
 // entries in [64, kLdsImageLimit/2], chains 1, 2 or 4; sink: one device u32
 hipError_t launch_lds_gather(uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid, uint32_t* sink,

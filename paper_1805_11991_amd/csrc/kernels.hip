@@ -1245,19 +1245,27 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 }
 
 // ----------------------------------------------------------------------------
-// one persistent launch over several plans: workgroups pop chunks of tiles
-// of one job, restage LDS when the job's plan differs from the staged one.
+// one persistent launch over several plans: waves pop the tiles of one job
+// at a time; a workgroup restages LDS when the job's plan differs from the
+// staged one.
 
+// GMAX: the largest genus of the batch; the kernel holds the tile code of
+// every genus up to it only, so its register budget (and with it the waves a
+// CU keeps in flight, which latency-bound device-memory tables need) is that
+// of the batch's genera, not of g = 4.
+template <int GMAX>
 __device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, uint64_t w) {
   const PlanDesc& P = *J.plan;
-#define HWC_JOB(GG)                                                                                    \
-  case GG:                                                                                             \
-    if (J.cb == 1)                                                                                     \
-      process_tile<GG, int8_t>(P, lb, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
-                               nullptr);                                                               \
-    else                                                                                               \
-      process_tile<GG, int16_t>(P, lb, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
-                                J.outN, nullptr);                                                      \
+#define HWC_JOB(GG)                                                                                      \
+  case GG:                                                                                               \
+    if constexpr (GG <= GMAX) {                                                                          \
+      if (J.cb == 1)                                                                                     \
+        process_tile<GG, int8_t>(P, lb, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
+                                 nullptr);                                                               \
+      else                                                                                               \
+        process_tile<GG, int16_t>(P, lb, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
+                                  J.outN, nullptr);                                                      \
+    }                                                                                                    \
     break;
   switch (J.g) {
     HWC_JOB(1) HWC_JOB(2) HWC_JOB(3) HWC_JOB(4)
@@ -1266,95 +1274,46 @@ __device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, 
 #undef HWC_JOB
 }
 
-// slot: byte offset, past every image, of the word that broadcasts the
-// popped chunk to the workgroup (inside the dynamic block, so the kernel has
-// no static LDS)
-__global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__ jobs,
-                                                     const uint64_t* __restrict__ chunks,
-                                                     const uint32_t* __restrict__ nchunks_p, uint32_t* queue,
+// One persistent launch over the jobs of a batch, taken in the order given
+// (most expensive tiles first).  Every wave pops tiles of the current job from
+// the job's own queue and moves to the next job when that queue is empty; a
+// workgroup restages its LDS image only when the next job that still has
+// tiles uses another plan, and only there waits at barriers.  slot: byte
+// offset, past every image, of the word that broadcasts whether a job still
+// has tiles (inside the dynamic block, so the kernel has no static LDS).
+template <int GMAX>
+__global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__ jobs, uint32_t njobs,
                                                      uint32_t slot) {
   extern __shared__ uint32_t lds32[];
-  uint64_t& sh_chunk = *reinterpret_cast<uint64_t*>(reinterpret_cast<uint8_t*>(lds32) + slot);
+  uint32_t& sh_open = *reinterpret_cast<uint32_t*>(reinterpret_cast<uint8_t*>(lds32) + slot);
   constexpr uint32_t lb = kImageBase;
-  const uint32_t wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  const uint32_t nchunks = *nchunks_p;
+  const uint32_t lane = threadIdx.x & (kWave - 1);
   const PlanDesc* staged = nullptr;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t c = atomicAdd(queue, 1u);
-      sh_chunk = c < nchunks ? chunks[c] : ~0ull;
-    }
-    __syncthreads();
-    const uint64_t cw = sh_chunk;
-    if (cw == ~0ull) break;
-    const uint32_t job = (uint32_t)(cw & 0xFFFFu), cnt = (uint32_t)((cw >> 16) & 0xFFFFu);
-    const uint32_t t0 = (uint32_t)(cw >> 32);
-    const JobDesc& J = jobs[job];
+  for (uint32_t k = 0; k < njobs; ++k) {
+    const JobDesc& J = jobs[k];
+    const uint32_t nt = *J.ntiles;
     const PlanDesc* P = J.plan;
     if (P != staged) {
+      __syncthreads();   // every wave is done with the image staged so far
+      if (threadIdx.x == 0) sh_open = atomicAdd(J.queue, 0u) < nt ? 1u : 0u;
+      __syncthreads();
+      if (!sh_open) continue;   // nothing left here: no restaging
       const uint32_t* img = P->image;
       const uint32_t nwords = P->image_bytes / 4;
-      for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) lds32[i] = img[i];
+      for (uint32_t w = threadIdx.x; w < nwords; w += blockDim.x) lds32[w] = img[w];
       __syncthreads();
       staged = P;
     }
-    for (uint32_t t = t0 + wave; t < t0 + cnt; t += nw) process_job_tile(J, lb, sload64(J.tiles, t));
-    __syncthreads();
-  }
-}
-
-// chunks for a multi-plan launch: job j contributes ceil(ntiles_j / per)
-// chunks of `per` tiles; ntiles_j sits at ntiles_base[j * stride].  One block
-// scans the per-job chunk counts into chunk_start[0..njobs]; chunk_fill_kernel
-// then writes the chunk words.
-__global__ __launch_bounds__(1024) void chunk_scan_kernel(const uint32_t* __restrict__ ntiles_base, uint32_t stride,
-                                                          uint32_t njobs, uint32_t per,
-                                                          uint32_t* __restrict__ chunk_start,
-                                                          uint32_t* __restrict__ nchunks,
-                                                          uint32_t* __restrict__ queue) {
-  __shared__ uint32_t sh[1024];
-  const uint32_t t = threadIdx.x;
-  const uint32_t span = (njobs + blockDim.x - 1) / blockDim.x;
-  const uint32_t j0 = t * span;
-  uint32_t s = 0;
-  for (uint32_t j = j0; j < j0 + span && j < njobs; ++j) s += (ntiles_base[(uint64_t)j * stride] + per - 1) / per;
-  sh[t] = s;
-  __syncthreads();
-  for (uint32_t off = 1; off < blockDim.x; off <<= 1) {
-    const uint32_t v = t >= off ? sh[t - off] : 0u;
-    __syncthreads();
-    sh[t] += v;
-    __syncthreads();
-  }
-  uint32_t pos = sh[t] - s;
-  for (uint32_t j = j0; j < j0 + span && j < njobs; ++j) {
-    chunk_start[j] = pos;
-    pos += (ntiles_base[(uint64_t)j * stride] + per - 1) / per;
-  }
-  if (t == blockDim.x - 1) {
-    chunk_start[njobs] = sh[t];
-    *nchunks = sh[t];
-    *queue = 0;
-  }
-}
-
-__global__ void chunk_fill_kernel(const uint32_t* __restrict__ ntiles_base, uint32_t stride, uint32_t njobs,
-                                  uint32_t per, const uint32_t* __restrict__ chunk_start,
-                                  uint64_t* __restrict__ chunks) {
-  const uint32_t total = chunk_start[njobs];
-  for (uint32_t c = blockIdx.x * blockDim.x + threadIdx.x; c < total; c += gridDim.x * blockDim.x) {
-    uint32_t lo = 0, hi = njobs;  // last job with chunk_start <= c (it owns c)
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (chunk_start[mid] <= c) lo = mid; else hi = mid;
+    for (;;) {
+      uint32_t v = 0;
+      if (lane == 0) v = atomicAdd(J.queue, 1u);
+      const uint32_t t = uniform(v);
+      if (t >= nt) break;
+      process_job_tile<GMAX>(J, lb, sload64(J.tiles, t));
     }
-    const uint32_t nt = ntiles_base[(uint64_t)lo * stride];
-    const uint32_t f = (c - chunk_start[lo]) * per;
-    chunks[c] = chunk_pack(lo, f, nt - f < per ? nt - f : per);
   }
 }
 
-// assembly after per-level launches
 template <int G, typename CT>
 __global__ __launch_bounds__(256) void assemble_kernel(PlanDesc P, const CT* __restrict__ codes, uint64_t n,
                                                        const uint32_t* __restrict__ lv, int32_t* __restrict__ outN) {
@@ -1730,9 +1689,12 @@ hipError_t prepare_kernels() {
   if (e == hipSuccess) e = allow_big_lds<GG, int16_t>();
   HWC_PREP(1) HWC_PREP(2) HWC_PREP(3) HWC_PREP(4)
 #undef HWC_PREP
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kLdsImageLimit + 16);
+#define HWC_PREP_BATCH(GG)                                                                                  \
+  if (e == hipSuccess)                                                                                      \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(&batch_kernel<GG>),                                \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsImageLimit + 16);
+  HWC_PREP_BATCH(1) HWC_PREP_BATCH(2) HWC_PREP_BATCH(3) HWC_PREP_BATCH(4)
+#undef HWC_PREP_BATCH
   // the table image must start at LDS address 0: no static LDS in these kernels
   auto no_static = [&](const void* f) {
     hipFuncAttributes a{};
@@ -1746,7 +1708,10 @@ hipError_t prepare_kernels() {
   HWC_NOSTATIC(1, int8_t) HWC_NOSTATIC(2, int8_t) HWC_NOSTATIC(3, int8_t) HWC_NOSTATIC(4, int8_t)
   HWC_NOSTATIC(1, int16_t) HWC_NOSTATIC(2, int16_t) HWC_NOSTATIC(3, int16_t) HWC_NOSTATIC(4, int16_t)
 #undef HWC_NOSTATIC
-  no_static(reinterpret_cast<const void*>(&batch_kernel));
+  no_static(reinterpret_cast<const void*>(&batch_kernel<1>));
+  no_static(reinterpret_cast<const void*>(&batch_kernel<2>));
+  no_static(reinterpret_cast<const void*>(&batch_kernel<3>));
+  no_static(reinterpret_cast<const void*>(&batch_kernel<4>));
   return e;
 }
 
@@ -1778,27 +1743,28 @@ hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, 
 #undef HWC_CASE
 }
 
-hipError_t launch_batch(const JobDesc* jobs, const uint64_t* chunks, const uint32_t* nchunks, uint32_t* queue,
-                        uint32_t lds_bytes, uint32_t grid, uint32_t block, hipStream_t s) {
+hipError_t launch_batch(const JobDesc* jobs, uint32_t njobs, uint32_t gmax, uint32_t lds_bytes, uint32_t grid,
+                        uint32_t block, hipStream_t s) {
   const uint32_t slot = (lds_bytes + 15u) & ~15u;
-  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(block), slot + 16, s, jobs, chunks, nchunks, queue, slot);
+  switch (gmax) {
+    case 1: hipLaunchKernelGGL(batch_kernel<1>, dim3(grid), dim3(block), slot + 16, s, jobs, njobs, slot); break;
+    case 2: hipLaunchKernelGGL(batch_kernel<2>, dim3(grid), dim3(block), slot + 16, s, jobs, njobs, slot); break;
+    case 3: hipLaunchKernelGGL(batch_kernel<3>, dim3(grid), dim3(block), slot + 16, s, jobs, njobs, slot); break;
+    case 4: hipLaunchKernelGGL(batch_kernel<4>, dim3(grid), dim3(block), slot + 16, s, jobs, njobs, slot); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_build(const uint32_t* ntiles_base, uint32_t stride, uint32_t njobs, uint32_t per,
-                              uint32_t* chunk_start, uint64_t* chunks, uint64_t max_chunks, uint32_t* nchunks,
-                              uint32_t* queue, hipStream_t s) {
-  hipLaunchKernelGGL(chunk_scan_kernel, dim3(1), dim3(1024), 0, s, ntiles_base, stride, njobs, per, chunk_start,
-                     nchunks, queue);
-  const uint32_t grid = (uint32_t)((max_chunks + 255) / 256 < 4096 ? (max_chunks + 255) / 256 : 4096);
-  hipLaunchKernelGGL(chunk_fill_kernel, dim3(grid ? grid : 1), dim3(256), 0, s, ntiles_base, stride, njobs, per,
-                     chunk_start, chunks);
-  return hipGetLastError();
-}
-
-hipError_t occupancy_batch(uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel, block,
-                                                      ((lds_bytes + 15u) & ~15u) + 16);
+hipError_t occupancy_batch(uint32_t gmax, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu) {
+  const size_t lds = ((lds_bytes + 15u) & ~15u) + 16;
+  switch (gmax) {
+    case 1: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<1>, block, lds);
+    case 2: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<2>, block, lds);
+    case 3: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<3>, block, lds);
+    case 4: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, batch_kernel<4>, block, lds);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename CT, int WPE>

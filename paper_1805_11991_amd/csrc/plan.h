@@ -159,14 +159,11 @@ struct JobDesc {
   const void* codes;      // [n][2g+3] int8 or int16
   const uint32_t* perm;   // bucketed order of the job's rows
   const uint64_t* tiles;  // the job's tile words
+  const uint32_t* ntiles; // number of tile words (written by the bucketing)
+  uint32_t* queue;        // the job's tile queue (set to 0 by the bucketing)
   int32_t* outN;          // [n][g]
   uint32_t cb, g;         // code bytes, genus
 };
-
-// chunk word of a multi-plan launch: job | tile count << 16 | first tile << 32
-__host__ __device__ inline uint64_t chunk_pack(uint32_t job, uint32_t first, uint32_t count) {
-  return (uint64_t)job | ((uint64_t)count << 16) | ((uint64_t)first << 32);
-}
 
 // A tile is up to 64 curves that share degree and zero pattern.
 // word = pattern | (count-1) << 16 | start << 32

@@ -48,7 +48,7 @@ EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_fie
            "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate",
            "hwc_translate_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile",
            "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option",
-           "hwc_ctx_reserve", "hwc_count_curves_dev_noalloc")
+           "hwc_ctx_reserve", "hwc_count_curves_dev_noalloc", "hwc_device_gather_rate")
 
 #: bytes of the static scratch array of hwc_count_curves_dev_noalloc (per GPU)
 HWC_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -119,6 +119,7 @@ def load():
         "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_single": (i32, [vp, u32, u32, vp, u32, vp, vp, u32]),
         "hwc_lds_gather_rate": (i32, [vp, u32, u32, ctypes.POINTER(ctypes.c_double)]),
+        "hwc_device_gather_rate": (i32, [vp, u64, u32, ctypes.POINTER(ctypes.c_double)]),
         "hwc_translate_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
         "hwc_ctx_status": (i32, [vp, vp]),
@@ -333,6 +334,12 @@ class Context:
         """Measured dependent random u16 LDS gathers per second (diagnostic)."""
         r = ctypes.c_double()
         self._check(load().hwc_lds_gather_rate(self._h, table_entries, chains, ctypes.byref(r)))
+        return r.value
+
+    def device_gather_rate(self, table_entries: int, chains: int = 4) -> float:
+        """Measured dependent random u32 gathers per second from a device-memory table (diagnostic)."""
+        r = ctypes.c_double()
+        self._check(load().hwc_device_gather_rate(self._h, table_entries, chains, ctypes.byref(r)))
         return r.value
 
     def count_batch(self, jobs: list[dict], flags: int = 0, stream=None):
