@@ -19,6 +19,8 @@ Also measured in the same run, each as its own object of the JSON line:
                    (vector ALU and LDS-read fractions, unpadded pairs)
   cfg2_batched     g = 2 over all 71 odd prime powers q < 300, 2^16 curves each,
                    one multi-plan launch against per-q plain launches
+  g3_fields_batched g = 3 over all 18 odd prime powers q < 50, 2^16 curves each,
+                   one multi-plan launch against per-q plain launches
   cfg3_batched     g = 4 over q in {3, 5, 7, 9, 11, 13} (q = 3 fully enumerated,
                    2^26 curves for the others) in one launch, and per q
   serving          continuous batching of Poisson request streams of mixed (q, g)
@@ -561,6 +563,12 @@ def main():
         log(f"cfg2 (71 fields, g=2): batched {extra['cfg2_batched']['batched']['ms_per_step']} ms, plain "
             f"{extra['cfg2_batched']['plain']['ms_per_step']} ms")
         del specs2
+        qs3 = [x for x in range(3, 50) if odd_prime_power(x)]
+        specsg3 = [(x, 3, curvegen.sample(x, 3, 1 << 16, seed=curvegen.BASE_SEED + 1 + x)) for x in qs3]
+        extra["g3_fields_batched"] = multi(ctx, specsg3, 5, "g3 fields")
+        log(f"g=3, 18 fields q<50: batched {extra['g3_fields_batched']['batched']['ms_per_step']} ms, plain "
+            f"{extra['g3_fields_batched']['plain']['ms_per_step']} ms")
+        del specsg3
         specs3 = [(3, 4, curvegen.enumerate_all(3, 4))]
         for x in (5, 7, 9, 11, 13):
             specs3.append((x, 4, curvegen.sample(x, 4, 1 << 26, seed=curvegen.BASE_SEED + 3 + x)))

@@ -434,6 +434,7 @@ uint32_t align16(uint32_t v) { return (v + 15u) & ~15u; }
 uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
   if (form == hwc::kFormA) return align16((uint32_t)(10 * M));
   if (form == hwc::kFormC) return align16((uint32_t)(4 * M));
+  if (form == hwc::kFormE) return align16((uint32_t)(2 * M));
   return 0;
 }
 
@@ -446,16 +447,26 @@ uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
   return 2;                                      // forms C/D: mu_4 or mu_2
 }
 
-// Forms of the levels: A where 6M fits u16, C where M fits 15 bits, else D;
-// then move the largest LDS levels to D until the image fits.
+// Forms of the levels: A where 6M fits u16, C where M fits 15 bits, E where
+// M fits 16 bits, else D; one level at most in an element form (C or E: its
+// table starts the image), the others above it in D; then move the largest
+// LDS levels to D until the image fits.
 std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
   uint64_t Qj = 1;
+  bool element = false;
   for (uint32_t j = 0; j < g; ++j) {
     Qj *= q;
     M[j] = Qj - 1;
-    form[j] = M[j] <= hwc::kFormAMaxM ? hwc::kFormA : (M[j] <= hwc::kFormCMaxM ? hwc::kFormC : hwc::kFormD);
+    form[j] = M[j] <= hwc::kFormAMaxM   ? hwc::kFormA
+              : M[j] <= hwc::kFormCMaxM ? hwc::kFormC
+              : M[j] <= hwc::kFormEMaxM ? hwc::kFormE
+                                        : hwc::kFormD;
+    if (form[j] == hwc::kFormC || form[j] == hwc::kFormE) {
+      if (element) form[j] = hwc::kFormD;
+      element = true;
+    }
   }
   auto total = [&]() {
     uint64_t t = 0;
@@ -711,17 +722,24 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   hwc::PlanDesc& D = P->desc;
   D.q = q; D.p = p; D.g = g; D.ncoef = 2 * g + 3; D.orbit = orbit;
   std::vector<std::vector<uint32_t>> gtabs(g);
-  // forms C and D hold 2 Z (byte units) with the marker 2M over two periods;
-  // the (single) form C table goes first, at byte offset 0 of the image
+  // forms C and D hold 2 Z (byte units) with the marker 2M over two periods,
+  // form E one period of Z with the marker M; the (single) form C or E table
+  // goes first, at byte offset 0 of the image
   for (uint32_t j = 0; j < g; ++j) {
-    if (form[j] != hwc::kFormC) continue;
+    if (form[j] != hwc::kFormC && form[j] != hwc::kFormE) continue;
     const hwc::Field& F = P->fields[j]->F;
     const uint32_t M = (uint32_t)F.M;
     if (!img.empty()) return fail(c, HWC_ERR_DEVICE, "two LDS levels in element form");
-    std::vector<uint16_t> tab(2 * (size_t)M);
-    for (uint32_t i = 0; i < 2 * M; ++i) {
-      const uint32_t z = F.zech[i % M];
-      tab[i] = (uint16_t)(z == M ? 2 * M : 2 * z);
+    std::vector<uint16_t> tab;
+    if (form[j] == hwc::kFormC) {
+      tab.resize(2 * (size_t)M);
+      for (uint32_t i = 0; i < 2 * M; ++i) {
+        const uint32_t z = F.zech[i % M];
+        tab[i] = (uint16_t)(z == M ? 2 * M : 2 * z);
+      }
+    } else {
+      tab.resize(M);
+      for (uint32_t i = 0; i < M; ++i) tab[i] = (uint16_t)F.zech[i];   // Z(i) < M, or the marker M
     }
     D.lv[j].tab_off = put(tab);
   }
@@ -909,7 +927,8 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   // relative cost of one tile, for ordering mixed batches (longest first)
   P->tile_cost = 0;
   for (uint32_t j = 0; j < g; ++j)
-    P->tile_cost += (double)D.lv[j].nx * (2 * g + 2) * (form[j] == hwc::kFormA ? 1.0 : form[j] == hwc::kFormC ? 1.5 : 6.0);
+    P->tile_cost += (double)D.lv[j].nx * (2 * g + 2) *
+                    (form[j] == hwc::kFormA ? 1.0 : form[j] == hwc::kFormC ? 1.5 : form[j] == hwc::kFormE ? 2.0 : 6.0);
   P->last_use = ++c->tick;
   *out = P.get();
   c->plans[key] = std::move(P);

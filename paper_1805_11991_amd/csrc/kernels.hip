@@ -636,7 +636,25 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t
   }
 }
 
-// Forms C and D work in byte units like form A: every log, delta and power
+__device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v, v - M); }  // [0, 2M) -> [0, M)
+
+// Table modes of the element-unit levels: kTabC (form C: two periods of 2 Z in
+// LDS), kTabD (form D: the same as u32 in device memory), kTabE (form E: one
+// period of Z in LDS, u16 entries for M <= 65534).
+constexpr int kTabC = 0, kTabD = 1, kTabE = 2;
+
+// Table entry at byte offset r in [0, 2 M2) (M2 = 2 M, the byte period):
+// 2 Z((r/2) mod M), or the marker M2 where 1 + gamma^(r/2) = 0.  Form E folds
+// the offset into its one period and doubles the entry it reads (its marker M
+// becomes M2).
+template <int TM>
+__device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M2, uint32_t r) {
+  if (TM == kTabD) return gtab[r >> 1];
+  if (TM == kTabE) return 2u * lds_u16(tab + fold(r, M2));
+  return lds_u16(tab + r);
+}
+
+// Forms C, D and E work in byte units like form A: every log, delta and power
 // is doubled, the period is M2 = 2M and the zero marker is M2, so a folded
 // index is the byte offset of the entry (form C's table sits at the start of
 // the LDS image) and a log's parity is its bit 1.  In the functions below
@@ -646,7 +664,7 @@ __device__ __forceinline__ void sweep_split_a(const LevelDesc& L, const uint32_t
 // two periods; reads of both chains inside one uniform branch per position).
 // Not EXACT: a vanishing partial sum sets hit and the caller redoes the pair
 // with EXACT, which restarts from the coefficient.
-template <int NC, bool EXACT, bool GLOBAL>
+template <int NC, bool EXACT, int TM>
 __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M,
                                           const uint32_t (&del)[NC], uint32_t d, uint32_t mask, uint32_t x0,
                                           uint32_t x1, uint32_t& a0, uint32_t& a1, uint32_t& pend0, uint32_t& pend1,
@@ -661,8 +679,8 @@ __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restri
       if ((mask >> i) & 1u) {
         const uint32_t r0 = min(a0 + del[i] + p0, a0 + del[i] + p0 - M);   // < 2M
         const uint32_t r1 = min(a1 + del[i] + p1, a1 + del[i] + p1 - M);
-        const uint32_t v0 = GLOBAL ? gtab[r0 >> 1] : lds_u16(tab + r0);
-        const uint32_t v1 = GLOBAL ? gtab[r1 >> 1] : lds_u16(tab + r1);
+        const uint32_t v0 = tab_c<TM>(tab, gtab, M, r0);
+        const uint32_t v1 = tab_c<TM>(tab, gtab, M, r1);
         if (EXACT) {
           a0 = (a0 == M) ? 0u : v0;
           a1 = (a1 == M) ? 0u : v1;
@@ -679,7 +697,7 @@ __device__ __forceinline__ void horner_c2(uint32_t tab, const uint32_t* __restri
   pend1 = p1;
 }
 
-template <int NC, bool GLOBAL>
+template <int NC, int TM>
 __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t* xs, uint32_t nx,
                                              const uint32_t (&del)[NC], uint32_t d, uint32_t mask, LevelCounts& c) {
   const uint32_t M = 2 * L.M, tab = L.tab_off;
@@ -693,26 +711,18 @@ __device__ __forceinline__ void sweep_form_c(const LevelDesc& L, const uint32_t*
     const uint32_t x1 = two ? 2 * (xs ? sload(xs, ix + 1) : ix + 1) : x0;
     bool hit = false;
     uint32_t p0, p1, a0, a1;
-    horner_c2<NC, false, GLOBAL>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
-    if (__ballot(hit)) horner_c2<NC, true, GLOBAL>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
+    horner_c2<NC, false, TM>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
+    if (__ballot(hit)) horner_c2<NC, true, TM>(tab, gtab, M, delb, d, mask, x0, x1, a0, a1, p0, p1, hit);
     c.add((p0 >> 1) & 1u, a0 == M, (a0 >> 1) & 1u);   // bit 1 of the marker 2M is 0
     if (two) c.add((p1 >> 1) & 1u, a1 == M, (a1 >> 1) & 1u);
   }
 }
 
-// Form C/D table entry at byte offset r in [0, 2 M2): 2 Z((r/2) mod M), or the
-// marker M2 where 1 + gamma^(r/2) = 0.
-template <bool GLOBAL>
-__device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t r) {
-  return GLOBAL ? gtab[r >> 1] : lds_u16(tab + r);
-}
-
-__device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v, v - M); }  // [0, 2M) -> [0, M)
 
 // Sub-polynomial r of the split on a form C/D level (byte units): as
 // horner_class, with the index folded into the table's two periods.  Not
 // EXACT: a vanishing partial sum sets hit (the caller redoes the tuple).
-template <int NC, int MS, int R, bool FULL, int D, bool EXACT, bool GLOBAL>
+template <int NC, int MS, int R, bool FULL, int D, bool EXACT, int TM>
 __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t* __restrict__ gtab,
                                                    const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
                                                    uint32_t Y, uint32_t& pend, bool& hit) {
@@ -721,7 +731,7 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
     constexpr int TOP = D - ((D - R) % MS);
 #pragma unroll
     for (int i = TOP - MS; i >= 0; i -= MS) {
-      const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a + sdel[i] + Y, M));   // index < 3M
+      const uint32_t v = tab_c<TM>(tab, gtab, M, fold(a + sdel[i] + Y, M));   // index < 3M
       if (EXACT) a = (a == M) ? 0u : v;
       else { hit |= v == M; a = v; }
     }
@@ -737,7 +747,7 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
     if (started) p = addmod(p, Y, M);
     if ((sup >> i) & 1u) {
       if (started) {
-        const uint32_t v = tab_c<GLOBAL>(tab, gtab, fold(a + sdel[i] + p, M));
+        const uint32_t v = tab_c<TM>(tab, gtab, M, fold(a + sdel[i] + p, M));
         if (EXACT) a = (a == M) ? 0u : v;
         else { hit |= v == M; a = v; }
       }
@@ -751,7 +761,7 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
 
 // The MS sub-polynomials of a sparse row on a form C/D level in one pass
 // (as horner_classes_a); not EXACT: a vanishing partial sum sets hit.
-template <int NC, int MS, bool EXACT, bool GLOBAL>
+template <int NC, int MS, bool EXACT, int TM>
 __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* __restrict__ gtab,
                                                  const uint32_t (&sdel)[NC], uint32_t M, uint32_t d, uint32_t sup,
                                                  uint32_t Y, uint32_t (&a)[4], uint32_t (&pend)[4], bool& hit) {
@@ -767,7 +777,7 @@ __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* _
     if (st[r]) p[r] = addmod(p[r], Y, M);
     const bool go = present && st[r];
     // a position that does not step reads entry 0 on every lane (a broadcast)
-    const uint32_t v = tab_c<GLOBAL>(tab, gtab, go ? fold(a[r] + sdel[i] + p[r], M) : 0u);
+    const uint32_t v = tab_c<TM>(tab, gtab, M, go ? fold(a[r] + sdel[i] + p[r], M) : 0u);
     if (EXACT) a[r] = go ? ((a[r] == M) ? 0u : v) : a[r];
     else {
       hit |= go && v == M;
@@ -783,13 +793,13 @@ __device__ __forceinline__ void horner_classes_c(uint32_t tab, const uint32_t* _
 }
 
 // Zero-safe sum (absolute logs in [0, M) or the zero marker M, byte units).
-template <bool GLOBAL>
+template <int TM>
 __device__ __forceinline__ uint32_t zadd_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M, uint32_t u,
                                            uint32_t v) {
   const bool uz = u == M, vz = v == M;
   uint32_t dd = v - u;
   dd = min(dd, dd + M);
-  const uint32_t r = tab_c<GLOBAL>(tab, gtab, (uz || vz) ? 0u : dd);
+  const uint32_t r = tab_c<TM>(tab, gtab, M, (uz || vz) ? 0u : dd);
   const uint32_t s = fold(u + r, M);
   return uz ? v : (vz ? u : (r == M ? M : s));
 }
@@ -800,7 +810,7 @@ __device__ __forceinline__ uint32_t zmul_c(uint32_t v, uint32_t k, uint32_t M) {
 
 // Radix-2x2 split over mu_4 cosets on a form C/D level: the same stages as the
 // MS = 4 case of sweep_split_a (byte units, K.ll doubled by the caller).
-template <int NC, bool FULL, int D, bool GLOBAL>
+template <int NC, bool FULL, int D, int TM>
 __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t (&sdel_e)[NC], uint32_t d,
                                               uint32_t mask, const SplitConst& Ke, LevelCounts& c) {
   uint32_t sdel[NC];
@@ -828,20 +838,20 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
     uint32_t a0, a1, a2, a3;
     bool hit = false;
     if (FULL) {
-      a0 = horner_class_c<NC, 4, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-      a1 = horner_class_c<NC, 4, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
-      a2 = horner_class_c<NC, 4, 2, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
-      a3 = horner_class_c<NC, 4, 3, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+      a0 = horner_class_c<NC, 4, 0, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+      a1 = horner_class_c<NC, 4, 1, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      a2 = horner_class_c<NC, 4, 2, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+      a3 = horner_class_c<NC, 4, 3, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
       if (__ballot(hit)) {
-        a0 = horner_class_c<NC, 4, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-        a1 = horner_class_c<NC, 4, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
-        a2 = horner_class_c<NC, 4, 2, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
-        a3 = horner_class_c<NC, 4, 3, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
+        a0 = horner_class_c<NC, 4, 0, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+        a1 = horner_class_c<NC, 4, 1, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+        a2 = horner_class_c<NC, 4, 2, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p2, hit);
+        a3 = horner_class_c<NC, 4, 3, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p3, hit);
       }
     } else {
       uint32_t av[4], pv[4];
-      horner_classes_c<NC, 4, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
-      if (__ballot(hit)) horner_classes_c<NC, 4, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      horner_classes_c<NC, 4, false, TM>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      if (__ballot(hit)) horner_classes_c<NC, 4, true, TM>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
       a0 = av[0]; a1 = av[1]; a2 = av[2]; a3 = av[3];
       p0 = pv[0]; p1 = pv[1]; p2 = pv[2]; p3 = pv[3];
     }
@@ -855,10 +865,10 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
     // recomputation, which keeps the common path free of selects.
     const bool rare = (a0 == M) | (a1 == M) | (a2 == M) | (a3 == M);
     const uint32_t FE = fold(K2 - a0, M), FO = fold(K3 - a1, M);    // [0, M)
-    const uint32_t Ep = tab_c<GLOBAL>(tab, gtab, fold(a2 + FE + uE, M));
-    const uint32_t Em = tab_c<GLOBAL>(tab, gtab, fold(a2 + FE + addmod(uE, h, M), M));
-    const uint32_t Op = tab_c<GLOBAL>(tab, gtab, fold(a3 + FO + uO, M));
-    const uint32_t Om = tab_c<GLOBAL>(tab, gtab, fold(a3 + FO + addmod(uO, h, M), M));
+    const uint32_t Ep = tab_c<TM>(tab, gtab, M, fold(a2 + FE + uE, M));
+    const uint32_t Em = tab_c<TM>(tab, gtab, M, fold(a2 + FE + addmod(uE, h, M), M));
+    const uint32_t Op = tab_c<TM>(tab, gtab, M, fold(a3 + FO + uO, M));
+    const uint32_t Om = tab_c<TM>(tab, gtab, M, fold(a3 + FO + addmod(uO, h, M), M));
     uint32_t zs = 0, odd;
     if (!__ballot(rare | (Ep == M) | (Em == M) | (Op == M) | (Om == M))) {
       const uint32_t G = fold(fold(a1 + K1 - a0, M), M) + M;       // [M, 2M)
@@ -871,7 +881,7 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
         const uint32_t E = (s & 1u) ? Em : Ep;
         const uint32_t O = (s & 1u) ? Om : Op;
         const uint32_t F = (s & 1u) ? Fm : Fp;
-        r[s] = tab_c<GLOBAL>(tab, gtab, fold(O + F + addmod(vf, s * step, M), M));
+        r[s] = tab_c<TM>(tab, gtab, M, fold(O + F + addmod(vf, s * step, M), M));
         u += ((E ^ r[s]) >> 1) & 1u;
         anyz |= r[s] == M;
       }
@@ -891,16 +901,16 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
       const uint32_t v1 = zmul_c(a1, addmod(K.ll[1], p1, M), M);
       const uint32_t v2 = zmul_c(a2, addmod(K.ll[2], p2, M), M);
       const uint32_t v3 = zmul_c(a3, addmod(K.ll[3], p3, M), M);
-      const uint32_t ep = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v2, x2, M));
-      const uint32_t em = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v2, addmod(x2, h, M), M));
-      const uint32_t op = zadd_c<GLOBAL>(tab, gtab, M, v1, zmul_c(v3, x2, M));
-      const uint32_t om = zadd_c<GLOBAL>(tab, gtab, M, v1, zmul_c(v3, addmod(x2, h, M), M));
+      const uint32_t ep = zadd_c<TM>(tab, gtab, M, v0, zmul_c(v2, x2, M));
+      const uint32_t em = zadd_c<TM>(tab, gtab, M, v0, zmul_c(v2, addmod(x2, h, M), M));
+      const uint32_t op = zadd_c<TM>(tab, gtab, M, v1, zmul_c(v3, x2, M));
+      const uint32_t om = zadd_c<TM>(tab, gtab, M, v1, zmul_c(v3, addmod(x2, h, M), M));
       odd = 0;
 #pragma unroll
       for (uint32_t s = 0; s < 4; ++s) {
         const uint32_t E = (s & 1u) ? em : ep;
         const uint32_t O = (s & 1u) ? om : op;
-        const uint32_t f = zadd_c<GLOBAL>(tab, gtab, M, E, zmul_c(O, addmod(x, s * step, M), M));
+        const uint32_t f = zadd_c<TM>(tab, gtab, M, E, zmul_c(O, addmod(x, s * step, M), M));
         const bool z = f == M;
         zs += z;
         odd += z ? 0u : (((f >> 1) ^ K.blane ^ cls) & 1u);
@@ -916,7 +926,7 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
 // each, f(+-x) = E (1 + (+-x) O / E).  Byte units as sweep_split_c; a
 // vanishing E or O sends the wave through the zero-safe addition on
 // absolute logs, a vanishing point value is recounted exactly.
-template <int NC, bool FULL, int D, bool GLOBAL>
+template <int NC, bool FULL, int D, int TM>
 __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_t (&sdel_e)[NC], uint32_t d,
                                                uint32_t mask, const SplitConst& Ke, LevelCounts& c) {
   uint32_t sdel[NC];
@@ -940,16 +950,16 @@ __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_
     uint32_t p0, p1, a0, a1;
     bool hit = false;
     if (FULL) {
-      a0 = horner_class_c<NC, 2, 0, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-      a1 = horner_class_c<NC, 2, 1, FULL, D, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+      a0 = horner_class_c<NC, 2, 0, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+      a1 = horner_class_c<NC, 2, 1, FULL, D, false, TM>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
       if (__ballot(hit)) {
-        a0 = horner_class_c<NC, 2, 0, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
-        a1 = horner_class_c<NC, 2, 1, FULL, D, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
+        a0 = horner_class_c<NC, 2, 0, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p0, hit);
+        a1 = horner_class_c<NC, 2, 1, FULL, D, true, TM>(tab, gtab, sdel, M, d, sup, Y, p1, hit);
       }
     } else {
       uint32_t av[4], pv[4];
-      horner_classes_c<NC, 2, false, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
-      if (__ballot(hit)) horner_classes_c<NC, 2, true, GLOBAL>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      horner_classes_c<NC, 2, false, TM>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
+      if (__ballot(hit)) horner_classes_c<NC, 2, true, TM>(tab, gtab, sdel, M, d, sup, Y, av, pv, hit);
       a0 = av[0]; a1 = av[1];
       p0 = pv[0]; p1 = pv[1];
     }
@@ -960,8 +970,8 @@ __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_
     if (!__ballot((a0 == M) | (a1 == M))) {
       // a1 < M, F1 < M and the power < M: every index stays under 3M
       const uint32_t F1 = fold(K1 - a0, M);                            // [0, M)
-      const uint32_t rp = tab_c<GLOBAL>(tab, gtab, fold(a1 + F1 + vf, M));
-      const uint32_t rm = tab_c<GLOBAL>(tab, gtab, fold(a1 + F1 + addmod(vf, h, M), M));
+      const uint32_t rp = tab_c<TM>(tab, gtab, M, fold(a1 + F1 + vf, M));
+      const uint32_t rm = tab_c<TM>(tab, gtab, M, fold(a1 + F1 + addmod(vf, h, M), M));
       uint32_t u = ((rp >> 1) & 1u) + ((rm >> 1) & 1u);
       if (__ballot((rp == M) | (rm == M))) {
         zs = (rp == M) + (rm == M);
@@ -974,7 +984,7 @@ __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_
       odd = 0;
 #pragma unroll
       for (uint32_t s = 0; s < 2; ++s) {
-        const uint32_t f = zadd_c<GLOBAL>(tab, gtab, M, v0, zmul_c(v1, addmod(x, s * h, M), M));
+        const uint32_t f = zadd_c<TM>(tab, gtab, M, v0, zmul_c(v1, addmod(x, s * h, M), M));
         const bool z = f == M;
         zs += z;
         odd += z ? 0u : (((f >> 1) ^ K.blane ^ cls) & 1u);
@@ -1089,7 +1099,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
       }
     }
   } else {
-    // byte units; form C's table starts the LDS image
+    // byte units; a form C or E table starts the LDS image
     L.tab_off = lb;
 #define HWC_FORM_C(GL)                                                                   \
   do {                                                                                   \
@@ -1113,8 +1123,9 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
       sweep_form_c<NC, GL>(L, L.xs, L.nx, del, d, mask, c);                              \
     }                                                                                    \
   } while (0)
-    if (L.form == kFormC) HWC_FORM_C(false);
-    else HWC_FORM_C(true);
+    if (L.form == kFormC) HWC_FORM_C(kTabC);
+    else if (L.form == kFormE) HWC_FORM_C(kTabE);
+    else HWC_FORM_C(kTabD);
 #undef HWC_FORM_C
   }
   const uint32_t n0 = L.nx - c.n1;

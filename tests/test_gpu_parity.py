@@ -247,6 +247,7 @@ def test_graph_replays_match_eager(gctx, curvegen_mod):
         Nrep.fill_(-1)
         hk.fill_(-1)
         hc.fill_(0)
+        torch.cuda.synchronize()   # the fills ran on torch's stream, the count runs on the context's
         gctx.count_curves_dev(13, 3, d, Nrep, hk, hc, hl)
         torch.cuda.synchronize()
         _ = (d.float().sum() * 2).item()      # unrelated eager work between replays
@@ -295,12 +296,34 @@ def test_full_size_g3_q13(gctx, mctx, oracle_mod, curvegen_mod):
     assert int(cref.sum()) == n
 
 
-@pytest.mark.parametrize("q,g,n", [(191, 2, 30), (211, 2, 24), (293, 2, 16), (37, 3, 6), (41, 3, 5), (43, 3, 4),
-                                   (49, 3, 3)])
+@pytest.mark.parametrize("q,g,n", [(191, 2, 30), (211, 2, 24), (257, 2, 16), (263, 2, 16), (293, 2, 16), (37, 3, 6),
+                                   (41, 3, 5), (43, 3, 4), (49, 3, 3)])
 def test_device_memory_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
-    # q^g - 1 > 32767: the top level's Zech table stays in device memory (form D)
+    # q^g - 1 > 65534: the top level's Zech table stays in device memory (form D);
+    # 32767 < q^g - 1 <= 65534: one period of u16 entries in LDS (form E)
     curves = curvegen_mod.sample(q, g, n, seed=777 + q, dtype=np.int16)
+    top = gctx.plan_info(q, g)[-1]
+    assert top["form"] == (3 if q ** g - 1 <= 65534 else 2), top
     _check(gctx, oracle_mod, q, g, curves)
+
+
+@pytest.mark.parametrize("q,g,n", [(191, 2, 40), (227, 2, 30), (241, 2, 30), (251, 2, 30), (37, 3, 8)])
+def test_one_period_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
+    """Top levels of 32 768 .. 65 534 nonzero elements: one period of u16 Zech
+    entries in LDS (form E), split over mu_4 (241, 37) or mu_2 (191, 227, 251),
+    on seeded rows and on rows with zero coefficients (the masked path), every
+    launch form against the oracle."""
+    assert gctx.plan_info(q, g)[-1]["form"] == 3
+    curves = curvegen_mod.sample(q, g, n, seed=778 + q, dtype=np.int16)
+    sparse = curves.copy()
+    for i in range(len(sparse)):           # zero one or two coefficients below the leading one
+        top = 2 * g + 2 if sparse[i, 2 * g + 2] else 2 * g + 1
+        for k in ((i % top), ((3 * i + 1) % top))[: 1 + i % 2]:
+            sparse[i, k] = 0
+    # a zeroed row need not stay square-free: the library and the oracle
+    # evaluate the same character sums on any row of that degree
+    _check(gctx, oracle_mod, q, g, curves)
+    _check(gctx, oracle_mod, q, g, sparse)
 
 
 def _batch_specs(curvegen_mod):
@@ -339,6 +362,7 @@ def test_multi_plan_batch(gctx, oracle_mod, curvegen_mod):
         for j in jobs:
             j["d_out_N"].fill_(-1)
             j["d_hist_len"].fill_(-1)
+        torch.cuda.synchronize()   # the fills ran on torch's stream, the batch runs on the context's
         gctx.count_batch(jobs, flags=flags)
         gctx.status()
         for (q, g, c), j, ref in zip(specs, jobs, refs):
