@@ -37,11 +37,12 @@
  * owns its tables and scratch memory.  Functions return HWC_OK (0) or a
  * negative HWC_ERR_* code; hwc_last_error() gives a message.  Calls on one
  * context are serialised internally.  Supported: 1 <= g <= 4, odd prime
- * powers q with q^g <= 2^24 and q <= 32768.  Level tables of up to 65534
+ * powers q with q^g <= 2^24 and q <= 32768.  Level tables of up to 131070
  * nonzero elements are staged in the 160 KiB LDS of a CU (e.g. q = 13 at
- * g = 4, q = 37 at g = 3, q = 251 at g = 2); larger levels (q = 257 .. 293
- * at g = 2, q = 41 .. 49 at g = 3) keep their Zech tables in device memory,
- * served by L2 and the MALL.  Histogram keys must fit 63 bits.
+ * g = 4, q = 49 at g = 3, q = 293 at g = 2; the largest as half tables, the
+ * rest following from the symmetry of the Zech logarithm); larger levels
+ * keep their Zech tables in device memory, served by L2 and the MALL.
+ * Histogram keys must fit 63 bits.
  */
 #ifndef HWCOUNT_H
 #define HWCOUNT_H
@@ -319,7 +320,8 @@ int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags
  * and cached if needed): per level j = 1..g, levels[j-1] receives the order
  * M of F_{q^j}^x, the table form (0: u16 in LDS, byte units; 1: u16 in LDS,
  * folded index over two periods; 2: u32 in device memory; 3: u16 in LDS, one
- * period, for M up to 65534), the number nx of swept x, the
+ * period, for M up to 65534; 4: half a period of 17-bit entries in LDS, for M
+ * up to 131070), the number nx of swept x, the
  * weight of each, the split factor m (0: plain Horner; else the sweep runs nt
  * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
  * x^m, plus ns single points), the LDS bytes of the plan, and mfma = 1 when

@@ -435,6 +435,10 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
   if (form == hwc::kFormA) return align16((uint32_t)(10 * M));
   if (form == hwc::kFormC) return align16((uint32_t)(4 * M));
   if (form == hwc::kFormE) return align16((uint32_t)(2 * M));
+  if (form == hwc::kFormF) {
+    const uint64_t h1 = M / 2 + 1;   // entries of the half table
+    return align16((uint32_t)(2 * h1)) + align16((uint32_t)(4 * ((h1 + 31) / 32)));
+  }
   return 0;
 }
 
@@ -448,9 +452,9 @@ uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
 }
 
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, E where
-// M fits 16 bits, else D; one level at most in an element form (C or E: its
-// table starts the image), the others above it in D; then move the largest
-// LDS levels to D until the image fits.
+// M fits 16 bits, F where it fits 17 bits, else D; one level at most in an
+// element form (C, E or F: its table starts the image), the others above it
+// in D; then move the largest LDS levels to D until the image fits.
 std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
@@ -462,8 +466,9 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask)
     form[j] = M[j] <= hwc::kFormAMaxM   ? hwc::kFormA
               : M[j] <= hwc::kFormCMaxM ? hwc::kFormC
               : M[j] <= hwc::kFormEMaxM ? hwc::kFormE
+              : M[j] <= hwc::kFormFMaxM ? hwc::kFormF
                                         : hwc::kFormD;
-    if (form[j] == hwc::kFormC || form[j] == hwc::kFormE) {
+    if (form[j] == hwc::kFormC || form[j] == hwc::kFormE || form[j] == hwc::kFormF) {
       if (element) form[j] = hwc::kFormD;
       element = true;
     }
@@ -726,7 +731,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   // form E one period of Z with the marker M; the (single) form C or E table
   // goes first, at byte offset 0 of the image
   for (uint32_t j = 0; j < g; ++j) {
-    if (form[j] != hwc::kFormC && form[j] != hwc::kFormE) continue;
+    if (form[j] != hwc::kFormC && form[j] != hwc::kFormE && form[j] != hwc::kFormF) continue;
     const hwc::Field& F = P->fields[j]->F;
     const uint32_t M = (uint32_t)F.M;
     if (!img.empty()) return fail(c, HWC_ERR_DEVICE, "two LDS levels in element form");
@@ -737,9 +742,24 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
         const uint32_t z = F.zech[i % M];
         tab[i] = (uint16_t)(z == M ? 2 * M : 2 * z);
       }
-    } else {
+    } else if (form[j] == hwc::kFormE) {
       tab.resize(M);
       for (uint32_t i = 0; i < M; ++i) tab[i] = (uint16_t)F.zech[i];   // Z(i) < M, or the marker M
+    } else {
+      // low halves of Z(0..M/2) (17-bit values, the marker M at M/2), padded
+      // to 16 bytes, then the 17th bits as u32 words (little-endian halves)
+      const uint32_t h1 = M / 2 + 1;
+      tab.assign(((size_t)h1 + 7) / 8 * 8, 0);
+      std::vector<uint32_t> bits(((size_t)h1 + 31) / 32, 0);
+      for (uint32_t i = 0; i < h1; ++i) {
+        const uint32_t z = F.zech[i];
+        tab[i] = (uint16_t)(z & 0xFFFFu);
+        bits[i >> 5] |= ((z >> 16) & 1u) << (i & 31);
+      }
+      for (uint32_t w : bits) {
+        tab.push_back((uint16_t)(w & 0xFFFFu));
+        tab.push_back((uint16_t)(w >> 16));
+      }
     }
     D.lv[j].tab_off = put(tab);
   }
@@ -928,7 +948,11 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   P->tile_cost = 0;
   for (uint32_t j = 0; j < g; ++j)
     P->tile_cost += (double)D.lv[j].nx * (2 * g + 2) *
-                    (form[j] == hwc::kFormA ? 1.0 : form[j] == hwc::kFormC ? 1.5 : form[j] == hwc::kFormE ? 2.0 : 6.0);
+                    (form[j] == hwc::kFormA   ? 1.0
+                     : form[j] == hwc::kFormC ? 1.5
+                     : form[j] == hwc::kFormE ? 2.0
+                     : form[j] == hwc::kFormF ? 3.0
+                                              : 6.0);
   P->last_use = ++c->tick;
   *out = P.get();
   c->plans[key] = std::move(P);

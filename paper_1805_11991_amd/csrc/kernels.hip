@@ -640,8 +640,9 @@ __device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v,
 
 // Table modes of the element-unit levels: kTabC (form C: two periods of 2 Z in
 // LDS), kTabD (form D: the same as u32 in device memory), kTabE (form E: one
-// period of Z in LDS, u16 entries for M <= 65534).
-constexpr int kTabC = 0, kTabD = 1, kTabE = 2;
+// period of Z in LDS, u16 entries for M <= 65534), kTabF (form F: half a
+// period of 17-bit Z in LDS, M <= 131070).
+constexpr int kTabC = 0, kTabD = 1, kTabE = 2, kTabF = 3;
 
 // Table entry at byte offset r in [0, 2 M2) (M2 = 2 M, the byte period):
 // 2 Z((r/2) mod M), or the marker M2 where 1 + gamma^(r/2) = 0.  Form E folds
@@ -651,6 +652,17 @@ template <int TM>
 __device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restrict__ gtab, uint32_t M2, uint32_t r) {
   if (TM == kTabD) return gtab[r >> 1];
   if (TM == kTabE) return 2u * lds_u16(tab + fold(r, M2));
+  if (TM == kTabF) {
+    // element k of one period; past the half, Z(k) = Z(M - k) + k mod M
+    const uint32_t M = M2 >> 1, h = M2 >> 2;
+    const uint32_t k = fold(r, M2) >> 1;
+    const bool up = k > h;
+    const uint32_t j = up ? M - k : k;                                    // j <= h
+    const uint32_t bits = tab + ((2u * (h + 1u) + 15u) & ~15u);           // the 17th bits after the low halves
+    const uint32_t z = lds_u16(tab + 2u * j) | (((lds_u32(bits + 4u * (j >> 5)) >> (j & 31u)) & 1u) << 16);
+    if (z == M) return M2;                                                // the marker sits at j = h only
+    return 2u * fold(z + (up ? k : 0u), M);
+  }
   return lds_u16(tab + r);
 }
 
@@ -1099,7 +1111,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
       }
     }
   } else {
-    // byte units; a form C or E table starts the LDS image
+    // byte units; a form C, E or F table starts the LDS image
     L.tab_off = lb;
 #define HWC_FORM_C(GL)                                                                   \
   do {                                                                                   \
@@ -1125,6 +1137,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
   } while (0)
     if (L.form == kFormC) HWC_FORM_C(kTabC);
     else if (L.form == kFormE) HWC_FORM_C(kTabE);
+    else if (L.form == kFormF) HWC_FORM_C(kTabF);
     else HWC_FORM_C(kTabD);
 #undef HWC_FORM_C
   }

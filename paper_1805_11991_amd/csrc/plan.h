@@ -16,6 +16,10 @@
 //           into the period once more than form C and doubles the entry it
 //           reads, so it shares form C's code; twice the field size of form C
 //           fits in LDS.
+//   form F  (M <= 131070)  "half table": Z(k) for k = 0..M/2 only, as u16
+//           low halves followed by a bitmap of the 17th bits; the other half
+//           follows from Z(-k) = Z(k) - k (1 + g^-k = g^-k (1 + g^k)), so
+//           Z(k) = Z(M - k) + k mod M for k > M/2.  Two reads per lookup.
 //   form D  (any M)  the form C layout with u32 entries, kept in device
 //           memory (L2/MALL-resident) when the level does not fit in LDS.
 //   emb     q u32 entries: log of the F_q code c in F_{q^j}, or M for c = 0.
@@ -31,10 +35,11 @@ namespace hwc {
 
 constexpr int kMaxG = 4;                 // genus handled by the kernels
 constexpr int kMaxCoef = 2 * kMaxG + 3;  // a_0 .. a_{2g+2}
-constexpr uint32_t kFormA = 0, kFormC = 1, kFormD = 2, kFormE = 3;
+constexpr uint32_t kFormA = 0, kFormC = 1, kFormD = 2, kFormE = 3, kFormF = 4;
 constexpr uint32_t kFormAMaxM = 10922;   // 6M must fit in u16
 constexpr uint32_t kFormCMaxM = 32767;   // M must fit in 15 bits
 constexpr uint32_t kFormEMaxM = 65534;   // M (the zero marker) must fit in u16
+constexpr uint32_t kFormFMaxM = 131070;  // M must fit in 17 bits, M/2 + 1 entries in the half table
 constexpr int kWave = 64;
 // LDS of one CU is 160 KiB; 256 bytes stay free for the kernels' own variables
 constexpr uint32_t kLdsImageLimit = 160 * 1024 - 256;
@@ -45,7 +50,7 @@ constexpr uint32_t kShiftTries = 8;
 
 struct LevelDesc {
   uint32_t M;         // |F_{q^j}^x|
-  uint32_t form;      // kFormA, kFormC, kFormD or kFormE
+  uint32_t form;      // kFormA, kFormC, kFormD, kFormE or kFormF
   uint32_t tab_off;   // byte offset of the level's table in the image
   uint32_t emb_off;   // byte offset of the level's emb table in the image
   uint32_t nx;        // number of x logs swept at this level

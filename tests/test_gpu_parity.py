@@ -298,13 +298,42 @@ def test_full_size_g3_q13(gctx, mctx, oracle_mod, curvegen_mod):
 
 @pytest.mark.parametrize("q,g,n", [(191, 2, 30), (211, 2, 24), (257, 2, 16), (263, 2, 16), (293, 2, 16), (37, 3, 6),
                                    (41, 3, 5), (43, 3, 4), (49, 3, 3)])
-def test_device_memory_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
-    # q^g - 1 > 65534: the top level's Zech table stays in device memory (form D);
-    # 32767 < q^g - 1 <= 65534: one period of u16 entries in LDS (form E)
+def test_large_level_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
+    # 32767 < q^g - 1 <= 65534: one period of u16 entries in LDS (form E);
+    # up to 131070: half a period of 17-bit entries in LDS (form F)
     curves = curvegen_mod.sample(q, g, n, seed=777 + q, dtype=np.int16)
     top = gctx.plan_info(q, g)[-1]
-    assert top["form"] == (3 if q ** g - 1 <= 65534 else 2), top
+    assert top["form"] == (3 if q ** g - 1 <= 65534 else 4), top
     _check(gctx, oracle_mod, q, g, curves)
+
+
+@pytest.mark.parametrize("q,g,n", [(211, 2, 20), (293, 2, 16), (43, 3, 4)])
+def test_device_memory_tables(oracle_mod, curvegen_mod, q, g, n):
+    """The top level's Zech table placed in device memory (form D, served by
+    L2 and the MALL) by the table-placement option."""
+    from paper_1805_11991_amd import hwcount as hw
+    curves = curvegen_mod.sample(q, g, n, seed=779 + q, dtype=np.int16)
+    with hw.Context(device=0, autotune_db=None) as ctx:
+        ctx.set_option(hw.HWC_OPT_DEVICE_TABLES, 1 << (g - 1))
+        assert ctx.plan_info(q, g)[-1]["form"] == 2
+        _check(ctx, oracle_mod, q, g, curves)
+
+
+@pytest.mark.parametrize("q,g,n", [(257, 2, 24), (283, 2, 20), (293, 2, 20), (41, 3, 6), (47, 3, 5)])
+def test_half_period_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
+    """Top levels of 65 535 .. 131 070 nonzero elements: Z(k) for k <= M/2 as
+    17-bit entries in LDS, the rest through Z(-k) = Z(k) - k (form F), split over
+    mu_4 (257, 293, 41) or mu_2 (283, 47), on seeded rows and on rows with zero
+    coefficients, every launch form against the oracle."""
+    assert gctx.plan_info(q, g)[-1]["form"] == 4
+    curves = curvegen_mod.sample(q, g, n, seed=780 + q, dtype=np.int16)
+    sparse = curves.copy()
+    for i in range(len(sparse)):
+        top = 2 * g + 2 if sparse[i, 2 * g + 2] else 2 * g + 1
+        for k in ((i % top), ((3 * i + 1) % top))[: 1 + i % 2]:
+            sparse[i, k] = 0
+    _check(gctx, oracle_mod, q, g, curves)
+    _check(gctx, oracle_mod, q, g, sparse)
 
 
 @pytest.mark.parametrize("q,g,n", [(191, 2, 40), (227, 2, 30), (241, 2, 30), (251, 2, 30), (37, 3, 8)])
