@@ -40,11 +40,11 @@ hipError_t launch_assemble(const PlanDesc& P, int coeff_bytes, const void* codes
                            int32_t* outN, hipStream_t s);
 hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n, uint32_t q, const uint32_t* step,
-                        void* out, hipStream_t s);
+                        void* out, uint16_t* pid, uint32_t* counts, uint32_t* err, hipStream_t s);
 hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_t q, uint32_t g, uint16_t* pid,
                          uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
                          uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
-                         uint64_t max_tiles, hipStream_t s);
+                         uint64_t max_tiles, bool classified, hipStream_t s);
 hipError_t launch_batch(const JobDesc* jobs, uint32_t njobs, uint32_t gmax, uint32_t lds_bytes, uint32_t grid,
                         uint32_t block, hipStream_t s);
 hipError_t occupancy_batch(uint32_t gmax, uint32_t block, uint32_t lds_bytes, int* blocks_per_cu);
@@ -1112,12 +1112,14 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
     }
     return HWC_OK;
   }
-  if (P->d_shift && n > 0) {
-    HIPX(c, hwc::launch_shift(cb, g, codes, n, P->q, P->d_shift, S.tcodes, s));
+  const bool shifted = P->d_shift && n > 0;
+  if (shifted) {   // translate and classify in one pass
+    HIPX(c, hwc::launch_fill(S.counts, 0, hwc::pattern_count(g), s));
+    HIPX(c, hwc::launch_shift(cb, g, codes, n, P->q, P->d_shift, S.tcodes, S.pid, S.counts, c->d_err, s));
     codes = S.tcodes;
   }
   HIPX(c, hwc::launch_bucket(cb, codes, n, P->q, g, S.pid, S.counts, c->d_err, S.bucket_start, S.tile_start,
-                             S.cursor, S.ntiles, S.queue, S.tiles, S.perm, S.max_tiles, s));
+                             S.cursor, S.ntiles, S.queue, S.tiles, S.perm, S.max_tiles, shifted, s));
   if (record) HIPX(c, hipEventRecord(ev[1], s));
   if (n > 0) {
     if (flags & HWC_PLAIN) {
@@ -1317,11 +1319,15 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, const BatchPlan& B, const hwc
       const DevPlan* P = B.plans[B.order[r]];
       uint32_t* sm = small + r * kSmallStride;
       const void* rows = batch_rows(st, J, B, r);
-      if (rows != J.d_coeffs)
-        HIPX(c, hwc::launch_shift(J.coeff_bytes, J.g, J.d_coeffs, J.n, P->q, P->d_shift, const_cast<void*>(rows), s));
+      const bool shifted = rows != J.d_coeffs;
+      if (shifted) {   // translate and classify in one pass
+        HIPX(c, hwc::launch_fill(sm, 0, hwc::pattern_count(J.g), s));
+        HIPX(c, hwc::launch_shift(J.coeff_bytes, J.g, J.d_coeffs, J.n, P->q, P->d_shift, const_cast<void*>(rows),
+                                  pid + B.off[r], sm, c->d_err, s));
+      }
       HIPX(c, hwc::launch_bucket(J.coeff_bytes, rows, J.n, P->q, P->g, pid + B.off[r], sm, c->d_err, sm + 2048,
                                  sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
-                                 B.max_tiles[r], s));
+                                 B.max_tiles[r], shifted, s));
     }
     for (const BatchSeg& G : B.segs)
       HIPX(c, hwc::launch_batch(d_jobs + G.begin, (uint32_t)(G.end - G.begin), G.gmax, G.lds, G.grid, G.block, s));
@@ -2191,7 +2197,7 @@ int hwc_translate_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* d_coeffs, 
   DevPlan* P = nullptr;
   if ((rc = get_plan(c, q, g, 1u, &P))) return rc;
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : c->stream;
-  if (P->d_shift) HIPX(c, hwc::launch_shift(coeff_bytes, g, d_coeffs, n, q, P->d_shift, d_out, s));
+  if (P->d_shift) HIPX(c, hwc::launch_shift(coeff_bytes, g, d_coeffs, n, q, P->d_shift, d_out, nullptr, nullptr, nullptr, s));
   else HIPX(c, hipMemcpyAsync(d_out, d_coeffs, bytes, hipMemcpyDeviceToDevice, s));
   return HWC_OK;
 }

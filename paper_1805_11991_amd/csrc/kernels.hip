@@ -68,6 +68,19 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
 // classification: validate rows, compute the pattern of each row and the
 // number of rows per pattern.
 
+// hist[pat] += 1 for every active lane, one LDS atomic per distinct pattern in
+// the wave (rows of a wave mostly share one or two patterns, so per-lane
+// atomics would serialize on the same address).
+__device__ __forceinline__ void wave_count(uint32_t* hist, uint32_t pat, bool active) {
+  uint64_t left = __ballot(active);
+  while (left) {
+    const uint32_t leader = uniform((uint32_t)__builtin_amdgcn_readlane((int)pat, (int)__builtin_ctzll(left)));
+    const uint64_t same = __ballot(active && pat == leader);
+    if ((threadIdx.x & (kWave - 1)) == (uint32_t)__builtin_ctzll(left)) atomicAdd(&hist[leader], (uint32_t)__popcll(same));
+    left &= ~same;
+  }
+}
+
 template <typename CT>
 __global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ codes, uint64_t n, uint32_t q,
                                                        uint32_t g, uint16_t* __restrict__ pid,
@@ -78,20 +91,28 @@ __global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ co
   for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   uint32_t bad = 0;
-  for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const CT* row = codes + i * nc;
-    uint32_t mask = 0;
-    const int top = (int)row[nc - 1], sub = (int)row[nc - 2];
-    const uint32_t d = top ? nc - 1 : nc - 2;
-    for (uint32_t j = 0; j < nc; ++j) {
-      const int c = (int)row[j];
-      if (c < 0 || c >= (int)q) bad |= 1u;
-      if (j < d && c != 0) mask |= 1u << j;
+  // every lane of a wave runs the same number of iterations (wave_count has ballots)
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  for (uint64_t w0 = base; w0 < n; w0 += stride) {
+    const uint64_t i = w0 + (threadIdx.x & (kWave - 1));
+    const bool live = i < n;
+    uint32_t pat = 0;
+    if (live) {
+      const CT* row = codes + i * nc;
+      uint32_t mask = 0;
+      const int top = (int)row[nc - 1], sub = (int)row[nc - 2];
+      const uint32_t d = top ? nc - 1 : nc - 2;
+      for (uint32_t j = 0; j < nc; ++j) {
+        const int c = (int)row[j];
+        if (c < 0 || c >= (int)q) bad |= 1u;
+        if (j < d && c != 0) mask |= 1u << j;
+      }
+      if (top == 0 && sub == 0) bad |= 2u;
+      pat = (top ? (1u << (nc - 1)) : 0u) | mask;
+      pid[i] = (uint16_t)pat;
     }
-    if (top == 0 && sub == 0) bad |= 2u;
-    const uint32_t pat = (top ? (1u << (nc - 1)) : 0u) | mask;
-    pid[i] = (uint16_t)pat;
-    atomicAdd(&hist[pat], 1u);
+    wave_count(hist, pat, live);
   }
   if (bad) atomicOr(err, bad);
   __syncthreads();
@@ -113,21 +134,37 @@ __global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ co
 // k = 0 .. D-1 and i = D-1 down to k, w_i <- w_i + t w_{i+1}.  Each step is one
 // read of the LDS table step[t][a][b] = a + t b (F_q codes, q^3 bytes); fully
 // unrolled, the steps' dependences form a triangle whose longest chain is 2D.
+//
+// With pid given, the kernel also classifies the rows it writes, as
+// classify_kernel does (pattern per row, rows per pattern added to counts,
+// error bits), so the bucketing needs no second pass over them.
 template <int NC, typename CT>
 __global__ __launch_bounds__(256) void shift_kernel(const CT* __restrict__ in, uint64_t n, uint32_t q,
-                                                    const uint32_t* __restrict__ step, CT* __restrict__ out) {
+                                                    const uint32_t* __restrict__ step, CT* __restrict__ out,
+                                                    uint16_t* __restrict__ pid, uint32_t* __restrict__ counts,
+                                                    uint32_t* __restrict__ err) {
   extern __shared__ uint32_t sh32[];
+  constexpr uint32_t npat = 1u << NC;
   const uint32_t qq = q * q, words = (qq * q + 3) / 4;
+  uint32_t* hist = sh32 + (words + 3) / 4 * 4;     // after the step table
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) sh32[i] = step[i];
+  if (pid)
+    for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   const uint8_t* tab = reinterpret_cast<const uint8_t*>(sh32);
-  for (uint64_t r = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; r < n; r += (uint64_t)gridDim.x * blockDim.x) {
+  uint32_t bad = 0;
+  // every lane of a wave runs the same number of iterations (ballots below)
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t base = blockIdx.x * (uint64_t)blockDim.x + (threadIdx.x & ~(uint32_t)(kWave - 1));
+  for (uint64_t w0 = base; w0 < n; w0 += stride) {
+    const uint64_t r = w0 + (threadIdx.x & (kWave - 1));
+    const bool live = r < n;
     CT raw[NC];
     uint32_t c[NC];
-    bool valid = true;
+    bool valid = live;
 #pragma unroll
     for (int i = 0; i < NC; ++i) {
-      raw[i] = in[r * NC + i];
+      raw[i] = live ? in[r * NC + i] : (CT)0;
       const int v = (int)raw[i];
       valid = valid && v >= 0 && v < (int)q;
       c[i] = (v >= 0 && v < (int)q) ? (uint32_t)v : 0u;
@@ -161,8 +198,33 @@ __global__ __launch_bounds__(256) void shift_kernel(const CT* __restrict__ in, u
         done = true;
       }
     }
+    if (live) {
 #pragma unroll
-    for (int i = 0; i < NC; ++i) out[r * NC + i] = done ? (CT)w[i] : raw[i];
+      for (int i = 0; i < NC; ++i) out[r * NC + i] = done ? (CT)w[i] : raw[i];
+    }
+    if (pid) {
+      // the pattern of the row as written (classify_kernel's rule)
+      uint32_t mask = 0;
+      int o[NC];
+#pragma unroll
+      for (int i = 0; i < NC; ++i) o[i] = done ? (int)w[i] : (int)raw[i];
+      const uint32_t dd = o[NC - 1] ? NC - 1 : NC - 2;
+#pragma unroll
+      for (int i = 0; i < NC; ++i) {
+        if (live && (o[i] < 0 || o[i] >= (int)q)) bad |= 1u;
+        if ((uint32_t)i < dd && o[i] != 0) mask |= 1u << i;
+      }
+      if (live && o[NC - 1] == 0 && o[NC - 2] == 0) bad |= 2u;
+      const uint32_t pat = (o[NC - 1] ? (1u << (NC - 1)) : 0u) | mask;
+      if (live) pid[r] = (uint16_t)pat;
+      wave_count(hist, pat, live);
+    }
+  }
+  if (pid) {
+    if (bad) atomicOr(err, bad);
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x)
+      if (hist[i]) atomicAdd(&counts[i], hist[i]);
   }
 }
 
@@ -1842,20 +1904,22 @@ hipError_t launch_fill(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// pid (may be null): also classify the rows written into pid, counts (rows
+// per pattern, added to; the caller clears it) and err, as classify_kernel
 hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n, uint32_t q, const uint32_t* step,
-                        void* out, hipStream_t s) {
+                        void* out, uint16_t* pid, uint32_t* counts, uint32_t* err, hipStream_t s) {
   if (n == 0) return hipSuccess;
   if (q > kShiftMaxQ || q < 3) return hipErrorInvalidValue;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
-  const uint32_t lds = (q * q * q + 3) / 4 * 4;
+  const uint32_t lds = (q * q * q + 15) / 16 * 16 + (pid ? 4u * pattern_count(g) : 0u);
 #define HWC_SHIFT(GG)                                                                                       \
   case GG:                                                                                                  \
     if (coeff_bytes == 1)                                                                                   \
       hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int8_t>), dim3(grid), dim3(256), lds, s,                   \
-                         static_cast<const int8_t*>(in), n, q, step, static_cast<int8_t*>(out));           \
+                         static_cast<const int8_t*>(in), n, q, step, static_cast<int8_t*>(out), pid, counts, err); \
     else                                                                                                    \
       hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int16_t>), dim3(grid), dim3(256), lds, s,                  \
-                         static_cast<const int16_t*>(in), n, q, step, static_cast<int16_t*>(out));         \
+                         static_cast<const int16_t*>(in), n, q, step, static_cast<int16_t*>(out), pid, counts, err); \
     break;
   switch (g) {
     HWC_SHIFT(1) HWC_SHIFT(2) HWC_SHIFT(3) HWC_SHIFT(4)
@@ -1865,14 +1929,17 @@ hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n,
   return hipGetLastError();
 }
 
+// classified: pid and counts were written by launch_shift (counts cleared
+// before it), so the classification pass is skipped
 hipError_t launch_bucket(int coeff_bytes, const void* codes, uint64_t n, uint32_t q, uint32_t g, uint16_t* pid,
                          uint32_t* counts, uint32_t* err, uint32_t* bucket_start, uint32_t* tile_start,
                          uint32_t* cursor, uint32_t* ntiles, uint32_t* queue, uint64_t* tiles, uint32_t* perm,
-                         uint64_t max_tiles, hipStream_t s) {
+                         uint64_t max_tiles, bool classified, hipStream_t s) {
   const uint32_t npat = pattern_count(g);
-  hipError_t e = launch_fill(counts, 0, npat, s);
+  hipError_t e = hipSuccess;
+  if (!classified) e = launch_fill(counts, 0, npat, s);
   if (e != hipSuccess) return e;
-  if (n > 0) {
+  if (n > 0 && !classified) {
     const uint32_t grid = (uint32_t)((n + 255) / 256 < 2048 ? (n + 255) / 256 : 2048);
     if (coeff_bytes == 1)
       hipLaunchKernelGGL(classify_kernel<int8_t>, dim3(grid), dim3(256), npat * 4, s,
