@@ -875,12 +875,26 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       return expq[(F1.emb[a] + F1.emb[b]) % (q - 1)];
     };
     const size_t q3 = (size_t)q * q * q;
-    std::vector<uint8_t> st((q3 + 3) / 4 * 4, 0);
+    const uint32_t nc = 2 * g + 3, tw = hwc::shift_tmat_words(nc), rw = hwc::shift_tmat_row_words(nc);
+    const size_t toff = (size_t)hwc::shift_tmat_offset_words(q) * 4;
+    std::vector<uint8_t> st(toff + (size_t)(hwc::kShiftTries + 1) * tw * 4, 0);
     for (uint32_t t = 0; t < q; ++t)
       for (uint32_t b = 0; b < q; ++b) {
         const uint32_t tb = mul(t, b);
         for (uint32_t a = 0; a < q; ++a) st[((size_t)t * q + a) * q + b] = (uint8_t)add(a, tb);
       }
+    if (e == 1) {   // prime q: the translate as a matrix, binom(j, i) t^(j-i) mod q
+      std::vector<uint32_t> binom((size_t)nc * nc, 0);
+      for (uint32_t j = 0; j < nc; ++j)
+        for (uint32_t i = 0; i <= j; ++i)
+          binom[j * nc + i] = (i == 0 || i == j) ? 1u : (binom[(j - 1) * nc + i - 1] + binom[(j - 1) * nc + i]) % q;
+      for (uint32_t t = 0; t <= hwc::kShiftTries && t < q; ++t)
+        for (uint32_t i = 0; i + 1 < nc; ++i) {
+          uint32_t tp = 1;   // t^(j-i)
+          for (uint32_t j = i; j < nc; ++j, tp = tp * t % q)
+            st[toff + ((size_t)t * tw + i * rw + j / 4) * 4 + j % 4] = (uint8_t)(binom[j * nc + i] * tp % q);
+        }
+    }
     HIPX(c, hipMalloc(&P->d_shift, st.size()));
     HIPX(c, hipMemcpy(P->d_shift, st.data(), st.size(), hipMemcpyHostToDevice));
     P->dev_bytes += st.size();

@@ -135,19 +135,28 @@ __global__ __launch_bounds__(256) void classify_kernel(const CT* __restrict__ co
 // read of the LDS table step[t][a][b] = a + t b (F_q codes, q^3 bytes); fully
 // unrolled, the steps' dependences form a triangle whose longest chain is 2D.
 //
+// DOT (prime q): the coefficients of f(x + t) are v_i = sum_{j >= i}
+// binom(j, i) t^(j-i) c_j mod q, an integer matrix product done with 4-byte
+// dot products (the matrix rows of each t come packed after the step table,
+// see shift_tmat_offset_words); the sums stay below NC (q-1)^2 < 2^14, and
+// v mod q = v - q floor(v qm / 2^20) with qm = ceil(2^20 / q) is exact for
+// v < 2^20 / q.  No LDS reads: the vector ALU does what the table did.
+//
 // With pid given, the kernel also classifies the rows it writes, as
 // classify_kernel does (pattern per row, rows per pattern added to counts,
 // error bits), so the bucketing needs no second pass over them.
-template <int NC, typename CT>
+template <int NC, typename CT, bool DOT>
 __global__ __launch_bounds__(256) void shift_kernel(const CT* __restrict__ in, uint64_t n, uint32_t q,
                                                     const uint32_t* __restrict__ step, CT* __restrict__ out,
                                                     uint16_t* __restrict__ pid, uint32_t* __restrict__ counts,
-                                                    uint32_t* __restrict__ err) {
+                                                    uint32_t* __restrict__ err, uint32_t qm) {
   extern __shared__ uint32_t sh32[];
   constexpr uint32_t npat = 1u << NC;
-  const uint32_t qq = q * q, words = (qq * q + 3) / 4;
+  constexpr uint32_t NW = shift_tmat_row_words(NC);
+  const uint32_t qq = q * q, words = DOT ? 0u : (qq * q + 3) / 4;
   uint32_t* hist = sh32 + (words + 3) / 4 * 4;     // after the step table
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) sh32[i] = step[i];
+  const uint32_t* __restrict__ tmat = step + shift_tmat_offset_words(q);
   if (pid)
     for (uint32_t i = threadIdx.x; i < npat; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -178,16 +187,40 @@ __global__ __launch_bounds__(256) void shift_kernel(const CT* __restrict__ in, u
     uint32_t w[NC];
 #pragma unroll
     for (int i = 0; i < NC; ++i) w[i] = c[i];
+    uint32_t cp[NW];
+    if constexpr (DOT) {
+#pragma unroll
+      for (uint32_t w = 0; w < NW; ++w) {
+        uint32_t word = 0;
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b)
+          if (4 * w + b < (uint32_t)NC) word |= c[4 * w + b] << (8 * b);
+        cp[w] = word;
+      }
+    }
     for (uint32_t t = 1; t < q && t <= kShiftTries; ++t) {
       if (!__ballot(need && !done)) break;
-      const uint32_t base = t * qq;
       uint32_t v[NC];
+      if constexpr (DOT) {
+        const uint32_t* Tt = tmat + t * shift_tmat_words(NC);
 #pragma unroll
-      for (int i = 0; i < NC; ++i) v[i] = c[i];
+        for (int i = 0; i < NC - 1; ++i) {
+          uint32_t acc = 0;
 #pragma unroll
-      for (int k = 0; k < NC - 1; ++k) {
+          for (uint32_t w = (uint32_t)i / 4; w < NW; ++w)
+            acc = __builtin_amdgcn_udot4(Tt[i * NW + w], cp[w], acc, false);
+          v[i] = acc - __umul24(q, __umul24(acc, qm) >> 20);   // 24-bit products, full rate
+        }
+        v[NC - 1] = c[NC - 1];
+      } else {
+        const uint32_t base = t * qq;
 #pragma unroll
-        for (int i = NC - 2; i >= k; --i) v[i] = tab[base + v[i] * q + v[i + 1]];
+        for (int i = 0; i < NC; ++i) v[i] = c[i];
+#pragma unroll
+        for (int k = 0; k < NC - 1; ++k) {
+#pragma unroll
+          for (int i = NC - 2; i >= k; --i) v[i] = tab[base + v[i] * q + v[i + 1]];
+        }
       }
       bool dense = true;
 #pragma unroll
@@ -1215,8 +1248,8 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
 // N_k from the per-level counts (Sec. 1.1 decomposition; x = 0 and the
 // points at infinity of the model in P(1, g+1, 1) added here).
 template <int G>
-__device__ void assemble(const PlanDesc& P, const uint32_t (&lv)[G], uint32_t c0, uint32_t ctop, uint32_t log0,
-                         uint32_t logtop, int32_t* out) {
+__device__ __forceinline__ void assemble(const PlanDesc& P, const uint32_t (&lv)[G], uint32_t c0, uint32_t ctop,
+                                         uint32_t log0, uint32_t logtop, int32_t* out) {
 #pragma unroll
   for (int k = 1; k <= G; ++k) {
     const int chi0 = (k % 2 == 0) ? 1 : ((log0 & 1u) ? -1 : 1);
@@ -1911,21 +1944,29 @@ hipError_t launch_shift(int coeff_bytes, uint32_t g, const void* in, uint64_t n,
   if (n == 0) return hipSuccess;
   if (q > kShiftMaxQ || q < 3) return hipErrorInvalidValue;
   const uint32_t grid = (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096);
-  const uint32_t lds = (q * q * q + 15) / 16 * 16 + (pid ? 4u * pattern_count(g) : 0u);
+  bool prime = true;
+  for (uint32_t d = 2; d * d <= q; ++d) prime = prime && q % d != 0;
+  const uint32_t qm = ((1u << 20) + q - 1) / q;
+  const uint32_t lds = (prime ? 0u : (q * q * q + 15) / 16 * 16) + (pid ? 4u * pattern_count(g) : 0u);
+#define HWC_SHIFT1(GG, CT, DOT)                                                                          \
+  hipLaunchKernelGGL((shift_kernel<2 * GG + 3, CT, DOT>), dim3(grid), dim3(256), lds, s,                  \
+                     static_cast<const CT*>(in), n, q, step, static_cast<CT*>(out), pid, counts, err, qm)
 #define HWC_SHIFT(GG)                                                                                       \
   case GG:                                                                                                  \
-    if (coeff_bytes == 1)                                                                                   \
-      hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int8_t>), dim3(grid), dim3(256), lds, s,                   \
-                         static_cast<const int8_t*>(in), n, q, step, static_cast<int8_t*>(out), pid, counts, err); \
-    else                                                                                                    \
-      hipLaunchKernelGGL((shift_kernel<2 * GG + 3, int16_t>), dim3(grid), dim3(256), lds, s,                  \
-                         static_cast<const int16_t*>(in), n, q, step, static_cast<int16_t*>(out), pid, counts, err); \
+    if (coeff_bytes == 1) {                                                                                 \
+      if (prime) HWC_SHIFT1(GG, int8_t, true);                                                              \
+      else HWC_SHIFT1(GG, int8_t, false);                                                                   \
+    } else {                                                                                                \
+      if (prime) HWC_SHIFT1(GG, int16_t, true);                                                             \
+      else HWC_SHIFT1(GG, int16_t, false);                                                                  \
+    }                                                                                                       \
     break;
   switch (g) {
     HWC_SHIFT(1) HWC_SHIFT(2) HWC_SHIFT(3) HWC_SHIFT(4)
     default: return hipErrorInvalidValue;
   }
 #undef HWC_SHIFT
+#undef HWC_SHIFT1
   return hipGetLastError();
 }
 

@@ -47,6 +47,13 @@ constexpr uint32_t kLdsImageLimit = 160 * 1024 - 256;
 // q <= kShiftMaxQ, whose q^3-byte step table fits LDS, at most kShiftTries t.
 constexpr uint32_t kShiftMaxQ = 32;
 constexpr uint32_t kShiftTries = 8;
+// For prime q the translate is also an integer matrix product: after the
+// step table (q^3 bytes, padded to 16) the shift buffer holds, for t = 0 ..
+// kShiftTries, the rows i = 0 .. NC-2 of binom(j, i) t^(j-i) mod q (j >= i,
+// zero below), bytes packed four to a word: shift_tmat_words(NC) words per t.
+inline constexpr uint32_t shift_tmat_offset_words(uint32_t q) { return (q * q * q + 15) / 16 * 4; }
+inline constexpr uint32_t shift_tmat_row_words(uint32_t nc) { return (nc + 3) / 4; }
+inline constexpr uint32_t shift_tmat_words(uint32_t nc) { return (nc - 1) * shift_tmat_row_words(nc); }
 
 struct LevelDesc {
   uint32_t M;         // |F_{q^j}^x|

@@ -120,3 +120,35 @@ def test_translate_entry_point(sctx, oracle_mod, curvegen_mod):
     assert np.array_equal(o37.cpu().numpy(), rows37)
     with pytest.raises(hw.HwcError):
         sctx.translate_dev(q, g, d, d)
+
+
+@pytest.mark.parametrize("q,p,e,g", [(13, 13, 1, 3), (31, 31, 1, 4), (5, 5, 1, 2), (7, 7, 1, 1),
+                                     (9, 3, 2, 3), (27, 3, 3, 2)])
+def test_translate_takes_the_first_dense_t(sctx, oracle_mod, curvegen_mod, q, p, e, g):
+    """Each row with a zero below its leading coefficient becomes f(x + t) for
+    the first t = 1 .. min(q - 1, 8) that leaves none (prime q: the integer
+    matrix form of the translate; prime powers: the step table), computed
+    here by the binomial theorem over F_q from the oracle's field product."""
+    import torch
+    from paper_1805_11991_amd import hwcount as hw
+    from test_translation_pins import _translate
+    n = 160
+    rows = _sparse_rows(curvegen_mod, q, g, n, seed=900 + q * 5 + g, frac=0.3)
+    nc = rows.shape[1]
+    want = rows.astype(np.int64).copy()
+    for r in range(n):
+        row = [int(v) for v in rows[r]]
+        d = nc - 1 if row[-1] else nc - 2
+        if all(row[i] != 0 for i in range(d)):
+            continue
+        for t in range(1, min(q - 1, 8) + 1):
+            v = _translate(oracle_mod, row, t, p, e)
+            if all(v[i] != 0 for i in range(d)):
+                want[r] = v
+                break
+    sctx.set_plan_option(q, g, hw.HWC_OPT_SHIFT, 1)
+    d = torch.from_numpy(rows).cuda()
+    out = torch.empty_like(d)
+    sctx.translate_dev(q, g, d, out)
+    sctx.status()
+    assert np.array_equal(out.cpu().numpy().astype(np.int64), want)
