@@ -12,9 +12,10 @@ Also measured in the same run, each as its own object of the JSON line:
   zech_path        the Zech path at g=3 and g=4 over F_13: batched and plain
                    (one launch per level, no graph) with per-step spread,
                    lookups/s against the LDS peak and the measured gather ceiling
-  device_tables    g = 2 over F_283, whose top-level Zech table (171 696 u32)
-                   lives in device memory: lookups/s against the measured
-                   ceiling of random gathers from such a table
+  largest_field_g2 g = 2 over F_283: the top level's Zech table as a half
+                   table in LDS (the default), and placed in device memory
+                   (lookups/s against the measured ceiling of random gathers
+                   from such a table, L2/MALL-served)
   matrix_core_path the opt-in int8 matrix-product formulation on the same sets
                    (vector ALU and LDS-read fractions, unpadded pairs)
   cfg2_batched     g = 2 over all 71 odd prime powers q < 300, 2^16 curves each,
@@ -490,27 +491,42 @@ def main():
         del bufs4, N4
         torch.cuda.empty_cache()
 
-        # ---------------- a top level too large for LDS: tables in device memory ----------------
+        # ---------------- the largest field of the g=2 range: half table in LDS, and in device memory ----------------
         qd, gd, nd = 283, 2, 1 << 20
         bufsd = setup(qd, gd, nd, curvegen.BASE_SEED + 2 + qd)
+        lv_d = ctx.plan_info(qd, gd)
+        Md = lv_d[-1]["M"]
         td = timed_steps(torch, stream, runner(ctx, qd, gd, bufsd, 0), 5, 1)
         tdp = timed_steps(torch, stream, runner(ctx, qd, gd, bufsd, hwcount.HWC_PLAIN), 5, 1)
         ctx.status()
+        Nd = bufsd[2].cpu().numpy()
         kd = kernel_ms(ctx, runner(ctx, qd, gd, bufsd, 0), 3)
-        lv_d = ctx.plan_info(qd, gd)
-        Md = lv_d[-1]["M"]
-        dev_ceiling = ctx.device_gather_rate(2 * Md, chains=4)
-        rd = zech_roofline(ctx, qd, gd, bufsd, kd["count_ms"], ceiling=dev_ceiling)
-        rd["bound"] = "l2"
-        rd["kernel"] = "count_kernel<2,int16> (top level's Zech table in device memory)"
-        rd["gather_ceiling_kind"] = (f"measured dependent random u32 gathers from a {2 * Md}-entry device-memory "
-                                     f"table (hwc_device_gather_rate)")
-        extra["device_tables"] = {"q": qd, "g": gd, "curves": nd, "batched": td, "plain": tdp,
-                                  "batched_vs_plain": ratio(tdp, td),
-                                  "curves_per_s": round(nd / (td["ms_per_step"] * 1e-3), 1), "roofline": rd}
-        log(f"q={qd} g={gd} (device-memory tables): batched {td['ms_per_step']} ms, plain {tdp['ms_per_step']} ms, "
-            f"{rd['performed_lookups_per_s'] / 1e9:.1f} G performed lookups/s, "
-            f"{rd['performed_frac_of_gather_ceiling']} of the measured device gather ceiling")
+        rd = zech_roofline(ctx, qd, gd, bufsd, kd["count_ms"])
+        rd["kernel"] = "count_kernel<2,int16> (top level as a half table in LDS, form F)"
+        big = {"q": qd, "g": gd, "curves": nd, "top_level_form": lv_d[-1]["form"], "batched": td, "plain": tdp,
+               "batched_vs_plain": ratio(tdp, td), "curves_per_s": round(nd / (td["ms_per_step"] * 1e-3), 1),
+               "roofline": rd}
+        # the same level with its table placed in device memory (L2/MALL)
+        dctx = hwcount.Context(device=0, autotune_db=None)
+        dctx.set_option(hwcount.HWC_OPT_DEVICE_TABLES, 1 << (gd - 1))
+        tdd = timed_steps(torch, stream, runner(dctx, qd, gd, bufsd, 0), 3, 1)
+        dctx.status()
+        assert np.array_equal(bufsd[2].cpu().numpy(), Nd), "device-memory tables differ from the LDS half table"
+        kdd = kernel_ms(dctx, runner(dctx, qd, gd, bufsd, 0), 2)
+        dev_ceiling = dctx.device_gather_rate(2 * Md, chains=4)
+        rdd = zech_roofline(dctx, qd, gd, bufsd, kdd["count_ms"], ceiling=dev_ceiling)
+        rdd["bound"] = "l2"
+        rdd["kernel"] = "count_kernel<2,int16> (top level's Zech table in device memory, form D)"
+        rdd["gather_ceiling_kind"] = (f"measured dependent random u32 gathers from a {2 * Md}-entry device-memory "
+                                      f"table (hwc_device_gather_rate)")
+        big["device_memory_tables"] = {"batched": tdd, "curves_per_s": round(nd / (tdd["ms_per_step"] * 1e-3), 1),
+                                       "roofline": rdd,
+                                       "lds_half_table_speedup": round(tdd["ms_per_step"] / td["ms_per_step"], 3)}
+        dctx.close()
+        extra["largest_field_g2"] = big
+        log(f"q={qd} g={gd}: half table in LDS {td['ms_per_step']} ms (plain {tdp['ms_per_step']} ms), "
+            f"tables in device memory {tdd['ms_per_step']} ms, {rdd['performed_lookups_per_s'] / 1e9:.1f} G performed "
+            f"lookups/s there = {rdd['performed_frac_of_gather_ceiling']} of the measured device gather ceiling")
         del bufsd
         torch.cuda.empty_cache()
 

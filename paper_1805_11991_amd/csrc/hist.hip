@@ -142,10 +142,14 @@ __device__ __forceinline__ uint64_t digit_peers(bool valid, uint32_t dig) {
   return peers;
 }
 
+// top: the keys' most significant digit, which takes few values (N_1
+// leads the key and clusters around q + 1): one LDS add per distinct digit of
+// a wave instead of per-lane adds that would serialize on one counter.  The
+// lower digits are spread out, and per-lane adds cost less than the ballots.
 template <typename K, int RB>
 __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __restrict__ keys, uint64_t n,
                                                                   uint32_t shift, uint32_t nblocks,
-                                                                  uint32_t* __restrict__ bh) {
+                                                                  uint32_t* __restrict__ bh, bool top) {
   constexpr uint32_t kRadixBins = 1u << RB;
   __shared__ uint32_t cnt[kRadixBins];
   for (uint32_t i = threadIdx.x; i < kRadixBins; i += blockDim.x) cnt[i] = 0;
@@ -158,9 +162,21 @@ __global__ __launch_bounds__(kSortThreads) void radix_hist_kernel(const K* __res
     const uint64_t i = base + (uint64_t)r * kSortThreads + threadIdx.x;
     v[r] = i < n ? keys[i] : (K)0;
   }
+  if (top) {   // uniform branch
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-  for (int r = 0; r < kSortItems; ++r)
-    if (base + (uint64_t)r * kSortThreads + threadIdx.x < n) atomicAdd(&cnt[(v[r] >> shift) & (kRadixBins - 1)], 1u);
+    for (int r = 0; r < kSortItems; ++r) {
+      const bool valid = base + (uint64_t)r * kSortThreads + threadIdx.x < n;
+      const uint32_t dig = (uint32_t)((v[r] >> shift) & (kRadixBins - 1));
+      const uint64_t peers = digit_peers<RB>(valid, dig);
+      if (valid && (peers & lt) == 0) atomicAdd(&cnt[dig], (uint32_t)__popcll(peers));
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < kSortItems; ++r)
+      if (base + (uint64_t)r * kSortThreads + threadIdx.x < n) atomicAdd(&cnt[(v[r] >> shift) & (kRadixBins - 1)], 1u);
+  }
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < kRadixBins; d += blockDim.x) bh[(uint64_t)d * nblocks + tile] = cnt[d];
 }
@@ -481,7 +497,7 @@ static hipError_t sort_and_count(const int32_t* N, const uint32_t* lam, uint64_t
     const uint32_t shift = pass * RB;
     if (pass > 0)   // the first digit's counts come from make_keys_kernel
       hipLaunchKernelGGL((radix_hist_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n,
-                         shift, (uint32_t)nb_sort, bh);
+                         shift, (uint32_t)nb_sort, bh, pass + 1 == npass);
     hipError_t e = scan_exclusive(bh, nbh, bh, sums, nullptr, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((radix_scatter_kernel<K, RB>), dim3((uint32_t)nb_sort), dim3(kSortThreads), 0, s, keysA, n, shift,
