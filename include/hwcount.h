@@ -321,7 +321,8 @@ int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags
  * M of F_{q^j}^x, the table form (0: u16 in LDS, byte units; 1: u16 in LDS,
  * folded index over two periods; 2: u32 in device memory; 3: u16 in LDS, one
  * period, for M up to 65534; 4: half a period of 17-bit entries in LDS, for M
- * up to 131070), the number nx of swept x, the
+ * up to 131070; 5: the same half period as u32 entries in LDS, where it fits
+ * the LDS image), the number nx of swept x, the
  * weight of each, the split factor m (0: plain Horner; else the sweep runs nt
  * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
  * x^m, plus ns single points), the LDS bytes of the plan, and mfma = 1 when

@@ -439,6 +439,7 @@ uint32_t lds_table_bytes(uint32_t form, uint64_t M) {
     const uint64_t h1 = M / 2 + 1;   // entries of the half table
     return align16((uint32_t)(2 * h1)) + align16((uint32_t)(4 * ((h1 + 31) / 32)));
   }
+  if (form == hwc::kFormG) return align16((uint32_t)(4 * (M / 2 + 1)));
   return 0;
 }
 
@@ -452,9 +453,11 @@ uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
 }
 
 // Forms of the levels: A where 6M fits u16, C where M fits 15 bits, E where
-// M fits 16 bits, F where it fits 17 bits, else D; one level at most in an
-// element form (C, E or F: its table starts the image), the others above it
-// in D; then move the largest LDS levels to D until the image fits.
+// M fits 16 bits, G (u32 half table) or else F (17-bit half table) where it
+// fits 17 bits, else D; one level at most in an element form (C, E, F or G:
+// its table starts the image), the others above it in D; a G level that
+// leaves the image too large becomes F; then move the largest LDS levels to D
+// until the image fits.
 std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
@@ -466,9 +469,9 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask)
     form[j] = M[j] <= hwc::kFormAMaxM   ? hwc::kFormA
               : M[j] <= hwc::kFormCMaxM ? hwc::kFormC
               : M[j] <= hwc::kFormEMaxM ? hwc::kFormE
-              : M[j] <= hwc::kFormFMaxM ? hwc::kFormF
+              : M[j] <= hwc::kFormFMaxM ? hwc::kFormG
                                         : hwc::kFormD;
-    if (form[j] == hwc::kFormC || form[j] == hwc::kFormE || form[j] == hwc::kFormF) {
+    if (form[j] == hwc::kFormC || form[j] == hwc::kFormE || form[j] == hwc::kFormG) {
       if (element) form[j] = hwc::kFormD;
       element = true;
     }
@@ -480,6 +483,8 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask)
   };
   for (uint32_t j = 0; j < g; ++j)
     if ((device_mask >> j) & 1u) form[j] = hwc::kFormD;
+  for (uint32_t j = 0; j < g; ++j)
+    if (form[j] == hwc::kFormG && total() > kLdsLimit) form[j] = hwc::kFormF;
   for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
   return form;
 }
@@ -731,7 +736,8 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
   // form E one period of Z with the marker M; the (single) form C or E table
   // goes first, at byte offset 0 of the image
   for (uint32_t j = 0; j < g; ++j) {
-    if (form[j] != hwc::kFormC && form[j] != hwc::kFormE && form[j] != hwc::kFormF) continue;
+    if (form[j] != hwc::kFormC && form[j] != hwc::kFormE && form[j] != hwc::kFormF && form[j] != hwc::kFormG)
+      continue;
     const hwc::Field& F = P->fields[j]->F;
     const uint32_t M = (uint32_t)F.M;
     if (!img.empty()) return fail(c, HWC_ERR_DEVICE, "two LDS levels in element form");
@@ -745,7 +751,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
     } else if (form[j] == hwc::kFormE) {
       tab.resize(M);
       for (uint32_t i = 0; i < M; ++i) tab[i] = (uint16_t)F.zech[i];   // Z(i) < M, or the marker M
-    } else {
+    } else if (form[j] == hwc::kFormF) {
       // low halves of Z(0..M/2) (17-bit values, the marker M at M/2), padded
       // to 16 bytes, then the 17th bits as u32 words (little-endian halves)
       const uint32_t h1 = M / 2 + 1;
@@ -759,6 +765,17 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       for (uint32_t w : bits) {
         tab.push_back((uint16_t)(w & 0xFFFFu));
         tab.push_back((uint16_t)(w >> 16));
+      }
+    } else {
+      // u32 halves of 2 Z(0..M/2) (byte units; little-endian pairs of u16),
+      // the marker 2 M2 = 4M at M/2, so that folding it by M2 gives M2
+      const uint32_t h1 = M / 2 + 1;
+      tab.assign(2 * (size_t)h1, 0);
+      for (uint32_t i = 0; i < h1; ++i) {
+        const uint32_t z = F.zech[i];
+        const uint32_t v = z == M ? 4 * M : 2 * z;
+        tab[2 * (size_t)i] = (uint16_t)(v & 0xFFFFu);
+        tab[2 * (size_t)i + 1] = (uint16_t)(v >> 16);
       }
     }
     D.lv[j].tab_off = put(tab);
@@ -874,7 +891,6 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
       if (a == 0 || b == 0) return 0;
       return expq[(F1.emb[a] + F1.emb[b]) % (q - 1)];
     };
-    const size_t q3 = (size_t)q * q * q;
     const uint32_t nc = 2 * g + 3, tw = hwc::shift_tmat_words(nc), rw = hwc::shift_tmat_row_words(nc);
     const size_t toff = (size_t)hwc::shift_tmat_offset_words(q) * 4;
     std::vector<uint8_t> st(toff + (size_t)(hwc::kShiftTries + 1) * tw * 4, 0);
@@ -966,6 +982,7 @@ int get_plan(hwc_ctx* c, uint32_t q, uint32_t g, uint32_t orbit, DevPlan** out) 
                      : form[j] == hwc::kFormC ? 1.5
                      : form[j] == hwc::kFormE ? 2.0
                      : form[j] == hwc::kFormF ? 3.0
+                     : form[j] == hwc::kFormG ? 2.5
                                               : 6.0);
   P->last_use = ++c->tick;
   *out = P.get();

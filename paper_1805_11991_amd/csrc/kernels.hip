@@ -736,8 +736,9 @@ __device__ __forceinline__ uint32_t fold(uint32_t v, uint32_t M) { return min(v,
 // Table modes of the element-unit levels: kTabC (form C: two periods of 2 Z in
 // LDS), kTabD (form D: the same as u32 in device memory), kTabE (form E: one
 // period of Z in LDS, u16 entries for M <= 65534), kTabF (form F: half a
-// period of 17-bit Z in LDS, M <= 131070).
-constexpr int kTabC = 0, kTabD = 1, kTabE = 2, kTabF = 3;
+// period of 17-bit Z in LDS, M <= 131070), kTabG (form G: the same half period
+// as u32 entries in byte units, where it fits).
+constexpr int kTabC = 0, kTabD = 1, kTabE = 2, kTabF = 3, kTabG = 4;
 
 // Table entry at byte offset r in [0, 2 M2) (M2 = 2 M, the byte period):
 // 2 Z((r/2) mod M), or the marker M2 where 1 + gamma^(r/2) = 0.  Form E folds
@@ -757,6 +758,14 @@ __device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restri
     const uint32_t z = lds_u16(tab + 2u * j) | (((lds_u32(bits + 4u * (j >> 5)) >> (j & 31u)) & 1u) << 16);
     if (z == M) return M2;                                                // the marker sits at j = h only
     return 2u * fold(z + (up ? k : 0u), M);
+  }
+  if (TM == kTabG) {
+    // entries 2 Z(j), j <= M/2, and 2 M2 at j = M/2 (the marker, which the
+    // final fold turns into M2); past the half, 2 Z(k) = 2 Z(M - k) + 2k mod M2
+    const uint32_t rr = fold(r, M2);                                      // 2k
+    const bool up = rr > (M2 >> 1);
+    const uint32_t z2 = lds_u32(tab + 2u * (up ? M2 - rr : rr));
+    return fold(z2 + (up ? rr : 0u), M2);
   }
   return lds_u16(tab + r);
 }
@@ -1206,7 +1215,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
       }
     }
   } else {
-    // byte units; a form C, E or F table starts the LDS image
+    // byte units; a form C, E, F or G table starts the LDS image
     L.tab_off = lb;
 #define HWC_FORM_C(GL)                                                                   \
   do {                                                                                   \
@@ -1233,6 +1242,7 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
     if (L.form == kFormC) HWC_FORM_C(kTabC);
     else if (L.form == kFormE) HWC_FORM_C(kTabE);
     else if (L.form == kFormF) HWC_FORM_C(kTabF);
+    else if (L.form == kFormG) HWC_FORM_C(kTabG);
     else HWC_FORM_C(kTabD);
 #undef HWC_FORM_C
   }

@@ -35,11 +35,13 @@ namespace hwc {
 
 constexpr int kMaxG = 4;                 // genus handled by the kernels
 constexpr int kMaxCoef = 2 * kMaxG + 3;  // a_0 .. a_{2g+2}
-constexpr uint32_t kFormA = 0, kFormC = 1, kFormD = 2, kFormE = 3, kFormF = 4;
+constexpr uint32_t kFormA = 0, kFormC = 1, kFormD = 2, kFormE = 3, kFormF = 4, kFormG = 5;
 constexpr uint32_t kFormAMaxM = 10922;   // 6M must fit in u16
 constexpr uint32_t kFormCMaxM = 32767;   // M must fit in 15 bits
 constexpr uint32_t kFormEMaxM = 65534;   // M (the zero marker) must fit in u16
 constexpr uint32_t kFormFMaxM = 131070;  // M must fit in 17 bits, M/2 + 1 entries in the half table
+// Form G: the half table of form F as u32 entries in byte units (one read, no
+// bit plane), used where its 4 (M/2 + 1) bytes fit the LDS image
 constexpr int kWave = 64;
 // LDS of one CU is 160 KiB; 256 bytes stay free for the kernels' own variables
 constexpr uint32_t kLdsImageLimit = 160 * 1024 - 256;
@@ -57,7 +59,7 @@ inline constexpr uint32_t shift_tmat_words(uint32_t nc) { return (nc - 1) * shif
 
 struct LevelDesc {
   uint32_t M;         // |F_{q^j}^x|
-  uint32_t form;      // kFormA, kFormC, kFormD, kFormE or kFormF
+  uint32_t form;      // kFormA, kFormC, kFormD, kFormE, kFormF or kFormG
   uint32_t tab_off;   // byte offset of the level's table in the image
   uint32_t emb_off;   // byte offset of the level's emb table in the image
   uint32_t nx;        // number of x logs swept at this level

@@ -300,10 +300,11 @@ def test_full_size_g3_q13(gctx, mctx, oracle_mod, curvegen_mod):
                                    (41, 3, 5), (43, 3, 4), (49, 3, 3)])
 def test_large_level_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
     # 32767 < q^g - 1 <= 65534: one period of u16 entries in LDS (form E);
-    # up to 131070: half a period of 17-bit entries in LDS (form F)
+    # up to 131070: half a period in LDS, as u32 entries where the image fits
+    # (form G), else as 17-bit entries (form F)
     curves = curvegen_mod.sample(q, g, n, seed=777 + q, dtype=np.int16)
     top = gctx.plan_info(q, g)[-1]
-    assert top["form"] == (3 if q ** g - 1 <= 65534 else 4), top
+    assert top["form"] == (3 if q ** g - 1 <= 65534 else 5 if (q, g) in HALF_U32 else 4), top
     _check(gctx, oracle_mod, q, g, curves)
 
 
@@ -319,14 +320,37 @@ def test_device_memory_tables(oracle_mod, curvegen_mod, q, g, n):
         _check(ctx, oracle_mod, q, g, curves)
 
 
-@pytest.mark.parametrize("q,g,n", [(257, 2, 24), (283, 2, 20), (293, 2, 20), (41, 3, 6), (47, 3, 5)])
+# top levels whose u32 half table fits the LDS image with the levels below
+# (4 (M/2 + 1) bytes; q = 281 at g = 2 leaves under 600 bytes)
+HALF_U32 = {(257, 2), (263, 2), (269, 2), (271, 2), (277, 2), (281, 2), (41, 3)}
+
+
+@pytest.mark.parametrize("q,g,n", [(283, 2, 20), (293, 2, 20), (43, 3, 5), (47, 3, 5), (49, 3, 4)])
 def test_half_period_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
-    """Top levels of 65 535 .. 131 070 nonzero elements: Z(k) for k <= M/2 as
-    17-bit entries in LDS, the rest through Z(-k) = Z(k) - k (form F), split over
-    mu_4 (257, 293, 41) or mu_2 (283, 47), on seeded rows and on rows with zero
-    coefficients, every launch form against the oracle."""
+    """Top levels of 65 535 .. 131 070 nonzero elements whose u32 half table
+    would not fit: Z(k) for k <= M/2 as 17-bit entries in LDS, the rest through
+    Z(-k) = Z(k) - k (form F), split over mu_4 (293, 49) or mu_2 (283, 43, 47), on
+    seeded rows and on rows with zero coefficients, every launch form against
+    the oracle."""
     assert gctx.plan_info(q, g)[-1]["form"] == 4
     curves = curvegen_mod.sample(q, g, n, seed=780 + q, dtype=np.int16)
+    sparse = curves.copy()
+    for i in range(len(sparse)):
+        top = 2 * g + 2 if sparse[i, 2 * g + 2] else 2 * g + 1
+        for k in ((i % top), ((3 * i + 1) % top))[: 1 + i % 2]:
+            sparse[i, k] = 0
+    _check(gctx, oracle_mod, q, g, curves)
+    _check(gctx, oracle_mod, q, g, sparse)
+
+
+@pytest.mark.parametrize("q,g,n", [(257, 2, 24), (263, 2, 20), (281, 2, 20), (41, 3, 6)])
+def test_half_period_u32_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
+    """The same half period as u32 entries in byte units (form G, one read per
+    lookup, the zero marker folding to itself) where the image fits, split over
+    mu_4 (257, 281, 41) or mu_2 (263), on seeded rows and on rows with zero
+    coefficients, every launch form against the oracle."""
+    assert (q, g) in HALF_U32 and gctx.plan_info(q, g)[-1]["form"] == 5
+    curves = curvegen_mod.sample(q, g, n, seed=781 + q, dtype=np.int16)
     sparse = curves.copy()
     for i in range(len(sparse)):
         top = 2 * g + 2 if sparse[i, 2 * g + 2] else 2 * g + 1
