@@ -54,7 +54,8 @@ TRAFFIC_SUMMARY = {"zech": os.path.join(PROFILES, "count_kernel_g3_q13_2p24_hbm_
                    "mfma": os.path.join(PROFILES, "vcount_kernel_g3_q13_2p24_hbm_traffic.md")}
 COUNTER_SUMMARY = {"zech": os.path.join(PROFILES, "count_kernel_g3_q13_2p24_counters.md"),
                    "mfma": os.path.join(PROFILES, "vcount_kernel_g3_q13_2p24_counters.md")}
-KERNEL_SOURCES = {"zech": ("paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
+KERNEL_SOURCES = {"zech": ("paper_1805_11991_amd/csrc/count_impl.h", "paper_1805_11991_amd/csrc/count_launch.h",
+                           "paper_1805_11991_amd/csrc/kernels.hip", "paper_1805_11991_amd/csrc/plan.h",
                            "paper_1805_11991_amd/autotune/gfx950.json"),
                   "mfma": ("paper_1805_11991_amd/csrc/vcount.hip", "paper_1805_11991_amd/csrc/plan.h")}
 

@@ -22,7 +22,8 @@ LIB = os.path.join(HERE, "libhwcount.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-SOURCES = ["kernels.hip", "vcount.hip", "hist.hip", "diag.hip", "capi.cpp", "field.cpp"]
+SOURCES = ["count_g4.hip", "count_g3.hip", "count_g2.hip", "count_g1.hip", "kernels.hip", "vcount.hip", "hist.hip",
+           "diag.hip", "capi.cpp", "field.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", os.path.join(ROOT, "include")]
