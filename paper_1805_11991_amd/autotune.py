@@ -35,7 +35,7 @@ DB_DIR = os.path.join(HERE, "autotune")
 
 SPACE = {
     "split": [1, 0],
-    "split_min_m": [64, 2048],
+    "split_min_m": [0, 64, 2048],    # 0: every level split, the base field included
     "block": [256, 512, 1024],
     "waves_per_simd": [1, 6],
     "device_tables": ["none", "top"],
