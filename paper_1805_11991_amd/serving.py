@@ -74,6 +74,13 @@ class Chunk:
     req: Request
     lo: int
     hi: int
+    seq: int = 0                       # order of intake
+
+
+def work_estimate(q: int, g: int, n: int) -> float:
+    """Relative device work of n curves of genus g over F_q: the top level's
+    points swept with the Frobenius orbits, q^g / g per curve, dominates."""
+    return n * (q ** g) / g
 
 
 def validate(req: Request) -> str | None:
@@ -113,8 +120,13 @@ def merge_hist(parts: list[tuple[np.ndarray, np.ndarray]], g: int):
 
 class Server:
     def __init__(self, executor, batch_curves: int = 1 << 22, max_inflight: int = 2, clock=time.perf_counter,
-                 max_jobs: int | None = None):
+                 max_jobs: int | None = None, max_wait: float = 0.05):
         self.ex = executor
+        # batches take the least work first, so that small requests do not
+        # wait behind large ones; a chunk that has waited max_wait seconds
+        # (from its request's arrival) goes ahead of the rest, oldest first
+        self.max_wait = max_wait
+        self._seq = 0
         self.batch_curves = batch_curves
         # an executor with slots of its own bounds the batches in flight and their bytes
         self.max_inflight = min(max_inflight, getattr(executor, "slots", max_inflight))
@@ -145,7 +157,8 @@ class Server:
             per = max(1, min(per, (self.batch_bytes - 4096) // per_curve))
         req.chunks_left = math.ceil(n / per)
         for lo in range(0, n, per):
-            self.pending.append(Chunk(req, lo, min(n, lo + per)))
+            self.pending.append(Chunk(req, lo, min(n, lo + per), self._seq))
+            self._seq += 1
 
     # -- the loop
     def step(self) -> int:
@@ -157,19 +170,22 @@ class Server:
             self._collect(handle, chunks)
         while self.pending and len(self.inflight) < self.max_inflight:
             batch, room, room_b = [], self.batch_curves, self.batch_bytes
-            while self.pending and len(batch) < self.max_jobs:
-                ch = self.pending[0]
+            taken = set()
+            for ch in self._order(self.clock()):
+                if len(batch) >= self.max_jobs:
+                    break
                 m = ch.hi - ch.lo
                 b = self._bytes(ch)
                 if m > room or (room_b is not None and b > room_b):
-                    break
-                self.pending.popleft()
+                    continue                  # a smaller chunk may still fit
+                taken.add(ch.seq)
                 if ch.req.error:          # an earlier chunk of the request failed
                     continue
                 batch.append(ch)
                 room -= m
                 if room_b is not None:
                     room_b -= b
+            self.pending = deque(ch for ch in self.pending if ch.seq not in taken)
             if not batch:
                 break
             self._launch(batch)
@@ -181,6 +197,13 @@ class Server:
                 self.ex.wait_any([h for h, _ in self.inflight])
 
     # -- internals
+    def _order(self, now: float) -> list[Chunk]:
+        def key(ch: Chunk):
+            if now - ch.req.arrival >= self.max_wait:
+                return (0, 0.0, ch.seq)
+            return (1, work_estimate(ch.req.q, ch.req.g, ch.hi - ch.lo), ch.seq)
+        return sorted(self.pending, key=key)
+
     def _bytes(self, ch: Chunk) -> int:
         if self.batch_bytes is None:
             return 0

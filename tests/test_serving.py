@@ -66,6 +66,29 @@ def test_batches_respect_budget_and_split_large_requests():
     assert reqs[0].latency is not None and srv.curves_done == 3500
 
 
+def test_least_work_first_with_aging():
+    # batches take the least work first; a chunk older than max_wait goes
+    # ahead of newer ones whatever its size
+    t = [0.0]
+    ex = FakeExecutor(delay=0)
+    srv = serving.Server(ex, batch_curves=920, max_inflight=1, clock=lambda: t[0], max_wait=1.0)
+    big, s1, s2 = _req(0, 13, 4, 900), _req(1, 5, 2, 50), _req(2, 5, 2, 50)
+    for r in (big, s1, s2):
+        r.arrival = 0.0
+        srv.submit(r)
+    srv.step()
+    assert ex.submitted == [[(5, 2, 50), (5, 2, 50)]]
+    t[0] = 2.0
+    s3 = _req(3, 5, 2, 50)
+    s3.arrival = 2.0
+    srv.submit(s3)
+    srv.step()
+    assert ex.submitted[1] == [(13, 4, 900)]
+    srv.drain()
+    assert ex.submitted[2] == [(5, 2, 50)]
+    assert all(r.error is None and r.N is not None for r in (big, s1, s2, s3))
+
+
 def test_invalid_requests_fail_alone():
     ex = FakeExecutor()
     srv = serving.Server(ex, batch_curves=1 << 12)
