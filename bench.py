@@ -256,9 +256,10 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB copy kernel (scale for the traffic counters)")
-    ap.add_argument("--profile-case", choices=("g2_q283_lds", "g2_q283_device"),
+    ap.add_argument("--profile-case", choices=("g2_q283_lds", "g2_q283_device", "g4_q13"),
                     help="counter runs only: time this case alone (g=2 q=283, 2^20 curves, the top level's "
-                         "table as a half table in LDS or in device memory) and print its line")
+                         "table as a half table in LDS or in device memory; g=4 q=13, 2^26 curves) and "
+                         "print its line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the counter has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -373,12 +374,12 @@ def main():
         }
 
     if args.profile_case:
-        qp, gp, npc = 283, 2, 1 << 20
+        qp, gp, npc = (13, 4, 1 << 26) if args.profile_case == "g4_q13" else (283, 2, 1 << 20)
         pctx = ctx
         if args.profile_case == "g2_q283_device":
             pctx = hwcount.Context(device=0, autotune_db=None)
             pctx.set_option(hwcount.HWC_OPT_DEVICE_TABLES, 1 << (gp - 1))
-        pb = setup(qp, gp, npc, curvegen.BASE_SEED + 2 + qp)
+        pb = setup(qp, gp, npc, curvegen.BASE_SEED + (3 if qp == 13 else 2 + qp))   # the sets of the full run
         tp = timed_steps(torch, stream, runner(pctx, qp, gp, pb, 0), args.steps, args.warmup)
         kp = kernel_ms(pctx, runner(pctx, qp, gp, pb, 0), 2)
         pctx.status()
@@ -386,7 +387,8 @@ def main():
         print(json.dumps({"metric": "curves/s", "value": round(npc / (tp["ms_per_step"] * 1e-3), 1),
                           "unit": "curves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
                           "ms_per_step": tp["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-                          "vs_baseline": None, "dtype": "int16 codes, integer logs", "data": "synthetic",
+                          "vs_baseline": None, "dtype": f"int{8 * pb[1].element_size()} codes, integer logs",
+                          "data": "synthetic",
                           "config": {"workload": f"profile case {args.profile_case}", "q": qp, "g": gp,
                                      "curves": npc},
                           "count_kernel_ms": round(kp["count_ms"], 4)}))
