@@ -550,7 +550,10 @@ __device__ __forceinline__ uint32_t horner_class_c(uint32_t tab, const uint32_t*
     constexpr int TOP = D - ((D - R) % MS);
 #pragma unroll
     for (int i = TOP - MS; i >= 0; i -= MS) {
-      const uint32_t v = tab_c<TM>(tab, gtab, M, fold(a + sdel[i] + Y, M));   // index < 3M
+      // index < 3M, folded below 2M, which every form reads; the first step
+      // (a = 0) is below 2M already
+      const uint32_t r = (i == TOP - MS) ? sdel[i] + Y : fold(a + sdel[i] + Y, M);
+      const uint32_t v = tab_c<TM>(tab, gtab, M, r);
       if (EXACT) a = (a == M) ? 0u : v;
       else { hit |= v == M; a = v; }
     }
@@ -678,29 +681,33 @@ __device__ __forceinline__ void sweep_split_c(const LevelDesc& L, const uint32_t
     const uint32_t uE = addmod(addmod(x2, p2, M), p0 ? M - p0 : 0u, M);
     const uint32_t uO = addmod(addmod(x2, p3, M), p1 ? M - p1 : 0u, M);
     const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
-    // Every index below stays under 3M whatever the marker values (a_r <= M,
-    // folded offsets < M), so no clamps are needed.  Any vanishing
+    // Every index below stays under 2M, the table's two periods, whatever the
+    // marker values (a_r <= M, folded bases and offsets < M), so no clamps are
+    // needed.  Any vanishing
     // sub-polynomial, E or O value sends the wave through the zero-safe
     // recomputation, which keeps the common path free of selects.
     const bool rare = (a0 == M) | (a1 == M) | (a2 == M) | (a3 == M);
     const uint32_t FE = fold(K2 - a0, M), FO = fold(K3 - a1, M);    // [0, M)
-    const uint32_t Ep = tab_c<TM>(tab, gtab, M, fold(a2 + FE + uE, M));
-    const uint32_t Em = tab_c<TM>(tab, gtab, M, fold(a2 + FE + addmod(uE, h, M), M));
-    const uint32_t Op = tab_c<TM>(tab, gtab, M, fold(a3 + FO + uO, M));
-    const uint32_t Om = tab_c<TM>(tab, gtab, M, fold(a3 + FO + addmod(uO, h, M), M));
+    // the bases a2 + FE, a3 + FO folded once each ([0, M)), so that the two
+    // reads of each (offsets uE, uE + h below M) need no fold of their own
+    const uint32_t bE = fold(a2 + FE, M), bO = fold(a3 + FO, M);
+    const uint32_t Ep = tab_c<TM>(tab, gtab, M, bE + uE);
+    const uint32_t Em = tab_c<TM>(tab, gtab, M, bE + addmod(uE, h, M));
+    const uint32_t Op = tab_c<TM>(tab, gtab, M, bO + uO);
+    const uint32_t Om = tab_c<TM>(tab, gtab, M, bO + addmod(uO, h, M));
     uint32_t zs = 0, odd;
     if (!__ballot(rare | (Ep == M) | (Em == M) | (Op == M) | (Om == M))) {
       const uint32_t G = fold(fold(a1 + K1 - a0, M), M) + M;       // [M, 2M)
-      const uint32_t Fp = fold(G - Ep, M), Fm = fold(G - Em, M);
+      // O + F for the points x, -x (s even) and ix, -ix (s odd), folded once
+      const uint32_t OFp = fold(Op + fold(G - Ep, M), M), OFm = fold(Om + fold(G - Em, M), M);
       uint32_t u = 0;
       uint32_t r[4];
       bool anyz = false;
 #pragma unroll
       for (uint32_t s = 0; s < 4; ++s) {
         const uint32_t E = (s & 1u) ? Em : Ep;
-        const uint32_t O = (s & 1u) ? Om : Op;
-        const uint32_t F = (s & 1u) ? Fm : Fp;
-        r[s] = tab_c<TM>(tab, gtab, M, fold(O + F + addmod(vf, s * step, M), M));
+        const uint32_t OF = (s & 1u) ? OFm : OFp;
+        r[s] = tab_c<TM>(tab, gtab, M, OF + addmod(vf, s * step, M));
         u += ((E ^ r[s]) >> 1) & 1u;
         anyz |= r[s] == M;
       }
@@ -787,10 +794,12 @@ __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_
     const uint32_t vf = addmod(addmod(x, p1, M), p0 ? M - p0 : 0u, M);
     uint32_t zs = 0, odd;
     if (!__ballot((a0 == M) | (a1 == M))) {
-      // a1 < M, F1 < M and the power < M: every index stays under 3M
+      // a1 < M and F1 < M: the base a1 + F1 folded once ([0, M)), so that
+      // both reads (offsets below M) stay under 2M with no fold of their own
       const uint32_t F1 = fold(K1 - a0, M);                            // [0, M)
-      const uint32_t rp = tab_c<TM>(tab, gtab, M, fold(a1 + F1 + vf, M));
-      const uint32_t rm = tab_c<TM>(tab, gtab, M, fold(a1 + F1 + addmod(vf, h, M), M));
+      const uint32_t b1 = fold(a1 + F1, M);
+      const uint32_t rp = tab_c<TM>(tab, gtab, M, b1 + vf);
+      const uint32_t rm = tab_c<TM>(tab, gtab, M, b1 + addmod(vf, h, M));
       uint32_t u = ((rp >> 1) & 1u) + ((rm >> 1) & 1u);
       if (__ballot((rp == M) | (rm == M))) {
         zs = (rp == M) + (rm == M);
