@@ -12,7 +12,7 @@ Also measured in the same run, each as its own object of the JSON line:
   zech_path        the Zech path at g=3 and g=4 over F_13: batched and plain
                    (one launch per level, no graph) with per-step spread,
                    lookups/s against the LDS peak and the measured gather ceiling
-  largest_field_g2 g = 2 over F_283: the top level's Zech table as a half
+  largest_field_g2 g = 2 over F_293: the top level's Zech table as a half
                    table in LDS (the default), and placed in device memory
                    (lookups/s against the measured ceiling of random gathers
                    from such a table, L2/MALL-served)
@@ -256,8 +256,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB copy kernel (scale for the traffic counters)")
-    ap.add_argument("--profile-case", choices=("g2_q283_lds", "g2_q283_device", "g4_q13"),
-                    help="counter runs only: time this case alone (g=2 q=283, 2^20 curves, the top level's "
+    ap.add_argument("--profile-case", choices=("g2_q293_lds", "g2_q293_device", "g4_q13"),
+                    help="counter runs only: time this case alone (g=2 q=293, 2^20 curves, the top level's "
                          "table as a half table in LDS or in device memory; g=4 q=13, 2^26 curves) and "
                          "print its line")
     args = ap.parse_args()
@@ -374,9 +374,9 @@ def main():
         }
 
     if args.profile_case:
-        qp, gp, npc = (13, 4, 1 << 26) if args.profile_case == "g4_q13" else (283, 2, 1 << 20)
+        qp, gp, npc = (13, 4, 1 << 26) if args.profile_case == "g4_q13" else (293, 2, 1 << 20)
         pctx = ctx
-        if args.profile_case == "g2_q283_device":
+        if args.profile_case == "g2_q293_device":
             pctx = hwcount.Context(device=0, autotune_db=None)
             pctx.set_option(hwcount.HWC_OPT_DEVICE_TABLES, 1 << (gp - 1))
         pb = setup(qp, gp, npc, curvegen.BASE_SEED + (3 if qp == 13 else 2 + qp))   # the sets of the full run
@@ -532,7 +532,7 @@ def main():
         torch.cuda.empty_cache()
 
         # ---------------- the largest field of the g=2 range: half table in LDS, and in device memory ----------------
-        qd, gd, nd = 283, 2, 1 << 20
+        qd, gd, nd = 293, 2, 1 << 20
         bufsd = setup(qd, gd, nd, curvegen.BASE_SEED + 2 + qd)
         lv_d = ctx.plan_info(qd, gd)
         Md = lv_d[-1]["M"]

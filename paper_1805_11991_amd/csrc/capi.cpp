@@ -456,8 +456,10 @@ uint32_t split_factor(uint32_t q, uint32_t form, uint32_t M, const Tuning& T) {
 // M fits 16 bits, G (u32 half table) or else F (17-bit half table) where it
 // fits 17 bits, else D; one level at most in an element form (C, E, F or G:
 // its table starts the image), the others above it in D; a G level that
-// leaves the image too large becomes F; then move the largest LDS levels to D
-// until the image fits.
+// leaves the image too large first moves the levels below it to device
+// memory, smallest first (a level of F_{q^i} below F_{q^j} holds about
+// q^(i-j) of the points), and becomes F only if that is not enough; then move
+// the largest LDS levels to D until the image fits.
 std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask) {
   std::vector<uint32_t> form(g);
   std::vector<uint64_t> M(g);
@@ -483,8 +485,15 @@ std::vector<uint32_t> choose_forms(uint32_t q, uint32_t g, uint32_t device_mask)
   };
   for (uint32_t j = 0; j < g; ++j)
     if ((device_mask >> j) & 1u) form[j] = hwc::kFormD;
-  for (uint32_t j = 0; j < g; ++j)
-    if (form[j] == hwc::kFormG && total() > kLdsLimit) form[j] = hwc::kFormF;
+  for (uint32_t j = 0; j < g; ++j) {
+    if (form[j] != hwc::kFormG || total() <= kLdsLimit) continue;
+    const std::vector<uint32_t> keep = form;
+    for (uint32_t i = 0; i < j && total() > kLdsLimit; ++i) form[i] = hwc::kFormD;
+    if (total() > kLdsLimit) {
+      form = keep;
+      form[j] = hwc::kFormF;
+    }
+  }
   for (int j = (int)g - 1; j >= 0 && total() > kLdsLimit; --j) form[j] = hwc::kFormD;
   return form;
 }

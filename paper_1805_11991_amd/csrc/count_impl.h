@@ -459,8 +459,11 @@ __device__ __forceinline__ uint32_t tab_c(uint32_t tab, const uint32_t* __restri
     const uint32_t j = up ? M - k : k;                                    // j <= h
     const uint32_t bits = tab + ((2u * (h + 1u) + 15u) & ~15u);           // the 17th bits after the low halves
     const uint32_t z = lds_u16(tab + 2u * j) | (((lds_u32(bits + 4u * (j >> 5)) >> (j & 31u)) & 1u) << 16);
-    if (z == M) return M2;                                                // the marker sits at j = h only
-    return 2u * fold(z + (up ? k : 0u), M);
+    // Z(k) is never 0 (1 + gamma^k = 1 has no solution), so the sum is
+    // reduced into [1, M] instead of [0, M): the same value for every entry,
+    // and the marker M (at j = h, not mirrored) stays M, i.e. M2 in bytes
+    const uint32_t y = z + (up ? k : 0u) - 1u;                            // < 2M - 1
+    return 2u * fold(y, M) + 2u;
   }
   if (TM == kTabG) {
     // entries 2 Z(j), j <= M/2, and 2 M2 at j = M/2 (the marker, which the

@@ -320,16 +320,18 @@ def test_device_memory_tables(oracle_mod, curvegen_mod, q, g, n):
         _check(ctx, oracle_mod, q, g, curves)
 
 
-# top levels whose u32 half table fits the LDS image with the levels below
-# (4 (M/2 + 1) bytes; q = 281 at g = 2 leaves under 600 bytes)
-HALF_U32 = {(257, 2), (263, 2), (269, 2), (271, 2), (277, 2), (281, 2), (41, 3)}
+# top levels whose u32 half table (4 (M/2 + 1) bytes) fits the LDS image: with
+# the levels below (q = 281 at g = 2 leaves under 600 bytes), or once those
+# levels are moved to device memory (q = 283 at g = 2, 43 at g = 3)
+HALF_U32 = {(257, 2), (263, 2), (269, 2), (271, 2), (277, 2), (281, 2), (283, 2), (41, 3), (43, 3)}
+LOWER_IN_DEVICE = {(283, 2), (43, 3)}
 
 
-@pytest.mark.parametrize("q,g,n", [(283, 2, 20), (293, 2, 20), (43, 3, 5), (47, 3, 5), (49, 3, 4)])
+@pytest.mark.parametrize("q,g,n", [(289, 2, 20), (293, 2, 20), (47, 3, 5), (49, 3, 4)])
 def test_half_period_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
     """Top levels of 65 535 .. 131 070 nonzero elements whose u32 half table
     would not fit: Z(k) for k <= M/2 as 17-bit entries in LDS, the rest through
-    Z(-k) = Z(k) - k (form F), split over mu_4 (293, 49) or mu_2 (283, 43, 47), on
+    Z(-k) = Z(k) - k (form F), split over mu_4 (289, 293, 49) or mu_2 (47), on
     seeded rows and on rows with zero coefficients, every launch form against
     the oracle."""
     assert gctx.plan_info(q, g)[-1]["form"] == 4
@@ -343,13 +345,16 @@ def test_half_period_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
     _check(gctx, oracle_mod, q, g, sparse)
 
 
-@pytest.mark.parametrize("q,g,n", [(257, 2, 24), (263, 2, 20), (281, 2, 20), (41, 3, 6)])
+@pytest.mark.parametrize("q,g,n", [(257, 2, 24), (263, 2, 20), (281, 2, 20), (283, 2, 20), (41, 3, 6), (43, 3, 5)])
 def test_half_period_u32_lds_tables(gctx, oracle_mod, curvegen_mod, q, g, n):
     """The same half period as u32 entries in byte units (form G, one read per
-    lookup, the zero marker folding to itself) where the image fits, split over
-    mu_4 (257, 281, 41) or mu_2 (263), on seeded rows and on rows with zero
-    coefficients, every launch form against the oracle."""
-    assert (q, g) in HALF_U32 and gctx.plan_info(q, g)[-1]["form"] == 5
+    lookup, the zero marker folding to itself) where the image fits, with the
+    levels below in device memory (form D) where only that makes it fit (283,
+    43), split over mu_4 (257, 281, 41) or mu_2 (263, 283, 43), on seeded rows
+    and on rows with zero coefficients, every launch form against the oracle."""
+    levels = gctx.plan_info(q, g)
+    assert (q, g) in HALF_U32 and levels[-1]["form"] == 5
+    assert all((L["form"] == 2) == ((q, g) in LOWER_IN_DEVICE) for L in levels[:-1]), levels
     curves = curvegen_mod.sample(q, g, n, seed=781 + q, dtype=np.int16)
     sparse = curves.copy()
     for i in range(len(sparse)):
@@ -388,6 +393,7 @@ def _batch_specs(curvegen_mod):
     specs.append((9, 2, curvegen_mod.sample(9, 2, 500, seed=91)))
     specs.append((293, 2, curvegen_mod.sample(293, 2, 10, seed=92)))
     specs.append((49, 3, curvegen_mod.sample(49, 3, 3, seed=93)))
+    specs.append((283, 2, curvegen_mod.sample(283, 2, 8, seed=97)))
     specs.append((7, 1, curvegen_mod.sample(7, 1, 300, seed=94)))
     specs.append((13, 3, curvegen_mod.sample(13, 3, 0, seed=95)))          # empty request
     specs.append((11, 4, curvegen_mod.sample(11, 4, 33, seed=96)))
