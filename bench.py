@@ -391,7 +391,11 @@ def main():
                           "data": "synthetic",
                           "config": {"workload": f"profile case {args.profile_case}", "q": qp, "g": gp,
                                      "curves": npc},
-                          "count_kernel_ms": round(kp["count_ms"], 4)}))
+                          "count_kernel_ms": round(kp["count_ms"], 4),
+                          "levels": [{k: L[k] for k in ("M", "form", "nx", "msplit")} for L in pctx.plan_info(qp, gp)],
+                          "algorithmic_lookups_per_launch": algorithmic_lookups(pb[0], pctx.plan_info(qp, gp)),
+                          "performed_lookups_per_launch": lookups_per_batch(
+                              evaluated_rows(pctx, qp, gp, pb[1]), pctx.plan_info(qp, gp))[0]}))
         if args.calib_copy:
             calibration_copy(torch, dev)
         return

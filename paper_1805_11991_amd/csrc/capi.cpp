@@ -188,6 +188,10 @@ struct JobSlot {          // job descriptors of a direct multi-plan launch
 };
 
 constexpr uint32_t kSmallStride = 4 * 2048 + 16;   // per-job bucketing words (u32)
+// tile parts of a batch job: for top levels of at least this many swept
+// points, up to 2^kPartMaxLog parts per tile
+constexpr uint32_t kPartMinPoints = 8192;
+constexpr uint32_t kPartMaxLog = 3;
 constexpr int kJobSlots = 4;
 
 // Scratch of the work enqueued on one stream.  Calls on different streams
@@ -197,7 +201,7 @@ constexpr int kJobSlots = 4;
 // chain and its event, once complete, means all of it is.
 struct ScratchSet {
   Buf pid, small, tiles, perm, lv, hist, tcodes;                     // one request
-  Buf bpid, bperm, btiles, bsmall, btcodes;   // multi-plan launches
+  Buf bpid, bperm, btiles, bsmall, btcodes, bacc;   // multi-plan launches
   JobSlot slots[kJobSlots];
   int next_slot = 0;
   hipStream_t last = nullptr;
@@ -1329,7 +1333,10 @@ struct BatchPlan {
   std::vector<uint64_t> max_tiles;
   std::vector<uint64_t> tco;        // byte offset of the job's dense translates, or kNoShift
   std::vector<BatchSeg> segs;       // launches over `order`
-  uint64_t ntot = 0, tiles_tot = 0, nhist = 0, tbytes = 0, nlv = 0;
+  std::vector<uint32_t> plog;       // tile parts (log2) per sorted job
+  std::vector<uint64_t> aoff;       // word offset of the job's part counts in bacc
+  uint64_t ntot = 0, tiles_tot = 0, nhist = 0, tbytes = 0, nlv = 0, acc_words = 0;
+  uint64_t resident = 0;            // waves the batch launch keeps in flight
 };
 
 
@@ -1369,6 +1376,9 @@ int enqueue_batch(hwc_ctx* c, const hwc_job* jobs, const BatchPlan& B, const hwc
                                  sm + 4096, sm + 6144, sm + 8192, sm + 8196, tiles + B.toff[r], perm + B.off[r],
                                  B.max_tiles[r], shifted, s));
     }
+    // the part counts and finished-part counters start at zero (a fill
+    // kernel, which graph capture records as an ordinary kernel node)
+    if (B.acc_words) HIPX(c, hwc::launch_fill(static_cast<uint32_t*>(st.bacc.p), 0, B.acc_words, s));
     for (const BatchSeg& G : B.segs)
       HIPX(c, hwc::launch_batch(d_jobs + G.begin, (uint32_t)(G.end - G.begin), G.gmax, G.lds, G.grid, G.block, s));
     for (size_t r = 0; r < nz; ++r) {
@@ -1446,7 +1456,9 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
   const size_t nz = B.order.size();
   // one launch over every job: the workgroup holds the largest image, the
   // kernel the largest genus, and the block size is the one that keeps the
-  // most waves resident (the smaller on a tie).  (One launch per LDS size
+  // most waves busy -- resident, and no more than there are tiles -- the
+  // smaller on a tie, so that a small batch spreads over every CU instead of
+  // filling a few with large workgroups.  (One launch per LDS size
   // class, so that small plans keep more workgroups per CU, measured slower
   // on the 71 fields below 300: each launch costs at least one tile's
   // latency, and the classes' tiles no longer share the CUs.)
@@ -1461,17 +1473,20 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     }
     uint64_t tiles = 0;
     for (size_t k = G.begin; k < G.end; ++k) tiles += (jobs[B.order[k]].n + hwc::kWave - 1) / hwc::kWave + 4;
-    int best = -1, bpc_best = 1;
+    int64_t best = -1;
+    int bpc_best = 1;
     for (uint32_t b : {256u, 512u, 1024u}) {
       int n = 0;
       HIPX(c, hwc::occupancy_batch(G.gmax, b, G.lds, &n));
-      if (n * (int)(b / hwc::kWave) > best) {
-        best = n * (int)(b / hwc::kWave);
+      const int64_t busy = std::min<int64_t>((int64_t)tiles, (int64_t)n * (b / hwc::kWave) * c->cus);
+      if (busy > best) {
+        best = busy;
         G.block = b;
         bpc_best = std::max(n, 1);
       }
     }
     G.grid = persistent_grid((uint32_t)(c->cus * bpc_best), G.block, tiles);
+    B.resident = (uint64_t)c->cus * bpc_best * (G.block / hwc::kWave);
     B.segs.push_back(G);
   }
   for (size_t r = 0; r < nz; ++r) {
@@ -1482,6 +1497,16 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     B.max_tiles.push_back(mt);
     B.ntot += J.n;
     B.tiles_tot += mt;
+    // a job of few expensive tiles (a large top level swept by orbits) has
+    // each tile's top level cut into parts, so that its work spreads over the
+    // waves in flight instead of holding a few of them for the whole launch
+    const hwc::LevelDesc& top = B.plans[B.order[r]]->desc.lv[J.g - 1];
+    uint32_t pl = 0;
+    if (orbit && top.xs && top.nx >= kPartMinPoints)
+      while (pl < kPartMaxLog && (J.n / hwc::kWave + 1) << pl < B.resident) ++pl;
+    B.plog.push_back(pl);
+    B.aoff.push_back(B.acc_words);
+    if (pl) B.acc_words += J.n * J.g + mt;
     if (B.plans[B.order[r]]->d_shift && J.n > 0) {
       B.tco.push_back(B.tbytes);
       B.tbytes += (J.n * (2 * J.g + 3) * J.coeff_bytes + 255) / 256 * 256;
@@ -1499,6 +1524,7 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
   }
   if (B.nhist && (rc = ensure(c, set, st.hist, hwc::hist_scratch_bytes(B.nhist)))) return rc;
   if (B.nlv && (rc = ensure(c, set, st.lv, B.nlv * 4))) return rc;
+  if (B.acc_words && (rc = ensure(c, set, st.bacc, B.acc_words * 4))) return rc;
   std::vector<hwc::JobDesc> hj(std::max<size_t>(nz, 1));
   for (size_t r = 0; r < nz; ++r) {
     const hwc_job& J = jobs[B.order[r]];
@@ -1513,6 +1539,9 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     hj[r].outN = J.d_out_N;
     hj[r].cb = (uint32_t)J.coeff_bytes;
     hj[r].g = J.g;
+    hj[r].plog = B.plog[r];
+    hj[r].acc = B.plog[r] ? static_cast<uint32_t*>(st.bacc.p) + B.aoff[r] : nullptr;
+    hj[r].done = B.plog[r] ? hj[r].acc + J.n * J.g : nullptr;
   }
   const size_t jbytes = std::max<size_t>(nz, 1) * sizeof(hwc::JobDesc);
   if ((rc = order_begin(c, set, s))) return rc;
@@ -2042,7 +2071,7 @@ void hwc_ctx_destroy(hwc_ctx* c) {
       if (b->p) (void)hipFree(b->p);
     for (auto& st : c->sets) {
       for (Buf* b : {&st.pid, &st.small, &st.tiles, &st.perm, &st.lv, &st.hist, &st.tcodes, &st.bpid, &st.bperm,
-                     &st.btiles, &st.bsmall, &st.btcodes})
+                     &st.btiles, &st.bsmall, &st.btcodes, &st.bacc})
         if (b->p) (void)hipFree(b->p);
       for (auto& sl : st.slots) {
         if (sl.p) (void)hipFree(sl.p);
@@ -2478,6 +2507,7 @@ int hwc_ctx_reserve(hwc_ctx* c, uint64_t max_curves, uint32_t max_jobs, void* st
   if ((rc = ensure(c, set, st.btiles, tiles * 8))) return rc;
   if ((rc = ensure(c, set, st.bsmall, J * kSmallStride * 4))) return rc;
   if ((rc = ensure(c, set, st.btcodes, N * (2 * hwc::kMaxG + 3) * 2 + J * 256))) return rc;
+  if ((rc = ensure(c, set, st.bacc, (N * hwc::kMaxG + tiles) * 4))) return rc;
   const size_t jbytes = std::max<size_t>(J, 64) * sizeof(hwc::JobDesc);
   for (auto& sl : st.slots) {
     if (sl.bytes >= jbytes) continue;

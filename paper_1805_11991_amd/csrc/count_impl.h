@@ -826,10 +826,13 @@ __device__ __forceinline__ void sweep_split2_c(const LevelDesc& L, const uint32_
 }
 
 // Counts for one level: returns z | ns << 8 (roots and non-squares among the
-// swept x; squares are nx - z - ns).
+// swept x; squares are nx - z - ns).  plog > 0: only part `part` of 2^plog
+// consecutive shares of the level's point lists (the counts of the parts add
+// up to the level's); where a list is implicit (full sweep), part 0 sweeps
+// the whole level and the other parts nothing.
 template <int G>
 __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb, const uint32_t (&code)[2 * G + 3],
-                                uint32_t top, uint32_t mask) {
+                                uint32_t top, uint32_t mask, uint32_t part = 0, uint32_t plog = 0) {
   constexpr int NC = 2 * G + 3;
   // the level with its table offsets made absolute LDS addresses
   LevelDesc L = Lp;
@@ -870,6 +873,25 @@ __device__ __forceinline__ uint32_t count_level(const LevelDesc& Lp, uint32_t lb
     for (int i = 0; i < NC; ++i)
       if ((sup >> i) & 1u) cls_mask |= 1u << (ms == 4 ? i % 4 : (ms == 3 ? i % 3 : i % 2));
     if (cls_mask != (1u << ms) - 1u) ms = 0;
+  }
+  if (plog) {
+    if (ms ? (L.xs_t != nullptr && L.xs_s != nullptr) : (L.xs != nullptr)) {
+      if (ms) {
+        const uint32_t t0 = (L.nt * part) >> plog, t1 = (L.nt * (part + 1)) >> plog;
+        const uint32_t s0 = (L.ns * part) >> plog, s1 = (L.ns * (part + 1)) >> plog;
+        L.xs_t += t0;
+        L.nt = t1 - t0;
+        L.xs_s += s0;
+        L.ns = s1 - s0;
+        L.nx = L.nt * ms + L.ns;
+      } else {
+        const uint32_t x0 = (L.nx * part) >> plog, x1 = (L.nx * (part + 1)) >> plog;
+        L.xs += x0;
+        L.nx = x1 - x0;
+      }
+    } else if (part) {
+      L.nx = L.nt = L.ns = 0;
+    }
   }
   // per-class relative deltas (element units) and lowest-coefficient logs
   uint32_t sdel[NC];
@@ -999,11 +1021,17 @@ __device__ __forceinline__ void assemble(const PlanDesc& P, const uint32_t (&lv)
 }
 
 // One tile (up to 64 curves of one pattern) through levels lvl_lo..lvl_hi.
+// With plog > 0 this is part `part` of tile `tile`: the levels below the top
+// belong to part 0, the top level's points are shared out (count_level); the
+// part adds its counts into acc, and the tile's last part to finish reads the
+// sums back and assembles N.
 template <int G, typename CT>
 __device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, const CT* __restrict__ codes,
                                              const uint32_t* __restrict__ perm, uint64_t w, uint32_t lvl_lo,
                                              uint32_t lvl_hi, int32_t* __restrict__ outN,
-                                             uint32_t* __restrict__ outLv) {
+                                             uint32_t* __restrict__ outLv, uint32_t tile = 0, uint32_t part = 0,
+                                             uint32_t plog = 0, uint32_t* __restrict__ acc = nullptr,
+                                             uint32_t* __restrict__ done = nullptr) {
   constexpr int NC = 2 * G + 3;
   const uint32_t lane = threadIdx.x & (kWave - 1);
   const uint32_t pat = uniform((uint32_t)(w & 0xFFFFu));
@@ -1030,9 +1058,27 @@ __device__ __forceinline__ void process_tile(const PlanDesc& P, uint32_t lb, con
   for (int j = 0; j < G; ++j) lv[j] = 0;
 #pragma unroll 1
   for (uint32_t j = lvl_lo; j <= lvl_hi; ++j) {
-    const uint32_t v = count_level<G>(load_level(P, j), lb, code, top, mask);
+    const bool shared = j + 1 == (uint32_t)G;
+    if (part && !shared) continue;
+    const uint32_t v = count_level<G>(load_level(P, j), lb, code, top, mask, shared ? part : 0u, shared ? plog : 0u);
 #pragma unroll
     for (int k = 0; k < G; ++k) lv[k] = (uint32_t)k == j ? v : lv[k];
+  }
+  if (plog) {
+    // packed counts add without carries: a level's zeros stay below 256
+    if (live) {
+#pragma unroll
+      for (int k = 0; k < G; ++k)
+        if (lv[k]) atomicAdd(acc + (uint64_t)curve * G + k, lv[k]);
+    }
+    __threadfence();
+    uint32_t prior = 0;
+    if (lane == 0) prior = atomicAdd(done + tile, 1u);
+    if (uniform(prior) != (1u << plog) - 1u) return;
+    __threadfence();
+#pragma unroll
+    for (int k = 0; k < G; ++k)
+      lv[k] = __hip_atomic_load(acc + (uint64_t)curve * G + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
   if (outN) {
@@ -1098,17 +1144,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
 // CU keeps in flight, which latency-bound device-memory tables need) is that
 // of the batch's genera, not of g = 4.
 template <int GMAX>
-__device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, uint64_t w) {
+__device__ __forceinline__ void process_job_tile(const JobDesc& J, uint32_t lb, uint32_t u) {
   const PlanDesc& P = *J.plan;
+  const uint32_t plog = J.plog, tile = u >> plog, part = u & ((1u << plog) - 1u);
+  const uint64_t w = sload64(J.tiles, tile);
 #define HWC_JOB(GG)                                                                                      \
   case GG:                                                                                               \
     if constexpr (GG <= GMAX) {                                                                          \
       if (J.cb == 1)                                                                                     \
         process_tile<GG, int8_t>(P, lb, static_cast<const int8_t*>(J.codes), J.perm, w, 0, GG - 1, J.outN, \
-                                 nullptr);                                                               \
+                                 nullptr, tile, part, plog, J.acc, J.done);                              \
       else                                                                                               \
         process_tile<GG, int16_t>(P, lb, static_cast<const int16_t*>(J.codes), J.perm, w, 0, GG - 1,     \
-                                  J.outN, nullptr);                                                      \
+                                  J.outN, nullptr, tile, part, plog, J.acc, J.done);                     \
     }                                                                                                    \
     break;
   switch (J.g) {
@@ -1135,7 +1183,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__
   const PlanDesc* staged = nullptr;
   for (uint32_t k = 0; k < njobs; ++k) {
     const JobDesc& J = jobs[k];
-    const uint32_t nt = *J.ntiles;
+    const uint32_t nt = *J.ntiles << J.plog;   // queue entries: tiles, or parts of tiles
     const PlanDesc* P = J.plan;
     if (P != staged) {
       __syncthreads();   // every wave is done with the image staged so far
@@ -1153,7 +1201,7 @@ __global__ __launch_bounds__(1024) void batch_kernel(const JobDesc* __restrict__
       if (lane == 0) v = atomicAdd(J.queue, 1u);
       const uint32_t t = uniform(v);
       if (t >= nt) break;
-      process_job_tile<GMAX>(J, lb, sload64(J.tiles, t));
+      process_job_tile<GMAX>(J, lb, t);
     }
   }
 }

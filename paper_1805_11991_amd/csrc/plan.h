@@ -183,6 +183,13 @@ struct JobDesc {
   uint32_t* queue;        // the job's tile queue (set to 0 by the bucketing)
   int32_t* outN;          // [n][g]
   uint32_t cb, g;         // code bytes, genus
+  // The top level's sweep of every tile cut into 2^plog parts (queue entry
+  // u: tile u >> plog, part u & (2^plog - 1)) when a job has few tiles for
+  // the waves in flight: the parts add their level counts into acc and the
+  // last part of a tile (counted in done) assembles N.  plog = 0: whole tiles.
+  uint32_t plog;
+  uint32_t* acc;          // [n][g] packed level counts (zero before the launch)
+  uint32_t* done;         // [tiles] parts finished (zero before the launch)
 };
 
 // A tile is up to 64 curves that share degree and zero pattern.

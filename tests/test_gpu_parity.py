@@ -437,6 +437,42 @@ def test_multi_plan_batch(gctx, oracle_mod, curvegen_mod):
                 assert L == 0
 
 
+@pytest.mark.parametrize("q,g,n", [(293, 2, 3000), (47, 3, 600)])
+def test_batch_tile_parts(gctx, oracle_mod, curvegen_mod, q, g, n):
+    """A batch job of few tiles over a large top level: each tile's top-level
+    sweep is cut into parts whose counts are summed before the tile's last part
+    assembles N.  On dense rows and on rows with zero coefficients (the split
+    and the unsplit point lists), over several tiles with a ragged last one, N
+    of the batch equals the single-request path's on every row, in the
+    captured graph, its replays and the direct launch, and the oracle's on a
+    sample of rows."""
+    import torch
+    from paper_1805_11991_amd import hwcount
+    dense = curvegen_mod.sample(q, g, n, seed=790 + q, dtype=np.int16)
+    sparse = dense[: n // 3].copy()
+    for i in range(len(sparse)):
+        top = 2 * g + 2 if sparse[i, 2 * g + 2] else 2 * g + 1
+        for k in ((i % top), ((3 * i + 1) % top))[: 1 + i % 2]:
+            sparse[i, k] = 0
+    rows = np.concatenate([dense, sparse])
+    m = len(rows)
+    d = torch.from_numpy(rows).cuda()
+    single = torch.empty((m, g), dtype=torch.int32, device="cuda")
+    gctx.count_curves_dev(q, g, d, single)
+    gctx.status()
+    ref = single.cpu().numpy()
+    sample = np.r_[0:20, n - 10:n, m - 20:m]
+    assert np.array_equal(ref[sample], oracle_mod.count_curves(q, g, rows[sample]))
+    job = dict(q=q, g=g, d_coeffs=d, d_out_N=torch.empty((m, g), dtype=torch.int32, device="cuda"))
+    for rep, flags in enumerate((0, 0, 0, hwcount.HWC_NO_GRAPH)):
+        print(f"  parts rep {rep} flags {flags}", flush=True)
+        job["d_out_N"].fill_(-1)
+        torch.cuda.synchronize()
+        gctx.count_batch([job], flags=flags)
+        gctx.status()
+        assert np.array_equal(job["d_out_N"].cpu().numpy(), ref), (rep, q, g)
+
+
 def test_two_streams_are_ordered(gctx, oracle_mod, curvegen_mod):
     """Calls of one context on different streams share scratch; the library
     orders them, so results stay exact when they are issued back to back."""
