@@ -264,8 +264,11 @@ int hwc_device_gather_rate(hwc_ctx* ctx, uint64_t table_entries, uint32_t chains
  * `stream`: the rows of every Zech-path job are bucketed, then a persistent
  * multi-plan launch takes the jobs one after another, most expensive tiles
  * first, every wave popping tiles from the current job's queue (the LDS
- * image restaged only when a workgroup moves to a job of another plan) --
- * the loops over the curves and fields of Algorithm 1 in one launch, where
+ * image restaged only when a workgroup moves to a job of another plan; a
+ * job of few tiles over a large top level has each tile's top-level sweep
+ * shared out over up to 8 waves, whose counts are summed before N is
+ * assembled) -- the loops over the curves and fields of Algorithm 1 in one
+ * launch, where
  * the paper launches once per curve and field (Sec. 3.3); jobs on the
  * opt-in matrix-product path follow as their own launches on the same
  * stream.
@@ -322,7 +325,8 @@ int hwc_ctx_set_plan_option(hwc_ctx* ctx, uint32_t q, uint32_t g, uint32_t flags
  * folded index over two periods; 2: u32 in device memory; 3: u16 in LDS, one
  * period, for M up to 65534; 4: half a period of 17-bit entries in LDS, for M
  * up to 131070; 5: the same half period as u32 entries in LDS, where it fits
- * the LDS image), the number nx of swept x, the
+ * the LDS image, if need be with the levels below it in device memory),
+ * the number nx of swept x, the
  * weight of each, the split factor m (0: plain Horner; else the sweep runs nt
  * tuples of m points x w^s, w^m = 1, sharing the sub-polynomial values at
  * x^m, plus ns single points), the LDS bytes of the plan, and mfma = 1 when
