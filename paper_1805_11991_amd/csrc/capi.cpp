@@ -27,7 +27,8 @@
 namespace hwc {
 hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
-                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s);
+                        int32_t* outN, uint32_t* outLv, uint32_t plog, uint32_t* acc, uint32_t* done, uint32_t grid,
+                        uint32_t block, uint32_t wpe, hipStream_t s);
 hipError_t occupancy_count(uint32_t g, int coeff_bytes, uint32_t block, uint32_t lds_bytes, uint32_t wpe,
                            int* blocks_per_cu);
 hipError_t prepare_kernels();
@@ -188,10 +189,13 @@ struct JobSlot {          // job descriptors of a direct multi-plan launch
 };
 
 constexpr uint32_t kSmallStride = 4 * 2048 + 16;   // per-job bucketing words (u32)
-// tile parts of a batch job: for top levels of at least this many swept
-// points, up to 2^kPartMaxLog parts per tile
+// Tile parts: a request whose top level sweeps at least this many points by
+// orbits has each tile's top-level sweep cut into 2^kPartLog parts, so that
+// the last tiles of a launch do not hold a few waves long after the rest of
+// the GPU has run dry (one 2^20-curve request at q = 293, g = 2: 80 -> 72 ms)
+// and a job of few tiles spreads over the waves in flight
 constexpr uint32_t kPartMinPoints = 8192;
-constexpr uint32_t kPartMaxLog = 3;
+constexpr uint32_t kPartLog = 3;
 constexpr int kJobSlots = 4;
 
 // Scratch of the work enqueued on one stream.  Calls on different streams
@@ -200,7 +204,7 @@ constexpr int kJobSlots = 4;
 // work when that work went to another stream), so every set's work forms one
 // chain and its event, once complete, means all of it is.
 struct ScratchSet {
-  Buf pid, small, tiles, perm, lv, hist, tcodes;                     // one request
+  Buf pid, small, tiles, perm, lv, hist, tcodes, acc;                // one request
   Buf bpid, bperm, btiles, bsmall, btcodes, bacc;   // multi-plan launches
   JobSlot slots[kJobSlots];
   int next_slot = 0;
@@ -1011,6 +1015,7 @@ struct Scratch {
   uint32_t* lv;
   void* hist;
   void* tcodes;   // dense translates of the rows (plans with a step table)
+  uint32_t* acc;  // tile parts: [n][g] summed level counts, then [max_tiles] finished parts
   uint64_t max_tiles;
 };
 
@@ -1018,10 +1023,10 @@ struct Scratch {
 // results, also needed for the factorization partition and the passes of the
 // matrix-product path; tcodes: dense translates of the rows).
 struct ScratchSizes {
-  uint64_t pid, small, tiles, perm, lv, hist, tcodes;
+  uint64_t pid, small, tiles, perm, lv, hist, tcodes, acc;
   uint64_t max_tiles;
 };
-ScratchSizes scratch_sizes(uint64_t n, uint32_t g, int cb, bool plain, bool hist, bool tcodes) {
+ScratchSizes scratch_sizes(uint64_t n, uint32_t g, int cb, bool plain, bool hist, bool tcodes, bool parts = false) {
   const uint32_t npat = hwc::pattern_count(g);
   ScratchSizes z{};
   z.max_tiles = n / hwc::kWave + npat + 1;
@@ -1032,6 +1037,7 @@ ScratchSizes scratch_sizes(uint64_t n, uint32_t g, int cb, bool plain, bool hist
   z.lv = plain ? std::max<uint64_t>(n, 1) * g * 4 : 0;
   z.hist = hist ? hwc::hist_scratch_bytes(n) : 0;
   z.tcodes = tcodes ? std::max<uint64_t>(n, 1) * (2 * g + 3) * (uint64_t)cb : 0;
+  z.acc = parts ? (n * g + z.max_tiles) * 4 : 0;
   return z;
 }
 
@@ -1058,12 +1064,13 @@ uint64_t carve_scratch(const ScratchSizes& z, uint32_t g, uint8_t* base, Scratch
   s->lv = static_cast<uint32_t*>(take(z.lv));
   s->hist = take(z.hist);
   s->tcodes = take(z.tcodes);
+  s->acc = static_cast<uint32_t*>(take(z.acc));
   return off;
 }
 
 int get_scratch(hwc_ctx* c, int set, uint64_t n, uint32_t g, int cb, bool plain, bool hist, bool tcodes,
-                Scratch* s) {
-  const ScratchSizes z = scratch_sizes(n, g, cb, plain, hist, tcodes);
+                bool parts, Scratch* s) {
+  const ScratchSizes z = scratch_sizes(n, g, cb, plain, hist, tcodes, parts);
   ScratchSet& st = c->sets[set];
   int rc;
   if ((rc = ensure(c, set, st.pid, z.pid))) return rc;
@@ -1073,6 +1080,7 @@ int get_scratch(hwc_ctx* c, int set, uint64_t n, uint32_t g, int cb, bool plain,
   if (plain && (rc = ensure(c, set, st.lv, z.lv))) return rc;
   if (hist && (rc = ensure(c, set, st.hist, z.hist))) return rc;
   if (tcodes && (rc = ensure(c, set, st.tcodes, z.tcodes))) return rc;
+  if (parts && (rc = ensure(c, set, st.acc, z.acc))) return rc;
   const uint32_t npat = hwc::pattern_count(g);
   s->max_tiles = z.max_tiles;
   s->pid = static_cast<uint16_t*>(st.pid.p);
@@ -1088,6 +1096,7 @@ int get_scratch(hwc_ctx* c, int set, uint64_t n, uint32_t g, int cb, bool plain,
   s->lv = plain ? static_cast<uint32_t*>(st.lv.p) : nullptr;
   s->hist = hist ? st.hist.p : nullptr;
   s->tcodes = tcodes ? st.tcodes.p : nullptr;
+  s->acc = parts ? static_cast<uint32_t*>(st.acc.p) : nullptr;
   return HWC_OK;
 }
 
@@ -1100,6 +1109,15 @@ uint32_t persistent_grid(uint32_t resident, uint32_t block, uint64_t tiles) {
   const uint64_t per = std::max<uint32_t>(block / hwc::kWave, 1);
   const uint64_t need = (tiles + per - 1) / per;
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(resident, need));
+}
+
+// log2 of the parts each tile's top-level sweep is cut into (kPartMinPoints):
+// orbit sweeps of the Zech path only (the point lists are explicit), not the
+// plain form (one launch per level, whole tiles)
+uint32_t part_log(const DevPlan* P, uint32_t flags) {
+  if (P->vpath || !P->orbit || (flags & HWC_PLAIN)) return 0;
+  const hwc::LevelDesc& top = P->desc.lv[P->g - 1];
+  return top.xs && top.nx >= kPartMinPoints ? kPartLog : 0;
 }
 
 // Enqueue the whole count of one request on stream s.
@@ -1169,14 +1187,17 @@ int enqueue(hwc_ctx* c, DevPlan* P, const Scratch& S, const void* codes, int cb,
     if (flags & HWC_PLAIN) {
       for (uint32_t j = 0; j < g; ++j)
         HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, nullptr, j, j, nullptr, S.lv,
-                                  P->grid, P->block, P->wpe, s));
+                                  0, nullptr, nullptr, P->grid, P->block, P->wpe, s));
       HIPX(c, hwc::launch_assemble(P->desc, cb, codes, n, S.lv, N, s));
     } else {
       // a tile per bucket's ragged end besides the full ones (translated rows
       // fall in a few buckets; more tiles are still all counted)
       const uint32_t grid = persistent_grid(P->grid, P->block, (n + hwc::kWave - 1) / hwc::kWave + 4);
+      const uint32_t plog = S.acc ? part_log(P, flags) : 0u;
+      if (plog) HIPX(c, hwc::launch_fill(S.acc, 0, n * g + S.max_tiles, s));
       HIPX(c, hwc::launch_count(P->desc, P->d_desc, cb, codes, S.perm, S.tiles, S.ntiles, S.queue, 0, g - 1, N,
-                                lam ? S.lv : nullptr, grid, P->block, P->wpe, s));
+                                lam ? S.lv : nullptr, plog, plog ? S.acc : nullptr, plog ? S.acc + n * g : nullptr,
+                                grid, P->block, P->wpe, s));
     }
     if (lam) HIPX(c, hwc::launch_lambda(P->desc, P->d_desc, cb, codes, n, S.lv, lam, (flags & kFlagSqf) ? 1u : 0u, s));
   }
@@ -1248,7 +1269,9 @@ int run_dev(hwc_ctx* c, uint32_t q, uint32_t g, const void* codes, int cb, uint6
   const int set = set_for(c, s);
   (void)reap(c, false);
   Scratch S;
-  if ((rc = get_scratch(c, set, n, g, cb, needs_lv(P, flags, lam), hk != nullptr, needs_tcodes(P), &S))) return rc;
+  if ((rc = get_scratch(c, set, n, g, cb, needs_lv(P, flags, lam), hk != nullptr, needs_tcodes(P),
+                        part_log(P, flags) > 0, &S)))
+    return rc;
   const bool use_graph = !(flags & (HWC_PLAIN | HWC_NO_GRAPH)) && n > 0 && !c->profile;
   if ((rc = order_begin(c, set, s))) return rc;
   if (!use_graph) {
@@ -1336,7 +1359,6 @@ struct BatchPlan {
   std::vector<uint32_t> plog;       // tile parts (log2) per sorted job
   std::vector<uint64_t> aoff;       // word offset of the job's part counts in bacc
   uint64_t ntot = 0, tiles_tot = 0, nhist = 0, tbytes = 0, nlv = 0, acc_words = 0;
-  uint64_t resident = 0;            // waves the batch launch keeps in flight
 };
 
 
@@ -1486,7 +1508,6 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
       }
     }
     G.grid = persistent_grid((uint32_t)(c->cus * bpc_best), G.block, tiles);
-    B.resident = (uint64_t)c->cus * bpc_best * (G.block / hwc::kWave);
     B.segs.push_back(G);
   }
   for (size_t r = 0; r < nz; ++r) {
@@ -1497,13 +1518,7 @@ int run_batch(hwc_ctx* c, const hwc_job* jobs, size_t njobs, uint32_t flags, hip
     B.max_tiles.push_back(mt);
     B.ntot += J.n;
     B.tiles_tot += mt;
-    // a job of few expensive tiles (a large top level swept by orbits) has
-    // each tile's top level cut into parts, so that its work spreads over the
-    // waves in flight instead of holding a few of them for the whole launch
-    const hwc::LevelDesc& top = B.plans[B.order[r]]->desc.lv[J.g - 1];
-    uint32_t pl = 0;
-    if (orbit && top.xs && top.nx >= kPartMinPoints)
-      while (pl < kPartMaxLog && (J.n / hwc::kWave + 1) << pl < B.resident) ++pl;
+    const uint32_t pl = part_log(B.plans[B.order[r]], flags);
     B.plog.push_back(pl);
     B.aoff.push_back(B.acc_words);
     if (pl) B.acc_words += J.n * J.g + mt;
@@ -2070,8 +2085,8 @@ void hwc_ctx_destroy(hwc_ctx* c) {
     for (Buf* b : {&c->N, &c->codes, &c->hout, &c->mcodes, &c->mN, &c->mlam, &c->mhk, &c->mhc, &c->mcj})
       if (b->p) (void)hipFree(b->p);
     for (auto& st : c->sets) {
-      for (Buf* b : {&st.pid, &st.small, &st.tiles, &st.perm, &st.lv, &st.hist, &st.tcodes, &st.bpid, &st.bperm,
-                     &st.btiles, &st.bsmall, &st.btcodes, &st.bacc})
+      for (Buf* b : {&st.pid, &st.small, &st.tiles, &st.perm, &st.lv, &st.hist, &st.tcodes, &st.acc, &st.bpid,
+                     &st.bperm, &st.btiles, &st.bsmall, &st.btcodes, &st.bacc})
         if (b->p) (void)hipFree(b->p);
       for (auto& sl : st.slots) {
         if (sl.p) (void)hipFree(sl.p);
@@ -2490,7 +2505,7 @@ int hwc_ctx_reserve(hwc_ctx* c, uint64_t max_curves, uint32_t max_jobs, void* st
   ScratchSet& st = c->sets[set];
   const uint64_t N = std::max<uint64_t>(max_curves, 1), J = max_jobs;
   // one request of N rows at the largest genus and code width, every optional part
-  const ScratchSizes z = scratch_sizes(N, hwc::kMaxG, 2, true, true, true);
+  const ScratchSizes z = scratch_sizes(N, hwc::kMaxG, 2, true, true, true, true);
   int rc;
   if ((rc = ensure(c, set, st.pid, z.pid))) return rc;
   if ((rc = ensure(c, set, st.small, z.small))) return rc;
@@ -2499,6 +2514,7 @@ int hwc_ctx_reserve(hwc_ctx* c, uint64_t max_curves, uint32_t max_jobs, void* st
   if ((rc = ensure(c, set, st.lv, z.lv))) return rc;
   if ((rc = ensure(c, set, st.hist, z.hist))) return rc;
   if ((rc = ensure(c, set, st.tcodes, z.tcodes))) return rc;
+  if ((rc = ensure(c, set, st.acc, z.acc))) return rc;
   // a multi-plan batch of N rows over at most J jobs (run_batch's sizes, bounded
   // with every job at the largest genus)
   const uint64_t tiles = N / hwc::kWave + J * (hwc::pattern_count(hwc::kMaxG) + 1);

@@ -15,11 +15,13 @@ namespace hwc {
 template <int G>
 struct CountEntry {
   // count_kernel<G, CT, WPE> over levels lo..hi (CT from coeff_bytes, the
-  // register budget WPE = 1, 6 or 8 waves per SIMD from wpe)
+  // register budget WPE = 1, 6 or 8 waves per SIMD from wpe); plog > 0 (with
+  // a queue and every level): each tile's top level in 2^plog parts, their
+  // counts summed in acc ([n][G], zeroed) and counted per tile in done
   static hipError_t launch(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes,
                            const uint32_t* perm, const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue,
-                           uint32_t lo, uint32_t hi, int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block,
-                           uint32_t wpe, hipStream_t s);
+                           uint32_t lo, uint32_t hi, int32_t* outN, uint32_t* outLv, uint32_t plog, uint32_t* acc,
+                           uint32_t* done, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s);
   // batch_kernel<G> over njobs jobs, image slot of `slot` bytes
   static hipError_t batch(const JobDesc* jobs, uint32_t njobs, uint32_t slot, uint32_t grid, uint32_t block,
                           hipStream_t s);

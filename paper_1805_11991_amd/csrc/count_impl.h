@@ -1105,14 +1105,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
                                                      const uint64_t* __restrict__ tiles,
                                                      const uint32_t* __restrict__ ntiles_p, uint32_t* queue,
                                                      uint32_t lvl_lo, uint32_t lvl_hi, int32_t* __restrict__ outN,
-                                                     uint32_t* __restrict__ outLv) {
+                                                     uint32_t* __restrict__ outLv, uint32_t plog,
+                                                     uint32_t* __restrict__ acc, uint32_t* __restrict__ done) {
   const PlanDesc& P = *Pd;
   extern __shared__ uint32_t lds32[];
   constexpr uint32_t lb = kImageBase;
   for (uint32_t i = threadIdx.x; i < P.image_bytes / 4; i += blockDim.x) lds32[i] = P.image[i];
   __syncthreads();
   const uint32_t lane = threadIdx.x & (kWave - 1);
-  const uint32_t ntiles = *ntiles_p;
+  // queue entries: tiles, or (plog > 0, levels 0..G-1 through the queue) the
+  // 2^plog parts of every tile, as in the batch kernel
+  const uint32_t ntiles = *ntiles_p << plog;
+  const uint32_t pmask = (1u << plog) - 1u;
   const uint32_t nwaves = (gridDim.x * blockDim.x) / kWave;
   uint32_t t;
   if (queue) {
@@ -1123,7 +1127,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(WPE))) voi
     t = uniform((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   }
   while (t < ntiles) {
-    process_tile<G, CT>(P, lb, codes, perm, sload64(tiles, t), lvl_lo, lvl_hi, outN, outLv);
+    process_tile<G, CT>(P, lb, codes, perm, sload64(tiles, t >> plog), lvl_lo, lvl_hi, outN, outLv, t >> plog,
+                        t & pmask, plog, acc, done);
     if (queue) {
       uint32_t v = 0;
       if (lane == 0) v = atomicAdd(queue, 1u);

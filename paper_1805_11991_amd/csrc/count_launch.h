@@ -9,11 +9,12 @@ namespace hwc {
 template <int G>
 hipError_t CountEntry<G>::launch(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes,
                                  const uint32_t* perm, const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue,
-                                 uint32_t lo, uint32_t hi, int32_t* outN, uint32_t* outLv, uint32_t grid,
-                                 uint32_t block, uint32_t wpe, hipStream_t s) {
+                                 uint32_t lo, uint32_t hi, int32_t* outN, uint32_t* outLv, uint32_t plog,
+                                 uint32_t* acc, uint32_t* done, uint32_t grid, uint32_t block, uint32_t wpe,
+                                 hipStream_t s) {
 #define HWC_LAUNCH(CT, W)                                                                                   \
   hipLaunchKernelGGL((count_kernel<G, CT, W>), dim3(grid), dim3(block), P.image_bytes, s, dP,                \
-                     static_cast<const CT*>(codes), perm, tiles, ntiles, queue, lo, hi, outN, outLv)
+                     static_cast<const CT*>(codes), perm, tiles, ntiles, queue, lo, hi, outN, outLv, plog, acc, done)
   if (coeff_bytes == 1) {
     if (wpe >= 8) HWC_LAUNCH(int8_t, 8);
     else if (wpe >= 6) HWC_LAUNCH(int8_t, 6);

@@ -673,11 +673,12 @@ hipError_t prepare_kernels() {
 
 hipError_t launch_count(const PlanDesc& P, const PlanDesc* dP, int coeff_bytes, const void* codes, const uint32_t* perm,
                         const uint64_t* tiles, const uint32_t* ntiles, uint32_t* queue, uint32_t lo, uint32_t hi,
-                        int32_t* outN, uint32_t* outLv, uint32_t grid, uint32_t block, uint32_t wpe, hipStream_t s) {
+                        int32_t* outN, uint32_t* outLv, uint32_t plog, uint32_t* acc, uint32_t* done, uint32_t grid,
+                        uint32_t block, uint32_t wpe, hipStream_t s) {
 #define HWC_CASE(GG)                                                                                         \
   case GG:                                                                                                   \
     return CountEntry<GG>::launch(P, dP, coeff_bytes, codes, perm, tiles, ntiles, queue, lo, hi, outN, outLv, \
-                                  grid, block, wpe, s);
+                                  plog, acc, done, grid, block, wpe, s);
   switch (P.g) {
     HWC_CASE(1) HWC_CASE(2) HWC_CASE(3) HWC_CASE(4)
     default: return hipErrorInvalidValue;

@@ -45,7 +45,7 @@ def _run(ctx, q, g, curves, flags=0, hist=True):
 
 CASES = [(3, 1, 300), (5, 1, 300), (3, 2, 800), (5, 2, 600), (7, 2, 400), (9, 2, 300), (13, 2, 300),
          (25, 2, 120), (3, 3, 400), (5, 3, 300), (13, 3, 300), (9, 3, 100), (17, 3, 60), (3, 4, 300),
-         (5, 4, 150), (13, 4, 80)]
+         (5, 4, 150), (13, 4, 80), (37, 3, 40)]   # 37^3: the top level's sweep in tile parts
 
 
 @pytest.mark.parametrize("q,g,n", CASES)
