@@ -433,6 +433,10 @@ def main():
     roofline["traffic_unit"] = "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     roofline["traffic_detail"] = traffic
     roofline["counters"] = measured_counters(args.path)
+    # the other resource the count kernel saturates: the measured issue rate of
+    # plain 32-bit vector instructions, per CU and clock (counters' units)
+    valu_rate = ctx.valu_issue_rate()
+    roofline["valu_issue_ceiling_per_cu_clock"] = round(valu_rate / (NUM_CU * CLOCK_HZ), 4)
     roofline["prep_ms"] = round(km["prep_ms"], 4)
     roofline["hist_ms"] = round(km["hist_ms"], 4)
     log(f"roofline: {roofline['kernel']} {km['count_ms']:.3f} ms, {roofline['achieved']} {roofline['unit']} "
@@ -471,6 +475,7 @@ def main():
         mroof["traffic"] = None if mtraffic is None else mtraffic["fetch"] + mtraffic["write"]
         mroof["traffic_detail"] = mtraffic
         mroof["counters"] = measured_counters("mfma")
+        mroof["valu_issue_ceiling_per_cu_clock"] = roofline["valu_issue_ceiling_per_cu_clock"]
         mroof["kernel"] = "vcount_kernel<3,int8>"
         mp["g3_q13"] = {"curves": n, "batched": mb, "plain": mpl, "batched_vs_plain": ratio(mpl, mb),
                         "curves_per_s": round(n / (mb["ms_per_step"] * 1e-3), 1), "roofline": mroof,

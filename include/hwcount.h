@@ -250,6 +250,13 @@ int hwc_count_single(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs
  * best of two timed runs.  Synchronous. */
 int hwc_lds_gather_rate(hwc_ctx* ctx, uint32_t table_entries, uint32_t chains, double* lookups_per_s);
 
+/* Diagnostic: the issue rate of plain 32-bit vector instructions (chains of
+ * add, subtract and min, eight independent chains per lane, eight waves per
+ * SIMD), in wave64 instructions per second over the whole device -- the
+ * other resource the count kernels' table walks (Sec. 3.3) saturate.  Best of
+ * two timed runs; synchronous. */
+int hwc_valu_issue_rate(hwc_ctx* ctx, double* insts_per_s);
+
 /* Diagnostic: the rate of dependent random u32 gathers from a table of
  * table_entries entries (64 .. 2^26) in device memory -- the placement of
  * Zech tables too large for LDS (Sec. 3.2 tables read at random, served by

@@ -63,6 +63,7 @@ hipError_t launch_single(const uint32_t* zech, const uint32_t* xs, uint64_t nx, 
 hipError_t launch_dev_table_fill(uint32_t* tab, uint32_t entries, hipStream_t s);
 hipError_t launch_dev_gather(const uint32_t* tab, uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid,
                              uint32_t* sink, hipStream_t s);
+hipError_t launch_valu_issue(uint32_t iters, uint32_t grid, uint32_t* sink, hipStream_t s);
 hipError_t launch_lds_gather(uint32_t entries, uint32_t chains, uint32_t steps, uint32_t grid, uint32_t* sink,
                              hipStream_t s);
 }  // namespace hwc
@@ -2337,6 +2338,41 @@ int hwc_lds_gather_rate(hwc_ctx* c, uint32_t table_entries, uint32_t chains, dou
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   *lookups_per_s = (double)grid * 256.0 * steps * chains / (best * 1e-3);
+  return HWC_OK;
+}
+
+int hwc_valu_issue_rate(hwc_ctx* c, double* insts_per_s) {
+  if (!c || !insts_per_s) return HWC_ERR_ARG;
+  std::lock_guard<std::mutex> lk(c->mu);
+  c->err.clear();
+  if (c->device < 0) return fail(c, HWC_ERR_NO_DEVICE, "host-only context");
+  HIPX(c, hipSetDevice(c->device));
+  int rc;
+  if ((rc = ensure_sync(c, c->hout, 64))) return rc;
+  int ncu = 0;
+  HIPX(c, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device));
+  const uint32_t grid = (uint32_t)ncu * 8, iters = 4096;   // 8 waves per SIMD
+  uint32_t* sink = static_cast<uint32_t*>(c->hout.p);
+  hipEvent_t e0, e1;
+  HIPX(c, hipEventCreate(&e0));
+  HIPX(c, hipEventCreate(&e1));
+  float best = 0;
+  for (int rep = 0; rep < 3; ++rep) {   // warm-up, then the best of two
+    if (hipEventRecord(e0, c->stream) != hipSuccess ||
+        hwc::launch_valu_issue(iters, grid, sink, c->stream) != hipSuccess ||
+        hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      return fail(c, HWC_ERR_DEVICE, "issue-rate benchmark failed");
+    }
+    float ms = 0;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (rep > 0 && (best == 0 || ms < best)) best = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  // wave64 instructions: waves x iterations x 192
+  *insts_per_s = (double)grid * (256 / hwc::kWave) * iters * 192.0 / (best * 1e-3);
   return HWC_OK;
 }
 

@@ -7,7 +7,9 @@
 // every lane of a full grid.  The rate it reaches is the practical ceiling
 // the count kernel is compared against beside the HBM and MFMA peaks.
 // dev_gather_kernel does the same over a u32 table in device memory, the
-// placement of Zech tables too large for LDS.
+// placement of Zech tables too large for LDS.  valu_issue_kernel measures the
+// other resource the count kernels saturate: the issue rate of plain 32-bit
+// vector instructions.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -102,7 +104,34 @@ hipError_t launch_dev_ch(const uint32_t* tab, uint32_t entries, uint32_t steps, 
   return hipGetLastError();
 }
 
+// Eight independent chains per lane of a = min(a + b, a - c): three plain
+// 32-bit VALU instructions per chain and step (v_add, v_sub, v_min), no
+// dependence between the chains, 8 x 8 x 3 = 192 per loop iteration.
+__global__ __launch_bounds__(256) void valu_issue_kernel(uint32_t iters, uint32_t b, uint32_t c, uint32_t odd,
+                                                         uint32_t* __restrict__ sink) {
+  uint32_t a[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = (threadIdx.x * (k + 3)) ^ blockIdx.x;
+  for (uint32_t i = 0; i < iters; ++i) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) a[k] = min(a[k] + b, a[k] - c);
+    }
+  }
+  uint32_t x = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x ^= a[k];
+  if (x == odd && b == c) sink[0] = x;   // b != c in every launch: keeps the chains live
+}
+
 }  // namespace
+
+hipError_t launch_valu_issue(uint32_t iters, uint32_t grid, uint32_t* sink, hipStream_t s) {
+  if (grid == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(valu_issue_kernel, dim3(grid), dim3(256), 0, s, iters, 7u, 5u, 1u, sink);
+  return hipGetLastError();
+}
 
 // tab: `entries` u32 of device memory, entries in [64, 2^26]
 hipError_t launch_dev_table_fill(uint32_t* tab, uint32_t entries, hipStream_t s) {

@@ -45,7 +45,7 @@ HWC_OPT_MFMA = 8
 #: every symbol the header declares
 EXPORTS = ("hwc_ctx_create", "hwc_ctx_destroy", "hwc_last_error", "hwc_build_field", "hwc_field_info",
            "hwc_field_tables", "hwc_field_release", "hwc_count_curves", "hwc_count_curves_dev",
-           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate",
+           "hwc_count_lambda_dev", "hwc_count_map", "hwc_count_single", "hwc_lds_gather_rate", "hwc_valu_issue_rate",
            "hwc_translate_dev", "hwc_count_batch", "hwc_ctx_status", "hwc_ctx_stats", "hwc_ctx_profile",
            "hwc_ctx_profile_read", "hwc_plan_info", "hwc_ctx_set_option", "hwc_ctx_set_plan_option",
            "hwc_ctx_reserve", "hwc_count_curves_dev_noalloc", "hwc_device_gather_rate")
@@ -119,6 +119,7 @@ def load():
         "hwc_count_map": (i32, [vp, u32, u32, vp, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(u64), u32]),
         "hwc_count_single": (i32, [vp, u32, u32, vp, u32, vp, vp, u32]),
         "hwc_lds_gather_rate": (i32, [vp, u32, u32, ctypes.POINTER(ctypes.c_double)]),
+        "hwc_valu_issue_rate": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
         "hwc_device_gather_rate": (i32, [vp, u64, u32, ctypes.POINTER(ctypes.c_double)]),
         "hwc_translate_dev": (i32, [vp, u32, u32, vp, i32, u64, vp, vp]),
         "hwc_count_batch": (i32, [vp, ctypes.POINTER(hwc_job), ctypes.c_size_t, u32, vp]),
@@ -334,6 +335,12 @@ class Context:
         """Measured dependent random u16 LDS gathers per second (diagnostic)."""
         r = ctypes.c_double()
         self._check(load().hwc_lds_gather_rate(self._h, table_entries, chains, ctypes.byref(r)))
+        return r.value
+
+    def valu_issue_rate(self) -> float:
+        """Measured wave64 issue rate of plain 32-bit vector instructions, per second (diagnostic)."""
+        r = ctypes.c_double()
+        self._check(load().hwc_valu_issue_rate(self._h, ctypes.byref(r)))
         return r.value
 
     def device_gather_rate(self, table_entries: int, chains: int = 4) -> float:

@@ -673,6 +673,15 @@ def test_batch_g4_small_fields_sampled(gctx, oracle_mod, curvegen_mod):
 
 
 @pytest.mark.gpu
+def test_valu_issue_rate_is_at_most_one_per_cu_clock(gctx):
+    # the diagnostic issue-rate kernel: plain 32-bit instructions reach at most
+    # one wave64 instruction per CU per clock (4 SIMDs x 16 lanes), 256 CUs at
+    # no more than 2.4 GHz, and well above a quarter of it
+    r = gctx.valu_issue_rate()
+    assert 0.25 * 256 * 2.4e9 < r <= 1.05 * 256 * 2.4e9, r
+
+
+@pytest.mark.gpu
 def test_lds_gather_rate_is_below_the_bank_peak(gctx):
     from paper_1805_11991_amd import hwcount
     # the diagnostic gather kernel: a positive rate no faster than 32 u16 reads
