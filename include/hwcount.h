@@ -153,7 +153,10 @@ int hwc_count_curves(hwc_ctx* ctx, uint32_t q, uint32_t g, const int16_t* coeffs
  * found on the device and reported by hwc_ctx_status.  The histogram is
  * written when d_hist_keys is not NULL (d_hist_len receives its length; at
  * most hist_capacity entries are written).  Buffers must stay valid until
- * the stream reaches this work. */
+ * the stream reaches this work.  Where the top level sweeps at least 8192
+ * points by Frobenius orbits, every tile's top-level sweep is shared out over
+ * 8 waves whose counts are summed before N is assembled (not in the plain
+ * form, which keeps one launch per level over whole tiles). */
 int hwc_count_curves_dev(hwc_ctx* ctx, uint32_t q, uint32_t g, const void* d_coeffs, int coeff_bytes, uint64_t n,
                          int32_t* d_out_N, int32_t* d_hist_keys, uint64_t* d_hist_counts, uint64_t hist_capacity,
                          uint64_t* d_hist_len, uint32_t flags, void* stream);
@@ -272,9 +275,9 @@ int hwc_device_gather_rate(hwc_ctx* ctx, uint64_t table_entries, uint32_t chains
  * multi-plan launch takes the jobs one after another, most expensive tiles
  * first, every wave popping tiles from the current job's queue (the LDS
  * image restaged only when a workgroup moves to a job of another plan; a
- * job of few tiles over a large top level has each tile's top-level sweep
- * shared out over up to 8 waves, whose counts are summed before N is
- * assembled) -- the loops over the curves and fields of Algorithm 1 in one
+ * job whose top level sweeps at least 8192 points by orbits has each tile's
+ * top-level sweep shared out over 8 waves, whose counts are summed before N
+ * is assembled) -- the loops over the curves and fields of Algorithm 1 in one
  * launch, where
  * the paper launches once per curve and field (Sec. 3.3); jobs on the
  * opt-in matrix-product path follow as their own launches on the same
